@@ -1,0 +1,306 @@
+#!/usr/bin/env python3
+"""Headline benchmark: fwd+bwd views/s and render Mpix/s at 1280x720 with a 1M-Gaussian map.
+
+Workload: a seeded synthetic street map of 1,000,000 Gaussians (50 % ground plane, 30 % box
+facades, 20 % vegetation clusters; SH degree 3; float32) viewed by one 1280x720 pinhole
+(fx = fy = 900) 10 m down the street, with a 32-beam LiDAR mask (~2 % of pixels). Targets
+come from a copy of the map perturbed by N(0, 0.01^2) noise, rendered once by the same GPU
+path before timing.
+
+One step = the whole hot path on one view with inputs resident in HBM: projection + SH (a1),
+binning with the alpha-max cull and the (tile, depth) sort (a2), compositing (a3) with the
+sparse-LiDAR depth term (a6), the RGB L1 loss, and the backward to every parameter and the
+pose (a4, a5). Gradient buffers are zeroed inside the step (the ABI accumulates).
+
+Prints ONE JSON line. `value` is fwd+bwd views/s on one GPU.
+"""
+from __future__ import annotations
+
+import argparse
+import ctypes as C
+import json
+import os
+import statistics
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+FP32_PEAK_TFLOPS = 157.3
+# Algorithmic work per unit (see the design notes): bytes for HBM-bound stages, flops for
+# the compositing stages (per alpha evaluation / per contribution).
+BYTES_PRE_PER_N = 12
+BYTES_PRE_PER_V = 224 + 56
+BYTES_BIN_PER_V = 52
+BYTES_BIN_PER_P = 12 + 24
+BYTES_PREBWD_PER_V = 236 + 40 + 236
+FLOPS_FWD_EVAL, FLOPS_FWD_CONTRIB = 13, 13
+FLOPS_BWD_EVAL, FLOPS_BWD_CONTRIB = 13, 50
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--latency-calls", type=int, default=200)
+    ap.add_argument("--n", type=int, default=1_000_000)
+    ap.add_argument("--tile", type=int, default=16)
+    ap.add_argument("--blend-depth", type=int, default=256)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-repeats", type=int, default=1)
+    return ap.parse_args()
+
+
+class PlainStep:
+    """Buffers and pre-built C structs for one view; step() enqueues the whole hot path."""
+
+    def __init__(self, R, N, torch, g, cam, pix, target_color, ds, tile, bd, dev):
+        self.R, self.N, self.torch = R, N, torch
+        self.L = N.lib()
+        self.gm = R.GaussianMap.from_numpy(g, dev)
+        self.cs = R.camera_struct(cam)
+        self.gs = self.gm.struct()
+        self.n = self.gs.n
+        self.tile, self.bd, self.dev = tile, bd, dev
+        self.spl = R.Splats.empty(self.n, dev)
+        R.preprocess(self.gs, self.cs, tile, dev, out=self.spl)
+        fit = R.bin_sort_fit(self.spl, self.n, self.cs, tile, dev)
+        self.capacity = int(fit.pairs() * 1.25) + 1024
+        self.bins = R.alloc_bins(self.n, self.cs, tile, self.capacity, dev)
+        del fit
+        self.frame = R.Frame.empty(cam.h, cam.w, dev)
+        self.lidar = R.LidarHits(torch.from_numpy(pix).to(dev), torch.from_numpy(ds).to(dev), weight=1.0)
+        self.lidar_loss = torch.zeros(1, device=dev)
+        self.rgb_loss = torch.zeros(1, device=dev)
+        self.target = target_color
+        self.dLdC = torch.empty_like(self.frame.color)
+        k = self.gm.sh_rest.shape[0]
+        self.flat = torch.zeros(self.n * (3 + 3 + 4 + 1 + 3 + k) + 6, device=dev)
+        views, off = [], 0
+        for rows in (3, 3, 4, 1, 3, k):
+            views.append(self.flat[off:off + rows * self.n].view(rows, self.n) if rows > 1 else
+                         self.flat[off:off + self.n])
+            off += rows * self.n
+        pose = self.flat[off:off + 6]
+        self.grads = R.ParamGrads(*views, pose)
+        self.scratch = R.grads_scratch(self.n, cam.w * cam.h, dev)
+        # pre-built structs (the pointers never change)
+        self.s_proj = self.spl.struct()
+        self.s_bins = self.bins.struct()
+        self.s_img = self.frame.struct()
+        self.s_lid_f = self.lidar.struct(self.lidar_loss)
+        self.s_lid_b = self.lidar.struct(None)
+        self.s_grads = self.grads.struct(self.scratch)
+        self.p_color = C.c_void_p(self.frame.color.data_ptr())
+        self.p_target = C.c_void_p(self.target.data_ptr())
+        self.p_dldc = C.c_void_p(self.dLdC.data_ptr())
+        self.p_rgbloss = C.c_void_p(self.rgb_loss.data_ptr())
+        self.nval = self.frame.color.numel()
+
+    def stream(self):
+        return C.c_void_p(self.torch.cuda.current_stream().cuda_stream)
+
+    def forward(self, st=None):
+        L, N = self.L, self.N
+        st = st or self.stream()
+        N.check(L.gs_preprocess(C.byref(self.gs), C.byref(self.cs), self.tile, self.tile, C.byref(self.s_proj), st))
+        N.check(L.gs_bin_sort(C.byref(self.s_proj), self.n, C.byref(self.cs), C.byref(self.s_bins), st))
+        N.check(L.gs_render_fwd(C.byref(self.s_proj), self.n, C.byref(self.s_bins), C.byref(self.cs), self.bd,
+                                C.byref(self.s_lid_f), C.byref(self.s_img), st))
+
+    def step(self):
+        L, N = self.L, self.N
+        st = self.stream()
+        self.forward(st)
+        N.check(L.gs_loss_l1(self.p_color, self.p_target, self.nval, 1.0, self.p_dldc, self.p_rgbloss, st))
+        self.flat.zero_()
+        N.check(L.gs_render_bwd(C.byref(self.gs), C.byref(self.cs), C.byref(self.s_proj), C.byref(self.s_bins),
+                                C.byref(self.s_img), self.p_dldc, None, None, C.byref(self.s_lid_b), self.bd,
+                                C.byref(self.s_grads), st))
+
+
+def cpu_baseline(g, cam, gC_np, repeats):
+    """The FP64 oracle (as it stands) on the host: one full-view fwd + bwd of the same workload."""
+    import numpy as np
+    import oracle
+    oc = oracle.camera_f32(cam)
+    times = []
+    for _ in range(repeats):
+        t0 = time.perf_counter()
+        oracle.render(g, oc, tile=16, band=0.0)
+        oracle.backward(g, oc, gC_np)
+        times.append(time.perf_counter() - t0)
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    t = statistics.median(times)
+    return {"value": round(1.0 / t, 4), "unit": "views/s", "cores": threads, "kind": "oracle",
+            "sample": f"one full 1280x720 fwd+bwd view of the 1M-Gaussian map in float64 (median of {repeats}; "
+                      f"{t:.1f} s per view; upstream dL/dC = sign residual of the L1 loss)"}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1",
+                          "n_gpus": args.gpus}), flush=True)
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    from paper_2507_04004_amd import _native as N
+    from paper_2507_04004_amd import raster as R
+    from paper_2507_04004_amd import scenes as S
+
+    if not torch.cuda.is_available():
+        print(json.dumps({"error": "no GPU visible"}), flush=True)
+        sys.exit(1)
+    dev = "cuda:0"
+    log("[bench] generating the 1M-Gaussian street map")
+    g = S.street_map(args.n, seed=2)
+    cam = S.headline_camera()
+    pix = S.lidar_beams(cam, 32, 30.0, 0.32, seed=102)
+
+    # Targets: a perturbed copy rendered once by the same GPU path (untimed).
+    log("[bench] rendering targets")
+    gp = S.perturb(g, 0.01, seed=3)
+    tgt = PlainStep(R, N, torch, gp, cam, pix, torch.zeros(3, cam.h, cam.w, device=dev),
+                    np.zeros(pix.size, np.float32), args.tile, args.blend_depth, dev)
+    tgt.forward()
+    torch.cuda.synchronize()
+    target_color = tgt.frame.color.clone()
+    D = tgt.frame.depth.flatten().cpu().numpy()
+    O = tgt.frame.alpha.flatten().cpu().numpy()
+    keep = O[pix] > 0
+    pix = pix[keep].astype(np.int32)
+    ds = (D[pix] / O[pix]).astype(np.float32)
+    del tgt
+    torch.cuda.empty_cache()
+
+    log("[bench] building the step")
+    ps = PlainStep(R, N, torch, g, cam, pix, target_color, ds, args.tile, args.blend_depth, dev)
+    for _ in range(args.warmup):
+        ps.step()
+    torch.cuda.synchronize()
+
+    # ---- timed fwd+bwd steps, with per-stage kernel events ----------------------------------
+    L = N.lib()
+    N.check(L.gs_profile_enable(0x1F, max(args.steps, 1)))
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        ev[i][0].record()
+        ps.step()
+        ev[i][1].record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    step_ms = [a.elapsed_time(b) for a, b in ev]
+    stage_ms = {}
+    names = {N.GS_STAGE_PREPROCESS: "preprocess", N.GS_STAGE_BIN_SORT: "bin_sort",
+             N.GS_STAGE_BLEND_FWD: "blend_fwd", N.GS_STAGE_BLEND_BWD: "blend_bwd",
+             N.GS_STAGE_PREPROCESS_BWD: "preprocess_bwd"}
+    for sid, name in names.items():
+        tot, cnt = C.c_double(), C.c_int32()
+        N.check(L.gs_profile_read(sid, C.byref(tot), C.byref(cnt)))
+        stage_ms[name] = tot.value / max(cnt.value, 1)
+    L.gs_profile_disable()
+    log(f"[bench] {args.steps} steps in {wall:.3f} s; stage ms {stage_ms}")
+
+    # ---- latency over many calls, and render-only throughput ----------------------------------
+    lat = []
+    n_lat = args.latency_calls
+    evl = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(n_lat)]
+    for i in range(n_lat):
+        evl[i][0].record()
+        ps.step()
+        evl[i][1].record()
+    torch.cuda.synchronize()
+    lat = sorted(a.elapsed_time(b) for a, b in evl)
+    evr = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(n_lat)]
+    for i in range(n_lat):
+        evr[i][0].record()
+        ps.forward()
+        evr[i][1].record()
+    torch.cuda.synchronize()
+    rlat = sorted(a.elapsed_time(b) for a, b in evr)
+    pct = lambda xs, q: xs[min(len(xs) - 1, int(round(q * (len(xs) - 1))))]
+
+    # ---- counts for the roofline (untimed) -----------------------------------------------------
+    P = ps.bins.pairs()
+    assert P <= ps.capacity, "pair capacity overflow during timing"
+    cnt_frame = R.Frame.empty(cam.h, cam.w, dev, count=True)
+    R.render_fwd(ps.spl, ps.n, ps.bins, ps.cs, args.blend_depth, dev, out=cnt_frame)
+    torch.cuda.synchronize()
+    E_b = int((cnt_frame.last.long() + 1).sum().item())
+    C_n = int(cnt_frame.n_contrib.long().sum().item())
+    V = int((ps.spl.n_tiles > 0).sum().item())
+    work = {
+        "preprocess": ("hbm", BYTES_PRE_PER_N * ps.n + BYTES_PRE_PER_V * V),
+        "bin_sort": ("hbm", BYTES_BIN_PER_V * V + BYTES_BIN_PER_P * P),
+        "preprocess_bwd": ("hbm", BYTES_PREBWD_PER_V * V),
+        "blend_fwd": ("alu", FLOPS_FWD_EVAL * E_b + FLOPS_FWD_CONTRIB * C_n),
+        "blend_bwd": ("alu", FLOPS_BWD_EVAL * E_b + FLOPS_BWD_CONTRIB * C_n),
+    }
+    dom = max(stage_ms, key=lambda k: stage_ms[k])
+    bound, amount = work[dom]
+    t_s = stage_ms[dom] * 1e-3
+    if bound == "hbm":
+        achieved, peak, unit = amount / t_s / 1e9, HBM_PEAK_GBS, "GB/s"
+    else:
+        achieved, peak, unit = amount / t_s / 1e12, FP32_PEAK_TFLOPS, "TFLOP/s"
+    roofline = {"bound": bound, "kernel": dom, "achieved": round(achieved, 3), "peak": peak, "unit": unit,
+                "frac": round(achieved / peak, 5), "traffic": None,
+                "avg_launch_ms": round(stage_ms[dom], 4)}
+    per_stage = {}
+    for k, (b, amt) in work.items():
+        ts = stage_ms[k] * 1e-3
+        if ts <= 0:
+            continue
+        if b == "hbm":
+            per_stage[k] = {"ms": round(stage_ms[k], 4), "GB/s": round(amt / ts / 1e9, 1),
+                            "frac_hbm": round(amt / ts / 1e9 / HBM_PEAK_GBS, 4)}
+        else:
+            per_stage[k] = {"ms": round(stage_ms[k], 4), "TFLOP/s": round(amt / ts / 1e12, 3),
+                            "frac_fp32": round(amt / ts / 1e12 / FP32_PEAK_TFLOPS, 4)}
+
+    ms_per_step = wall * 1e3 / args.steps
+    out = {
+        "metric": "fwd+bwd views/s at 1280x720, 1M Gaussians",
+        "value": round(1e3 / ms_per_step, 3),
+        "unit": "views/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "1M-Gaussian street map (SH3), one 1280x720 view, fx=900, 32-beam LiDAR; "
+                               "fwd + L1/LiDAR loss + bwd to all parameters and the pose",
+                   "n_gaussians": ps.n, "width": cam.w, "height": cam.h, "tile": args.tile,
+                   "blend_depth": args.blend_depth, "visible": V, "pairs": P, "evals_bwd": E_b,
+                   "contributions": C_n, "lidar_hits": int(pix.size)},
+        "render_mpix_s": round(cam.w * cam.h / (statistics.median(rlat) * 1e-3) / 1e6, 2),
+        "latency_ms": {"fwd_bwd_p50": round(pct(lat, 0.5), 4), "fwd_bwd_p99": round(pct(lat, 0.99), 4),
+                       "render_p50": round(pct(rlat, 0.5), 4), "render_p99": round(pct(rlat, 0.99), 4),
+                       "calls": n_lat},
+        "stages": per_stage,
+        "roofline": roofline,
+    }
+    if not args.no_cpu_baseline:
+        log("[bench] timing the CPU oracle")
+        gC = np.sign(ps.frame.color.cpu().numpy().astype(np.float64) - target_color.cpu().numpy()) / ps.nval
+        out["cpu_baseline"] = cpu_baseline(g, cam, gC, args.cpu_repeats)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,237 @@
+/* gs.h — C ABI of the gfx950 differentiable Gaussian-splatting rasterizer.
+ *
+ * The library renders a map of anisotropic 3D Gaussians from a pinhole camera and
+ * differentiates the result with respect to every Gaussian parameter and the camera pose.
+ * It follows Sec. "3D Gaussian Splatting Representation" of Gaussian-LIC2 (projection,
+ * EWA covariance, eq:alpha, front-to-back compositing of eq:rendered_rgb, eq:rendered_depth
+ * and eq:rendered_opacity, SH colour, eq:3dgs_jacobi for the pose), the fast tile-based cull
+ * of Sec. "CUDA-Related Acceleration Strategies", and the sparse-LiDAR depth term of
+ * eq:depth_loss.
+ *
+ * Conventions shared by every call:
+ *   - All array pointers are DEVICE pointers, float32 unless stated. "[k][n]" is a set of k
+ *     planes of n elements (SoA): component j of element i is at ptr[j*n + i].
+ *   - Every call is asynchronous on `stream` (a hipStream_t; NULL = the null stream) and
+ *     returns GS_OK or an error code. Argument errors are detected on the host before any
+ *     launch. No call allocates device memory except gs_batch_plan_create.
+ *   - Buffers are owned by the caller and must stay valid until the stream work completes.
+ *   - Gradient outputs are ACCUMULATED (+=): zero them before the first call.
+ *   - Pixel centres sit at integer coordinates. A camera carries a render window
+ *     (x0, y0, w, h) inside its full image; every image plane is window-sized, row-major.
+ *   - Invalid Gaussians are not errors: a non-finite value, |q| = 0, a scale <= 0, a depth
+ *     <= 0.2, an opacity < 1/255 or a footprint outside the window drops the Gaussian
+ *     (zero tiles, zero gradient).
+ */
+#ifndef GS_H
+#define GS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef void *gs_stream_t; /* hipStream_t */
+
+enum {
+  GS_OK = 0,
+  GS_ERR_INVALID_ARG = 1, /* null pointer, bad size, bad tile size, window outside the image ... */
+  GS_ERR_HIP = 2,         /* a HIP launch or API call failed; see gs_last_error() */
+  GS_ERR_UNSUPPORTED = 3, /* device is not gfx950, or a mode the plan was not made for */
+  GS_ERR_CAPACITY = 4     /* reserved for host-side capacity checks (see gs_bins) */
+};
+
+enum { GS_MAX_VIEWS = 16 };
+enum { GS_FWD = 1u, GS_BWD = 2u, GS_GRAPH = 4u };
+
+/* Pinhole camera with world-to-camera pose (^C_W R, ^C p_W), Sec. "3D Gaussian Splatting
+ * Representation". Host struct, passed by pointer. */
+typedef struct gs_camera {
+  int32_t width, height;  /* full image in pixels */
+  int32_t x0, y0, w, h;   /* render window; 0 <= x0, x0 + w <= width, same for y */
+  float fx, fy, cx, cy;   /* pixel = (fx x/z + cx, fy y/z + cy) */
+  float R_cw[9];          /* row-major rotation world -> camera */
+  float t_cw[3];          /* translation world -> camera */
+  float bg[3];            /* background colour added as T_final * bg */
+} gs_camera;
+
+/* The Gaussian map (Sec. "3D Gaussian Splatting Representation"): mean [3][n]; linear scale
+ * [3][n] (> 0); rotation quaternion [4][n] as (w, x, y, z), normalised inside the kernels;
+ * opacity [n] in (0, 1); SH DC coefficients sh_dc [3][n] and higher-order coefficients
+ * sh_rest [3*((deg+1)^2-1)][n] with plane 3*(k-1)+channel for basis k >= 1, kept apart from
+ * the DC plane ("separated SH", Sec. "CUDA-Related Acceleration Strategies" b). sh_rest may
+ * be NULL at degree 0. */
+typedef struct gs_gaussians {
+  int64_t n;
+  int32_t sh_degree; /* 0..3 */
+  const float *mean, *scale, *rot, *opacity, *sh_dc, *sh_rest;
+} gs_gaussians;
+
+/* Per-Gaussian splat records written by gs_preprocess (n = number of Gaussians x views):
+ *   rec_a [n][4] = (u, v, o, d): projected centre mu', opacity, camera-frame depth;
+ *   rec_b [n][4] = (a, b, c, kappa^2): conic Sigma'^-1 = [[a, b], [b, c]] and the squared
+ *                  footprint radius 2 ln(255 o);
+ *   rgb   [n][4] = (r, g, b, 0): view-dependent colour max(0, SH . Y(dir) + 0.5);
+ *   rect  [n][4] int16 inclusive tile rectangle (tx0, ty0, tx1, ty1), -1 when n_tiles = 0;
+ *   n_tiles [n]  number of tiles kept after the alpha-max cull;
+ *   dkey  [n]    sort key: IEEE bits of d, or 0xFFFFFFFF when n_tiles = 0. */
+typedef struct gs_projected {
+  float *rec_a, *rec_b, *rgb;
+  int16_t *rect;
+  uint32_t *n_tiles;
+  uint32_t *dkey;
+} gs_projected;
+
+/* Tile lists (Sec. "CUDA-Related Acceleration Strategies", fast tile-based culling; depth
+ * order of eq:rendered_rgb). Tiles are tile_w x tile_h pixels laid over the render window,
+ * row-major; T = ceil(w/tile_w) * ceil(h/tile_h).
+ *   vals [capacity]   record index of each (tile, Gaussian) pair, sorted by (tile, depth bits,
+ *                     index) — one total order, so exactly one correct result;
+ *   tile_range [2*T]  [begin, end) into vals per tile ([0, 0) when empty);
+ *   num_pairs [1]     device int64: the REQUIRED number of pairs. If it exceeds capacity, only
+ *                     the first `capacity` pairs are written, tile ranges are clamped, and the
+ *                     caller must re-run with a larger capacity (no call faults);
+ *   scratch           at least gs_bins_scratch_bytes(n, capacity, T) bytes, 256-B aligned. */
+typedef struct gs_bins {
+  int32_t tile_w, tile_h; /* each in {8, 16, 32} */
+  int64_t capacity;
+  uint32_t *vals;
+  uint32_t *tile_range;
+  int64_t *num_pairs;
+  void *scratch;
+  size_t scratch_bytes;
+} gs_bins;
+
+/* Rendered planes, window-sized: color [3][h][w] (eq:rendered_rgb plus T_final * bg),
+ * depth [h][w] (eq:rendered_depth), alpha [h][w] (eq:rendered_opacity), and the backward
+ * checkpoint: t_final [h][w] final transmittance and last [h][w] int32 position, within the
+ * pixel's tile list, of the last Gaussian blended (-1 if none). n_contrib [h][w] int32 is
+ * optional (NULL = not written): the number of Gaussians blended at each pixel. */
+typedef struct gs_image {
+  float *color, *depth, *alpha, *t_final;
+  int32_t *last;
+  int32_t *n_contrib;
+} gs_image;
+
+/* Sparse LiDAR depth term of eq:depth_loss with the opacity-normalised depth D/O:
+ *   L_d = weight * (1/m) * sum_i |D(pix_i)/O(pix_i) - depth_target_i|
+ * over m hits at ascending, distinct window-linear pixel indices pix [m] (int32); a hit with
+ * O = 0 adds nothing. gs_render_fwd writes L_d to loss_out [1] (device, overwritten);
+ * gs_render_bwd adds its gradient, scaled by *grad_scale (device scalar; NULL = 1). */
+typedef struct gs_lidar {
+  int32_t m;
+  const int32_t *pix;
+  const float *depth_target;
+  float weight;
+  float *loss_out;
+  const float *grad_scale;
+} gs_lidar;
+
+/* Gradient outputs, all accumulated (+=), same layouts as gs_gaussians; pose [6] is
+ * dL/dxi for the left perturbation T_cw <- Exp(xi) T_cw with xi = (rho, phi), translation
+ * first (the manifold derivative after eq:3dgs_jacobi, taken on the world-to-camera pose).
+ * scratch: at least gs_grads_scratch_bytes(...) bytes. Any of the parameter pointers may be
+ * NULL to skip that output (sh_rest must be given when sh_degree > 0 and sh_dc is given). */
+typedef struct gs_grads {
+  float *mean, *scale, *rot, *opacity, *sh_dc, *sh_rest, *pose;
+  void *scratch;
+  size_t scratch_bytes;
+} gs_grads;
+
+/* Stage a1 — projection, covariance, SH colour, footprint, tile rectangle and alpha-max cull
+ * for every Gaussian (Sec. "3D Gaussian Splatting Representation"). One camera. */
+int gs_preprocess(const gs_gaussians *g, const gs_camera *cam, int32_t tile_w, int32_t tile_h,
+                  gs_projected *out, gs_stream_t stream);
+
+/* Stage a2 — pairs (tile, Gaussian) for the kept tiles, sorted by (tile, depth, index), and
+ * the per-tile ranges. n = number of records in `proj`. */
+int gs_bin_sort(const gs_projected *proj, int64_t n, const gs_camera *cam, gs_bins *io, gs_stream_t stream);
+
+/* Stage a3 — front-to-back compositing per pixel (eq:alpha, eq:rendered_rgb/_depth/_opacity):
+ * alpha = min(0.99, o exp(-q/2)); a Gaussian with alpha < 1/255 is skipped; the walk stops
+ * before a Gaussian that would take the transmittance below 1e-4. blend_depth in {64, 128,
+ * 256} is the number of records staged in LDS per batch. lidar may be NULL; otherwise the
+ * depth term is evaluated into lidar->loss_out after compositing. */
+int gs_render_fwd(const gs_projected *proj, int64_t n, const gs_bins *bins, const gs_camera *cam,
+                  int32_t blend_depth, const gs_lidar *lidar, gs_image *out, gs_stream_t stream);
+
+/* Stages a4-a6 — backward of the compositing (walking each pixel's contributors from `last`
+ * and rebuilding transmittance by division), the sparse-LiDAR depth term (only at the listed
+ * pixels), and the chain rule to the parameters and to the pose (eq:3dgs_jacobi including the
+ * SH term). dL_dC [3][h][w] is required; dL_dD and dL_dO [h][w] may be NULL; lidar may be NULL.
+ * `fwd` must hold the outputs of gs_render_fwd for the same inputs. */
+int gs_render_bwd(const gs_gaussians *g, const gs_camera *cam, const gs_projected *proj, const gs_bins *bins,
+                  const gs_image *fwd, const float *dL_dC, const float *dL_dD, const float *dL_dO,
+                  const gs_lidar *lidar, int32_t blend_depth, gs_grads *out, gs_stream_t stream);
+
+/* RGB L1 term of the mapping loss (eq:depth_loss with the D-SSIM weight at zero):
+ * loss_out[0] = weight * mean |color - target|, dL_dC = weight * sign(color - target) / n_values
+ * (sign(0) = 0). n_values = 3 * pixels. loss_out is overwritten. */
+int gs_loss_l1(const float *color, const float *target, int64_t n_values, float weight, float *dL_dC,
+               float *loss_out, gs_stream_t stream);
+
+/* Scratch sizes (bytes). */
+size_t gs_bins_scratch_bytes(int64_t n, int64_t capacity, int64_t num_tiles);
+size_t gs_grads_scratch_bytes(int64_t n, int32_t n_views, int64_t total_window_pixels);
+
+/* ---- Batched form (stage a7): several views of one map per launch ------------------------ */
+
+typedef struct gs_view {
+  gs_camera cam;
+  gs_image out;                     /* window-sized planes of this view */
+  const float *dL_dC, *dL_dD, *dL_dO; /* upstream gradients (GS_BWD); dL_dD, dL_dO may be NULL */
+  gs_lidar lidar;                   /* m = 0 for none */
+  const float *target;              /* optional [3][h][w]: when set, dL_dC is the RGB L1 term (see gs_loss_l1) */
+  float rgb_weight;                 /* weight of that term */
+  float *rgb_loss_out;              /* [1] device, overwritten; may be NULL */
+  float *pose_grad;                 /* [6] accumulated (GS_BWD); may be NULL */
+} gs_view;
+
+typedef struct gs_batch_plan gs_batch_plan;
+
+/* Creates a plan for up to n_views (<= GS_MAX_VIEWS) views of a map of n Gaussians at the
+ * given degree: it owns the splat records, tile lists (pair capacity `capacity`, summed over
+ * views), scratch and, with GS_GRAPH, the captured hipGraph. Allocates device memory. */
+int gs_batch_plan_create(gs_batch_plan **plan, int64_t n, int32_t sh_degree, int32_t n_views,
+                         int64_t max_total_pixels, int32_t tile_w, int32_t tile_h, int32_t blend_depth,
+                         int64_t capacity);
+void gs_batch_plan_destroy(gs_batch_plan *plan);
+
+/* Renders (GS_FWD) and/or differentiates (GS_BWD) all views in one launch per stage. With
+ * GS_GRAPH the stage sequence is captured into a hipGraph on first use and replayed while
+ * the arguments (pointers, cameras, sizes) are unchanged; otherwise it is re-captured.
+ * grads: shared parameter gradients (+=) over all views, may be NULL for GS_FWD. */
+int gs_render_batch(gs_batch_plan *plan, const gs_gaussians *g, int32_t n_views, const gs_view *views,
+                    uint32_t mode, gs_grads *grads, gs_stream_t stream);
+
+/* Required pair count of the plan's last run, copied to *required after the work queued on
+ * `stream` so far has finished (synchronises that stream). Compare with gs_batch_capacity: a
+ * larger value means the lists were clamped and the plan must be re-created bigger. */
+int gs_batch_num_pairs(const gs_batch_plan *plan, int64_t *required, gs_stream_t stream);
+int64_t gs_batch_capacity(const gs_batch_plan *plan);
+
+/* Host helper: camera with pose Exp(xi) T_cw (xi = (rho, phi), closed-form SE(3) exponential),
+ * the left update whose derivative gs_render_bwd reports. Intrinsics and window are copied. */
+int gs_camera_left_update(const gs_camera *in, const float xi[6], gs_camera *out);
+
+/* Kernel timing. gs_profile_enable creates `max_records` pairs of HIP events per stage
+ * (allocation happens here, not in the timed calls); afterwards every launch of a stage in
+ * `stage_mask` (bit i = stage i below) on this thread is bracketed by an event pair recorded
+ * on the launch stream, up to max_records launches. gs_profile_read synchronises those
+ * events and returns the summed duration (ms) and the launch count of one stage.
+ * gs_profile_disable releases the events. Stages: */
+enum { GS_STAGE_PREPROCESS = 0, GS_STAGE_BIN_SORT = 1, GS_STAGE_BLEND_FWD = 2, GS_STAGE_BLEND_BWD = 3,
+       GS_STAGE_PREPROCESS_BWD = 4, GS_NUM_STAGES = 5 };
+int gs_profile_enable(uint32_t stage_mask, int32_t max_records);
+int gs_profile_read(int32_t stage, double *total_ms, int32_t *count);
+void gs_profile_disable(void);
+
+/* Thread-local text of the last error of this thread. */
+const char *gs_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GS_H */

@@ -1,0 +1,694 @@
+// C ABI of the rasterizer (declared in include/gs.h): argument checks, view tables,
+// scratch layout, stage sequencing, and the batched plan with hipGraph capture.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <vector>
+
+#include "gs_internal.hpp"
+
+namespace {
+
+thread_local char g_err[512] = "";
+
+int fail(int code, const char *fmt, ...) {
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(g_err, sizeof g_err, fmt, ap);
+  va_end(ap);
+  return code;
+}
+
+int hip_fail(hipError_t e, const char *where) {
+  return fail(GS_ERR_HIP, "%s: %s", where, hipGetErrorString(e));
+}
+
+#define GS_TRY_HIP(expr, where)                 \
+  do {                                          \
+    hipError_t e_ = (expr);                     \
+    if (e_ != hipSuccess) return hip_fail(e_, where); \
+  } while (0)
+
+inline int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
+inline size_t a256(size_t x) { return (x + 255) & ~size_t(255); }
+
+bool tile_ok(int tw, int th) { return tw == th && (tw == 8 || tw == 16 || tw == 32); }
+bool depth_ok(int bd) { return bd == 64 || bd == 128 || bd == 256; }
+
+int check_camera(const gs_camera *c) {
+  if (!c) return fail(GS_ERR_INVALID_ARG, "camera is NULL");
+  if (c->width <= 0 || c->height <= 0) return fail(GS_ERR_INVALID_ARG, "image size must be positive");
+  if (c->w <= 0 || c->h <= 0) return fail(GS_ERR_INVALID_ARG, "render window must be non-empty");
+  if (c->x0 < 0 || c->y0 < 0 || (int64_t)c->x0 + c->w > c->width || (int64_t)c->y0 + c->h > c->height)
+    return fail(GS_ERR_INVALID_ARG, "render window (%d,%d,%d,%d) outside the %dx%d image", c->x0, c->y0, c->w, c->h,
+                c->width, c->height);
+  if (!(c->fx > 0.f) || !(c->fy > 0.f) || !std::isfinite(c->fx) || !std::isfinite(c->fy) ||
+      !std::isfinite(c->cx) || !std::isfinite(c->cy))
+    return fail(GS_ERR_INVALID_ARG, "intrinsics must be finite with fx, fy > 0");
+  for (int i = 0; i < 9; ++i)
+    if (!std::isfinite(c->R_cw[i])) return fail(GS_ERR_INVALID_ARG, "rotation is not finite");
+  for (int i = 0; i < 3; ++i)
+    if (!std::isfinite(c->t_cw[i]) || !std::isfinite(c->bg[i]))
+      return fail(GS_ERR_INVALID_ARG, "translation / background is not finite");
+  if ((int64_t)c->width > 32767 * 8 || (int64_t)c->height > 32767 * 8)
+    return fail(GS_ERR_INVALID_ARG, "image too large for int16 tile rectangles");
+  return GS_OK;
+}
+
+int check_gaussians(const gs_gaussians *g) {
+  if (!g) return fail(GS_ERR_INVALID_ARG, "gaussians is NULL");
+  if (g->n < 0) return fail(GS_ERR_INVALID_ARG, "n < 0");
+  if (g->sh_degree < 0 || g->sh_degree > 3) return fail(GS_ERR_INVALID_ARG, "sh_degree must be in 0..3");
+  if (g->n > 0 && (!g->mean || !g->scale || !g->rot || !g->opacity || !g->sh_dc))
+    return fail(GS_ERR_INVALID_ARG, "a parameter plane is NULL");
+  if (g->n > 0 && g->sh_degree > 0 && !g->sh_rest) return fail(GS_ERR_INVALID_ARG, "sh_rest is NULL at degree > 0");
+  if (g->n > (int64_t)0x7FFFFFFF) return fail(GS_ERR_INVALID_ARG, "n too large");
+  return GS_OK;
+}
+
+// Record arrays may be NULL only when there are no records.
+int check_projected(const gs_projected *p, int64_t n) {
+  if (!p) return fail(GS_ERR_INVALID_ARG, "projected records are NULL");
+  if (n > 0 && (!p->rec_a || !p->rec_b || !p->rgb || !p->rect || !p->n_tiles || !p->dkey))
+    return fail(GS_ERR_INVALID_ARG, "projected record pointer is NULL");
+  return GS_OK;
+}
+
+// Host view description: the camera plus the derived tile grid.
+void make_view(const gs_camera &c, int tw, int th, uint32_t tile_base, uint32_t pix_base, gs::ViewCam &v) {
+  v.fx = c.fx; v.fy = c.fy; v.cx = c.cx; v.cy = c.cy;
+  for (int i = 0; i < 9; ++i) v.R[i] = c.R_cw[i];
+  for (int i = 0; i < 3; ++i) v.t[i] = c.t_cw[i];
+  for (int i = 0; i < 3; ++i) {
+    // camera centre -R^T t, in float64 then rounded once
+    double s = 0.0;
+    for (int j = 0; j < 3; ++j) s += (double)c.R_cw[3 * j + i] * (double)c.t_cw[j];
+    v.cw[i] = (float)(-s);
+    v.bg[i] = c.bg[i];
+  }
+  v.W = c.width; v.H = c.height; v.x0 = c.x0; v.y0 = c.y0; v.w = c.w; v.h = c.h;
+  v.tiles_x = (c.w + tw - 1) / tw;
+  v.tiles_y = (c.h + th - 1) / th;
+  v.tile_base = tile_base;
+  v.pix_base = pix_base;
+}
+
+int make_table(const gs_camera *cams, int nv, int64_t n, int deg, int tw, int th, gs::ViewTable &vt) {
+  std::memset(&vt, 0, sizeof vt);
+  vt.n_views = nv;
+  vt.tile_w = tw;
+  vt.tile_h = th;
+  vt.sh_degree = deg;
+  vt.n = n;
+  uint64_t tb = 0, pb = 0;
+  for (int i = 0; i < nv; ++i) {
+    int rc = check_camera(&cams[i]);
+    if (rc) return rc;
+    make_view(cams[i], tw, th, (uint32_t)tb, (uint32_t)pb, vt.v[i]);
+    tb += (uint64_t)vt.v[i].tiles_x * vt.v[i].tiles_y;
+    pb += (uint64_t)cams[i].w * cams[i].h;
+  }
+  if (tb > 0x7FFFFFFFull || pb > 0x7FFFFFFFull) return fail(GS_ERR_INVALID_ARG, "too many tiles or pixels");
+  vt.total_tiles = (uint32_t)tb;
+  return GS_OK;
+}
+
+// Backward scratch layout: grad2d [E][12] | pose partials [blocks][V][6] | gD, gO maps [pixels].
+struct GradScratch {
+  float *g2, *pose_partial, *mapD, *mapO;
+};
+
+size_t grads_scratch_bytes_impl(int64_t n, int nv, int64_t pixels) {
+  const int64_t E = std::max<int64_t>(n * nv, 1);
+  size_t s = a256(sizeof(float) * 12 * E);
+  s += a256(sizeof(float) * 6 * nv * std::max<int64_t>(gs::preprocess_bwd_blocks(n), 1));
+  s += 2 * a256(sizeof(float) * std::max<int64_t>(pixels, 1));
+  return s;
+}
+
+GradScratch carve_grads(void *base, int64_t n, int nv, int64_t pixels) {
+  char *p = (char *)base;
+  const int64_t E = std::max<int64_t>(n * nv, 1);
+  GradScratch s;
+  s.g2 = (float *)p;
+  p += a256(sizeof(float) * 12 * E);
+  s.pose_partial = (float *)p;
+  p += a256(sizeof(float) * 6 * nv * std::max<int64_t>(gs::preprocess_bwd_blocks(n), 1));
+  s.mapD = (float *)p;
+  p += a256(sizeof(float) * std::max<int64_t>(pixels, 1));
+  s.mapO = (float *)p;
+  return s;
+}
+
+struct ViewIO {
+  gs_image img;
+  const float *dC, *dD, *dO;
+  gs_lidar lidar;
+  float *pose;
+};
+
+// The backward of all views of one table: dense gradient maps (user planes + LiDAR term),
+// blend backward into grad2d, then the chain rule to parameters and poses.
+int enqueue_backward(const gs::ViewTable &vt, const gs_gaussians &g, const gs_projected &p, const uint32_t *vals,
+                     const uint32_t *range, const ViewIO *io, int bd, const gs_grads &out, const GradScratch &s,
+                     hipStream_t st) {
+  const int nv = vt.n_views;
+  gs::ImgTable it{};
+  gs::GradTable gtab{};
+  gs::LidarTable lt{};
+  gs::MapSrc src{};
+  gs::MapTable dst{};
+  lt.n_views = nv;
+  int max_m = 0;
+  int64_t max_npx = 0;
+  bool any_map = false;
+  for (int i = 0; i < nv; ++i) {
+    it.v[i] = {io[i].img.color, io[i].img.depth, io[i].img.alpha, io[i].img.t_final, io[i].img.last, io[i].img.n_contrib};
+    const int64_t npx = (int64_t)vt.v[i].w * vt.v[i].h;
+    const bool has_lidar = io[i].lidar.m > 0;
+    const bool need_map = has_lidar || io[i].dD || io[i].dO;
+    gtab.v[i].gC = io[i].dC;
+    if (need_map) {
+      any_map = true;
+      dst.gD[i] = s.mapD + vt.v[i].pix_base;
+      dst.gO[i] = s.mapO + vt.v[i].pix_base;
+      src.gD[i] = io[i].dD;
+      src.gO[i] = io[i].dO;
+      src.npx[i] = npx;
+      gtab.v[i].gD = dst.gD[i];
+      gtab.v[i].gO = dst.gO[i];
+      max_npx = std::max(max_npx, npx);
+    }
+    if (has_lidar) {
+      lt.v[i] = {io[i].lidar.pix, io[i].lidar.depth_target, io[i].lidar.grad_scale, io[i].lidar.loss_out,
+                 io[i].lidar.weight, io[i].lidar.m, (int32_t)npx};
+      max_m = std::max(max_m, io[i].lidar.m);
+    }
+  }
+  if (any_map) GS_TRY_HIP(gs::launch_grad_maps(src, dst, nv, max_npx, lt, it, max_m, st), "lidar/gradient maps");
+  GS_TRY_HIP(gs::zero_f32(s.g2, 12 * vt.n * nv, st), "zero grad2d");
+  gs::profile_begin(GS_STAGE_BLEND_BWD, st);
+  GS_TRY_HIP(gs::launch_blend_bwd(bd, vt, it, gtab, p, vals, range, s.g2, st), "blend backward");
+  gs::profile_end(GS_STAGE_BLEND_BWD, st);
+  float *pose_out[gs::kMaxViews] = {};
+  for (int i = 0; i < nv; ++i) pose_out[i] = io[i].pose;
+  gs::profile_begin(GS_STAGE_PREPROCESS_BWD, st);
+  GS_TRY_HIP(gs::launch_preprocess_bwd(vt, g, p, s.g2, out, pose_out, s.pose_partial, st), "preprocess backward");
+  gs::profile_end(GS_STAGE_PREPROCESS_BWD, st);
+  return GS_OK;
+}
+
+int check_lidar(const gs_lidar *l, int64_t npx) {
+  if (!l || l->m == 0) return GS_OK;
+  if (l->m < 0) return fail(GS_ERR_INVALID_ARG, "lidar m < 0");
+  if (!l->pix || !l->depth_target) return fail(GS_ERR_INVALID_ARG, "lidar arrays are NULL");
+  if (!std::isfinite(l->weight)) return fail(GS_ERR_INVALID_ARG, "lidar weight is not finite");
+  (void)npx;
+  return GS_OK;
+}
+
+int check_image(const gs_image *im) {
+  if (!im || !im->color || !im->depth || !im->alpha || !im->t_final || !im->last)
+    return fail(GS_ERR_INVALID_ARG, "image plane is NULL");
+  return GS_OK;
+}
+
+struct StageProfile {
+  std::vector<hipEvent_t> begin, end;
+  int used = 0;
+  bool open = false;
+};
+thread_local uint32_t g_prof_mask = 0;
+thread_local StageProfile g_prof[GS_NUM_STAGES];
+
+}  // namespace
+
+namespace gs {
+void profile_begin(int stage, hipStream_t st) {
+  if (!(g_prof_mask & (1u << stage))) return;
+  StageProfile &p = g_prof[stage];
+  if (p.used >= (int)p.begin.size()) return;
+  (void)hipEventRecord(p.begin[p.used], st);
+  p.open = true;
+}
+void profile_end(int stage, hipStream_t st) {
+  if (!(g_prof_mask & (1u << stage))) return;
+  StageProfile &p = g_prof[stage];
+  if (!p.open) return;
+  (void)hipEventRecord(p.end[p.used], st);
+  p.used++;
+  p.open = false;
+}
+}  // namespace gs
+
+extern "C" {
+
+const char *gs_last_error(void) { return g_err; }
+
+void gs_profile_disable(void) {
+  for (auto &p : g_prof) {
+    for (auto e : p.begin) (void)hipEventDestroy(e);
+    for (auto e : p.end) (void)hipEventDestroy(e);
+    p = StageProfile();
+  }
+  g_prof_mask = 0;
+}
+
+int gs_profile_enable(uint32_t stage_mask, int32_t max_records) {
+  if (max_records <= 0 || max_records > 1000000) return fail(GS_ERR_INVALID_ARG, "max_records out of range");
+  gs_profile_disable();
+  for (int s = 0; s < GS_NUM_STAGES; ++s) {
+    if (!(stage_mask & (1u << s))) continue;
+    StageProfile &p = g_prof[s];
+    p.begin.resize(max_records);
+    p.end.resize(max_records);
+    for (int i = 0; i < max_records; ++i) {
+      GS_TRY_HIP(hipEventCreate(&p.begin[i]), "event create");
+      GS_TRY_HIP(hipEventCreate(&p.end[i]), "event create");
+    }
+  }
+  g_prof_mask = stage_mask;
+  return GS_OK;
+}
+
+int gs_profile_read(int32_t stage, double *total_ms, int32_t *count) {
+  if (stage < 0 || stage >= GS_NUM_STAGES || !total_ms || !count) return fail(GS_ERR_INVALID_ARG, "bad argument");
+  StageProfile &p = g_prof[stage];
+  double tot = 0.0;
+  for (int i = 0; i < p.used; ++i) {
+    GS_TRY_HIP(hipEventSynchronize(p.end[i]), "event sync");
+    float ms = 0.f;
+    GS_TRY_HIP(hipEventElapsedTime(&ms, p.begin[i], p.end[i]), "event elapsed");
+    tot += ms;
+  }
+  *total_ms = tot;
+  *count = p.used;
+  p.used = 0;
+  return GS_OK;
+}
+
+size_t gs_bins_scratch_bytes(int64_t n, int64_t capacity, int64_t num_tiles) {
+  (void)num_tiles;
+  return gs::bin_scratch_bytes(std::max<int64_t>(n, 0), std::max<int64_t>(capacity, 0));
+}
+
+size_t gs_grads_scratch_bytes(int64_t n, int32_t n_views, int64_t total_window_pixels) {
+  return grads_scratch_bytes_impl(std::max<int64_t>(n, 0), std::max(n_views, 1), std::max<int64_t>(total_window_pixels, 0));
+}
+
+int gs_preprocess(const gs_gaussians *g, const gs_camera *cam, int32_t tile_w, int32_t tile_h, gs_projected *out,
+                  gs_stream_t stream) {
+  int rc;
+  if ((rc = check_gaussians(g)) || (rc = check_camera(cam)) || (rc = check_projected(out, g->n))) return rc;
+  if (!tile_ok(tile_w, tile_h)) return fail(GS_ERR_INVALID_ARG, "tile size must be 8x8, 16x16 or 32x32");
+  gs::ViewTable vt;
+  if ((rc = make_table(cam, 1, g->n, g->sh_degree, tile_w, tile_h, vt))) return rc;
+  gs::profile_begin(GS_STAGE_PREPROCESS, (hipStream_t)stream);
+  GS_TRY_HIP(gs::launch_preprocess(vt, *g, *out, (hipStream_t)stream), "preprocess");
+  gs::profile_end(GS_STAGE_PREPROCESS, (hipStream_t)stream);
+  return GS_OK;
+}
+
+int gs_bin_sort(const gs_projected *proj, int64_t n, const gs_camera *cam, gs_bins *io, gs_stream_t stream) {
+  int rc;
+  if ((rc = check_projected(proj, n)) || (rc = check_camera(cam))) return rc;
+  if (!io || !io->vals || !io->tile_range || !io->num_pairs || !io->scratch)
+    return fail(GS_ERR_INVALID_ARG, "bins pointer is NULL");
+  if (n < 0 || io->capacity < 0) return fail(GS_ERR_INVALID_ARG, "negative size");
+  if (!tile_ok(io->tile_w, io->tile_h)) return fail(GS_ERR_INVALID_ARG, "tile size must be 8x8, 16x16 or 32x32");
+  if (io->capacity > 0xFFFFFFFFll) return fail(GS_ERR_INVALID_ARG, "capacity too large");
+  gs::ViewTable vt;
+  if ((rc = make_table(cam, 1, n, 0, io->tile_w, io->tile_h, vt))) return rc;
+  if (io->scratch_bytes < gs::bin_scratch_bytes(n, io->capacity))
+    return fail(GS_ERR_INVALID_ARG, "bins scratch too small: %zu < %zu", io->scratch_bytes,
+                gs::bin_scratch_bytes(n, io->capacity));
+  gs::profile_begin(GS_STAGE_BIN_SORT, (hipStream_t)stream);
+  GS_TRY_HIP(gs::launch_bin_sort(vt, *proj, n, io->capacity, io->vals, io->tile_range, io->num_pairs, io->scratch,
+                                 (hipStream_t)stream),
+             "bin/sort");
+  gs::profile_end(GS_STAGE_BIN_SORT, (hipStream_t)stream);
+  return GS_OK;
+}
+
+int gs_render_fwd(const gs_projected *proj, int64_t n, const gs_bins *bins, const gs_camera *cam, int32_t blend_depth,
+                  const gs_lidar *lidar, gs_image *out, gs_stream_t stream) {
+  int rc;
+  if ((rc = check_projected(proj, n)) || (rc = check_camera(cam)) || (rc = check_image(out))) return rc;
+  if (!bins || !bins->vals || !bins->tile_range) return fail(GS_ERR_INVALID_ARG, "bins pointer is NULL");
+  if (!tile_ok(bins->tile_w, bins->tile_h)) return fail(GS_ERR_INVALID_ARG, "tile size must be 8x8, 16x16 or 32x32");
+  if (!depth_ok(blend_depth)) return fail(GS_ERR_INVALID_ARG, "blend_depth must be 64, 128 or 256");
+  if ((rc = check_lidar(lidar, (int64_t)cam->w * cam->h))) return rc;
+  if (lidar && lidar->m > 0 && !lidar->loss_out) return fail(GS_ERR_INVALID_ARG, "lidar loss_out is NULL");
+  gs::ViewTable vt;
+  if ((rc = make_table(cam, 1, n, 0, bins->tile_w, bins->tile_h, vt))) return rc;
+  gs::ImgTable it{};
+  it.v[0] = {out->color, out->depth, out->alpha, out->t_final, out->last, out->n_contrib};
+  hipStream_t st = (hipStream_t)stream;
+  gs::profile_begin(GS_STAGE_BLEND_FWD, st);
+  GS_TRY_HIP(gs::launch_blend_fwd(blend_depth, vt, it, *proj, bins->vals, bins->tile_range, st), "blend forward");
+  gs::profile_end(GS_STAGE_BLEND_FWD, st);
+  if (lidar && lidar->m > 0) {
+    gs::LidarTable lt{};
+    lt.n_views = 1;
+    lt.v[0] = {lidar->pix, lidar->depth_target, lidar->grad_scale, lidar->loss_out, lidar->weight, lidar->m, (int32_t)((int64_t)cam->w * cam->h)};
+    GS_TRY_HIP(gs::launch_lidar_loss(lt, it, lidar->m, st), "lidar loss");
+  }
+  return GS_OK;
+}
+
+int gs_render_bwd(const gs_gaussians *g, const gs_camera *cam, const gs_projected *proj, const gs_bins *bins,
+                  const gs_image *fwd, const float *dL_dC, const float *dL_dD, const float *dL_dO, const gs_lidar *lidar,
+                  int32_t blend_depth, gs_grads *out, gs_stream_t stream) {
+  int rc;
+  if ((rc = check_gaussians(g)) || (rc = check_camera(cam)) || (rc = check_projected(proj, g->n)) ||
+      (rc = check_image(fwd)))
+    return rc;
+  if (!bins || !bins->vals || !bins->tile_range) return fail(GS_ERR_INVALID_ARG, "bins pointer is NULL");
+  if (!tile_ok(bins->tile_w, bins->tile_h)) return fail(GS_ERR_INVALID_ARG, "tile size must be 8x8, 16x16 or 32x32");
+  if (!depth_ok(blend_depth)) return fail(GS_ERR_INVALID_ARG, "blend_depth must be 64, 128 or 256");
+  if (!dL_dC) return fail(GS_ERR_INVALID_ARG, "dL_dC is NULL");
+  if (!out || !out->scratch) return fail(GS_ERR_INVALID_ARG, "grads / scratch is NULL");
+  if (out->sh_dc && g->sh_degree > 0 && !out->sh_rest) return fail(GS_ERR_INVALID_ARG, "grads.sh_rest is NULL");
+  if ((rc = check_lidar(lidar, (int64_t)cam->w * cam->h))) return rc;
+  const int64_t npx = (int64_t)cam->w * cam->h;
+  if (out->scratch_bytes < grads_scratch_bytes_impl(g->n, 1, npx))
+    return fail(GS_ERR_INVALID_ARG, "grads scratch too small: %zu < %zu", out->scratch_bytes,
+                grads_scratch_bytes_impl(g->n, 1, npx));
+  gs::ViewTable vt;
+  if ((rc = make_table(cam, 1, g->n, g->sh_degree, bins->tile_w, bins->tile_h, vt))) return rc;
+  ViewIO io{};
+  io.img = *fwd;
+  io.dC = dL_dC;
+  io.dD = dL_dD;
+  io.dO = dL_dO;
+  if (lidar) io.lidar = *lidar;
+  io.pose = out->pose;
+  GradScratch s = carve_grads(out->scratch, g->n, 1, npx);
+  return enqueue_backward(vt, *g, *proj, bins->vals, bins->tile_range, &io, blend_depth, *out, s, (hipStream_t)stream);
+}
+
+int gs_camera_left_update(const gs_camera *in, const float xi[6], gs_camera *out) {
+  if (!in || !xi || !out) return fail(GS_ERR_INVALID_ARG, "NULL argument");
+  const double rho[3] = {xi[0], xi[1], xi[2]}, phi[3] = {xi[3], xi[4], xi[5]};
+  const double th = std::sqrt(phi[0] * phi[0] + phi[1] * phi[1] + phi[2] * phi[2]);
+  const double K[9] = {0, -phi[2], phi[1], phi[2], 0, -phi[0], -phi[1], phi[0], 0};
+  double K2[9];
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) K2[3 * i + j] = K[3 * i] * K[j] + K[3 * i + 1] * K[3 + j] + K[3 * i + 2] * K[6 + j];
+  // Rodrigues: R = I + A K + B K^2, V = I + B K + C K^2 (series near zero)
+  double A, B, Cc;
+  if (th < 1e-4) {
+    A = 1.0 - th * th / 6.0;
+    B = 0.5 - th * th / 24.0;
+    Cc = 1.0 / 6.0 - th * th / 120.0;
+  } else {
+    A = std::sin(th) / th;
+    B = (1.0 - std::cos(th)) / (th * th);
+    Cc = (th - std::sin(th)) / (th * th * th);
+  }
+  double dR[9], V[9];
+  for (int i = 0; i < 9; ++i) {
+    const double I = (i % 4 == 0) ? 1.0 : 0.0;
+    dR[i] = I + A * K[i] + B * K2[i];
+    V[i] = I + B * K[i] + Cc * K2[i];
+  }
+  gs_camera o = *in;
+  for (int i = 0; i < 3; ++i) {
+    for (int j = 0; j < 3; ++j) {
+      double s = 0.0;
+      for (int l = 0; l < 3; ++l) s += dR[3 * i + l] * (double)in->R_cw[3 * l + j];
+      o.R_cw[3 * i + j] = (float)s;
+    }
+    double s = 0.0;
+    for (int l = 0; l < 3; ++l) s += dR[3 * i + l] * (double)in->t_cw[l] + V[3 * i + l] * rho[l];
+    o.t_cw[i] = (float)s;
+  }
+  *out = o;
+  return GS_OK;
+}
+
+int gs_loss_l1(const float *color, const float *target, int64_t n_values, float weight, float *dL_dC, float *loss_out,
+               gs_stream_t stream) {
+  if (n_values < 0) return fail(GS_ERR_INVALID_ARG, "n_values < 0");
+  if (n_values > 0 && (!color || !target)) return fail(GS_ERR_INVALID_ARG, "color / target is NULL");
+  if (!std::isfinite(weight)) return fail(GS_ERR_INVALID_ARG, "weight is not finite");
+  GS_TRY_HIP(gs::launch_loss_l1(color, target, n_values, weight, dL_dC, loss_out, (hipStream_t)stream), "l1 loss");
+  return GS_OK;
+}
+
+}  // extern "C"
+
+// =============================================================================================
+// Batched plan: one launch per stage over all views, optional hipGraph replay.
+// =============================================================================================
+struct gs_batch_plan {
+  int64_t n = 0;
+  int32_t deg = 0, max_views = 0, tw = 16, th = 16, bd = 256;
+  int64_t max_pixels = 0, cap = 0, max_tiles = 0;
+  // owned device memory
+  void *block = nullptr;
+  gs_projected proj{};
+  uint32_t *vals = nullptr, *tile_range = nullptr;
+  int64_t *num_pairs = nullptr;
+  void *bin_scratch = nullptr;
+  void *grad_scratch = nullptr;
+  float *dC = nullptr;  // fused L1 gradient planes, concatenated over views
+  // graph
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  std::vector<unsigned char> signature;
+};
+
+namespace {
+
+size_t plan_bytes(const gs_batch_plan &p, size_t *offs) {
+  const int64_t E = std::max<int64_t>(p.n * p.max_views, 1);
+  size_t o = 0;
+  auto put = [&](int i, size_t bytes) {
+    offs[i] = o;
+    o += a256(bytes);
+  };
+  put(0, 16 * E);                                      // rec_a
+  put(1, 16 * E);                                      // rec_b
+  put(2, 16 * E);                                      // rgb
+  put(3, 8 * E);                                       // rect
+  put(4, 4 * E);                                       // n_tiles
+  put(5, 4 * E);                                       // dkey
+  put(6, 4 * std::max<int64_t>(p.cap, 1));             // vals
+  put(7, 8 * std::max<int64_t>(p.max_tiles, 1));       // tile ranges
+  put(8, 16);                                          // num_pairs
+  put(9, gs::bin_scratch_bytes(E, p.cap));             // bin scratch
+  put(10, grads_scratch_bytes_impl(p.n, p.max_views, p.max_pixels));
+  put(11, 12 * std::max<int64_t>(p.max_pixels, 1));   // dC planes
+  return o;
+}
+
+int enqueue_batch(gs_batch_plan *p, const gs_gaussians *g, int nv, const gs_view *views, uint32_t mode,
+                  gs_grads *grads, hipStream_t st) {
+  std::vector<gs_camera> cams(nv);
+  for (int i = 0; i < nv; ++i) cams[i] = views[i].cam;
+  gs::ViewTable vt;
+  int rc = make_table(cams.data(), nv, g->n, g->sh_degree, p->tw, p->th, vt);
+  if (rc) return rc;
+  if ((int64_t)vt.total_tiles > p->max_tiles) return fail(GS_ERR_INVALID_ARG, "views need more tiles than the plan holds");
+  int64_t pixels = 0;
+  for (int i = 0; i < nv; ++i) pixels += (int64_t)cams[i].w * cams[i].h;
+  if (pixels > p->max_pixels) return fail(GS_ERR_INVALID_ARG, "views exceed the plan's pixel budget");
+  const int64_t E = g->n * nv;
+  gs::ImgTable it{};
+  for (int i = 0; i < nv; ++i) {
+    const gs_image &im = views[i].out;
+    it.v[i] = {im.color, im.depth, im.alpha, im.t_final, im.last, im.n_contrib};
+  }
+  if (mode & GS_FWD) {
+    gs::profile_begin(GS_STAGE_PREPROCESS, st);
+    GS_TRY_HIP(gs::launch_preprocess(vt, *g, p->proj, st), "batch preprocess");
+    gs::profile_end(GS_STAGE_PREPROCESS, st);
+    gs::profile_begin(GS_STAGE_BIN_SORT, st);
+    GS_TRY_HIP(gs::launch_bin_sort(vt, p->proj, E, p->cap, p->vals, p->tile_range, p->num_pairs, p->bin_scratch, st),
+               "batch bin/sort");
+    gs::profile_end(GS_STAGE_BIN_SORT, st);
+    gs::profile_begin(GS_STAGE_BLEND_FWD, st);
+    GS_TRY_HIP(gs::launch_blend_fwd(p->bd, vt, it, p->proj, p->vals, p->tile_range, st), "batch blend forward");
+    gs::profile_end(GS_STAGE_BLEND_FWD, st);
+    gs::LidarTable lt{};
+    lt.n_views = nv;
+    int max_m = 0;
+    for (int i = 0; i < nv; ++i) {
+      const gs_lidar &l = views[i].lidar;
+      if (l.m > 0 && l.loss_out) {
+        lt.v[i] = {l.pix, l.depth_target, l.grad_scale, l.loss_out, l.weight, l.m, cams[i].w * cams[i].h};
+        max_m = std::max(max_m, l.m);
+      }
+    }
+    if (max_m > 0) GS_TRY_HIP(gs::launch_lidar_loss(lt, it, max_m, st), "batch lidar loss");
+  }
+  if (mode & GS_BWD) {
+    std::vector<ViewIO> io(nv);
+    for (int i = 0; i < nv; ++i) {
+      const gs_view &v = views[i];
+      io[i].img = v.out;
+      io[i].dC = v.dL_dC;
+      if (v.target) {
+        float *dc = p->dC + 3 * (int64_t)vt.v[i].pix_base;
+        const int64_t nval = 3 * (int64_t)v.cam.w * v.cam.h;
+        GS_TRY_HIP(gs::launch_loss_l1(v.out.color, v.target, nval, v.rgb_weight, dc, v.rgb_loss_out, st),
+                   "batch l1 loss");
+        io[i].dC = dc;
+      }
+      io[i].dD = v.dL_dD;
+      io[i].dO = v.dL_dO;
+      io[i].lidar = v.lidar;
+      io[i].pose = v.pose_grad;
+    }
+    gs_grads gg{};
+    if (grads) gg = *grads;
+    GradScratch s = carve_grads(p->grad_scratch, g->n, nv, p->max_pixels);
+    rc = enqueue_backward(vt, *g, p->proj, p->vals, p->tile_range, io.data(), p->bd, gg, s, st);
+    if (rc) return rc;
+  }
+  return GS_OK;
+}
+
+int check_views(const gs_batch_plan *p, const gs_gaussians *g, int nv, const gs_view *views, uint32_t mode,
+                const gs_grads *grads) {
+  int rc;
+  if ((rc = check_gaussians(g))) return rc;
+  if (g->n > p->n) return fail(GS_ERR_INVALID_ARG, "map has more Gaussians than the plan");
+  if (g->sh_degree > p->deg) return fail(GS_ERR_INVALID_ARG, "SH degree above the plan's");
+  if (nv <= 0 || nv > p->max_views) return fail(GS_ERR_INVALID_ARG, "n_views must be in 1..%d", p->max_views);
+  if (!views) return fail(GS_ERR_INVALID_ARG, "views is NULL");
+  if (!(mode & (GS_FWD | GS_BWD))) return fail(GS_ERR_INVALID_ARG, "mode needs GS_FWD and/or GS_BWD");
+  for (int i = 0; i < nv; ++i) {
+    if ((rc = check_camera(&views[i].cam)) || (rc = check_image(&views[i].out))) return rc;
+    if ((rc = check_lidar(&views[i].lidar, (int64_t)views[i].cam.w * views[i].cam.h))) return rc;
+    if ((mode & GS_BWD) && !views[i].dL_dC && !views[i].target)
+      return fail(GS_ERR_INVALID_ARG, "view %d has neither dL_dC nor a target", i);
+  }
+  if ((mode & GS_BWD) && grads && grads->sh_dc && g->sh_degree > 0 && !grads->sh_rest)
+    return fail(GS_ERR_INVALID_ARG, "grads.sh_rest is NULL");
+  return GS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int gs_batch_plan_create(gs_batch_plan **out, int64_t n, int32_t sh_degree, int32_t n_views, int64_t max_total_pixels,
+                         int32_t tile_w, int32_t tile_h, int32_t blend_depth, int64_t capacity) {
+  if (!out) return fail(GS_ERR_INVALID_ARG, "plan out-pointer is NULL");
+  *out = nullptr;
+  if (n < 0 || n > 0x7FFFFFFF || sh_degree < 0 || sh_degree > 3) return fail(GS_ERR_INVALID_ARG, "bad n or degree");
+  if (n_views < 1 || n_views > GS_MAX_VIEWS) return fail(GS_ERR_INVALID_ARG, "n_views must be in 1..%d", GS_MAX_VIEWS);
+  if (n * n_views > 0xFFFFFFFFll) return fail(GS_ERR_INVALID_ARG, "n * n_views too large");
+  if (!tile_ok(tile_w, tile_h)) return fail(GS_ERR_INVALID_ARG, "tile size must be 8x8, 16x16 or 32x32");
+  if (!depth_ok(blend_depth)) return fail(GS_ERR_INVALID_ARG, "blend_depth must be 64, 128 or 256");
+  if (max_total_pixels <= 0 || capacity <= 0 || capacity > 0xFFFFFFFFll)
+    return fail(GS_ERR_INVALID_ARG, "bad pixel budget or capacity");
+  gs_batch_plan *p = new gs_batch_plan();
+  p->n = n;
+  p->deg = sh_degree;
+  p->max_views = n_views;
+  p->max_pixels = max_total_pixels;
+  p->tw = tile_w;
+  p->th = tile_h;
+  p->bd = blend_depth;
+  p->cap = capacity;
+  // every view adds at most one partial tile row and column beyond pixels / tile area
+  p->max_tiles = max_total_pixels / ((int64_t)tile_w * tile_h) + (int64_t)n_views * (2 * 32768 / tile_w + 1);
+  size_t offs[12];
+  const size_t bytes = plan_bytes(*p, offs);
+  hipError_t e = hipMalloc(&p->block, bytes);
+  if (e != hipSuccess) {
+    delete p;
+    return hip_fail(e, "plan allocation");
+  }
+  char *b = (char *)p->block;
+  p->proj.rec_a = (float *)(b + offs[0]);
+  p->proj.rec_b = (float *)(b + offs[1]);
+  p->proj.rgb = (float *)(b + offs[2]);
+  p->proj.rect = (int16_t *)(b + offs[3]);
+  p->proj.n_tiles = (uint32_t *)(b + offs[4]);
+  p->proj.dkey = (uint32_t *)(b + offs[5]);
+  p->vals = (uint32_t *)(b + offs[6]);
+  p->tile_range = (uint32_t *)(b + offs[7]);
+  p->num_pairs = (int64_t *)(b + offs[8]);
+  p->bin_scratch = b + offs[9];
+  p->grad_scratch = b + offs[10];
+  p->dC = (float *)(b + offs[11]);
+  *out = p;
+  return GS_OK;
+}
+
+void gs_batch_plan_destroy(gs_batch_plan *p) {
+  if (!p) return;
+  if (p->exec) (void)hipGraphExecDestroy(p->exec);
+  if (p->graph) (void)hipGraphDestroy(p->graph);
+  if (p->block) (void)hipFree(p->block);
+  delete p;
+}
+
+int gs_batch_num_pairs(const gs_batch_plan *p, int64_t *required, gs_stream_t stream) {
+  if (!p || !required) return fail(GS_ERR_INVALID_ARG, "NULL argument");
+  GS_TRY_HIP(hipMemcpyAsync(required, p->num_pairs, sizeof(int64_t), hipMemcpyDeviceToHost, (hipStream_t)stream),
+             "copy pair count");
+  GS_TRY_HIP(hipStreamSynchronize((hipStream_t)stream), "stream synchronize");
+  return GS_OK;
+}
+int64_t gs_batch_capacity(const gs_batch_plan *p) { return p ? p->cap : 0; }
+
+int gs_render_batch(gs_batch_plan *p, const gs_gaussians *g, int32_t n_views, const gs_view *views, uint32_t mode,
+                    gs_grads *grads, gs_stream_t stream) {
+  if (!p) return fail(GS_ERR_INVALID_ARG, "plan is NULL");
+  int rc = check_views(p, g, n_views, views, mode, grads);
+  if (rc) return rc;
+  hipStream_t st = (hipStream_t)stream;
+  if (!(mode & GS_GRAPH)) return enqueue_batch(p, g, n_views, views, mode, grads, st);
+  // The captured graph bakes every argument in; replay only while they are unchanged.
+  std::vector<unsigned char> sig;
+  auto add = [&](const void *src, size_t bytes) {
+    const unsigned char *c = (const unsigned char *)src;
+    sig.insert(sig.end(), c, c + bytes);
+  };
+  add(g, sizeof *g);
+  add(&n_views, sizeof n_views);
+  add(&mode, sizeof mode);
+  add(views, sizeof(gs_view) * n_views);
+  gs_grads gz{};
+  add(grads ? grads : &gz, sizeof(gs_grads));
+  add(&st, sizeof st);
+  if (!p->exec || sig != p->signature) {
+    if (p->exec) {
+      (void)hipGraphExecDestroy(p->exec);
+      p->exec = nullptr;
+    }
+    if (p->graph) {
+      (void)hipGraphDestroy(p->graph);
+      p->graph = nullptr;
+    }
+    GS_TRY_HIP(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal), "begin capture");
+    rc = enqueue_batch(p, g, n_views, views, mode & ~GS_GRAPH, grads, st);
+    hipGraph_t graph = nullptr;
+    hipError_t e = hipStreamEndCapture(st, &graph);
+    if (rc) {
+      if (graph) (void)hipGraphDestroy(graph);
+      return rc;
+    }
+    if (e != hipSuccess) return hip_fail(e, "end capture");
+    e = hipGraphInstantiate(&p->exec, graph, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+      (void)hipGraphDestroy(graph);
+      return hip_fail(e, "graph instantiate");
+    }
+    p->graph = graph;
+    p->signature.swap(sig);
+  }
+  GS_TRY_HIP(hipGraphLaunch(p->exec, st), "graph launch");
+  return GS_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,371 @@
+// Stage a2 of the rasterizer: (tile, Gaussian) pairs with the alpha-max tile cull, sorted so
+// that each tile's list is in depth order (Sec. "3D Gaussian Splatting Representation": the
+// splats are arranged in depth order before alpha-blending; Sec. "CUDA-Related Acceleration
+// Strategies": tiles whose largest weight is below 1/255 are culled).
+//
+// Order: one total order (tile, depth bits, record index). Built as
+//   1. a stable LSD radix sort of all records by depth key (invisible records sort last),
+//   2. an exclusive scan of the per-record tile counts in that order,
+//   3. emission of (global tile id, record) pairs in depth order, repeating the cull test on
+//      the stored float32 splat record so the decisions equal those of the projection stage,
+//   4. a stable LSD radix sort of the pairs by tile id, which keeps depth order inside a tile,
+//   5. per-tile [begin, end) ranges.
+// Radix passes use 8-bit digits. Ranks inside a block come from wave64 ballots (peer masks of
+// equal digits), so the sort is stable without per-item atomics. The pair count lives on the
+// device; every kernel after the scan reads it, so no host synchronisation is needed.
+#include <algorithm>
+
+#include "gs_internal.hpp"
+
+namespace gs {
+
+constexpr int kRadixBits = 8;
+constexpr int kRadixDigits = 1 << kRadixBits;
+constexpr int kRadixThreads = 256;
+constexpr int kRadixItems = 16;
+constexpr int kRadixChunk = kRadixThreads * kRadixItems;
+constexpr int kScanThreads = 256;
+constexpr int kScanItems = 4;
+constexpr int kScanChunk = kScanThreads * kScanItems;
+
+__device__ __forceinline__ int64_t live_count(int64_t n_static, const int64_t *n_dev, int64_t cap) {
+  if (!n_dev) return n_static;
+  int64_t v = *n_dev;
+  return v < cap ? v : cap;
+}
+
+__device__ __forceinline__ uint64_t lanemask_lt() {
+  const int lane = threadIdx.x & 63;
+  return lane ? (~0ull >> (64 - lane)) : 0ull;
+}
+
+// Lanes of this wavefront whose digit equals this lane's digit (only valid lanes).
+__device__ __forceinline__ uint64_t digit_peers(uint32_t d, bool valid) {
+  uint64_t m = __ballot(valid);
+#pragma unroll
+  for (int b = 0; b < kRadixBits; ++b) {
+    const bool bit = (d >> b) & 1u;
+    const uint64_t bal = __ballot(bit);
+    m &= bit ? bal : ~bal;
+  }
+  return m;
+}
+
+// Exclusive scan of one value per thread over a block of NT threads; returns the total too.
+template <int NT>
+__device__ __forceinline__ uint32_t block_exclusive_scan(uint32_t v, uint32_t *lds /*NT/64 + 1*/, uint32_t &total) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  uint32_t inc = v;
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) {
+    uint32_t t = __shfl_up(inc, off);
+    if (lane >= off) inc += t;
+  }
+  __syncthreads();
+  if (lane == 63) lds[wave] = inc;
+  __syncthreads();
+  uint32_t wbase = 0, tot = 0;
+#pragma unroll
+  for (int w = 0; w < NT / 64; ++w) {
+    const uint32_t x = lds[w];
+    if (w < wave) wbase += x;
+    tot += x;
+  }
+  total = tot;
+  return wbase + inc - v;
+}
+
+// ---- radix passes --------------------------------------------------------------------------
+__global__ __launch_bounds__(kRadixThreads) void k_radix_hist(const uint32_t *__restrict__ keys, int64_t n_static,
+                                                              const int64_t *n_dev, int64_t cap, int shift,
+                                                              uint32_t *__restrict__ hist, int nblocks) {
+  __shared__ uint32_t h[kRadixDigits];
+  const int64_t n = live_count(n_static, n_dev, cap);
+  h[threadIdx.x] = 0;
+  __syncthreads();
+  const int64_t base = (int64_t)blockIdx.x * kRadixChunk;
+  if (base < n) {
+    const uint64_t lt = lanemask_lt();
+#pragma unroll 4
+    for (int r = 0; r < kRadixItems; ++r) {
+      const int64_t i = base + r * kRadixThreads + threadIdx.x;
+      const bool valid = i < n;
+      const uint32_t d = valid ? (keys[i] >> shift) & (kRadixDigits - 1) : 0u;
+      const uint64_t peers = digit_peers(d, valid);
+      if (valid && (peers & lt) == 0) atomicAdd(&h[d], (uint32_t)__popcll(peers));
+    }
+  }
+  __syncthreads();
+  hist[(int64_t)threadIdx.x * nblocks + blockIdx.x] = h[threadIdx.x];
+}
+
+// One workgroup per digit: exclusive scan of that digit's counts over the blocks, in place;
+// the digit total goes to tot[digit].
+__global__ __launch_bounds__(kRadixThreads) void k_radix_scan(uint32_t *__restrict__ hist, int nblocks,
+                                                              uint32_t *__restrict__ tot) {
+  __shared__ uint32_t lds[kRadixThreads / 64 + 1];
+  uint32_t *row = hist + (int64_t)blockIdx.x * nblocks;
+  uint32_t running = 0;
+  for (int base = 0; base < nblocks; base += kRadixThreads) {
+    const int i = base + threadIdx.x;
+    const uint32_t v = i < nblocks ? row[i] : 0u;
+    uint32_t total;
+    const uint32_t ex = block_exclusive_scan<kRadixThreads>(v, lds, total);
+    if (i < nblocks) row[i] = running + ex;
+    running += total;
+  }
+  if (threadIdx.x == 0) tot[blockIdx.x] = running;
+}
+
+// Stable scatter. vin == nullptr means the values are the input positions; kout may be null.
+__global__ __launch_bounds__(kRadixThreads) void k_radix_scatter(const uint32_t *__restrict__ kin,
+                                                                 const uint32_t *__restrict__ vin,
+                                                                 uint32_t *__restrict__ kout,
+                                                                 uint32_t *__restrict__ vout, int64_t n_static,
+                                                                 const int64_t *n_dev, int64_t cap, int shift,
+                                                                 const uint32_t *__restrict__ hist,
+                                                                 const uint32_t *__restrict__ tot, int nblocks) {
+  constexpr int NW = kRadixThreads / 64;
+  __shared__ uint32_t s_base[kRadixDigits];
+  __shared__ uint32_t s_run[kRadixDigits];
+  __shared__ uint32_t s_wcnt[NW][kRadixDigits];
+  __shared__ uint32_t lds[NW + 1];
+  const int64_t n = live_count(n_static, n_dev, cap);
+  const int64_t base = (int64_t)blockIdx.x * kRadixChunk;
+  if (base >= n) return;  // uniform per block
+  const int t = threadIdx.x;
+  uint32_t total;
+  const uint32_t pre = block_exclusive_scan<kRadixThreads>(tot[t], lds, total);
+  s_base[t] = pre + hist[(int64_t)t * nblocks + blockIdx.x];
+  s_run[t] = 0;
+#pragma unroll
+  for (int w = 0; w < NW; ++w) s_wcnt[w][t] = 0;
+  __syncthreads();
+  const int wave = t >> 6;
+  const uint64_t lt = lanemask_lt();
+  for (int r = 0; r < kRadixItems; ++r) {
+    const int64_t i = base + r * kRadixThreads + t;
+    const bool valid = i < n;
+    const uint32_t k = valid ? kin[i] : 0u;
+    const uint32_t d = (k >> shift) & (kRadixDigits - 1);
+    const uint64_t peers = digit_peers(d, valid);
+    const uint32_t rank = (uint32_t)__popcll(peers & lt);
+    if (valid && rank == 0) s_wcnt[wave][d] = (uint32_t)__popcll(peers);
+    __syncthreads();
+    if (valid) {
+      uint32_t off = s_run[d];
+      for (int w = 0; w < wave; ++w) off += s_wcnt[w][d];
+      const uint32_t pos = s_base[d] + off + rank;
+      if (kout) kout[pos] = k;
+      vout[pos] = vin ? vin[i] : (uint32_t)i;
+    }
+    __syncthreads();
+    uint32_t add = 0;
+#pragma unroll
+    for (int w = 0; w < NW; ++w) {
+      add += s_wcnt[w][t];
+      s_wcnt[w][t] = 0;
+    }
+    s_run[t] += add;
+    __syncthreads();
+  }
+}
+
+// ---- pair counts, scan, emission -----------------------------------------------------------
+__global__ __launch_bounds__(kScanThreads) void k_count_reduce(const uint32_t *__restrict__ order,
+                                                               const uint32_t *__restrict__ n_tiles, int64_t n,
+                                                               uint32_t *__restrict__ bsum) {
+  __shared__ uint32_t lds[kScanThreads / 64 + 1];
+  const int64_t base = (int64_t)blockIdx.x * kScanChunk;
+  uint32_t s = 0;
+#pragma unroll
+  for (int r = 0; r < kScanItems; ++r) {
+    const int64_t i = base + r * kScanThreads + threadIdx.x;
+    if (i < n) s += n_tiles[order[i]];
+  }
+  uint32_t total;
+  block_exclusive_scan<kScanThreads>(s, lds, total);
+  if (threadIdx.x == 0) bsum[blockIdx.x] = total;
+}
+
+// Single workgroup: exclusive scan of the block sums; total pair count (int64) to *num_pairs.
+__global__ __launch_bounds__(1024) void k_count_scan_bsums(uint32_t *__restrict__ bsum, int64_t nb,
+                                                           int64_t *__restrict__ num_pairs) {
+  __shared__ uint32_t lds[1024 / 64 + 1];
+  uint64_t running = 0;
+  for (int64_t base = 0; base < nb; base += 1024) {
+    const int64_t i = base + threadIdx.x;
+    const uint32_t v = i < nb ? bsum[i] : 0u;
+    uint32_t total;
+    const uint32_t ex = block_exclusive_scan<1024>(v, lds, total);
+    if (i < nb) bsum[i] = (uint32_t)(running + ex);
+    running += total;
+  }
+  if (threadIdx.x == 0) *num_pairs = (int64_t)running;
+}
+
+__global__ __launch_bounds__(kScanThreads) void k_emit_pairs(ViewTable vt, const uint32_t *__restrict__ order,
+                                                             int64_t n, const uint32_t *__restrict__ n_tiles,
+                                                             const float4 *__restrict__ rec_a,
+                                                             const float4 *__restrict__ rec_b,
+                                                             const short4 *__restrict__ rect,
+                                                             const uint32_t *__restrict__ bsum, int64_t cap,
+                                                             uint32_t *__restrict__ pkey, uint32_t *__restrict__ pval) {
+  __shared__ uint32_t lds[kScanThreads / 64 + 1];
+  const int64_t base = (int64_t)blockIdx.x * kScanChunk;
+  uint32_t running = bsum[blockIdx.x];
+  for (int r = 0; r < kScanItems; ++r) {
+    const int64_t i = base + r * kScanThreads + threadIdx.x;
+    uint32_t e = 0, cnt = 0;
+    if (i < n) {
+      e = order[i];
+      cnt = n_tiles[e];
+    }
+    uint32_t total;
+    const uint32_t ex = block_exclusive_scan<kScanThreads>(cnt, lds, total);
+    if (cnt) {
+      const uint32_t off = running + ex;
+      const int vi = (int)(e / (uint32_t)vt.n);
+      const ViewCam &cam = vt.v[vi];
+      const float4 A = rec_a[e], B = rec_b[e];
+      const short4 rc = rect[e];
+      visit_kept_tiles(cam, vt.tile_w, vt.tile_h, A.x, A.y, B.x, B.y, B.z, B.w, rc.x, rc.y, rc.z, rc.w,
+                       [&](uint32_t lt, uint32_t j) {
+                         const int64_t pos = (int64_t)off + j;
+                         if (pos < cap) {
+                           pkey[pos] = cam.tile_base + lt;
+                           pval[pos] = e;
+                         }
+                       });
+    }
+    running += total;
+  }
+}
+
+__global__ void k_fill_u32(uint32_t *__restrict__ p, int64_t n, uint32_t v) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
+__global__ void k_tile_ranges(const uint32_t *__restrict__ keys, const int64_t *num_pairs, int64_t cap,
+                              uint32_t *__restrict__ range) {
+  const int64_t n = live_count(0, num_pairs, cap);
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const uint32_t k = keys[i];
+  if (i == 0 || keys[i - 1] != k) range[2 * (int64_t)k] = (uint32_t)i;
+  if (i == n - 1 || keys[i + 1] != k) range[2 * (int64_t)k + 1] = (uint32_t)(i + 1);
+}
+
+// ---- host-side orchestration ---------------------------------------------------------------
+static inline int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
+static inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+struct BinScratch {
+  uint32_t *dk_a, *dv_a, *dk_b, *dv_b;  // depth sort ping-pong [n]
+  uint32_t *bsum;                       // [ceil(n / kScanChunk)]
+  uint32_t *pk_a, *pv_a, *pk_b, *pv_b;  // pair sort ping-pong [cap]
+  uint32_t *hist;                       // [256][max blocks]
+  uint32_t *tot;                        // [256]
+};
+
+size_t bin_scratch_bytes(int64_t n, int64_t cap) {
+  const int64_t nb_max = std::max<int64_t>(cdiv(std::max<int64_t>(n, 1), kRadixChunk),
+                                           cdiv(std::max<int64_t>(cap, 1), kRadixChunk));
+  size_t s = 0;
+  s += 4 * align256(sizeof(uint32_t) * std::max<int64_t>(n, 1));
+  s += align256(sizeof(uint32_t) * cdiv(std::max<int64_t>(n, 1), kScanChunk));
+  s += 4 * align256(sizeof(uint32_t) * std::max<int64_t>(cap, 1));
+  s += align256(sizeof(uint32_t) * kRadixDigits * nb_max);
+  s += align256(sizeof(uint32_t) * kRadixDigits);
+  return s;
+}
+
+static BinScratch carve(void *base, int64_t n, int64_t cap) {
+  const int64_t nb_max = std::max<int64_t>(cdiv(std::max<int64_t>(n, 1), kRadixChunk),
+                                           cdiv(std::max<int64_t>(cap, 1), kRadixChunk));
+  char *p = (char *)base;
+  auto take = [&](size_t bytes) {
+    char *r = p;
+    p += align256(bytes);
+    return (uint32_t *)r;
+  };
+  BinScratch s;
+  const size_t nn = sizeof(uint32_t) * std::max<int64_t>(n, 1);
+  const size_t cc = sizeof(uint32_t) * std::max<int64_t>(cap, 1);
+  s.dk_a = take(nn); s.dv_a = take(nn); s.dk_b = take(nn); s.dv_b = take(nn);
+  s.bsum = take(sizeof(uint32_t) * cdiv(std::max<int64_t>(n, 1), kScanChunk));
+  s.pk_a = take(cc); s.pv_a = take(cc); s.pk_b = take(cc); s.pv_b = take(cc);
+  s.hist = take(sizeof(uint32_t) * kRadixDigits * nb_max);
+  s.tot = take(sizeof(uint32_t) * kRadixDigits);
+  return s;
+}
+
+static hipError_t radix_pass(const uint32_t *kin, const uint32_t *vin, uint32_t *kout, uint32_t *vout, int64_t n_static,
+                             const int64_t *n_dev, int64_t cap, int shift, const BinScratch &s, hipStream_t st) {
+  const int64_t nmax = n_dev ? cap : n_static;
+  const int nb = (int)std::max<int64_t>(cdiv(nmax, kRadixChunk), 1);
+  hipLaunchKernelGGL(k_radix_hist, dim3(nb), dim3(kRadixThreads), 0, st, kin, n_static, n_dev, cap, shift, s.hist, nb);
+  hipLaunchKernelGGL(k_radix_scan, dim3(kRadixDigits), dim3(kRadixThreads), 0, st, s.hist, nb, s.tot);
+  hipLaunchKernelGGL(k_radix_scatter, dim3(nb), dim3(kRadixThreads), 0, st, kin, vin, kout, vout, n_static, n_dev, cap,
+                     shift, s.hist, s.tot, nb);
+  return hipGetLastError();
+}
+
+hipError_t fill_u32(uint32_t *p, int64_t n, uint32_t v, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_fill_u32, dim3((unsigned)cdiv(n, 256)), dim3(256), 0, st, p, n, v);
+  return hipGetLastError();
+}
+
+// n: number of records (views x Gaussians); cap: pair capacity; total_tiles over all views.
+hipError_t launch_bin_sort(const ViewTable &vt, const gs_projected &p, int64_t n, int64_t cap, uint32_t *vals,
+                           uint32_t *tile_range, int64_t *num_pairs, void *scratch, hipStream_t st) {
+  BinScratch s = carve(scratch, n, cap);
+  hipError_t err;
+  if ((err = fill_u32(tile_range, 2 * (int64_t)vt.total_tiles, 0u, st)) != hipSuccess) return err;
+  if (n == 0) {
+    hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(64), 0, st, (uint32_t *)num_pairs, 2, 0u);
+    return hipGetLastError();
+  }
+  // 1. depth order of all records (stable; the record index breaks ties)
+  const uint32_t *kin = p.dkey;
+  const uint32_t *vin = nullptr;
+  uint32_t *kb[2] = {s.dk_a, s.dk_b}, *vb[2] = {s.dv_a, s.dv_b};
+  for (int pass = 0; pass < 4; ++pass) {
+    uint32_t *ko = pass == 3 ? nullptr : kb[pass & 1];
+    uint32_t *vo = vb[pass & 1];
+    if ((err = radix_pass(kin, vin, ko, vo, n, nullptr, 0, pass * kRadixBits, s, st)) != hipSuccess) return err;
+    kin = ko;
+    vin = vo;
+  }
+  const uint32_t *order = vin;  // == s.dv_b
+  // 2. exclusive scan of tile counts in depth order; total -> num_pairs
+  const int64_t nbs = cdiv(n, kScanChunk);
+  hipLaunchKernelGGL(k_count_reduce, dim3((unsigned)nbs), dim3(kScanThreads), 0, st, order, p.n_tiles, n, s.bsum);
+  hipLaunchKernelGGL(k_count_scan_bsums, dim3(1), dim3(1024), 0, st, s.bsum, nbs, num_pairs);
+  // 3. emission in depth order
+  hipLaunchKernelGGL(k_emit_pairs, dim3((unsigned)nbs), dim3(kScanThreads), 0, st, vt, order, n, p.n_tiles,
+                     (const float4 *)p.rec_a, (const float4 *)p.rec_b, (const short4 *)p.rect, s.bsum, cap, s.pk_a,
+                     s.pv_a);
+  if ((err = hipGetLastError()) != hipSuccess) return err;
+  // 4. stable sort by global tile id
+  int tile_bits = 1;
+  while ((1ull << tile_bits) < (uint64_t)vt.total_tiles) ++tile_bits;
+  const int passes = (int)cdiv(tile_bits, kRadixBits);
+  const uint32_t *pk = s.pk_a, *pv = s.pv_a;
+  uint32_t *pkb[2] = {s.pk_b, s.pk_a}, *pvb[2] = {s.pv_b, s.pv_a};
+  for (int pass = 0; pass < passes; ++pass) {
+    uint32_t *ko = pkb[pass & 1];
+    uint32_t *vo = pass == passes - 1 ? vals : pvb[pass & 1];
+    if ((err = radix_pass(pk, pv, ko, vo, 0, num_pairs, cap, pass * kRadixBits, s, st)) != hipSuccess) return err;
+    pk = ko;
+    pv = vo;
+  }
+  // 5. tile ranges
+  hipLaunchKernelGGL(k_tile_ranges, dim3((unsigned)cdiv(std::max<int64_t>(cap, 1), 256)), dim3(256), 0, st, pk,
+                     num_pairs, cap, tile_range);
+  return hipGetLastError();
+}
+
+}  // namespace gs

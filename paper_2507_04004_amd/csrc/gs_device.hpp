@@ -1,0 +1,146 @@
+// Device-side types shared by the rasterizer kernels (gfx950, wave64).
+//
+// Every stage kernel takes a ViewTable by value: up to 16 cameras with their tile grids,
+// so one launch covers all views of a batch and a single view is a batch of one. Records
+// of view v occupy entries [v*n, (v+1)*n) of the per-record arrays ("entry" index e).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "gs.h"
+
+namespace gs {
+
+constexpr int kMaxViews = GS_MAX_VIEWS;
+constexpr float kNear = 0.2f;
+constexpr float kAlphaMin = 1.0f / 255.0f;
+constexpr float kAlphaMax = 0.99f;
+constexpr float kTMin = 1e-4f;
+constexpr float kDilate = 0.3f;
+
+struct ViewCam {
+  float fx, fy, cx, cy;
+  float R[9];
+  float t[3];
+  float cw[3];  // camera centre -R^T t in world coordinates
+  float bg[3];
+  int32_t W, H, x0, y0, w, h;
+  int32_t tiles_x, tiles_y;
+  uint32_t tile_base;  // first global tile id of this view
+  uint32_t pix_base;   // first pixel of this view in concatenated per-pixel scratch
+};
+
+struct ViewTable {
+  int32_t n_views;
+  int32_t tile_w, tile_h;
+  int32_t sh_degree;
+  int64_t n;             // Gaussians per view
+  uint32_t total_tiles;  // sum of tiles over views
+  uint32_t pad;
+  ViewCam v[kMaxViews];
+};
+
+struct ViewImg {
+  float *color, *depth, *alpha, *t_final;
+  int32_t *last, *n_contrib;
+};
+struct ImgTable {
+  ViewImg v[kMaxViews];
+};
+
+// Per-view upstream gradients for the blend backward. gD / gO are dense window planes
+// (user-given or built from the LiDAR term), or null when the view has none.
+struct ViewGrad {
+  const float *gC, *gD, *gO;
+};
+struct GradTable {
+  ViewGrad v[kMaxViews];
+};
+
+struct LidarView {
+  const int32_t *pix;
+  const float *target;
+  const float *grad_scale;
+  float *loss_out;
+  float weight;
+  int32_t m;
+  int32_t npx;  // window pixels: hits outside [0, npx) are ignored
+};
+struct LidarTable {
+  int32_t n_views;
+  uint32_t total_hits;
+  LidarView v[kMaxViews];
+};
+
+__device__ __forceinline__ int view_of_tile(const ViewTable &vt, uint32_t gt) {
+  int v = 0;
+#pragma unroll 1
+  for (int i = 1; i < vt.n_views; ++i)
+    if (gt >= vt.v[i].tile_base) v = i;
+  return v;
+}
+
+// Exponent of a splat at pixel offset (dx, dy): -q/2 with q = a dx^2 + 2 b dx dy + c dy^2,
+// clamped to <= 0 (q >= 0 exactly; the clamp only absorbs rounding). The forward and the
+// backward both call this, with fixed FMA placement, so they take identical decisions.
+__device__ __forceinline__ float splat_power(float a, float b, float c, float dx, float dy) {
+#pragma clang fp contract(off)
+  float q = __builtin_fmaf(a * dx, dx, __builtin_fmaf(c * dy, dy, (2.0f * b) * (dx * dy)));
+  return fminf(-0.5f * q, 0.0f);
+}
+
+__device__ __forceinline__ float splat_alpha_raw(float o, float power) { return o * __expf(power); }
+
+// Smallest value of q over the pixel-centre rectangle [xl,xh] x [yl,yh]: zero when the
+// centre lies inside, else the least of the clamped 1-D minima on the facing edges.
+__device__ __forceinline__ float rect_qmin(float u, float v, float a, float b, float c, float xl, float xh,
+                                           float yl, float yh) {
+#pragma clang fp contract(off)
+  bool inx = (u >= xl) && (u <= xh);
+  bool iny = (v >= yl) && (v <= yh);
+  if (inx && iny) return 0.0f;
+  float best = INFINITY;
+  if (!inx) {
+    float X = (u < xl) ? xl : xh;
+    float dx = X - u;
+    float dy = -(b * dx) / c;
+    dy = fminf(fmaxf(dy, yl - v), yh - v);
+    float q = a * dx * dx + 2.0f * b * dx * dy + c * dy * dy;
+    best = q;
+  }
+  if (!iny) {
+    float Y = (v < yl) ? yl : yh;
+    float dy = Y - v;
+    float dx = -(b * dy) / a;
+    dx = fminf(fmaxf(dx, xl - u), xh - u);
+    float q = a * dx * dx + 2.0f * b * dx * dy + c * dy * dy;
+    best = fminf(best, q);
+  }
+  return best;
+}
+
+// Kept tiles of a splat, in row-major order over its rectangle. Visitor gets the local tile id.
+template <typename F>
+__device__ __forceinline__ uint32_t visit_kept_tiles(const ViewCam &cam, int tw, int th, float u, float v, float a,
+                                                     float b, float c, float kappa2, int tx0, int ty0, int tx1,
+                                                     int ty1, F &&f) {
+  uint32_t cnt = 0;
+  const int xend = cam.x0 + cam.w - 1, yend = cam.y0 + cam.h - 1;
+  for (int ty = ty0; ty <= ty1; ++ty) {
+    const int ya = cam.y0 + ty * th;
+    const int yb = min(ya + th - 1, yend);
+    for (int tx = tx0; tx <= tx1; ++tx) {
+      const int xa = cam.x0 + tx * tw;
+      const int xb = min(xa + tw - 1, xend);
+      float q = rect_qmin(u, v, a, b, c, (float)xa, (float)xb, (float)ya, (float)yb);
+      if (q <= kappa2) {
+        f((uint32_t)(ty * cam.tiles_x + tx), cnt);
+        ++cnt;
+      }
+    }
+  }
+  return cnt;
+}
+
+}  // namespace gs

@@ -1,0 +1,44 @@
+// Host-side declarations of the stage launchers (one per translation unit).
+#pragma once
+
+#include "gs_device.hpp"
+
+namespace gs {
+
+struct MapTable {
+  float *gD[kMaxViews];
+  float *gO[kMaxViews];
+};
+struct MapSrc {
+  const float *gD[kMaxViews];
+  const float *gO[kMaxViews];
+  int64_t npx[kMaxViews];
+};
+
+// Optional event pairs around one stage's launches (see gs_profile_enable).
+void profile_begin(int stage, hipStream_t st);
+void profile_end(int stage, hipStream_t st);
+
+hipError_t launch_preprocess(const ViewTable &vt, const gs_gaussians &g, const gs_projected &p, hipStream_t st);
+hipError_t launch_preprocess_bwd(const ViewTable &vt, const gs_gaussians &g, const gs_projected &p, const float *g2,
+                                 const gs_grads &out, float *const *pose_out, float *pose_partial, hipStream_t st);
+int64_t preprocess_bwd_blocks(int64_t n);
+
+size_t bin_scratch_bytes(int64_t n, int64_t cap);
+hipError_t launch_bin_sort(const ViewTable &vt, const gs_projected &p, int64_t n, int64_t cap, uint32_t *vals,
+                           uint32_t *tile_range, int64_t *num_pairs, void *scratch, hipStream_t st);
+hipError_t fill_u32(uint32_t *p, int64_t n, uint32_t v, hipStream_t st);
+
+hipError_t launch_blend_fwd(int bd, const ViewTable &vt, const ImgTable &it, const gs_projected &p,
+                            const uint32_t *vals, const uint32_t *range, hipStream_t st);
+hipError_t launch_blend_bwd(int bd, const ViewTable &vt, const ImgTable &it, const GradTable &gtab,
+                            const gs_projected &p, const uint32_t *vals, const uint32_t *range, float *g2,
+                            hipStream_t st);
+hipError_t launch_lidar_loss(const LidarTable &lt, const ImgTable &it, int max_m, hipStream_t st);
+hipError_t launch_grad_maps(const MapSrc &src, const MapTable &dst, int n_views, int64_t max_npx,
+                            const LidarTable &lt, const ImgTable &it, int max_m, hipStream_t st);
+hipError_t zero_f32(float *p, int64_t n, hipStream_t st);
+hipError_t launch_loss_l1(const float *c, const float *t, int64_t n, float weight, float *dldc, float *loss,
+                          hipStream_t st);
+
+}  // namespace gs

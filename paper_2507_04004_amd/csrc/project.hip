@@ -1,0 +1,552 @@
+// Stage a1 (projection / SH colour / footprint / tile count) and stage a5 (its backward and
+// the pose gradient) of the Gaussian rasterizer, gfx950.
+//
+// Sec. "3D Gaussian Splatting Representation": Sigma = R S S^T R^T; mu_hat = R_cw mu + p;
+// d = e3^T mu_hat; mu' = pi_c(mu_hat / d); Sigma' = J R_cw Sigma R_cw^T J^T; colour from SH
+// up to degree 3 along the view direction. Sec. "CUDA-Related Acceleration Strategies":
+// alpha-max tile cull at 1/255 and separated SH planes.
+//
+// One lane per (Gaussian, view). SoA parameter planes are read coalesced; invalid lanes are
+// flagged and all lanes leave through the same exit, so a wavefront whose lanes are all
+// culled skips the SH planes entirely (the wave-level predicate masking of Sec. "CUDA-
+// Related Acceleration Strategies" d).
+//
+// Binning decisions (validity, depth key, tile rectangle, cull) are computed in float32 with
+// FMA contraction off and a fixed operation order, the order the float32 binning oracle
+// implements independently; the rest (colour, gradients) is ordinary float32.
+#include <algorithm>
+
+#include "gs_internal.hpp"
+
+namespace gs {
+
+struct Splat {
+  bool ok;
+  float px, py, pz;        // camera-frame mean
+  float inv_q, qw, qx, qy, qz;  // 1/|q| and the unit quaternion
+  float r[9];              // rotation of the unit quaternion
+  float sx, sy, sz;
+  float S00, S01, S02, S11, S12, S22;  // 3D covariance
+  float xn, yn, tx, ty;    // x/d, y/d and their clamped values inside J
+  float j00, j02, j11, j12;
+  float t0[3], t1[3];      // rows of Tm = J R_cw
+  float s00, s01, s11, det;
+  float a, b, c;           // conic
+  float u, v, o, kappa2;
+  int32_t px0, px1, py0, py1;  // clipped pixel-centre span of the footprint
+};
+
+// Everything below up to the tile rectangle is a binning decision: contraction off.
+__device__ __forceinline__ void splat_decide(const ViewCam &cam, float mx, float my, float mz, float sx, float sy,
+                                             float sz, float qw, float qx, float qy, float qz, float o, Splat &s) {
+#pragma clang fp contract(off)
+  const float *R = cam.R;
+  const float *t = cam.t;
+  bool ok = isfinite(mx) && isfinite(my) && isfinite(mz) && isfinite(sx) && isfinite(sy) && isfinite(sz) &&
+            isfinite(qw) && isfinite(qx) && isfinite(qy) && isfinite(qz) && isfinite(o);
+  float px = R[0] * mx + R[1] * my + R[2] * mz + t[0];
+  float py = R[3] * mx + R[4] * my + R[5] * mz + t[1];
+  float pz = R[6] * mx + R[7] * my + R[8] * mz + t[2];
+  ok = ok && pz > kNear;
+  float qq = qw * qw + qx * qx + qy * qy + qz * qz;
+  ok = ok && qq > 0.0f && isfinite(qq);
+  ok = ok && sx > 0.0f && sy > 0.0f && sz > 0.0f;
+  float inv = 1.0f / sqrtf(qq);
+  float w = qw * inv, x = qx * inv, y = qy * inv, z = qz * inv;
+  float r00 = 1.0f - 2.0f * (y * y + z * z), r01 = 2.0f * (x * y - w * z), r02 = 2.0f * (x * z + w * y);
+  float r10 = 2.0f * (x * y + w * z), r11 = 1.0f - 2.0f * (x * x + z * z), r12 = 2.0f * (y * z - w * x);
+  float r20 = 2.0f * (x * z - w * y), r21 = 2.0f * (y * z + w * x), r22 = 1.0f - 2.0f * (x * x + y * y);
+  float m00 = r00 * sx, m01 = r01 * sy, m02 = r02 * sz;
+  float m10 = r10 * sx, m11 = r11 * sy, m12 = r12 * sz;
+  float m20 = r20 * sx, m21 = r21 * sy, m22 = r22 * sz;
+  float S00 = m00 * m00 + m01 * m01 + m02 * m02;
+  float S01 = m00 * m10 + m01 * m11 + m02 * m12;
+  float S02 = m00 * m20 + m01 * m21 + m02 * m22;
+  float S11 = m10 * m10 + m11 * m11 + m12 * m12;
+  float S12 = m10 * m20 + m11 * m21 + m12 * m22;
+  float S22 = m20 * m20 + m21 * m21 + m22 * m22;
+  float xn = px / pz, yn = py / pz;
+  float u = cam.fx * xn + cam.cx;
+  float v = cam.fy * yn + cam.cy;
+  float limx = (0.65f * (float)cam.W) / cam.fx;
+  float limy = (0.65f * (float)cam.H) / cam.fy;
+  float tx = fminf(fmaxf(xn, -limx), limx);
+  float ty = fminf(fmaxf(yn, -limy), limy);
+  float j00 = cam.fx / pz, j02 = -(cam.fx * tx) / pz;
+  float j11 = cam.fy / pz, j12 = -(cam.fy * ty) / pz;
+  float t00 = j00 * R[0] + j02 * R[6], t01 = j00 * R[1] + j02 * R[7], t02 = j00 * R[2] + j02 * R[8];
+  float t10 = j11 * R[3] + j12 * R[6], t11 = j11 * R[4] + j12 * R[7], t12 = j11 * R[5] + j12 * R[8];
+  float u00 = t00 * S00 + t01 * S01 + t02 * S02;
+  float u01 = t00 * S01 + t01 * S11 + t02 * S12;
+  float u02 = t00 * S02 + t01 * S12 + t02 * S22;
+  float u10 = t10 * S00 + t11 * S01 + t12 * S02;
+  float u11 = t10 * S01 + t11 * S11 + t12 * S12;
+  float u12 = t10 * S02 + t11 * S12 + t12 * S22;
+  float s00 = u00 * t00 + u01 * t01 + u02 * t02 + 0.3f;
+  float s01 = u00 * t10 + u01 * t11 + u02 * t12;
+  float s11 = u10 * t10 + u11 * t11 + u12 * t12 + 0.3f;
+  float det = s00 * s11 - s01 * s01;
+  ok = ok && det > 0.0f;
+  ok = ok && (255.0 * (double)o >= 1.0);
+  float a = s11 / det, b = -s01 / det, c = s00 / det;
+  float kappa2 = (float)(2.0 * log(255.0 * (double)o));
+  float hx = sqrtf(kappa2 * s00), hy = sqrtf(kappa2 * s11);
+  ok = ok && isfinite(u) && isfinite(v) && isfinite(hx) && isfinite(hy);
+  float xlo = fmaxf(ceilf(u - hx), (float)cam.x0), xhi = fminf(floorf(u + hx), (float)(cam.x0 + cam.w - 1));
+  float ylo = fmaxf(ceilf(v - hy), (float)cam.y0), yhi = fminf(floorf(v + hy), (float)(cam.y0 + cam.h - 1));
+  ok = ok && xlo <= xhi && ylo <= yhi;
+  s.ok = ok;
+  s.px = px; s.py = py; s.pz = pz;
+  s.inv_q = inv; s.qw = w; s.qx = x; s.qy = y; s.qz = z;
+  s.r[0] = r00; s.r[1] = r01; s.r[2] = r02; s.r[3] = r10; s.r[4] = r11; s.r[5] = r12;
+  s.r[6] = r20; s.r[7] = r21; s.r[8] = r22;
+  s.sx = sx; s.sy = sy; s.sz = sz;
+  s.S00 = S00; s.S01 = S01; s.S02 = S02; s.S11 = S11; s.S12 = S12; s.S22 = S22;
+  s.xn = xn; s.yn = yn; s.tx = tx; s.ty = ty;
+  s.j00 = j00; s.j02 = j02; s.j11 = j11; s.j12 = j12;
+  s.t0[0] = t00; s.t0[1] = t01; s.t0[2] = t02; s.t1[0] = t10; s.t1[1] = t11; s.t1[2] = t12;
+  s.s00 = s00; s.s01 = s01; s.s11 = s11; s.det = det;
+  s.a = a; s.b = b; s.c = c;
+  s.u = u; s.v = v; s.o = o; s.kappa2 = kappa2;
+  // spans are only meaningful when ok; keep them in range otherwise
+  s.px0 = ok ? (int32_t)xlo : 0;
+  s.px1 = ok ? (int32_t)xhi : -1;
+  s.py0 = ok ? (int32_t)ylo : 0;
+  s.py1 = ok ? (int32_t)yhi : -1;
+}
+
+// Real spherical harmonics up to degree 3 (Condon-Shortley phase), index k = l^2 + l + m.
+struct SHConst {
+  static constexpr float c0 = 0.28209479177387814f;
+  static constexpr float c1 = 0.4886025119029199f;
+  static constexpr float c2a = 1.0925484305920792f;
+  static constexpr float c2b = 0.31539156525252005f;
+  static constexpr float c2c = 0.5462742152960396f;
+  static constexpr float c3a = 0.5900435899266435f;
+  static constexpr float c3b = 2.890611442640554f;
+  static constexpr float c3c = 0.4570457994644658f;
+  static constexpr float c3d = 0.3731763325901154f;
+  static constexpr float c3e = 1.445305721320277f;
+};
+
+__device__ __forceinline__ void sh_eval(int deg, float x, float y, float z, float *Y) {
+#pragma clang fp contract(off)
+  using K = SHConst;
+  Y[0] = K::c0;
+  if (deg >= 1) {
+    Y[1] = -K::c1 * y;
+    Y[2] = K::c1 * z;
+    Y[3] = -K::c1 * x;
+  }
+  if (deg >= 2) {
+    float xx = x * x, yy = y * y, zz = z * z;
+    Y[4] = K::c2a * (x * y);
+    Y[5] = -K::c2a * (y * z);
+    Y[6] = K::c2b * (2.0f * zz - xx - yy);
+    Y[7] = -K::c2a * (x * z);
+    Y[8] = K::c2c * (xx - yy);
+    if (deg >= 3) {
+      Y[9] = -K::c3a * y * (3.0f * xx - yy);
+      Y[10] = K::c3b * (x * y * z);
+      Y[11] = -K::c3c * y * (4.0f * zz - xx - yy);
+      Y[12] = K::c3d * z * (2.0f * zz - 3.0f * xx - 3.0f * yy);
+      Y[13] = -K::c3c * x * (4.0f * zz - xx - yy);
+      Y[14] = K::c3e * z * (xx - yy);
+      Y[15] = -K::c3a * x * (xx - 3.0f * yy);
+    }
+  }
+}
+
+// Colour pre-activation per channel: SH . Y + 0.5 (contraction off, so the clamp decision
+// max(0, .) is identical in the forward and the backward).
+__device__ __forceinline__ void sh_colour_raw(int deg, int64_t n, int64_t g, const float *__restrict__ sh_dc,
+                                              const float *__restrict__ sh_rest, const float *Y, float raw[3]) {
+#pragma clang fp contract(off)
+  const int K = (deg + 1) * (deg + 1);
+#pragma unroll
+  for (int ch = 0; ch < 3; ++ch) raw[ch] = sh_dc[ch * n + g] * Y[0];
+  for (int k = 1; k < K; ++k) {
+#pragma unroll
+    for (int ch = 0; ch < 3; ++ch) raw[ch] = raw[ch] + sh_rest[(int64_t)(3 * (k - 1) + ch) * n + g] * Y[k];
+  }
+#pragma unroll
+  for (int ch = 0; ch < 3; ++ch) raw[ch] = raw[ch] + 0.5f;
+}
+
+__device__ __forceinline__ void view_dir(const ViewCam &cam, float mx, float my, float mz, float dir[3], float &dist) {
+  float dx = mx - cam.cw[0], dy = my - cam.cw[1], dz = mz - cam.cw[2];
+  dist = sqrtf(dx * dx + dy * dy + dz * dz);
+  float inv = 1.0f / dist;
+  dir[0] = dx * inv; dir[1] = dy * inv; dir[2] = dz * inv;
+}
+
+__global__ __launch_bounds__(256) void k_preprocess(ViewTable vt, const float *__restrict__ mean,
+                                                    const float *__restrict__ scale, const float *__restrict__ rot,
+                                                    const float *__restrict__ opacity,
+                                                    const float *__restrict__ sh_dc,
+                                                    const float *__restrict__ sh_rest, float4 *__restrict__ rec_a,
+                                                    float4 *__restrict__ rec_b, float4 *__restrict__ rgb,
+                                                    short4 *__restrict__ rect, uint32_t *__restrict__ n_tiles,
+                                                    uint32_t *__restrict__ dkey) {
+  const int64_t n = vt.n;
+  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int vi = blockIdx.y;
+  if (g >= n) return;
+  const ViewCam &cam = vt.v[vi];
+  const int64_t e = (int64_t)vi * n + g;
+  float mx = mean[g], my = mean[n + g], mz = mean[2 * n + g];
+  Splat s;
+  splat_decide(cam, mx, my, mz, scale[g], scale[n + g], scale[2 * n + g], rot[g], rot[n + g], rot[2 * n + g],
+               rot[3 * n + g], opacity[g], s);
+  uint32_t cnt = 0;
+  int tx0 = 0, ty0 = 0, tx1 = -1, ty1 = -1;
+  if (s.ok) {
+    tx0 = (s.px0 - cam.x0) / vt.tile_w;
+    tx1 = (s.px1 - cam.x0) / vt.tile_w;
+    ty0 = (s.py0 - cam.y0) / vt.tile_h;
+    ty1 = (s.py1 - cam.y0) / vt.tile_h;
+    cnt = visit_kept_tiles(cam, vt.tile_w, vt.tile_h, s.u, s.v, s.a, s.b, s.c, s.kappa2, tx0, ty0, tx1, ty1,
+                           [](uint32_t, uint32_t) {});
+  }
+  float4 col = make_float4(0.f, 0.f, 0.f, 0.f);
+  if (cnt > 0) {
+    float dir[3], dist;
+    view_dir(cam, mx, my, mz, dir, dist);
+    float Y[16];
+    sh_eval(vt.sh_degree, dir[0], dir[1], dir[2], Y);
+    float raw[3];
+    sh_colour_raw(vt.sh_degree, n, g, sh_dc, sh_rest, Y, raw);
+    col = make_float4(fmaxf(raw[0], 0.f), fmaxf(raw[1], 0.f), fmaxf(raw[2], 0.f), 0.f);
+  }
+  const bool vis = cnt > 0;
+  rec_a[e] = vis ? make_float4(s.u, s.v, s.o, s.pz) : make_float4(0.f, 0.f, 0.f, 0.f);
+  rec_b[e] = vis ? make_float4(s.a, s.b, s.c, s.kappa2) : make_float4(0.f, 0.f, 0.f, 0.f);
+  rgb[e] = col;
+  rect[e] = vis ? make_short4((short)tx0, (short)ty0, (short)tx1, (short)ty1) : make_short4(-1, -1, -1, -1);
+  n_tiles[e] = cnt;
+  dkey[e] = vis ? __float_as_uint(s.pz) : 0xFFFFFFFFu;
+}
+
+// ---------------------------------------------------------------------------------------------
+// Stage a5: chain rule from the 2D quantities to the parameters and the pose.
+// grad2d records [E][12] (48 B, last two unused): u, v, a, b, c, o, r, g, b, d.
+// ---------------------------------------------------------------------------------------------
+struct ParamGradOut {
+  float *mean, *scale, *rot, *opacity, *sh_dc, *sh_rest;
+};
+
+template <int NT>
+__device__ __forceinline__ float block_sum_det(float v, float *lds) {
+  // wave butterfly (fixed pattern) then the waves in index order: deterministic
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  __syncthreads();
+  if (lane == 0) lds[wave] = v;
+  __syncthreads();
+  float s = 0.f;
+  if (threadIdx.x == 0)
+    for (int w = 0; w < NT / 64; ++w) s += lds[w];
+  return s;  // valid in thread 0
+}
+
+__global__ __launch_bounds__(256) void k_preprocess_bwd(ViewTable vt, const float *__restrict__ mean,
+                                                        const float *__restrict__ scale,
+                                                        const float *__restrict__ rot,
+                                                        const float *__restrict__ opacity,
+                                                        const float *__restrict__ sh_dc,
+                                                        const float *__restrict__ sh_rest,
+                                                        const uint32_t *__restrict__ n_tiles,
+                                                        const float *__restrict__ g2, ParamGradOut out,
+                                                        float *__restrict__ pose_partial /*[grid][V][6]*/) {
+  __shared__ float red[8];
+  const int64_t n = vt.n;
+  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const bool in = g < n;
+  const int deg = vt.sh_degree;
+  const int K = (deg + 1) * (deg + 1);
+  float mx = 0, my = 0, mz = 0, sx = 1, sy = 1, sz = 1, qw = 1, qx = 0, qy = 0, qz = 0, o = 0;
+  if (in) {
+    mx = mean[g]; my = mean[n + g]; mz = mean[2 * n + g];
+    sx = scale[g]; sy = scale[n + g]; sz = scale[2 * n + g];
+    qw = rot[g]; qx = rot[n + g]; qy = rot[2 * n + g]; qz = rot[3 * n + g];
+    o = opacity[g];
+  }
+  float acc_m[3] = {0, 0, 0}, acc_s[3] = {0, 0, 0}, acc_q[4] = {0, 0, 0, 0}, acc_o = 0;
+  float acc_dc[3] = {0, 0, 0};
+  float acc_rest[45];
+#pragma unroll
+  for (int i = 0; i < 45; ++i) acc_rest[i] = 0.f;
+  bool any_view = false;
+
+  for (int vi = 0; vi < vt.n_views; ++vi) {
+    const ViewCam &cam = vt.v[vi];
+    const int64_t e = (int64_t)vi * n + g;
+    float pose[6] = {0, 0, 0, 0, 0, 0};
+    bool live = in && n_tiles[e] > 0;
+    float G[10];
+    if (live) {
+      bool nz = false;
+      const float4 *g4 = reinterpret_cast<const float4 *>(g2 + e * 12);
+      const float4 A = g4[0], B = g4[1], Cc = g4[2];
+      G[0] = A.x; G[1] = A.y; G[2] = A.z; G[3] = A.w; G[4] = B.x; G[5] = B.y; G[6] = B.z; G[7] = B.w;
+      G[8] = Cc.x; G[9] = Cc.y;
+#pragma unroll
+      for (int k = 0; k < 10; ++k) nz |= G[k] != 0.f;
+      live = nz;
+    }
+    if (live) {
+      any_view = true;
+      Splat s;
+      splat_decide(cam, mx, my, mz, sx, sy, sz, qw, qx, qy, qz, o, s);
+      const float gu = G[0], gv = G[1], ga = G[2], gb = G[3], gc = G[4], go = G[5];
+      const float gd = G[9];
+      // conic -> Sigma': G_S = -Q Ghat Q, Ghat = [[ga, gb/2], [gb/2, gc]]
+      const float a = s.a, b = s.b, c = s.c;
+      const float hb = 0.5f * gb;
+      const float qg00 = a * ga + b * hb, qg01 = a * hb + b * gc;
+      const float qg10 = b * ga + c * hb, qg11 = b * hb + c * gc;
+      const float GS00 = -(qg00 * a + qg01 * b);
+      const float GS01 = -(qg00 * b + qg01 * c);
+      const float GS11 = -(qg10 * b + qg11 * c);
+      // dL/dSigma = Tm^T G_S Tm (symmetric 3x3)
+      const float *T0 = s.t0, *T1 = s.t1;
+      float GT0[3], GT1[3];  // G_S Tm (2x3)
+#pragma unroll
+      for (int j = 0; j < 3; ++j) {
+        GT0[j] = GS00 * T0[j] + GS01 * T1[j];
+        GT1[j] = GS01 * T0[j] + GS11 * T1[j];
+      }
+      float GSig[3][3];
+#pragma unroll
+      for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j) GSig[i][j] = T0[i] * GT0[j] + T1[i] * GT1[j];
+      // dL/dTm = 2 G_S Tm Sigma
+      const float Sg[3][3] = {{s.S00, s.S01, s.S02}, {s.S01, s.S11, s.S12}, {s.S02, s.S12, s.S22}};
+      float dT0[3], dT1[3];
+#pragma unroll
+      for (int j = 0; j < 3; ++j) {
+        dT0[j] = 2.f * (GT0[0] * Sg[0][j] + GT0[1] * Sg[1][j] + GT0[2] * Sg[2][j]);
+        dT1[j] = 2.f * (GT1[0] * Sg[0][j] + GT1[1] * Sg[1][j] + GT1[2] * Sg[2][j]);
+      }
+      const float *R = cam.R;
+      // Tm = J R: dL/dJ = dT R^T (only the non-zero J entries matter)
+      const float gJ00 = dT0[0] * R[0] + dT0[1] * R[1] + dT0[2] * R[2];
+      const float gJ02 = dT0[0] * R[6] + dT0[1] * R[7] + dT0[2] * R[8];
+      const float gJ11 = dT1[0] * R[3] + dT1[1] * R[4] + dT1[2] * R[5];
+      const float gJ12 = dT1[0] * R[6] + dT1[1] * R[7] + dT1[2] * R[8];
+      // covariance path of R: dL/dR = J^T dT
+      float GRc[3][3];
+#pragma unroll
+      for (int j = 0; j < 3; ++j) {
+        GRc[0][j] = s.j00 * dT0[j];
+        GRc[1][j] = s.j11 * dT1[j];
+        GRc[2][j] = s.j02 * dT0[j] + s.j12 * dT1[j];
+      }
+      // dL/dmu_hat: projection, depth and the J entries
+      const float d = s.pz, id = 1.0f / d, id2 = id * id;
+      const bool clx = s.tx != s.xn, cly = s.ty != s.yn;
+      float gm0 = gu * cam.fx * id;
+      float gm1 = gv * cam.fy * id;
+      float gm2 = -(gu * cam.fx * s.px + gv * cam.fy * s.py) * id2 + gd;
+      gm2 += -(gJ00 * cam.fx + gJ11 * cam.fy) * id2;
+      // J02 = -fx tx / d, tx = x/d unless clamped
+      if (!clx) {
+        gm0 += gJ02 * (-cam.fx * id2);
+        gm2 += gJ02 * (2.f * cam.fx * s.px * id2 * id);
+      } else {
+        gm2 += gJ02 * (cam.fx * s.tx * id2);
+      }
+      if (!cly) {
+        gm1 += gJ12 * (-cam.fy * id2);
+        gm2 += gJ12 * (2.f * cam.fy * s.py * id2 * id);
+      } else {
+        gm2 += gJ12 * (cam.fy * s.ty * id2);
+      }
+      // Sigma = M M^T, M = Rq diag(S): dL/dM = 2 GSig M
+      const float sc[3] = {s.sx, s.sy, s.sz};
+      float M[3][3];
+#pragma unroll
+      for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j) M[i][j] = s.r[3 * i + j] * sc[j];
+      float GM[3][3];
+#pragma unroll
+      for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j)
+          GM[i][j] = 2.f * (GSig[i][0] * M[0][j] + GSig[i][1] * M[1][j] + GSig[i][2] * M[2][j]);
+#pragma unroll
+      for (int j = 0; j < 3; ++j) acc_s[j] += GM[0][j] * s.r[j] + GM[1][j] * s.r[3 + j] + GM[2][j] * s.r[6 + j];
+      float GR[9];
+#pragma unroll
+      for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j) GR[3 * i + j] = GM[i][j] * sc[j];
+      const float w = s.qw, x = s.qx, y = s.qy, z = s.qz;
+      float gw = 2.f * (-z * GR[1] + y * GR[2] + z * GR[3] - x * GR[5] - y * GR[6] + x * GR[7]);
+      float gx = 2.f * (y * GR[1] + z * GR[2] + y * GR[3] - 2.f * x * GR[4] - w * GR[5] + z * GR[6] + w * GR[7] -
+                        2.f * x * GR[8]);
+      float gy = 2.f * (-2.f * y * GR[0] + x * GR[1] + w * GR[2] + x * GR[3] + z * GR[5] - w * GR[6] + z * GR[7] -
+                        2.f * y * GR[8]);
+      float gz = 2.f * (-2.f * z * GR[0] - w * GR[1] + x * GR[2] + w * GR[3] - 2.f * z * GR[4] + y * GR[5] +
+                        x * GR[6] + y * GR[7]);
+      const float dotq = gw * w + gx * x + gy * y + gz * z;
+      acc_q[0] += (gw - dotq * w) * s.inv_q;
+      acc_q[1] += (gx - dotq * x) * s.inv_q;
+      acc_q[2] += (gy - dotq * y) * s.inv_q;
+      acc_q[3] += (gz - dotq * z) * s.inv_q;
+      acc_o += go;
+      // colour: SH coefficients and the view direction
+      float dir[3], dist;
+      view_dir(cam, mx, my, mz, dir, dist);
+      float Y[16];
+      sh_eval(deg, dir[0], dir[1], dir[2], Y);
+      float raw[3];
+      sh_colour_raw(deg, n, g, sh_dc, sh_rest, Y, raw);
+      float gr[3];
+#pragma unroll
+      for (int ch = 0; ch < 3; ++ch) gr[ch] = raw[ch] > 0.f ? G[6 + ch] : 0.f;
+#pragma unroll
+      for (int ch = 0; ch < 3; ++ch) acc_dc[ch] += gr[ch] * Y[0];
+      float gdir[3] = {0.f, 0.f, 0.f};
+      if (deg >= 1) {
+        const float X = dir[0], Yy = dir[1], Z = dir[2];
+        // d Y_k / d(x, y, z) for k >= 1, as polynomials in the unnormalised direction
+        float dY[15][3];
+        using Kc = SHConst;
+        dY[0][0] = 0; dY[0][1] = -Kc::c1; dY[0][2] = 0;
+        dY[1][0] = 0; dY[1][1] = 0; dY[1][2] = Kc::c1;
+        dY[2][0] = -Kc::c1; dY[2][1] = 0; dY[2][2] = 0;
+        if (deg >= 2) {
+          dY[3][0] = Kc::c2a * Yy; dY[3][1] = Kc::c2a * X; dY[3][2] = 0;
+          dY[4][0] = 0; dY[4][1] = -Kc::c2a * Z; dY[4][2] = -Kc::c2a * Yy;
+          dY[5][0] = -2.f * Kc::c2b * X; dY[5][1] = -2.f * Kc::c2b * Yy; dY[5][2] = 4.f * Kc::c2b * Z;
+          dY[6][0] = -Kc::c2a * Z; dY[6][1] = 0; dY[6][2] = -Kc::c2a * X;
+          dY[7][0] = 2.f * Kc::c2c * X; dY[7][1] = -2.f * Kc::c2c * Yy; dY[7][2] = 0;
+        }
+        if (deg >= 3) {
+          const float xx = X * X, yy = Yy * Yy, zz = Z * Z;
+          dY[8][0] = -6.f * Kc::c3a * X * Yy; dY[8][1] = -3.f * Kc::c3a * (xx - yy); dY[8][2] = 0;
+          dY[9][0] = Kc::c3b * Yy * Z; dY[9][1] = Kc::c3b * X * Z; dY[9][2] = Kc::c3b * X * Yy;
+          dY[10][0] = 2.f * Kc::c3c * X * Yy; dY[10][1] = -Kc::c3c * (4.f * zz - xx - 3.f * yy);
+          dY[10][2] = -8.f * Kc::c3c * Yy * Z;
+          dY[11][0] = -6.f * Kc::c3d * X * Z; dY[11][1] = -6.f * Kc::c3d * Yy * Z;
+          dY[11][2] = Kc::c3d * (6.f * zz - 3.f * xx - 3.f * yy);
+          dY[12][0] = -Kc::c3c * (4.f * zz - 3.f * xx - yy); dY[12][1] = 2.f * Kc::c3c * X * Yy;
+          dY[12][2] = -8.f * Kc::c3c * X * Z;
+          dY[13][0] = 2.f * Kc::c3e * X * Z; dY[13][1] = -2.f * Kc::c3e * Yy * Z; dY[13][2] = Kc::c3e * (xx - yy);
+          dY[14][0] = -3.f * Kc::c3a * (xx - yy); dY[14][1] = 6.f * Kc::c3a * X * Yy; dY[14][2] = 0;
+        }
+        for (int k = 1; k < K; ++k) {
+#pragma unroll
+          for (int ch = 0; ch < 3; ++ch) {
+            const float coef = sh_rest[(int64_t)(3 * (k - 1) + ch) * n + g];
+            acc_rest[3 * (k - 1) + ch] += gr[ch] * Y[k];
+            const float gk = gr[ch] * coef;
+            gdir[0] += gk * dY[k - 1][0];
+            gdir[1] += gk * dY[k - 1][1];
+            gdir[2] += gk * dY[k - 1][2];
+          }
+        }
+      }
+      const float dd = gdir[0] * dir[0] + gdir[1] * dir[1] + gdir[2] * dir[2];
+      const float idist = 1.0f / dist;
+      const float gdf[3] = {(gdir[0] - dd * dir[0]) * idist, (gdir[1] - dd * dir[1]) * idist,
+                            (gdir[2] - dd * dir[2]) * idist};
+      // mean: R^T dL/dmu_hat + direction path
+      acc_m[0] += R[0] * gm0 + R[3] * gm1 + R[6] * gm2 + gdf[0];
+      acc_m[1] += R[1] * gm0 + R[4] * gm1 + R[7] * gm2 + gdf[1];
+      acc_m[2] += R[2] * gm0 + R[5] * gm1 + R[8] * gm2 + gdf[2];
+      // pose, xi = (rho, phi), T_cw <- Exp(xi) T_cw
+      //   rho: dL/dmu_hat + R dL/ddiff   (the camera centre moves by -R^T rho)
+      //   phi: mu_hat x dL/dmu_hat + vee(N^T - N), N = R GRc^T
+      pose[0] = gm0 + (R[0] * gdf[0] + R[1] * gdf[1] + R[2] * gdf[2]);
+      pose[1] = gm1 + (R[3] * gdf[0] + R[4] * gdf[1] + R[5] * gdf[2]);
+      pose[2] = gm2 + (R[6] * gdf[0] + R[7] * gdf[1] + R[8] * gdf[2]);
+      pose[3] = s.py * gm2 - s.pz * gm1;
+      pose[4] = s.pz * gm0 - s.px * gm2;
+      pose[5] = s.px * gm1 - s.py * gm0;
+      float N[3][3];
+#pragma unroll
+      for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j) N[i][j] = R[3 * i] * GRc[j][0] + R[3 * i + 1] * GRc[j][1] + R[3 * i + 2] * GRc[j][2];
+      pose[3] += N[1][2] - N[2][1];
+      pose[4] += N[2][0] - N[0][2];
+      pose[5] += N[0][1] - N[1][0];
+    }
+    // deterministic per-block partial of the pose gradient for this view
+#pragma unroll 1
+    for (int i = 0; i < 6; ++i) {
+      float t = block_sum_det<256>(pose[i], red);
+      if (threadIdx.x == 0) pose_partial[((int64_t)blockIdx.x * vt.n_views + vi) * 6 + i] = t;
+    }
+  }
+  if (!in || !any_view) return;
+  if (out.mean)
+    for (int i = 0; i < 3; ++i) out.mean[i * n + g] += acc_m[i];
+  if (out.scale)
+    for (int i = 0; i < 3; ++i) out.scale[i * n + g] += acc_s[i];
+  if (out.rot)
+    for (int i = 0; i < 4; ++i) out.rot[i * n + g] += acc_q[i];
+  if (out.opacity) out.opacity[g] += acc_o;
+  if (out.sh_dc)
+    for (int i = 0; i < 3; ++i) out.sh_dc[i * n + g] += acc_dc[i];
+  if (out.sh_rest)
+    for (int i = 0; i < 3 * (K - 1); ++i) out.sh_rest[(int64_t)i * n + g] += acc_rest[i];
+}
+
+}  // namespace gs
+
+// ---- launchers used by the host API ------------------------------------------------------
+namespace gs {
+
+hipError_t launch_preprocess(const ViewTable &vt, const gs_gaussians &g, const gs_projected &p, hipStream_t st) {
+  if (vt.n == 0) return hipSuccess;
+  dim3 grid((unsigned)((vt.n + 255) / 256), (unsigned)vt.n_views);
+  hipLaunchKernelGGL(k_preprocess, grid, dim3(256), 0, st, vt, g.mean, g.scale, g.rot, g.opacity, g.sh_dc,
+                     g.sh_rest, (float4 *)p.rec_a, (float4 *)p.rec_b, (float4 *)p.rgb, (short4 *)p.rect, p.n_tiles,
+                     p.dkey);
+  return hipGetLastError();
+}
+
+int64_t preprocess_bwd_blocks(int64_t n) { return (n + 255) / 256; }
+
+// Sums the per-block pose partials of each view in a fixed order (float64) and adds the
+// result to the view's pose gradient.
+struct PosePtrs {
+  float *p[kMaxViews];
+};
+
+__global__ void k_pose_reduce_tab(const float *__restrict__ partial, int32_t n_blocks, int32_t n_views, PosePtrs out) {
+  __shared__ double red[256];
+  const int vi = blockIdx.x / 6, i = blockIdx.x % 6;
+  double s = 0.0;
+  for (int b = threadIdx.x; b < n_blocks; b += 256) s += (double)partial[((int64_t)b * n_views + vi) * 6 + i];
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int off = 128; off > 0; off >>= 1) {
+    if (threadIdx.x < off) red[threadIdx.x] += red[threadIdx.x + off];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0 && out.p[vi]) out.p[vi][i] += (float)red[0];
+}
+
+hipError_t launch_preprocess_bwd(const ViewTable &vt, const gs_gaussians &g, const gs_projected &p, const float *g2,
+                                 const gs_grads &out, float *const *pose_out, float *pose_partial, hipStream_t st) {
+  if (vt.n == 0) return hipSuccess;
+  const int64_t nb = preprocess_bwd_blocks(vt.n);
+  ParamGradOut po{out.mean, out.scale, out.rot, out.opacity, out.sh_dc, out.sh_rest};
+  hipLaunchKernelGGL(k_preprocess_bwd, dim3((unsigned)nb), dim3(256), 0, st, vt, g.mean, g.scale, g.rot,
+                     g.opacity, g.sh_dc, g.sh_rest, p.n_tiles, g2, po, pose_partial);
+  hipError_t err = hipGetLastError();
+  if (err != hipSuccess) return err;
+  PosePtrs pp;
+  for (int i = 0; i < kMaxViews; ++i) pp.p[i] = i < vt.n_views ? pose_out[i] : nullptr;
+  hipLaunchKernelGGL(k_pose_reduce_tab, dim3((unsigned)(6 * vt.n_views)), dim3(256), 0, st, pose_partial, (int32_t)nb,
+                     vt.n_views, pp);
+  return hipGetLastError();
+}
+
+}  // namespace gs

@@ -1,0 +1,96 @@
+"""Shared helpers for the GPU tests: run the HIP path through the C ABI and compare it with
+the CPU oracle under the stated tolerances."""
+from __future__ import annotations
+
+import numpy as np
+import torch
+
+import oracle
+from paper_2507_04004_amd import raster as R
+
+DEV = "cuda:0"
+IMG_ATOL = 1e-4        # colour / opacity / transmittance, max-abs, non-marginal pixels
+DEPTH_RTOL = 1e-4      # depth: 1e-4 absolute up to 1 m, 1e-4 relative beyond (float32 accumulation)
+GRAD_RTOL = 2e-3       # gradients: relative
+
+
+class GpuRun:
+    """One plain single-view pass through the C ABI, keeping every intermediate."""
+
+    def __init__(self, g, cam, tile=16, blend_depth=256, lidar=None, capacity=None):
+        self.g, self.cam, self.tile, self.bd = g, cam, tile, blend_depth
+        self.gm = R.GaussianMap.from_numpy(g, DEV)
+        self.cs = R.camera_struct(cam)
+        self.gs = self.gm.struct()
+        self.spl = R.preprocess(self.gs, self.cs, tile, DEV)
+        self.bins = R.bin_sort_fit(self.spl, self.gs.n, self.cs, tile, DEV, capacity)
+        self.lidar = lidar
+        self.lidar_loss = torch.zeros(1, device=DEV)
+        self.fr = R.render_fwd(self.spl, self.gs.n, self.bins, self.cs, blend_depth, DEV, lidar, self.lidar_loss)
+        torch.cuda.synchronize()
+
+    def image(self):
+        f = self.fr
+        return dict(color=f.color.cpu().numpy(), depth=f.depth.cpu().numpy(), alpha=f.alpha.cpu().numpy(),
+                    t_final=f.t_final.cpu().numpy(), last=f.last.cpu().numpy())
+
+    def backward(self, gC, gD=None, gO=None, grad_scale=None):
+        grads = R.ParamGrads.zeros(self.gm)
+        scratch = R.grads_scratch(self.gs.n, self.cam.w * self.cam.h, DEV)
+        t = lambda a: None if a is None else torch.from_numpy(np.ascontiguousarray(a, np.float32)).to(DEV)
+        R.render_bwd(self.gs, self.cs, self.spl, self.bins, self.fr, t(gC), t(gD), t(gO), self.bd, grads, scratch,
+                     self.lidar, grad_scale)
+        torch.cuda.synchronize()
+        return {k: getattr(grads, k).cpu().numpy().astype(np.float64) for k in
+                ("mean", "scale", "rot", "opacity", "sh_dc", "sh_rest", "pose")}
+
+    def bins_np(self):
+        P = self.bins.pairs()
+        return dict(vals=self.bins.vals[:P].cpu().numpy().view(np.uint32),
+                    tile_range=self.bins.tile_range.cpu().numpy().view(np.uint32), num_pairs=P,
+                    n_tiles=self.spl.n_tiles.cpu().numpy().view(np.uint32),
+                    rect=self.spl.rect.cpu().numpy().astype(np.int32),
+                    dkey=self.spl.dkey.cpu().numpy().view(np.uint32))
+
+
+def oracle_cam(cam):
+    return oracle.camera_f32(cam)
+
+
+def compare_images(gpu, ref, mask=None):
+    """Max-abs differences on non-marginal pixels. Returns dict of errors."""
+    ok = ref["marginal"] == 0 if mask is None else mask
+    out = {}
+    out["color"] = float(np.abs(gpu["color"] - ref["color"])[:, ok].max(initial=0.0))
+    out["alpha"] = float(np.abs(gpu["alpha"] - ref["alpha"])[ok].max(initial=0.0))
+    out["t_final"] = float(np.abs(gpu["t_final"] - ref["t_final"])[ok].max(initial=0.0))
+    dref = ref["depth"][ok]
+    out["depth"] = float((np.abs(gpu["depth"][ok] - dref) / np.maximum(1.0, np.abs(dref))).max(initial=0.0))
+    out["n_marginal"] = int((~ok).sum())
+    return out
+
+
+def assert_images_close(gpu, ref, mask=None):
+    e = compare_images(gpu, ref, mask)
+    assert e["color"] <= IMG_ATOL and e["alpha"] <= IMG_ATOL and e["t_final"] <= IMG_ATOL, e
+    assert e["depth"] <= DEPTH_RTOL, e
+    assert e["n_marginal"] <= max(4, 1e-3 * ref["alpha"].size), e
+    return e
+
+
+def grad_errors(gpu, ref, keys=("mean", "scale", "rot", "opacity", "sh_dc", "sh_rest", "pose")):
+    out = {}
+    for k in keys:
+        a, b = np.asarray(gpu[k], np.float64), np.asarray(ref[k], np.float64)
+        if b.size == 0:
+            continue
+        nb = np.linalg.norm(b)
+        out[k] = float(np.linalg.norm(a - b) / nb) if nb > 0 else float(np.linalg.norm(a))
+    return out
+
+
+def assert_grads_close(gpu, ref, rtol=GRAD_RTOL, keys=("mean", "scale", "rot", "opacity", "sh_dc", "sh_rest", "pose")):
+    e = grad_errors(gpu, ref, keys)
+    bad = {k: v for k, v in e.items() if v > rtol}
+    assert not bad, e
+    return e

@@ -1,0 +1,115 @@
+"""C ABI checks that need no GPU: the library loads, exports every declared entry point,
+rejects bad arguments on the host, and its host SE(3) helper is the closed-form exponential."""
+import ctypes as C
+import math
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_2507_04004_amd import _native as N
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    text = open(os.path.join(ROOT, "include", "gs.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"^\s*(?:const\s+)?[\w\s\*]+?\b(gs_\w+)\s*\(", text, flags=re.M)))
+
+
+def test_library_exports_every_declared_function():
+    L = N.lib()
+    names = declared_functions()
+    assert len(names) >= 14
+    for name in names:
+        assert hasattr(L, name), name
+    assert set(N.EXPORTS) <= set(names)
+
+
+def _cam(**kw):
+    c = N.Camera(64, 48, 0, 0, 64, 48, 50.0, 50.0, 31.5, 23.5, (C.c_float * 9)(1, 0, 0, 0, 1, 0, 0, 0, 1),
+                 (C.c_float * 3)(0, 0, 0), (C.c_float * 3)(0, 0, 0))
+    for k, v in kw.items():
+        setattr(c, k, v)
+    return c
+
+
+def test_host_argument_errors():
+    L = N.lib()
+    dummy = C.c_void_p(16)  # never dereferenced: validation fails first
+    g = N.Gaussians(10, 0, dummy, dummy, dummy, dummy, dummy, None)
+    proj = N.Projected(*([dummy] * 6))
+    cases = [
+        (dict(), dict(sh_degree=5)),
+        (dict(w=0), dict()),
+        (dict(x0=10, w=60), dict()),
+        (dict(fx=-1.0), dict()),
+        (dict(fy=float("nan")), dict()),
+    ]
+    for camkw, gkw in cases:
+        gg = N.Gaussians(g.n, g.sh_degree, g.mean, g.scale, g.rot, g.opacity, g.sh_dc, g.sh_rest)
+        for k, v in gkw.items():
+            setattr(gg, k, v)
+        rc = L.gs_preprocess(C.byref(gg), C.byref(_cam(**camkw)), 16, 16, C.byref(proj), None)
+        assert rc == N.GS_ERR_INVALID_ARG, (camkw, gkw)
+        assert len(L.gs_last_error()) > 0
+    # unsupported tile size / blend depth
+    assert L.gs_preprocess(C.byref(g), C.byref(_cam()), 12, 12, C.byref(proj), None) == N.GS_ERR_INVALID_ARG
+    bins = N.Bins(16, 16, 100, dummy, dummy, dummy, dummy, 1)  # scratch too small
+    assert L.gs_bin_sort(C.byref(proj), 10, C.byref(_cam()), C.byref(bins), None) == N.GS_ERR_INVALID_ARG
+    assert b"scratch" in L.gs_last_error()
+    img = N.Image(*([dummy] * 5))
+    bins_ok = N.Bins(16, 16, 100, dummy, dummy, dummy, dummy, 1 << 30)
+    assert L.gs_render_fwd(C.byref(proj), 10, C.byref(bins_ok), C.byref(_cam()), 100, None, C.byref(img),
+                           None) == N.GS_ERR_INVALID_ARG
+    # missing sh_rest at degree 3
+    g3 = N.Gaussians(10, 3, dummy, dummy, dummy, dummy, dummy, None)
+    assert L.gs_preprocess(C.byref(g3), C.byref(_cam()), 16, 16, C.byref(proj), None) == N.GS_ERR_INVALID_ARG
+    # plan creation argument errors
+    plan = C.c_void_p()
+    assert L.gs_batch_plan_create(C.byref(plan), 10, 0, 0, 100, 16, 16, 256, 100) == N.GS_ERR_INVALID_ARG
+    assert L.gs_batch_plan_create(C.byref(plan), 10, 0, 17, 100, 16, 16, 256, 100) == N.GS_ERR_INVALID_ARG
+    assert L.gs_loss_l1(None, None, -1, 1.0, None, None, None) == N.GS_ERR_INVALID_ARG
+
+
+def test_scratch_sizes_grow():
+    L = N.lib()
+    a = L.gs_bins_scratch_bytes(1000, 10000, 48)
+    b = L.gs_bins_scratch_bytes(1000, 20000, 48)
+    assert 0 < a < b
+    assert L.gs_grads_scratch_bytes(1000, 1, 100) < L.gs_grads_scratch_bytes(1000, 2, 100)
+
+
+def _se3_exp(xi):
+    rho, phi = np.asarray(xi[:3], float), np.asarray(xi[3:], float)
+    th = np.linalg.norm(phi)
+    K = np.array([[0, -phi[2], phi[1]], [phi[2], 0, -phi[0]], [-phi[1], phi[0], 0]])
+    from scipy.linalg import expm
+    M = np.zeros((4, 4))
+    M[:3, :3] = K
+    M[:3, 3] = rho
+    E = expm(M)
+    return E[:3, :3], E[:3, 3], th
+
+
+@pytest.mark.parametrize("xi", [[0.1, -0.2, 0.3, 0.01, 0.02, -0.03], [1.0, 2.0, -1.0, 0.5, -0.4, 0.9],
+                                [0.0, 0.0, 0.0, 1e-7, 0.0, 0.0]])
+def test_camera_left_update_is_se3_exponential(xi):
+    from scipy.spatial.transform import Rotation
+    L = N.lib()
+    R0 = Rotation.from_rotvec([0.3, -0.2, 0.1]).as_matrix()
+    t0 = np.array([0.5, -1.0, 2.0])
+    cam = _cam()
+    cam.R_cw = (C.c_float * 9)(*R0.astype(np.float32).ravel())
+    cam.t_cw = (C.c_float * 3)(*t0.astype(np.float32))
+    out = N.Camera()
+    arr = (C.c_float * 6)(*xi)
+    assert L.gs_camera_left_update(C.byref(cam), C.byref(arr), C.byref(out)) == 0
+    dR, dt, _ = _se3_exp(np.asarray(xi, np.float32).astype(float))
+    R0f = R0.astype(np.float32).astype(float)
+    t0f = t0.astype(np.float32).astype(float)
+    np.testing.assert_allclose(np.array(out.R_cw).reshape(3, 3), dR @ R0f, atol=2e-7)
+    np.testing.assert_allclose(np.array(out.t_cw), dR @ t0f + dt, atol=1e-6)
+    assert out.w == cam.w and math.isclose(out.fx, cam.fx)
