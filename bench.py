@@ -76,6 +76,7 @@ class PlainStep:
         self.bins = R.alloc_bins(self.n, self.cs, tile, self.capacity, dev)
         del fit
         self.frame = R.Frame.empty(cam.h, cam.w, dev)
+        self.frame.ensure_state(R.state_bytes(self.bins, self.cs, bd))
         self.lidar = R.LidarHits(torch.from_numpy(pix).to(dev), torch.from_numpy(ds).to(dev), weight=1.0)
         self.lidar_loss = torch.zeros(1, device=dev)
         self.rgb_loss = torch.zeros(1, device=dev)

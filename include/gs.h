@@ -107,11 +107,17 @@ typedef struct gs_bins {
  * depth [h][w] (eq:rendered_depth), alpha [h][w] (eq:rendered_opacity), and the backward
  * checkpoint: t_final [h][w] final transmittance and last [h][w] int32 position, within the
  * pixel's tile list, of the last Gaussian blended (-1 if none). n_contrib [h][w] int32 is
- * optional (NULL = not written): the number of Gaussians blended at each pixel. */
+ * optional (NULL = not written): the number of Gaussians blended at each pixel.
+ * state: device scratch of at least gs_image_state_bytes(...) bytes holding the chunk work
+ * list and, per (chunk, pixel) of tiles longer than one chunk, the transmittance and the
+ * composited colour behind the chunk (the backward's starting state). Written by
+ * gs_render_fwd, read by gs_render_bwd; the same bins and blend_depth must be passed to both. */
 typedef struct gs_image {
   float *color, *depth, *alpha, *t_final;
   int32_t *last;
   int32_t *n_contrib;
+  void *state;
+  size_t state_bytes;
 } gs_image;
 
 /* Sparse LiDAR depth term of eq:depth_loss with the opacity-normalised depth D/O:
@@ -151,7 +157,8 @@ int gs_bin_sort(const gs_projected *proj, int64_t n, const gs_camera *cam, gs_bi
 /* Stage a3 — front-to-back compositing per pixel (eq:alpha, eq:rendered_rgb/_depth/_opacity):
  * alpha = min(0.99, o exp(-q/2)); a Gaussian with alpha < 1/255 is skipped; the walk stops
  * before a Gaussian that would take the transmittance below 1e-4. blend_depth in {64, 128,
- * 256} is the number of records staged in LDS per batch. lidar may be NULL; otherwise the
+ * 256} is the chunk length: each tile's list is composited in chunks of that many records,
+ * one workgroup per chunk, and combined per pixel (exact up to float32 rounding order). lidar may be NULL; otherwise the
  * depth term is evaluated into lidar->loss_out after compositing. */
 int gs_render_fwd(const gs_projected *proj, int64_t n, const gs_bins *bins, const gs_camera *cam,
                   int32_t blend_depth, const gs_lidar *lidar, gs_image *out, gs_stream_t stream);
@@ -173,6 +180,7 @@ int gs_loss_l1(const float *color, const float *target, int64_t n_values, float 
 
 /* Scratch sizes (bytes). */
 size_t gs_bins_scratch_bytes(int64_t n, int64_t capacity, int64_t num_tiles);
+size_t gs_image_state_bytes(int64_t capacity, int64_t num_tiles, int32_t tile_w, int32_t tile_h, int32_t blend_depth);
 size_t gs_grads_scratch_bytes(int64_t n, int32_t n_views, int64_t total_window_pixels);
 
 /* ---- Batched form (stage a7): several views of one map per launch ------------------------ */

@@ -40,7 +40,8 @@ class Bins(C.Structure):
 
 
 class Image(C.Structure):
-    _fields_ = [(k, vp) for k in ("color", "depth", "alpha", "t_final", "last", "n_contrib")]
+    _fields_ = [(k, vp) for k in ("color", "depth", "alpha", "t_final", "last", "n_contrib", "state")] + [
+        ("state_bytes", C.c_size_t)]
 
 
 class Lidar(C.Structure):
@@ -65,7 +66,7 @@ class GSError(RuntimeError):
 _lib = None
 
 EXPORTS = ["gs_preprocess", "gs_bin_sort", "gs_render_fwd", "gs_render_bwd", "gs_render_batch", "gs_loss_l1",
-           "gs_bins_scratch_bytes", "gs_grads_scratch_bytes", "gs_batch_plan_create", "gs_batch_plan_destroy",
+           "gs_bins_scratch_bytes", "gs_image_state_bytes", "gs_grads_scratch_bytes", "gs_batch_plan_create", "gs_batch_plan_destroy",
            "gs_batch_num_pairs", "gs_batch_capacity", "gs_camera_left_update", "gs_last_error",
            "gs_profile_enable", "gs_profile_read", "gs_profile_disable"]
 GS_STAGE_PREPROCESS, GS_STAGE_BIN_SORT, GS_STAGE_BLEND_FWD, GS_STAGE_BLEND_BWD, GS_STAGE_PREPROCESS_BWD = range(5)
@@ -88,6 +89,8 @@ def lib():
     L.gs_loss_l1.argtypes = [vp, vp, C.c_int64, C.c_float, vp, vp, vp]
     L.gs_bins_scratch_bytes.argtypes = [C.c_int64, C.c_int64, C.c_int64]
     L.gs_bins_scratch_bytes.restype = C.c_size_t
+    L.gs_image_state_bytes.argtypes = [C.c_int64, C.c_int64, C.c_int32, C.c_int32, C.c_int32]
+    L.gs_image_state_bytes.restype = C.c_size_t
     L.gs_grads_scratch_bytes.argtypes = [C.c_int64, C.c_int32, C.c_int64]
     L.gs_grads_scratch_bytes.restype = C.c_size_t
     L.gs_batch_plan_create.argtypes = [P(vp), C.c_int64, C.c_int32, C.c_int32, C.c_int64, C.c_int32, C.c_int32,

@@ -154,8 +154,8 @@ struct ViewIO {
 // The backward of all views of one table: dense gradient maps (user planes + LiDAR term),
 // blend backward into grad2d, then the chain rule to parameters and poses.
 int enqueue_backward(const gs::ViewTable &vt, const gs_gaussians &g, const gs_projected &p, const uint32_t *vals,
-                     const uint32_t *range, const ViewIO *io, int bd, const gs_grads &out, const GradScratch &s,
-                     hipStream_t st) {
+                     const uint32_t *range, void *state, int64_t cap, const ViewIO *io, int bd, const gs_grads &out,
+                     const GradScratch &s, hipStream_t st) {
   const int nv = vt.n_views;
   gs::ImgTable it{};
   gs::GradTable gtab{};
@@ -167,7 +167,8 @@ int enqueue_backward(const gs::ViewTable &vt, const gs_gaussians &g, const gs_pr
   int64_t max_npx = 0;
   bool any_map = false;
   for (int i = 0; i < nv; ++i) {
-    it.v[i] = {io[i].img.color, io[i].img.depth, io[i].img.alpha, io[i].img.t_final, io[i].img.last, io[i].img.n_contrib};
+    it.v[i] = {io[i].img.color, io[i].img.depth, io[i].img.alpha, io[i].img.t_final, io[i].img.last,
+               io[i].img.n_contrib};
     const int64_t npx = (int64_t)vt.v[i].w * vt.v[i].h;
     const bool has_lidar = io[i].lidar.m > 0;
     const bool need_map = has_lidar || io[i].dD || io[i].dO;
@@ -192,7 +193,7 @@ int enqueue_backward(const gs::ViewTable &vt, const gs_gaussians &g, const gs_pr
   if (any_map) GS_TRY_HIP(gs::launch_grad_maps(src, dst, nv, max_npx, lt, it, max_m, st), "lidar/gradient maps");
   GS_TRY_HIP(gs::zero_f32(s.g2, 12 * vt.n * nv, st), "zero grad2d");
   gs::profile_begin(GS_STAGE_BLEND_BWD, st);
-  GS_TRY_HIP(gs::launch_blend_bwd(bd, vt, it, gtab, p, vals, range, s.g2, st), "blend backward");
+  GS_TRY_HIP(gs::launch_blend_bwd(bd, vt, it, gtab, p, vals, range, state, cap, s.g2, st), "blend backward");
   gs::profile_end(GS_STAGE_BLEND_BWD, st);
   float *pose_out[gs::kMaxViews] = {};
   for (int i = 0; i < nv; ++i) pose_out[i] = io[i].pose;
@@ -214,6 +215,13 @@ int check_lidar(const gs_lidar *l, int64_t npx) {
 int check_image(const gs_image *im) {
   if (!im || !im->color || !im->depth || !im->alpha || !im->t_final || !im->last)
     return fail(GS_ERR_INVALID_ARG, "image plane is NULL");
+  return GS_OK;
+}
+
+int check_state(const gs_image *im, int64_t cap, int64_t tiles, int tw, int th, int bd) {
+  const size_t need = gs::blend_state_bytes(tiles, cap, tw, th, bd);
+  if (!im->state || im->state_bytes < need)
+    return fail(GS_ERR_INVALID_ARG, "image state too small: %zu < %zu", im->state ? im->state_bytes : (size_t)0, need);
   return GS_OK;
 }
 
@@ -296,6 +304,11 @@ size_t gs_bins_scratch_bytes(int64_t n, int64_t capacity, int64_t num_tiles) {
   return gs::bin_scratch_bytes(std::max<int64_t>(n, 0), std::max<int64_t>(capacity, 0));
 }
 
+size_t gs_image_state_bytes(int64_t capacity, int64_t num_tiles, int32_t tile_w, int32_t tile_h, int32_t blend_depth) {
+  if (capacity < 0 || num_tiles < 0 || !tile_ok(tile_w, tile_h) || !depth_ok(blend_depth)) return 0;
+  return gs::blend_state_bytes(num_tiles, capacity, tile_w, tile_h, blend_depth);
+}
+
 size_t gs_grads_scratch_bytes(int64_t n, int32_t n_views, int64_t total_window_pixels) {
   return grads_scratch_bytes_impl(std::max<int64_t>(n, 0), std::max(n_views, 1), std::max<int64_t>(total_window_pixels, 0));
 }
@@ -345,11 +358,14 @@ int gs_render_fwd(const gs_projected *proj, int64_t n, const gs_bins *bins, cons
   if (lidar && lidar->m > 0 && !lidar->loss_out) return fail(GS_ERR_INVALID_ARG, "lidar loss_out is NULL");
   gs::ViewTable vt;
   if ((rc = make_table(cam, 1, n, 0, bins->tile_w, bins->tile_h, vt))) return rc;
+  if ((rc = check_state(out, bins->capacity, vt.total_tiles, bins->tile_w, bins->tile_h, blend_depth))) return rc;
   gs::ImgTable it{};
   it.v[0] = {out->color, out->depth, out->alpha, out->t_final, out->last, out->n_contrib};
   hipStream_t st = (hipStream_t)stream;
   gs::profile_begin(GS_STAGE_BLEND_FWD, st);
-  GS_TRY_HIP(gs::launch_blend_fwd(blend_depth, vt, it, *proj, bins->vals, bins->tile_range, st), "blend forward");
+  GS_TRY_HIP(gs::launch_blend_fwd(blend_depth, vt, it, *proj, bins->vals, bins->tile_range, out->state,
+                                  bins->capacity, st),
+             "blend forward");
   gs::profile_end(GS_STAGE_BLEND_FWD, st);
   if (lidar && lidar->m > 0) {
     gs::LidarTable lt{};
@@ -380,6 +396,7 @@ int gs_render_bwd(const gs_gaussians *g, const gs_camera *cam, const gs_projecte
                 grads_scratch_bytes_impl(g->n, 1, npx));
   gs::ViewTable vt;
   if ((rc = make_table(cam, 1, g->n, g->sh_degree, bins->tile_w, bins->tile_h, vt))) return rc;
+  if ((rc = check_state(fwd, bins->capacity, vt.total_tiles, bins->tile_w, bins->tile_h, blend_depth))) return rc;
   ViewIO io{};
   io.img = *fwd;
   io.dC = dL_dC;
@@ -388,7 +405,8 @@ int gs_render_bwd(const gs_gaussians *g, const gs_camera *cam, const gs_projecte
   if (lidar) io.lidar = *lidar;
   io.pose = out->pose;
   GradScratch s = carve_grads(out->scratch, g->n, 1, npx);
-  return enqueue_backward(vt, *g, *proj, bins->vals, bins->tile_range, &io, blend_depth, *out, s, (hipStream_t)stream);
+  return enqueue_backward(vt, *g, *proj, bins->vals, bins->tile_range, fwd->state, bins->capacity, &io, blend_depth,
+                          *out, s, (hipStream_t)stream);
 }
 
 int gs_camera_left_update(const gs_camera *in, const float xi[6], gs_camera *out) {
@@ -457,7 +475,10 @@ struct gs_batch_plan {
   void *bin_scratch = nullptr;
   void *grad_scratch = nullptr;
   float *dC = nullptr;  // fused L1 gradient planes, concatenated over views
-  // graph
+  void *blend_state = nullptr;
+  // graph: captured on the plan's own stream (capture is not allowed on the legacy null
+  // stream), launched on the caller's stream
+  hipStream_t capture_stream = nullptr;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
   std::vector<unsigned char> signature;
@@ -484,6 +505,7 @@ size_t plan_bytes(const gs_batch_plan &p, size_t *offs) {
   put(9, gs::bin_scratch_bytes(E, p.cap));             // bin scratch
   put(10, grads_scratch_bytes_impl(p.n, p.max_views, p.max_pixels));
   put(11, 12 * std::max<int64_t>(p.max_pixels, 1));   // dC planes
+  put(12, gs::blend_state_bytes(p.max_tiles, p.cap, p.tw, p.th, p.bd));
   return o;
 }
 
@@ -513,7 +535,8 @@ int enqueue_batch(gs_batch_plan *p, const gs_gaussians *g, int nv, const gs_view
                "batch bin/sort");
     gs::profile_end(GS_STAGE_BIN_SORT, st);
     gs::profile_begin(GS_STAGE_BLEND_FWD, st);
-    GS_TRY_HIP(gs::launch_blend_fwd(p->bd, vt, it, p->proj, p->vals, p->tile_range, st), "batch blend forward");
+    GS_TRY_HIP(gs::launch_blend_fwd(p->bd, vt, it, p->proj, p->vals, p->tile_range, p->blend_state, p->cap, st),
+               "batch blend forward");
     gs::profile_end(GS_STAGE_BLEND_FWD, st);
     gs::LidarTable lt{};
     lt.n_views = nv;
@@ -548,7 +571,8 @@ int enqueue_batch(gs_batch_plan *p, const gs_gaussians *g, int nv, const gs_view
     gs_grads gg{};
     if (grads) gg = *grads;
     GradScratch s = carve_grads(p->grad_scratch, g->n, nv, p->max_pixels);
-    rc = enqueue_backward(vt, *g, p->proj, p->vals, p->tile_range, io.data(), p->bd, gg, s, st);
+    rc = enqueue_backward(vt, *g, p->proj, p->vals, p->tile_range, p->blend_state, p->cap, io.data(), p->bd, gg, s,
+                          st);
     if (rc) return rc;
   }
   return GS_OK;
@@ -600,7 +624,7 @@ int gs_batch_plan_create(gs_batch_plan **out, int64_t n, int32_t sh_degree, int3
   p->cap = capacity;
   // every view adds at most one partial tile row and column beyond pixels / tile area
   p->max_tiles = max_total_pixels / ((int64_t)tile_w * tile_h) + (int64_t)n_views * (2 * 32768 / tile_w + 1);
-  size_t offs[12];
+  size_t offs[13];
   const size_t bytes = plan_bytes(*p, offs);
   hipError_t e = hipMalloc(&p->block, bytes);
   if (e != hipSuccess) {
@@ -620,6 +644,7 @@ int gs_batch_plan_create(gs_batch_plan **out, int64_t n, int32_t sh_degree, int3
   p->bin_scratch = b + offs[9];
   p->grad_scratch = b + offs[10];
   p->dC = (float *)(b + offs[11]);
+  p->blend_state = b + offs[12];
   *out = p;
   return GS_OK;
 }
@@ -628,6 +653,7 @@ void gs_batch_plan_destroy(gs_batch_plan *p) {
   if (!p) return;
   if (p->exec) (void)hipGraphExecDestroy(p->exec);
   if (p->graph) (void)hipGraphDestroy(p->graph);
+  if (p->capture_stream) (void)hipStreamDestroy(p->capture_stream);
   if (p->block) (void)hipFree(p->block);
   delete p;
 }
@@ -660,7 +686,7 @@ int gs_render_batch(gs_batch_plan *p, const gs_gaussians *g, int32_t n_views, co
   add(views, sizeof(gs_view) * n_views);
   gs_grads gz{};
   add(grads ? grads : &gz, sizeof(gs_grads));
-  add(&st, sizeof st);
+
   if (!p->exec || sig != p->signature) {
     if (p->exec) {
       (void)hipGraphExecDestroy(p->exec);
@@ -670,10 +696,13 @@ int gs_render_batch(gs_batch_plan *p, const gs_gaussians *g, int32_t n_views, co
       (void)hipGraphDestroy(p->graph);
       p->graph = nullptr;
     }
-    GS_TRY_HIP(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal), "begin capture");
-    rc = enqueue_batch(p, g, n_views, views, mode & ~GS_GRAPH, grads, st);
+    if (!p->capture_stream)
+      GS_TRY_HIP(hipStreamCreateWithFlags(&p->capture_stream, hipStreamNonBlocking), "capture stream");
+    hipStream_t cs = p->capture_stream;
+    GS_TRY_HIP(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal), "begin capture");
+    rc = enqueue_batch(p, g, n_views, views, mode & ~GS_GRAPH, grads, cs);
     hipGraph_t graph = nullptr;
-    hipError_t e = hipStreamEndCapture(st, &graph);
+    hipError_t e = hipStreamEndCapture(cs, &graph);
     if (rc) {
       if (graph) (void)hipGraphDestroy(graph);
       return rc;

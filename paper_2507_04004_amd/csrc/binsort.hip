@@ -25,18 +25,13 @@ constexpr int kRadixThreads = 256;
 constexpr int kRadixItems = 16;
 constexpr int kRadixChunk = kRadixThreads * kRadixItems;
 constexpr int kScanThreads = 256;
-constexpr int kScanItems = 4;
+constexpr int kScanItems = 1;
 constexpr int kScanChunk = kScanThreads * kScanItems;
 
 __device__ __forceinline__ int64_t live_count(int64_t n_static, const int64_t *n_dev, int64_t cap) {
   if (!n_dev) return n_static;
   int64_t v = *n_dev;
   return v < cap ? v : cap;
-}
-
-__device__ __forceinline__ uint64_t lanemask_lt() {
-  const int lane = threadIdx.x & 63;
-  return lane ? (~0ull >> (64 - lane)) : 0ull;
 }
 
 // Lanes of this wavefront whose digit equals this lane's digit (only valid lanes).
@@ -49,30 +44,6 @@ __device__ __forceinline__ uint64_t digit_peers(uint32_t d, bool valid) {
     m &= bit ? bal : ~bal;
   }
   return m;
-}
-
-// Exclusive scan of one value per thread over a block of NT threads; returns the total too.
-template <int NT>
-__device__ __forceinline__ uint32_t block_exclusive_scan(uint32_t v, uint32_t *lds /*NT/64 + 1*/, uint32_t &total) {
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  uint32_t inc = v;
-#pragma unroll
-  for (int off = 1; off < 64; off <<= 1) {
-    uint32_t t = __shfl_up(inc, off);
-    if (lane >= off) inc += t;
-  }
-  __syncthreads();
-  if (lane == 63) lds[wave] = inc;
-  __syncthreads();
-  uint32_t wbase = 0, tot = 0;
-#pragma unroll
-  for (int w = 0; w < NT / 64; ++w) {
-    const uint32_t x = lds[w];
-    if (w < wave) wbase += x;
-    tot += x;
-  }
-  total = tot;
-  return wbase + inc - v;
 }
 
 // ---- radix passes --------------------------------------------------------------------------
@@ -212,33 +183,56 @@ __global__ __launch_bounds__(kScanThreads) void k_emit_pairs(ViewTable vt, const
                                                              const uint32_t *__restrict__ bsum, int64_t cap,
                                                              uint32_t *__restrict__ pkey, uint32_t *__restrict__ pval) {
   __shared__ uint32_t lds[kScanThreads / 64 + 1];
-  const int64_t base = (int64_t)blockIdx.x * kScanChunk;
-  uint32_t running = bsum[blockIdx.x];
-  for (int r = 0; r < kScanItems; ++r) {
-    const int64_t i = base + r * kScanThreads + threadIdx.x;
-    uint32_t e = 0, cnt = 0;
-    if (i < n) {
-      e = order[i];
-      cnt = n_tiles[e];
-    }
-    uint32_t total;
-    const uint32_t ex = block_exclusive_scan<kScanThreads>(cnt, lds, total);
-    if (cnt) {
-      const uint32_t off = running + ex;
-      const int vi = (int)(e / (uint32_t)vt.n);
-      const ViewCam &cam = vt.v[vi];
-      const float4 A = rec_a[e], B = rec_b[e];
-      const short4 rc = rect[e];
-      visit_kept_tiles(cam, vt.tile_w, vt.tile_h, A.x, A.y, B.x, B.y, B.z, B.w, rc.x, rc.y, rc.z, rc.w,
-                       [&](uint32_t lt, uint32_t j) {
-                         const int64_t pos = (int64_t)off + j;
-                         if (pos < cap) {
-                           pkey[pos] = cam.tile_base + lt;
-                           pval[pos] = e;
-                         }
-                       });
-    }
-    running += total;
+  const int64_t i = (int64_t)blockIdx.x * kScanChunk + threadIdx.x;
+  uint32_t e = 0, cnt = 0;
+  if (i < n) {
+    e = order[i];
+    cnt = n_tiles[e];
+  }
+  uint32_t total;
+  const uint32_t off = bsum[blockIdx.x] + block_exclusive_scan<kScanThreads>(cnt, lds, total);
+  float4 A = make_float4(0.f, 0.f, 0.f, 0.f), B = A;
+  short4 rc = make_short4(0, 0, -1, -1);
+  int vi = 0;
+  if (cnt) {
+    vi = (int)(e / (uint32_t)vt.n);
+    A = rec_a[e];
+    B = rec_b[e];
+    rc = rect[e];
+  }
+  const int area = cnt ? (rc.z - rc.x + 1) * (rc.w - rc.y + 1) : 0;
+  // small rectangles: one lane each
+  if (cnt && area <= kCoopArea) {
+    const ViewCam &cam = vt.v[vi];
+    visit_kept_tiles(cam, vt.tile_w, vt.tile_h, A.x, A.y, B.x, B.y, B.z, B.w, rc.x, rc.y, rc.z, rc.w,
+                     [&](uint32_t lt, uint32_t j) {
+                       const int64_t pos = (int64_t)off + j;
+                       if (pos < cap) {
+                         pkey[pos] = cam.tile_base + lt;
+                         pval[pos] = e;
+                       }
+                     });
+  }
+  // large rectangles: the whole wavefront, one splat at a time
+  uint64_t big = __ballot(cnt && area > kCoopArea);
+  while (big) {
+    const int src = __ffsll((unsigned long long)big) - 1;
+    big &= big - 1;
+    const int bvi = __shfl(vi, src);
+    const ViewCam &cam = vt.v[bvi];
+    const float bu = __shfl(A.x, src), bv = __shfl(A.y, src);
+    const float ba = __shfl(B.x, src), bb = __shfl(B.y, src), bc = __shfl(B.z, src), bk = __shfl(B.w, src);
+    const int x0 = __shfl((int)rc.x, src), y0 = __shfl((int)rc.y, src);
+    const int x1 = __shfl((int)rc.z, src), y1 = __shfl((int)rc.w, src);
+    const uint32_t boff = __shfl(off, src), be = __shfl(e, src);
+    wave_visit_kept_tiles(cam, vt.tile_w, vt.tile_h, bu, bv, ba, bb, bc, bk, x0, y0, x1, y1,
+                          [&](uint32_t lt, uint32_t j) {
+                            const int64_t pos = (int64_t)boff + j;
+                            if (pos < cap) {
+                              pkey[pos] = cam.tile_base + lt;
+                              pval[pos] = be;
+                            }
+                          });
   }
 }
 

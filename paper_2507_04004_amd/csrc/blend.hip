@@ -1,0 +1,643 @@
+// Stages a3 and a4 of the rasterizer, load-balanced: front-to-back compositing of colour,
+// depth and opacity (eq:alpha, eq:rendered_rgb, eq:rendered_depth, eq:rendered_opacity) and
+// its backward.
+//
+// Per-tile list lengths vary by two orders of magnitude (a tile at the vanishing point of a
+// street holds tens of thousands of splats, the median tile a hundred), so one workgroup per
+// tile leaves the chip idle behind a few long tiles. Each tile's depth-sorted list is cut
+// into chunks of BD records; every (tile, chunk) is a work item of one workgroup (one lane per
+// pixel, records staged once through LDS and read as a broadcast).
+//
+// Compositing is associative: a chunk composited from transmittance 1 gives partial sums
+// (C_k, D_k, O_k) and a transmittance product T_k, and the pixel's result is
+// sum_k T_in,k * C_k with T_in,k the product of the earlier T_k. Only the early stop (stop
+// before a splat that would take the transmittance below 1e-4) needs the true incoming
+// transmittance, so:
+//   1. k_blend_chunk composites every chunk from T = 1. Chunk 0 is exact. A tile with one
+//      chunk writes its pixels directly (the common case).
+//   2. k_blend_scan walks the chunk partials of each multi-chunk tile in order per pixel. A
+//      chunk whose product keeps the transmittance at or above 1e-4 is accumulated as a whole;
+//      at the chunk in which the pixel stops it records the incoming state.
+//   3. k_blend_fix (one workgroup per chunk, in parallel) composites each pixel's stop chunk
+//      again record by record from the true incoming transmittance, which applies the stop
+//      rule exactly.
+//   4. k_blend_suffix stores, per chunk and pixel, the transmittance after the chunk and the
+//      colour / depth composited behind it (normalised by that transmittance): the backward's
+//      starting state.
+//   5. k_blend_bwd_chunk runs every chunk back to front in parallel from that state,
+//      rebuilding each transmittance by division, exactly as a sequential walk would from the
+//      last blended splat.
+// The per-pixel checkpoint of the forward stays T_final and the position of the last
+// blended splat in the tile list; the per-chunk state is 32 B per (chunk, pixel).
+#include <algorithm>
+
+#include "gs_internal.hpp"
+
+namespace gs {
+
+struct ChunkRec {
+  float c0, c1, c2, d, o, t;
+  uint32_t info;  // bits 0-9: local last + 1 (0 = none); 10-19: contributions; 20: stopped inside
+  float pad;
+};
+static_assert(sizeof(ChunkRec) == 32, "chunk record is 32 B");
+
+__host__ __device__ __forceinline__ uint32_t n_chunks(uint32_t len, int bd) { return (len + bd - 1) / bd; }
+
+// ---- work items: (tile, chunk) pairs --------------------------------------------------------
+constexpr int kItemThreads = 256;
+constexpr int kItemPer = 4;
+constexpr int kItemChunk = kItemThreads * kItemPer;
+
+__global__ __launch_bounds__(kItemThreads) void k_items_reduce(const uint32_t *__restrict__ range, uint32_t T, int bd,
+                                                                uint32_t *__restrict__ bsum) {
+  __shared__ uint32_t lds[kItemThreads / 64 + 1];
+  uint32_t s = 0;
+#pragma unroll
+  for (int r = 0; r < kItemPer; ++r) {
+    const uint32_t t = blockIdx.x * kItemChunk + r * kItemThreads + threadIdx.x;
+    if (t < T) s += n_chunks(range[2 * t + 1] - range[2 * t], bd);
+  }
+  uint32_t total;
+  block_exclusive_scan<kItemThreads>(s, lds, total);
+  if (threadIdx.x == 0) bsum[blockIdx.x] = total;
+}
+
+__global__ __launch_bounds__(1024) void k_items_scan(uint32_t *__restrict__ bsum, uint32_t nb,
+                                                      uint32_t *__restrict__ n_items, uint32_t *__restrict__ item_base,
+                                                      uint32_t T) {
+  __shared__ uint32_t lds[1024 / 64 + 1];
+  uint32_t running = 0;
+  for (uint32_t base = 0; base < nb; base += 1024) {
+    const uint32_t i = base + threadIdx.x;
+    const uint32_t v = i < nb ? bsum[i] : 0u;
+    uint32_t total;
+    const uint32_t ex = block_exclusive_scan<1024>(v, lds, total);
+    if (i < nb) bsum[i] = running + ex;
+    running += total;
+  }
+  if (threadIdx.x == 0) {
+    *n_items = running;
+    item_base[T] = running;
+  }
+}
+
+__global__ __launch_bounds__(kItemThreads) void k_items_apply(const uint32_t *__restrict__ range, uint32_t T, int bd,
+                                                               const uint32_t *__restrict__ bsum,
+                                                               uint32_t *__restrict__ item_base,
+                                                               uint2 *__restrict__ items) {
+  __shared__ uint32_t lds[kItemThreads / 64 + 1];
+  uint32_t running = bsum[blockIdx.x];
+  for (int r = 0; r < kItemPer; ++r) {
+    const uint32_t t = blockIdx.x * kItemChunk + r * kItemThreads + threadIdx.x;
+    const uint32_t k = t < T ? n_chunks(range[2 * t + 1] - range[2 * t], bd) : 0u;
+    uint32_t total;
+    const uint32_t ex = block_exclusive_scan<kItemThreads>(k, lds, total);
+    if (t < T) {
+      const uint32_t b = running + ex;
+      item_base[t] = b;
+      for (uint32_t c = 0; c < k; ++c) items[b + c] = make_uint2(t, c);
+    }
+    running += total;
+  }
+}
+
+// ---- shared per-pixel setup ----------------------------------------------------------------
+template <int TW, int TH>
+struct PixelCtx {
+  int vi, wx, wy;
+  bool inside;
+  float px, py;
+  int64_t pi, npx;
+
+  __device__ __forceinline__ PixelCtx(const ViewTable &vt, uint32_t gt) {
+    vi = view_of_tile(vt, gt);
+    const ViewCam &cam = vt.v[vi];
+    const uint32_t lt = gt - cam.tile_base;
+    const int tx = (int)(lt % (uint32_t)cam.tiles_x), ty = (int)(lt / (uint32_t)cam.tiles_x);
+    wx = tx * TW + (int)threadIdx.x % TW;
+    wy = ty * TH + (int)threadIdx.x / TW;
+    inside = wx < cam.w && wy < cam.h;
+    px = (float)(cam.x0 + wx);
+    py = (float)(cam.y0 + wy);
+    npx = (int64_t)cam.w * cam.h;
+    pi = (int64_t)wy * cam.w + wx;
+  }
+};
+
+template <int BD, int NT>
+__device__ __forceinline__ void stage(const uint32_t *__restrict__ vals, uint32_t start, int cnt,
+                                      const float4 *__restrict__ rec_a, const float4 *__restrict__ rec_b,
+                                      const float4 *__restrict__ rgb, float4 *s_a, float4 *s_b, float4 *s_c,
+                                      uint32_t *s_e) {
+  for (int k = threadIdx.x; k < cnt; k += NT) {
+    const uint32_t e = vals[start + k];
+    if (s_e) s_e[k] = e;
+    s_a[k] = rec_a[e];
+    s_b[k] = rec_b[e];
+    s_c[k] = rgb[e];
+  }
+}
+
+__device__ __forceinline__ void write_pixel(const ViewImg &im, const ViewCam &cam, int64_t pi, int64_t npx, float C0,
+                                            float C1, float C2, float D, float O, float T, int32_t last, int32_t nc) {
+  im.color[pi] = C0 + T * cam.bg[0];
+  im.color[npx + pi] = C1 + T * cam.bg[1];
+  im.color[2 * npx + pi] = C2 + T * cam.bg[2];
+  im.depth[pi] = D;
+  im.alpha[pi] = O;
+  im.t_final[pi] = T;
+  im.last[pi] = last;
+  if (im.n_contrib) im.n_contrib[pi] = nc;
+}
+
+// ---- forward pass 1: every chunk from transmittance 1 ------------------------------------
+template <int TW, int TH, int BD>
+__global__ __launch_bounds__(TW *TH) void k_blend_chunk(ViewTable vt, ImgTable it, const float4 *__restrict__ rec_a,
+                                                        const float4 *__restrict__ rec_b,
+                                                        const float4 *__restrict__ rgb,
+                                                        const uint32_t *__restrict__ vals,
+                                                        const uint32_t *__restrict__ range,
+                                                        const uint2 *__restrict__ items,
+                                                        const uint32_t *__restrict__ n_items,
+                                                        ChunkRec *__restrict__ chunk) {
+  constexpr int NT = TW * TH;
+  __shared__ float4 s_a[BD], s_b[BD], s_c[BD];
+  const uint32_t item = blockIdx.x;
+  if (item >= *n_items) return;
+  const uint2 tc = items[item];
+  const uint32_t gt = tc.x, c = tc.y;
+  const PixelCtx<TW, TH> px(vt, gt);
+  const uint32_t s0 = range[2 * gt], e0 = range[2 * gt + 1];
+  const uint32_t K = n_chunks(e0 - s0, BD);
+  const uint32_t cs = s0 + c * BD;
+  const int cnt = (int)min<uint32_t>(BD, e0 - cs);
+  stage<BD, NT>(vals, cs, cnt, rec_a, rec_b, rgb, s_a, s_b, s_c, nullptr);
+  __syncthreads();
+
+  float T = 1.f, C0 = 0.f, C1 = 0.f, C2 = 0.f, D = 0.f, O = 0.f;
+  int32_t last = -1, nc = 0;
+  bool cut = false;
+  if (px.inside) {
+    for (int j = 0; j < cnt; ++j) {
+      const float4 A = s_a[j], B = s_b[j];
+      const float power = splat_power(B.x, B.y, B.z, px.px - A.x, px.py - A.y);
+      const float alpha = fminf(kAlphaMax, splat_alpha_raw(A.z, power));
+      if (alpha < kAlphaMin) continue;
+      const float Tn = T * (1.f - alpha);
+      if (Tn < kTMin) {
+        cut = true;
+        break;
+      }
+      const float w = alpha * T;
+      const float4 Cc = s_c[j];
+      C0 += w * Cc.x;
+      C1 += w * Cc.y;
+      C2 += w * Cc.z;
+      D += w * A.w;
+      O += w;
+      T = Tn;
+      last = j;
+      ++nc;
+    }
+  }
+  if (!px.inside) return;
+  if (K == 1) {
+    write_pixel(it.v[px.vi], vt.v[px.vi], px.pi, px.npx, C0, C1, C2, D, O, T, last, nc);
+  } else {
+    ChunkRec r;
+    r.c0 = C0; r.c1 = C1; r.c2 = C2; r.d = D; r.o = O; r.t = T;
+    r.info = (uint32_t)(last + 1) | ((uint32_t)nc << 10) | ((uint32_t)cut << 20);
+    r.pad = 0.f;
+    chunk[(int64_t)item * NT + threadIdx.x] = r;
+  }
+}
+
+// ---- forward pass 2: per multi-chunk tile, chunk partials in order ------------------------
+// Slot flags after this pass: kPending = the pixel stops inside this chunk (slot holds the
+// state before it: colour, depth, opacity, transmittance, last + 1, count in pad); kAfter =
+// the chunk lies behind the pixel's stop. Otherwise the slot holds the chunk's absolute
+// colour / depth and the transmittance after it.
+constexpr uint32_t kPending = 1u << 31;
+constexpr uint32_t kAfter = 1u << 30;
+
+template <int TW, int TH, int BD>
+__global__ __launch_bounds__(TW *TH) void k_blend_scan(ViewTable vt, ImgTable it, const uint32_t *__restrict__ range,
+                                                       const uint32_t *__restrict__ item_base,
+                                                       ChunkRec *__restrict__ chunk) {
+  constexpr int NT = TW * TH;
+  const uint32_t gt = blockIdx.x;
+  const uint32_t s0 = range[2 * gt], e0 = range[2 * gt + 1];
+  const uint32_t K = n_chunks(e0 - s0, BD);
+  if (K == 1) return;  // written by k_blend_chunk
+  const PixelCtx<TW, TH> px(vt, gt);
+  if (!px.inside) return;
+  const ViewCam &cam = vt.v[px.vi];
+  if (K == 0) {
+    write_pixel(it.v[px.vi], cam, px.pi, px.npx, 0.f, 0.f, 0.f, 0.f, 0.f, 1.f, -1, 0);
+    return;
+  }
+  ChunkRec *base = chunk + (int64_t)item_base[gt] * NT + threadIdx.x;
+  float T = 1.f, C0 = 0.f, C1 = 0.f, C2 = 0.f, D = 0.f, O = 0.f;
+  int32_t last = -1, nc = 0;
+  bool finished = false, pending = false;
+  ChunkRec nxt = base[0];
+  for (uint32_t k = 0; k < K; ++k) {
+    const ChunkRec r = nxt;
+    if (k + 1 < K) nxt = base[(int64_t)(k + 1) * NT];  // prefetch the next chunk's partial
+    ChunkRec w;
+    w.o = 0.f;
+    w.pad = 0.f;
+    if (finished || pending) {
+      w.c0 = w.c1 = w.c2 = w.d = 0.f;
+      w.t = T;
+      w.info = kAfter;
+    } else {
+      const int ll = (int)(r.info & 1023u) - 1;
+      const int ncl = (int)((r.info >> 10) & 1023u);
+      const bool cut = (r.info >> 20) & 1u;
+      const float Tafter = T * r.t;
+      if (!cut ? (Tafter >= kTMin) : (k == 0)) {
+        // the whole chunk blends (chunk 0 is exact from T = 1 even when it stops inside)
+        w.c0 = T * r.c0; w.c1 = T * r.c1; w.c2 = T * r.c2; w.d = T * r.d;
+        C0 += w.c0; C1 += w.c1; C2 += w.c2; D += w.d;
+        O += T * r.o;
+        if (ll >= 0) last = (int32_t)(k * BD) + ll;
+        nc += ncl;
+        T = Tafter;
+        w.t = T;
+        w.info = 0u;
+        finished = cut;
+      } else {
+        // the pixel stops inside this chunk: hand the incoming state to k_blend_fix
+        w.c0 = C0; w.c1 = C1; w.c2 = C2; w.d = D; w.o = O; w.t = T;
+        w.info = kPending | (uint32_t)(last + 1);
+        w.pad = __int_as_float(nc);
+        pending = true;
+      }
+    }
+    base[(int64_t)k * NT] = w;
+  }
+  if (!pending) write_pixel(it.v[px.vi], cam, px.pi, px.npx, C0, C1, C2, D, O, T, last, nc);
+}
+
+// ---- forward pass 3: exact compositing of each pixel's stop chunk (chunk-parallel) -------
+template <int TW, int TH, int BD>
+__global__ __launch_bounds__(TW *TH) void k_blend_fix(ViewTable vt, ImgTable it, const float4 *__restrict__ rec_a,
+                                                      const float4 *__restrict__ rec_b,
+                                                      const float4 *__restrict__ rgb,
+                                                      const uint32_t *__restrict__ vals,
+                                                      const uint32_t *__restrict__ range,
+                                                      const uint2 *__restrict__ items,
+                                                      const uint32_t *__restrict__ n_items,
+                                                      ChunkRec *__restrict__ chunk) {
+  constexpr int NT = TW * TH;
+  __shared__ float4 s_a[BD], s_b[BD], s_c[BD];
+  const uint32_t item = blockIdx.x;
+  if (item >= *n_items) return;
+  const uint2 tc = items[item];
+  const uint32_t gt = tc.x, c = tc.y;
+  const uint32_t s0 = range[2 * gt], e0 = range[2 * gt + 1];
+  if (n_chunks(e0 - s0, BD) < 2) return;
+  const PixelCtx<TW, TH> px(vt, gt);
+  ChunkRec *slot = chunk + (int64_t)item * NT + threadIdx.x;
+  ChunkRec r{};
+  if (px.inside) r = *slot;
+  const bool pending = px.inside && (r.info & kPending);
+  if (__syncthreads_count(pending) == 0) return;
+  const uint32_t cs = s0 + c * BD;
+  const int cnt = (int)min<uint32_t>(BD, e0 - cs);
+  stage<BD, NT>(vals, cs, cnt, rec_a, rec_b, rgb, s_a, s_b, s_c, nullptr);
+  __syncthreads();
+  if (!pending) return;
+  float T = r.t, O = r.o;
+  int32_t last = (int32_t)(r.info & 0x3FFFFFFFu) - 1, nc = __float_as_int(r.pad);
+  float a0 = 0.f, a1 = 0.f, a2 = 0.f, ad = 0.f;
+  for (int j = 0; j < cnt; ++j) {
+    const float4 A = s_a[j], B = s_b[j];
+    const float power = splat_power(B.x, B.y, B.z, px.px - A.x, px.py - A.y);
+    const float alpha = fminf(kAlphaMax, splat_alpha_raw(A.z, power));
+    if (alpha < kAlphaMin) continue;
+    const float Tn = T * (1.f - alpha);
+    if (Tn < kTMin) break;
+    const float w = alpha * T;
+    const float4 Cc = s_c[j];
+    a0 += w * Cc.x;
+    a1 += w * Cc.y;
+    a2 += w * Cc.z;
+    ad += w * A.w;
+    O += w;
+    T = Tn;
+    last = (int32_t)(c * BD) + j;
+    ++nc;
+  }
+  write_pixel(it.v[px.vi], vt.v[px.vi], px.pi, px.npx, r.c0 + a0, r.c1 + a1, r.c2 + a2, r.d + ad, O, T, last, nc);
+  ChunkRec w;
+  w.c0 = a0; w.c1 = a1; w.c2 = a2; w.d = ad; w.o = 0.f; w.t = T; w.info = 0u; w.pad = 0.f;
+  *slot = w;
+}
+
+// ---- forward pass 4: backward starting state per chunk (suffix sums, per tile) ------------
+// Colour / depth composited behind each chunk, normalised by the transmittance after it.
+template <int TW, int TH, int BD>
+__global__ __launch_bounds__(TW *TH) void k_blend_suffix(ViewTable vt, const uint32_t *__restrict__ range,
+                                                         const uint32_t *__restrict__ item_base,
+                                                         ChunkRec *__restrict__ chunk) {
+  constexpr int NT = TW * TH;
+  const uint32_t gt = blockIdx.x;
+  const uint32_t K = n_chunks(range[2 * gt + 1] - range[2 * gt], BD);
+  if (K < 2) return;
+  const PixelCtx<TW, TH> px(vt, gt);
+  if (!px.inside) return;
+  ChunkRec *base = chunk + (int64_t)item_base[gt] * NT + threadIdx.x;
+  float b0 = 0.f, b1 = 0.f, b2 = 0.f, bd = 0.f;
+  ChunkRec nxt = base[(int64_t)(K - 1) * NT];
+  for (int k = (int)K - 1; k >= 0; --k) {
+    const ChunkRec r = nxt;
+    if (k > 0) nxt = base[(int64_t)(k - 1) * NT];
+    if (r.info & kAfter) continue;
+    const float inv = 1.f / r.t;
+    ChunkRec w;
+    w.c0 = b0 * inv; w.c1 = b1 * inv; w.c2 = b2 * inv; w.d = bd * inv; w.o = 0.f; w.t = r.t; w.info = 0u;
+    w.pad = 0.f;
+    base[(int64_t)k * NT] = w;
+    b0 += r.c0; b1 += r.c1; b2 += r.c2; bd += r.d;
+  }
+}
+
+// ---- backward: every chunk back to front ---------------------------------------------------
+// Sum over the wavefront of ten values; the lane q < 10 returns value q's total.
+// Transposed reduction: four row-local DPP exchanges each halve the number of values a lane
+// carries (8, 4, 2, 1 of 16), then two cross-row swaps finish one value per lane.
+template <int CTRL>
+__device__ __forceinline__ float dpp(float v) {
+  return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), CTRL, 0xF, 0xF, false));
+}
+
+__device__ __forceinline__ float wave_reduce10(const float (&g)[10], int lane) {
+  // stage 1: partner lane i^15 within a 16-lane row (row_mirror); lanes < 8 keep values 0-7
+  float v8[8];
+  const bool lo1 = (lane & 8) == 0;
+#pragma unroll
+  for (int k = 0; k < 8; ++k) {
+    const float mine = (8 + k < 10) ? g[8 + k] : 0.f;
+    const float keep = lo1 ? g[k] : mine;
+    const float send = lo1 ? mine : g[k];
+    v8[k] = keep + dpp<0x140>(send);
+  }
+  // stage 2: partner i^7 within 8 (row_half_mirror); lanes with bit 2 clear keep 0-3
+  float v4[4];
+  const bool lo2 = (lane & 4) == 0;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const float keep = lo2 ? v8[k] : v8[4 + k];
+    const float send = lo2 ? v8[4 + k] : v8[k];
+    v4[k] = keep + dpp<0x141>(send);
+  }
+  // stage 3: partner i^2 (quad_perm [2,3,0,1]); bit 1 clear keeps 0-1
+  float v2[2];
+  const bool lo3 = (lane & 2) == 0;
+#pragma unroll
+  for (int k = 0; k < 2; ++k) {
+    const float keep = lo3 ? v4[k] : v4[2 + k];
+    const float send = lo3 ? v4[2 + k] : v4[k];
+    v2[k] = keep + dpp<0x4E>(send);
+  }
+  // stage 4: partner i^1 (quad_perm [1,0,3,2]); bit 0 clear keeps 0
+  const bool lo4 = (lane & 1) == 0;
+  const float keep = lo4 ? v2[0] : v2[1];
+  const float send = lo4 ? v2[1] : v2[0];
+  float v = keep + dpp<0xB1>(send);
+  // now lane l of each row holds the row sum of value idx(l) where idx = 8*!lo1 + 4*!lo2 + 2*!lo3 + !lo4
+  // stages 5-6: add the four rows (permlane swaps between rows 0/1, 2/3, then halves)
+  const auto s16 = __builtin_amdgcn_permlane16_swap(__float_as_uint(v), __float_as_uint(v), false, false);
+  v = __uint_as_float(s16[0]) + __uint_as_float(s16[1]);
+  const auto s32 = __builtin_amdgcn_permlane32_swap(__float_as_uint(v), __float_as_uint(v), false, false);
+  v = __uint_as_float(s32[0]) + __uint_as_float(s32[1]);
+  return v;  // lane l holds the total of value index(l & 15)
+}
+
+// value index held by lane l after wave_reduce10 (mirror pairings flip the low bits)
+__device__ __forceinline__ int reduce10_index(int lane) {
+  const int r = lane & 15;
+  return ((r & 8) ? 8 : 0) + ((r & 4) ? 4 : 0) + ((r & 2) ? 2 : 0) + ((r & 1) ? 1 : 0);
+}
+
+template <int TW, int TH, int BD>
+__global__ __launch_bounds__(TW *TH) void k_blend_bwd_chunk(ViewTable vt, ImgTable it, GradTable gtab,
+                                                            const float4 *__restrict__ rec_a,
+                                                            const float4 *__restrict__ rec_b,
+                                                            const float4 *__restrict__ rgb,
+                                                            const uint32_t *__restrict__ vals,
+                                                            const uint32_t *__restrict__ range,
+                                                            const uint2 *__restrict__ items,
+                                                            const uint32_t *__restrict__ n_items,
+                                                            const ChunkRec *__restrict__ chunk,
+                                                            float *__restrict__ g2 /*[E][12]*/) {
+  constexpr int NT = TW * TH;
+  __shared__ float4 s_a[BD], s_b[BD], s_c[BD];
+  __shared__ uint32_t s_e[BD];
+  __shared__ int s_max;
+  const uint32_t item = blockIdx.x;
+  if (item >= *n_items) return;
+  const uint2 tc = items[item];
+  const uint32_t gt = tc.x, c = tc.y;
+  const PixelCtx<TW, TH> px(vt, gt);
+  const ViewCam &cam = vt.v[px.vi];
+  const uint32_t s0 = range[2 * gt], e0 = range[2 * gt + 1];
+  const uint32_t K = n_chunks(e0 - s0, BD);
+  const uint32_t cs = s0 + c * BD;
+  const int cnt = (int)min<uint32_t>(BD, e0 - cs);
+  const ViewImg &im = it.v[px.vi];
+  const ViewGrad &vg = gtab.v[px.vi];
+
+  float Tfin = 1.f, gC0 = 0.f, gC1 = 0.f, gC2 = 0.f, gD = 0.f, gO = 0.f;
+  int ll = -1;
+  float T = 1.f, A0 = 0.f, A1 = 0.f, A2 = 0.f, AD = 0.f;
+  if (px.inside) {
+    Tfin = im.t_final[px.pi];
+    ll = min(im.last[px.pi] - (int)(c * BD), cnt - 1);
+    gC0 = vg.gC[px.pi];
+    gC1 = vg.gC[px.npx + px.pi];
+    gC2 = vg.gC[2 * px.npx + px.pi];
+    if (vg.gD) gD = vg.gD[px.pi];
+    if (vg.gO) gO = vg.gO[px.pi];
+    if (K == 1) {
+      T = Tfin;
+    } else if (ll >= 0) {
+      const ChunkRec r = chunk[(int64_t)item * NT + threadIdx.x];
+      T = r.t;
+      A0 = r.c0; A1 = r.c1; A2 = r.c2; AD = r.d;
+    }
+  }
+  if (threadIdx.x == 0) s_max = -1;
+  __syncthreads();
+  if (ll >= 0) atomicMax(&s_max, ll);
+  __syncthreads();
+  const int maxll = s_max;
+  if (maxll < 0) return;  // uniform: no pixel has a contributor in this chunk
+  stage<BD, NT>(vals, cs, maxll + 1, rec_a, rec_b, rgb, s_a, s_b, s_c, s_e);
+  __syncthreads();
+
+  const float gOb = gO - (gC0 * cam.bg[0] + gC1 * cam.bg[1] + gC2 * cam.bg[2]);
+  const int lane = threadIdx.x & 63;
+  const int q = reduce10_index(lane);
+  const bool depth_live = __any(gD != 0.f);
+  for (int j = maxll; j >= 0; --j) {
+    float g[10];
+#pragma unroll
+    for (int k = 0; k < 10; ++k) g[k] = 0.f;
+    bool contrib = false;
+    if (j <= ll) {
+      const float4 A = s_a[j], B = s_b[j];
+      const float dx = px.px - A.x, dy = px.py - A.y;
+      const float power = splat_power(B.x, B.y, B.z, dx, dy);
+      const float ex = __expf(power);
+      const float ar = A.z * ex;  // the same two operations as splat_alpha_raw
+      const float alpha = fminf(kAlphaMax, ar);
+      if (alpha >= kAlphaMin) {
+        contrib = true;
+        const float one_m = 1.f - alpha;
+        T = T / one_m;  // transmittance in front of this splat
+        const float w = alpha * T;
+        const float4 Cc = s_c[j];
+        g[6] = gC0 * w;
+        g[7] = gC1 * w;
+        g[8] = gC2 * w;
+        float dLda = gC0 * (Cc.x - A0) + gC1 * (Cc.y - A1) + gC2 * (Cc.z - A2);
+        A0 = alpha * Cc.x + one_m * A0;
+        A1 = alpha * Cc.y + one_m * A1;
+        A2 = alpha * Cc.z + one_m * A2;
+        if (depth_live) {
+          g[9] = gD * w;
+          dLda += gD * (A.w - AD);
+          AD = alpha * A.w + one_m * AD;
+        }
+        dLda = T * dLda + (Tfin / one_m) * gOb;
+        if (ar < kAlphaMax) {
+          g[5] = dLda * ex;
+          const float dp = dLda * ar;
+          g[0] = dp * (B.x * dx + B.y * dy);
+          g[1] = dp * (B.y * dx + B.z * dy);
+          g[2] = -0.5f * dp * dx * dx;
+          g[3] = -dp * dx * dy;
+          g[4] = -0.5f * dp * dy * dy;
+        }
+      }
+    }
+    if (__any(contrib)) {
+      const float tot = wave_reduce10(g, lane);
+      if (lane < 16 && q < 10 && tot != 0.f) unsafeAtomicAdd(&g2[(int64_t)s_e[j] * 12 + q], tot);
+    }
+  }
+}
+
+// ---- scratch layout and dispatch -----------------------------------------------------------
+static inline size_t a256(size_t x) { return (x + 255) & ~size_t(255); }
+
+int64_t max_items(int64_t total_tiles, int64_t cap, int bd) { return total_tiles + (cap + bd - 1) / bd + 1; }
+
+size_t blend_state_bytes(int64_t total_tiles, int64_t cap, int tw, int th, int bd) {
+  const int64_t T = std::max<int64_t>(total_tiles, 1);
+  const int64_t I = max_items(T, cap, bd);
+  size_t s = a256(4 * (T + 1));                                     // item_base
+  s += a256(8 * I);                                                 // items
+  s += a256(4 * ((T + kItemChunk - 1) / kItemChunk + 1));          // block sums
+  s += a256(16);                                                    // n_items
+  s += a256(sizeof(ChunkRec) * (size_t)I * tw * th);                // chunk records
+  return s;
+}
+
+struct BlendState {
+  uint32_t *item_base;
+  uint2 *items;
+  uint32_t *bsum;
+  uint32_t *n_items;
+  ChunkRec *chunk;
+  int64_t I;
+};
+
+static BlendState carve_state(void *base, int64_t total_tiles, int64_t cap, int tw, int th, int bd) {
+  const int64_t T = std::max<int64_t>(total_tiles, 1);
+  BlendState s;
+  s.I = max_items(T, cap, bd);
+  char *p = (char *)base;
+  s.item_base = (uint32_t *)p;
+  p += a256(4 * (T + 1));
+  s.items = (uint2 *)p;
+  p += a256(8 * s.I);
+  s.bsum = (uint32_t *)p;
+  p += a256(4 * ((T + kItemChunk - 1) / kItemChunk + 1));
+  s.n_items = (uint32_t *)p;
+  p += a256(16);
+  s.chunk = (ChunkRec *)p;
+  (void)tw; (void)th;
+  return s;
+}
+
+template <int TW, int TH, int BD>
+static hipError_t fwd_impl(const ViewTable &vt, const ImgTable &it, const gs_projected &p, const uint32_t *vals,
+                           const uint32_t *range, const BlendState &s, hipStream_t st) {
+  const uint32_t T = vt.total_tiles;
+  const uint32_t nb = (T + kItemChunk - 1) / kItemChunk;
+  hipLaunchKernelGGL(k_items_reduce, dim3(nb), dim3(kItemThreads), 0, st, range, T, BD, s.bsum);
+  hipLaunchKernelGGL(k_items_scan, dim3(1), dim3(1024), 0, st, s.bsum, nb, s.n_items, s.item_base, T);
+  hipLaunchKernelGGL(k_items_apply, dim3(nb), dim3(kItemThreads), 0, st, range, T, BD, s.bsum, s.item_base, s.items);
+  hipLaunchKernelGGL((k_blend_chunk<TW, TH, BD>), dim3((unsigned)s.I), dim3(TW * TH), 0, st, vt, it,
+                     (const float4 *)p.rec_a, (const float4 *)p.rec_b, (const float4 *)p.rgb, vals, range,
+                     (const uint2 *)s.items, (const uint32_t *)s.n_items, s.chunk);
+  hipLaunchKernelGGL((k_blend_scan<TW, TH, BD>), dim3(T), dim3(TW * TH), 0, st, vt, it, range,
+                     (const uint32_t *)s.item_base, s.chunk);
+  hipLaunchKernelGGL((k_blend_fix<TW, TH, BD>), dim3((unsigned)s.I), dim3(TW * TH), 0, st, vt, it,
+                     (const float4 *)p.rec_a, (const float4 *)p.rec_b, (const float4 *)p.rgb, vals, range,
+                     (const uint2 *)s.items, (const uint32_t *)s.n_items, s.chunk);
+  hipLaunchKernelGGL((k_blend_suffix<TW, TH, BD>), dim3(T), dim3(TW * TH), 0, st, vt, range,
+                     (const uint32_t *)s.item_base, s.chunk);
+  return hipGetLastError();
+}
+
+template <int TW, int TH, int BD>
+static hipError_t bwd_impl(const ViewTable &vt, const ImgTable &it, const GradTable &gtab, const gs_projected &p,
+                           const uint32_t *vals, const uint32_t *range, const BlendState &s, float *g2,
+                           hipStream_t st) {
+  hipLaunchKernelGGL((k_blend_bwd_chunk<TW, TH, BD>), dim3((unsigned)s.I), dim3(TW * TH), 0, st, vt, it, gtab,
+                     (const float4 *)p.rec_a, (const float4 *)p.rec_b, (const float4 *)p.rgb, vals, range,
+                     (const uint2 *)s.items, (const uint32_t *)s.n_items, (const ChunkRec *)s.chunk, g2);
+  return hipGetLastError();
+}
+
+#define GS_BLEND_DISPATCH(FN, ...)                                                             \
+  do {                                                                                         \
+    const int tw = vt.tile_w;                                                                  \
+    if (tw == 8) {                                                                             \
+      if (bd == 64) return FN<8, 8, 64>(__VA_ARGS__);                                          \
+      if (bd == 128) return FN<8, 8, 128>(__VA_ARGS__);                                        \
+      if (bd == 256) return FN<8, 8, 256>(__VA_ARGS__);                                        \
+    } else if (tw == 16) {                                                                     \
+      if (bd == 64) return FN<16, 16, 64>(__VA_ARGS__);                                        \
+      if (bd == 128) return FN<16, 16, 128>(__VA_ARGS__);                                      \
+      if (bd == 256) return FN<16, 16, 256>(__VA_ARGS__);                                      \
+    } else if (tw == 32) {                                                                     \
+      if (bd == 64) return FN<32, 32, 64>(__VA_ARGS__);                                        \
+      if (bd == 128) return FN<32, 32, 128>(__VA_ARGS__);                                      \
+      if (bd == 256) return FN<32, 32, 256>(__VA_ARGS__);                                      \
+    }                                                                                          \
+    return hipErrorInvalidValue;                                                               \
+  } while (0)
+
+hipError_t launch_blend_fwd(int bd, const ViewTable &vt, const ImgTable &it, const gs_projected &p,
+                            const uint32_t *vals, const uint32_t *range, void *state, int64_t cap, hipStream_t st) {
+  if (vt.total_tiles == 0) return hipSuccess;
+  const BlendState s = carve_state(state, vt.total_tiles, cap, vt.tile_w, vt.tile_h, bd);
+  GS_BLEND_DISPATCH(fwd_impl, vt, it, p, vals, range, s, st);
+}
+
+hipError_t launch_blend_bwd(int bd, const ViewTable &vt, const ImgTable &it, const GradTable &gtab,
+                            const gs_projected &p, const uint32_t *vals, const uint32_t *range, void *state,
+                            int64_t cap, float *g2, hipStream_t st) {
+  if (vt.total_tiles == 0) return hipSuccess;
+  const BlendState s = carve_state(state, vt.total_tiles, cap, vt.tile_w, vt.tile_h, bd);
+  GS_BLEND_DISPATCH(bwd_impl, vt, it, gtab, p, vals, range, s, g2, st);
+}
+
+}  // namespace gs

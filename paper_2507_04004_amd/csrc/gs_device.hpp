@@ -143,4 +143,67 @@ __device__ __forceinline__ uint32_t visit_kept_tiles(const ViewCam &cam, int tw,
   return cnt;
 }
 
+__device__ __forceinline__ uint64_t lanemask_lt() {
+  const int lane = threadIdx.x & 63;
+  return lane ? (~0ull >> (64 - lane)) : 0ull;
+}
+
+// Exclusive scan of one value per thread over a block of NT threads; returns the total too.
+template <int NT>
+__device__ __forceinline__ uint32_t block_exclusive_scan(uint32_t v, uint32_t *lds /*NT/64 + 1*/, uint32_t &total) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  uint32_t inc = v;
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) {
+    uint32_t t = __shfl_up(inc, off);
+    if (lane >= off) inc += t;
+  }
+  __syncthreads();
+  if (lane == 63) lds[wave] = inc;
+  __syncthreads();
+  uint32_t wbase = 0, tot = 0;
+#pragma unroll
+  for (int w = 0; w < NT / 64; ++w) {
+    const uint32_t x = lds[w];
+    if (w < wave) wbase += x;
+    tot += x;
+  }
+  total = tot;
+  return wbase + inc - v;
+}
+
+// Kept tiles of one splat visited by a whole wavefront: lane l tests tiles l, l + 64, ... of
+// the rectangle (row-major) and f(local tile id, rank) is called for kept tiles, where rank
+// counts kept tiles in row-major order. All lanes must call this with the same arguments.
+template <typename F>
+__device__ __forceinline__ uint32_t wave_visit_kept_tiles(const ViewCam &cam, int tw, int th, float u, float v,
+                                                          float a, float b, float c, float kappa2, int tx0, int ty0,
+                                                          int tx1, int ty1, F &&f) {
+  const int rw = tx1 - tx0 + 1;
+  const int area = rw * (ty1 - ty0 + 1);
+  const int lane = threadIdx.x & 63;
+  const uint64_t lt = lanemask_lt();
+  const int xend = cam.x0 + cam.w - 1, yend = cam.y0 + cam.h - 1;
+  uint32_t done = 0;
+  for (int t0 = 0; t0 < area; t0 += 64) {
+    const int t = t0 + lane;
+    bool keep = false;
+    int tx = 0, ty = 0;
+    if (t < area) {
+      tx = tx0 + t % rw;
+      ty = ty0 + t / rw;
+      const int xa = cam.x0 + tx * tw, ya = cam.y0 + ty * th;
+      const int xb = min(xa + tw - 1, xend), yb = min(ya + th - 1, yend);
+      keep = rect_qmin(u, v, a, b, c, (float)xa, (float)xb, (float)ya, (float)yb) <= kappa2;
+    }
+    const uint64_t m = __ballot(keep);
+    if (keep) f((uint32_t)(ty * cam.tiles_x + tx), done + (uint32_t)__popcll(m & lt));
+    done += (uint32_t)__popcll(m);
+  }
+  return done;
+}
+
+// Rectangles with more tiles than this are visited cooperatively by the whole wavefront.
+constexpr int kCoopArea = 32;
+
 }  // namespace gs

@@ -29,11 +29,12 @@ hipError_t launch_bin_sort(const ViewTable &vt, const gs_projected &p, int64_t n
                            uint32_t *tile_range, int64_t *num_pairs, void *scratch, hipStream_t st);
 hipError_t fill_u32(uint32_t *p, int64_t n, uint32_t v, hipStream_t st);
 
+size_t blend_state_bytes(int64_t total_tiles, int64_t cap, int tw, int th, int bd);
 hipError_t launch_blend_fwd(int bd, const ViewTable &vt, const ImgTable &it, const gs_projected &p,
-                            const uint32_t *vals, const uint32_t *range, hipStream_t st);
+                            const uint32_t *vals, const uint32_t *range, void *state, int64_t cap, hipStream_t st);
 hipError_t launch_blend_bwd(int bd, const ViewTable &vt, const ImgTable &it, const GradTable &gtab,
-                            const gs_projected &p, const uint32_t *vals, const uint32_t *range, float *g2,
-                            hipStream_t st);
+                            const gs_projected &p, const uint32_t *vals, const uint32_t *range, void *state,
+                            int64_t cap, float *g2, hipStream_t st);
 hipError_t launch_lidar_loss(const LidarTable &lt, const ImgTable &it, int max_m, hipStream_t st);
 hipError_t launch_grad_maps(const MapSrc &src, const MapTable &dst, int n_views, int64_t max_npx,
                             const LidarTable &lt, const ImgTable &it, int max_m, hipStream_t st);

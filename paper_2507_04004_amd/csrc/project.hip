@@ -191,13 +191,15 @@ __global__ __launch_bounds__(256) void k_preprocess(ViewTable vt, const float *_
   const int64_t n = vt.n;
   const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int vi = blockIdx.y;
-  if (g >= n) return;
+  const bool in = g < n;  // every lane stays active: the wavefront-wide tile visit below needs all
   const ViewCam &cam = vt.v[vi];
   const int64_t e = (int64_t)vi * n + g;
-  float mx = mean[g], my = mean[n + g], mz = mean[2 * n + g];
+  const int64_t gg = in ? g : 0;
+  float mx = mean[gg], my = mean[n + gg], mz = mean[2 * n + gg];
   Splat s;
-  splat_decide(cam, mx, my, mz, scale[g], scale[n + g], scale[2 * n + g], rot[g], rot[n + g], rot[2 * n + g],
-               rot[3 * n + g], opacity[g], s);
+  splat_decide(cam, mx, my, mz, scale[gg], scale[n + gg], scale[2 * n + gg], rot[gg], rot[n + gg], rot[2 * n + gg],
+               rot[3 * n + gg], opacity[gg], s);
+  s.ok = s.ok && in;
   uint32_t cnt = 0;
   int tx0 = 0, ty0 = 0, tx1 = -1, ty1 = -1;
   if (s.ok) {
@@ -205,8 +207,21 @@ __global__ __launch_bounds__(256) void k_preprocess(ViewTable vt, const float *_
     tx1 = (s.px1 - cam.x0) / vt.tile_w;
     ty0 = (s.py0 - cam.y0) / vt.tile_h;
     ty1 = (s.py1 - cam.y0) / vt.tile_h;
+  }
+  const int area = s.ok ? (tx1 - tx0 + 1) * (ty1 - ty0 + 1) : 0;
+  if (s.ok && area <= kCoopArea)
     cnt = visit_kept_tiles(cam, vt.tile_w, vt.tile_h, s.u, s.v, s.a, s.b, s.c, s.kappa2, tx0, ty0, tx1, ty1,
                            [](uint32_t, uint32_t) {});
+  // large rectangles are counted by the whole wavefront, one splat at a time
+  uint64_t big = __ballot(s.ok && area > kCoopArea);
+  while (big) {
+    const int src = __ffsll((unsigned long long)big) - 1;
+    big &= big - 1;
+    const uint32_t c = wave_visit_kept_tiles(
+        cam, vt.tile_w, vt.tile_h, __shfl(s.u, src), __shfl(s.v, src), __shfl(s.a, src), __shfl(s.b, src),
+        __shfl(s.c, src), __shfl(s.kappa2, src), __shfl(tx0, src), __shfl(ty0, src), __shfl(tx1, src),
+        __shfl(ty1, src), [](uint32_t, uint32_t) {});
+    if ((int)(threadIdx.x & 63) == src) cnt = c;
   }
   float4 col = make_float4(0.f, 0.f, 0.f, 0.f);
   if (cnt > 0) {
@@ -218,6 +233,7 @@ __global__ __launch_bounds__(256) void k_preprocess(ViewTable vt, const float *_
     sh_colour_raw(vt.sh_degree, n, g, sh_dc, sh_rest, Y, raw);
     col = make_float4(fmaxf(raw[0], 0.f), fmaxf(raw[1], 0.f), fmaxf(raw[2], 0.f), 0.f);
   }
+  if (!in) return;
   const bool vis = cnt > 0;
   rec_a[e] = vis ? make_float4(s.u, s.v, s.o, s.pz) : make_float4(0.f, 0.f, 0.f, 0.f);
   rec_b[e] = vis ? make_float4(s.a, s.b, s.c, s.kappa2) : make_float4(0.f, 0.f, 0.f, 0.f);
@@ -249,6 +265,7 @@ __device__ __forceinline__ float block_sum_det(float v, float *lds) {
   return s;  // valid in thread 0
 }
 
+template <int DEG>
 __global__ __launch_bounds__(256) void k_preprocess_bwd(ViewTable vt, const float *__restrict__ mean,
                                                         const float *__restrict__ scale,
                                                         const float *__restrict__ rot,
@@ -262,8 +279,8 @@ __global__ __launch_bounds__(256) void k_preprocess_bwd(ViewTable vt, const floa
   const int64_t n = vt.n;
   const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const bool in = g < n;
-  const int deg = vt.sh_degree;
-  const int K = (deg + 1) * (deg + 1);
+  constexpr int deg = DEG;
+  constexpr int K = (DEG + 1) * (DEG + 1);
   float mx = 0, my = 0, mz = 0, sx = 1, sy = 1, sz = 1, qw = 1, qx = 0, qy = 0, qz = 0, o = 0;
   if (in) {
     mx = mean[g]; my = mean[n + g]; mz = mean[2 * n + g];
@@ -273,9 +290,9 @@ __global__ __launch_bounds__(256) void k_preprocess_bwd(ViewTable vt, const floa
   }
   float acc_m[3] = {0, 0, 0}, acc_s[3] = {0, 0, 0}, acc_q[4] = {0, 0, 0, 0}, acc_o = 0;
   float acc_dc[3] = {0, 0, 0};
-  float acc_rest[45];
+  float acc_rest[3 * (K - 1) + 1];
 #pragma unroll
-  for (int i = 0; i < 45; ++i) acc_rest[i] = 0.f;
+  for (int i = 0; i < 3 * (K - 1) + 1; ++i) acc_rest[i] = 0.f;
   bool any_view = false;
 
   for (int vi = 0; vi < vt.n_views; ++vi) {
@@ -410,7 +427,7 @@ __global__ __launch_bounds__(256) void k_preprocess_bwd(ViewTable vt, const floa
 #pragma unroll
       for (int ch = 0; ch < 3; ++ch) acc_dc[ch] += gr[ch] * Y[0];
       float gdir[3] = {0.f, 0.f, 0.f};
-      if (deg >= 1) {
+      if constexpr (DEG >= 1) {
         const float X = dir[0], Yy = dir[1], Z = dir[2];
         // d Y_k / d(x, y, z) for k >= 1, as polynomials in the unnormalised direction
         float dY[15][3];
@@ -418,14 +435,14 @@ __global__ __launch_bounds__(256) void k_preprocess_bwd(ViewTable vt, const floa
         dY[0][0] = 0; dY[0][1] = -Kc::c1; dY[0][2] = 0;
         dY[1][0] = 0; dY[1][1] = 0; dY[1][2] = Kc::c1;
         dY[2][0] = -Kc::c1; dY[2][1] = 0; dY[2][2] = 0;
-        if (deg >= 2) {
+        if constexpr (DEG >= 2) {
           dY[3][0] = Kc::c2a * Yy; dY[3][1] = Kc::c2a * X; dY[3][2] = 0;
           dY[4][0] = 0; dY[4][1] = -Kc::c2a * Z; dY[4][2] = -Kc::c2a * Yy;
           dY[5][0] = -2.f * Kc::c2b * X; dY[5][1] = -2.f * Kc::c2b * Yy; dY[5][2] = 4.f * Kc::c2b * Z;
           dY[6][0] = -Kc::c2a * Z; dY[6][1] = 0; dY[6][2] = -Kc::c2a * X;
           dY[7][0] = 2.f * Kc::c2c * X; dY[7][1] = -2.f * Kc::c2c * Yy; dY[7][2] = 0;
         }
-        if (deg >= 3) {
+        if constexpr (DEG >= 3) {
           const float xx = X * X, yy = Yy * Yy, zz = Z * Z;
           dY[8][0] = -6.f * Kc::c3a * X * Yy; dY[8][1] = -3.f * Kc::c3a * (xx - yy); dY[8][2] = 0;
           dY[9][0] = Kc::c3b * Yy * Z; dY[9][1] = Kc::c3b * X * Z; dY[9][2] = Kc::c3b * X * Yy;
@@ -438,6 +455,7 @@ __global__ __launch_bounds__(256) void k_preprocess_bwd(ViewTable vt, const floa
           dY[13][0] = 2.f * Kc::c3e * X * Z; dY[13][1] = -2.f * Kc::c3e * Yy * Z; dY[13][2] = Kc::c3e * (xx - yy);
           dY[14][0] = -3.f * Kc::c3a * (xx - yy); dY[14][1] = 6.f * Kc::c3a * X * Yy; dY[14][2] = 0;
         }
+#pragma unroll
         for (int k = 1; k < K; ++k) {
 #pragma unroll
           for (int ch = 0; ch < 3; ++ch) {
@@ -494,6 +512,7 @@ __global__ __launch_bounds__(256) void k_preprocess_bwd(ViewTable vt, const floa
   if (out.sh_dc)
     for (int i = 0; i < 3; ++i) out.sh_dc[i * n + g] += acc_dc[i];
   if (out.sh_rest)
+#pragma unroll
     for (int i = 0; i < 3 * (K - 1); ++i) out.sh_rest[(int64_t)i * n + g] += acc_rest[i];
 }
 
@@ -538,8 +557,20 @@ hipError_t launch_preprocess_bwd(const ViewTable &vt, const gs_gaussians &g, con
   if (vt.n == 0) return hipSuccess;
   const int64_t nb = preprocess_bwd_blocks(vt.n);
   ParamGradOut po{out.mean, out.scale, out.rot, out.opacity, out.sh_dc, out.sh_rest};
-  hipLaunchKernelGGL(k_preprocess_bwd, dim3((unsigned)nb), dim3(256), 0, st, vt, g.mean, g.scale, g.rot,
-                     g.opacity, g.sh_dc, g.sh_rest, p.n_tiles, g2, po, pose_partial);
+  switch (vt.sh_degree) {
+#define GS_PRE_BWD(D)                                                                                          \
+  case D:                                                                                                      \
+    hipLaunchKernelGGL(k_preprocess_bwd<D>, dim3((unsigned)nb), dim3(256), 0, st, vt, g.mean, g.scale, g.rot,  \
+                       g.opacity, g.sh_dc, g.sh_rest, p.n_tiles, g2, po, pose_partial);                        \
+    break;
+    GS_PRE_BWD(0)
+    GS_PRE_BWD(1)
+    GS_PRE_BWD(2)
+    GS_PRE_BWD(3)
+#undef GS_PRE_BWD
+    default:
+      return hipErrorInvalidValue;
+  }
   hipError_t err = hipGetLastError();
   if (err != hipSuccess) return err;
   PosePtrs pp;

@@ -123,6 +123,7 @@ class Frame:
     t_final: torch.Tensor
     last: torch.Tensor
     n_contrib: torch.Tensor | None = None
+    state: torch.Tensor | None = None   # chunk work list + per-chunk backward state (uint8)
 
     @staticmethod
     def empty(h, w, device, count: bool = False) -> "Frame":
@@ -130,9 +131,14 @@ class Frame:
         i = lambda: torch.empty(h, w, dtype=torch.int32, device=device)
         return Frame(f(3, h, w), f(h, w), f(h, w), f(h, w), i(), i() if count else None)
 
+    def ensure_state(self, nbytes: int) -> None:
+        if self.state is None or self.state.numel() < nbytes:
+            self.state = torch.empty(nbytes, dtype=torch.uint8, device=self.color.device)
+
     def struct(self) -> N.Image:
+        st = self.state
         return N.Image(_p(self.color), _p(self.depth), _p(self.alpha), _p(self.t_final), _p(self.last),
-                       _p(self.n_contrib))
+                       _p(self.n_contrib), _p(st), st.numel() if st is not None else 0)
 
 
 @dataclasses.dataclass
@@ -189,10 +195,15 @@ def bin_sort_fit(spl: Splats, n: int, cs: N.Camera, tile: int, device, capacity:
         cap = int(math.ceil(need * 1.25))
 
 
+def state_bytes(bins: TileBins, cs: N.Camera, blend_depth: int) -> int:
+    return N.lib().gs_image_state_bytes(bins.capacity, tiles_of(cs, bins.tile), bins.tile, bins.tile, blend_depth)
+
+
 def render_fwd(spl: Splats, n: int, bins: TileBins, cs: N.Camera, blend_depth: int, device,
                lidar: LidarHits | None = None, lidar_loss: torch.Tensor | None = None,
                out: Frame | None = None) -> Frame:
     out = out or Frame.empty(cs.h, cs.w, device)
+    out.ensure_state(state_bytes(bins, cs, blend_depth))
     ls = lidar.struct(lidar_loss) if lidar is not None and lidar.m > 0 else None
     N.check(N.lib().gs_render_fwd(C.byref(spl.struct()), n, C.byref(bins.struct()), C.byref(cs), blend_depth,
                                   C.byref(ls) if ls is not None else None, C.byref(out.struct()), _stream()),
