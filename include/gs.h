@@ -72,7 +72,8 @@ typedef struct gs_gaussians {
  *   rec_a [n][4] = (u, v, o, d): projected centre mu', opacity, camera-frame depth;
  *   rec_b [n][4] = (a, b, c, kappa^2): conic Sigma'^-1 = [[a, b], [b, c]] and the squared
  *                  footprint radius 2 ln(255 o);
- *   rgb   [n][4] = (r, g, b, 0): view-dependent colour max(0, SH . Y(dir) + 0.5);
+ *   rgb   [n][4] = (r, g, b, m): view-dependent colour max(0, SH . Y(dir) + 0.5); the bits of
+ *                  m (a float holding an integer bit pattern) mark the channels not clamped;
  *   rect  [n][4] int16 inclusive tile rectangle (tx0, ty0, tx1, ty1), -1 when n_tiles = 0;
  *   n_tiles [n]  number of tiles kept after the alpha-max cull;
  *   dkey  [n]    sort key: IEEE bits of d, or 0xFFFFFFFF when n_tiles = 0. */

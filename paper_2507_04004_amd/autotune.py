@@ -31,6 +31,9 @@ def _time_candidate(gm, cams, tile, bd, backward, capacity, reps, warmup, device
     try:
         slots = [ViewSlot.make(c, device, backward=backward, target=targets[i] if targets else None)
                  for i, c in enumerate(cams)]
+        if backward and not targets:
+            for s, c in zip(slots, cams):  # a fixed upstream gradient stands in for the loss
+                s.dL_dC = torch.full((3, c.h, c.w), 1.0 / (3 * c.w * c.h), device=device)
         grads = R.ParamGrads.zeros(gm) if backward else None
         run = lambda: plan.run(gm, slots, fwd=True, bwd=backward, grads=grads, graph=True)
         run()

@@ -151,6 +151,41 @@ __device__ __forceinline__ void write_pixel(const ViewImg &im, const ViewCam &ca
   if (im.n_contrib) im.n_contrib[pi] = nc;
 }
 
+// Front-to-back over cnt staged splats, continuing the state (T, sums, last, count). A splat
+// with alpha < 1/255 is skipped; the walk stops before a splat that would take T below 1e-4
+// (stopped is then set). Written with selects instead of branches: a skipped splat adds an
+// exact zero, so the sums equal those of the branching walk bit for bit. `done` lanes (or
+// stopped ones) carry their state unchanged; the wavefront leaves once all its lanes stop.
+__device__ __forceinline__ void composite_run(const float4 *s_a, const float4 *s_b, const float4 *s_c, int cnt,
+                                              float px, float py, int pos0, float &T, float &C0, float &C1,
+                                              float &C2, float &D, float &O, int32_t &last, int32_t &nc,
+                                              bool &stopped) {
+  for (int j0 = 0; j0 < cnt; j0 += 8) {
+    if (__all(stopped)) break;
+    const int jn = min(cnt, j0 + 8);
+#pragma unroll 8
+    for (int j = j0; j < jn; ++j) {
+      const float4 A = s_a[j], B = s_b[j], Cc = s_c[j];
+      const float power = splat_power(B.x, B.y, B.z, px - A.x, py - A.y);
+      const float alpha = fminf(kAlphaMax, splat_alpha_raw(A.z, power));
+      const float Tn = T * (1.f - alpha);
+      const bool blend = !stopped && alpha >= kAlphaMin;
+      const bool stop = blend && Tn < kTMin;
+      const bool take = blend && !stop;
+      stopped = stopped || stop;
+      const float w = take ? alpha * T : 0.f;
+      C0 += w * Cc.x;
+      C1 += w * Cc.y;
+      C2 += w * Cc.z;
+      D += w * A.w;
+      O += w;
+      T = take ? Tn : T;
+      last = take ? pos0 + j : last;
+      nc += take ? 1 : 0;
+    }
+  }
+}
+
 // ---- forward pass 1: every chunk from transmittance 1 ------------------------------------
 template <int TW, int TH, int BD>
 __global__ __launch_bounds__(TW *TH) void k_blend_chunk(ViewTable vt, ImgTable it, const float4 *__restrict__ rec_a,
@@ -177,30 +212,9 @@ __global__ __launch_bounds__(TW *TH) void k_blend_chunk(ViewTable vt, ImgTable i
 
   float T = 1.f, C0 = 0.f, C1 = 0.f, C2 = 0.f, D = 0.f, O = 0.f;
   int32_t last = -1, nc = 0;
-  bool cut = false;
-  if (px.inside) {
-    for (int j = 0; j < cnt; ++j) {
-      const float4 A = s_a[j], B = s_b[j];
-      const float power = splat_power(B.x, B.y, B.z, px.px - A.x, px.py - A.y);
-      const float alpha = fminf(kAlphaMax, splat_alpha_raw(A.z, power));
-      if (alpha < kAlphaMin) continue;
-      const float Tn = T * (1.f - alpha);
-      if (Tn < kTMin) {
-        cut = true;
-        break;
-      }
-      const float w = alpha * T;
-      const float4 Cc = s_c[j];
-      C0 += w * Cc.x;
-      C1 += w * Cc.y;
-      C2 += w * Cc.z;
-      D += w * A.w;
-      O += w;
-      T = Tn;
-      last = j;
-      ++nc;
-    }
-  }
+  bool cut = !px.inside;
+  composite_run(s_a, s_b, s_c, cnt, px.px, px.py, 0, T, C0, C1, C2, D, O, last, nc, cut);
+  cut = cut && px.inside;
   if (!px.inside) return;
   if (K == 1) {
     write_pixel(it.v[px.vi], vt.v[px.vi], px.pi, px.npx, C0, C1, C2, D, O, T, last, nc);
@@ -313,24 +327,8 @@ __global__ __launch_bounds__(TW *TH) void k_blend_fix(ViewTable vt, ImgTable it,
   float T = r.t, O = r.o;
   int32_t last = (int32_t)(r.info & 0x3FFFFFFFu) - 1, nc = __float_as_int(r.pad);
   float a0 = 0.f, a1 = 0.f, a2 = 0.f, ad = 0.f;
-  for (int j = 0; j < cnt; ++j) {
-    const float4 A = s_a[j], B = s_b[j];
-    const float power = splat_power(B.x, B.y, B.z, px.px - A.x, px.py - A.y);
-    const float alpha = fminf(kAlphaMax, splat_alpha_raw(A.z, power));
-    if (alpha < kAlphaMin) continue;
-    const float Tn = T * (1.f - alpha);
-    if (Tn < kTMin) break;
-    const float w = alpha * T;
-    const float4 Cc = s_c[j];
-    a0 += w * Cc.x;
-    a1 += w * Cc.y;
-    a2 += w * Cc.z;
-    ad += w * A.w;
-    O += w;
-    T = Tn;
-    last = (int32_t)(c * BD) + j;
-    ++nc;
-  }
+  bool stopped = false;
+  composite_run(s_a, s_b, s_c, cnt, px.px, px.py, (int)(c * BD), T, a0, a1, a2, ad, O, last, nc, stopped);
   write_pixel(it.v[px.vi], vt.v[px.vi], px.pi, px.npx, r.c0 + a0, r.c1 + a1, r.c2 + a2, r.d + ad, O, T, last, nc);
   ChunkRec w;
   w.c0 = a0; w.c1 = a1; w.c2 = a2; w.d = ad; w.o = 0.f; w.t = T; w.info = 0u; w.pad = 0.f;

@@ -231,7 +231,8 @@ __global__ __launch_bounds__(256) void k_preprocess(ViewTable vt, const float *_
     sh_eval(vt.sh_degree, dir[0], dir[1], dir[2], Y);
     float raw[3];
     sh_colour_raw(vt.sh_degree, n, g, sh_dc, sh_rest, Y, raw);
-    col = make_float4(fmaxf(raw[0], 0.f), fmaxf(raw[1], 0.f), fmaxf(raw[2], 0.f), 0.f);
+    const uint32_t on = (raw[0] > 0.f ? 1u : 0u) | (raw[1] > 0.f ? 2u : 0u) | (raw[2] > 0.f ? 4u : 0u);
+    col = make_float4(fmaxf(raw[0], 0.f), fmaxf(raw[1], 0.f), fmaxf(raw[2], 0.f), __uint_as_float(on));
   }
   if (!in) return;
   const bool vis = cnt > 0;
@@ -265,13 +266,63 @@ __device__ __forceinline__ float block_sum_det(float v, float *lds) {
   return s;  // valid in thread 0
 }
 
-template <int DEG>
+// One real SH basis function Y_k (1 <= k <= 15) and its gradient as a polynomial of the
+// (unnormalised) direction; k is uniform across the wavefront, so the switch is a scalar branch.
+__device__ __forceinline__ void sh_term(int k, float x, float y, float z, float &yk, float &dx, float &dy, float &dz) {
+  using Kc = SHConst;
+  const float xx = x * x, yy = y * y, zz = z * z;
+  switch (k) {
+    case 1: yk = -Kc::c1 * y; dx = 0.f; dy = -Kc::c1; dz = 0.f; break;
+    case 2: yk = Kc::c1 * z; dx = 0.f; dy = 0.f; dz = Kc::c1; break;
+    case 3: yk = -Kc::c1 * x; dx = -Kc::c1; dy = 0.f; dz = 0.f; break;
+    case 4: yk = Kc::c2a * (x * y); dx = Kc::c2a * y; dy = Kc::c2a * x; dz = 0.f; break;
+    case 5: yk = -Kc::c2a * (y * z); dx = 0.f; dy = -Kc::c2a * z; dz = -Kc::c2a * y; break;
+    case 6:
+      yk = Kc::c2b * (2.0f * zz - xx - yy);
+      dx = -2.f * Kc::c2b * x; dy = -2.f * Kc::c2b * y; dz = 4.f * Kc::c2b * z;
+      break;
+    case 7: yk = -Kc::c2a * (x * z); dx = -Kc::c2a * z; dy = 0.f; dz = -Kc::c2a * x; break;
+    case 8: yk = Kc::c2c * (xx - yy); dx = 2.f * Kc::c2c * x; dy = -2.f * Kc::c2c * y; dz = 0.f; break;
+    case 9:
+      yk = -Kc::c3a * y * (3.0f * xx - yy);
+      dx = -6.f * Kc::c3a * x * y; dy = -3.f * Kc::c3a * (xx - yy); dz = 0.f;
+      break;
+    case 10:
+      yk = Kc::c3b * (x * y * z);
+      dx = Kc::c3b * y * z; dy = Kc::c3b * x * z; dz = Kc::c3b * x * y;
+      break;
+    case 11:
+      yk = -Kc::c3c * y * (4.0f * zz - xx - yy);
+      dx = 2.f * Kc::c3c * x * y; dy = -Kc::c3c * (4.f * zz - xx - 3.f * yy); dz = -8.f * Kc::c3c * y * z;
+      break;
+    case 12:
+      yk = Kc::c3d * z * (2.0f * zz - 3.0f * xx - 3.0f * yy);
+      dx = -6.f * Kc::c3d * x * z; dy = -6.f * Kc::c3d * y * z; dz = Kc::c3d * (6.f * zz - 3.f * xx - 3.f * yy);
+      break;
+    case 13:
+      yk = -Kc::c3c * x * (4.0f * zz - xx - yy);
+      dx = -Kc::c3c * (4.f * zz - 3.f * xx - yy); dy = 2.f * Kc::c3c * x * y; dz = -8.f * Kc::c3c * x * z;
+      break;
+    case 14:
+      yk = Kc::c3e * z * (xx - yy);
+      dx = 2.f * Kc::c3e * x * z; dy = -2.f * Kc::c3e * y * z; dz = Kc::c3e * (xx - yy);
+      break;
+    default:
+      yk = -Kc::c3a * x * (xx - 3.0f * yy);
+      dx = -3.f * Kc::c3a * (xx - yy); dy = 6.f * Kc::c3a * x * y; dz = 0.f;
+      break;
+  }
+}
+
+// SINGLE: one view, so SH gradients go straight to memory instead of per-view accumulators.
+template <int DEG, bool SINGLE>
 __global__ __launch_bounds__(256) void k_preprocess_bwd(ViewTable vt, const float *__restrict__ mean,
                                                         const float *__restrict__ scale,
                                                         const float *__restrict__ rot,
                                                         const float *__restrict__ opacity,
                                                         const float *__restrict__ sh_dc,
                                                         const float *__restrict__ sh_rest,
+                                                        const float4 *__restrict__ rgb,
                                                         const uint32_t *__restrict__ n_tiles,
                                                         const float *__restrict__ g2, ParamGradOut out,
                                                         float *__restrict__ pose_partial /*[grid][V][6]*/) {
@@ -290,9 +341,9 @@ __global__ __launch_bounds__(256) void k_preprocess_bwd(ViewTable vt, const floa
   }
   float acc_m[3] = {0, 0, 0}, acc_s[3] = {0, 0, 0}, acc_q[4] = {0, 0, 0, 0}, acc_o = 0;
   float acc_dc[3] = {0, 0, 0};
-  float acc_rest[3 * (K - 1) + 1];
+  float acc_rest[SINGLE ? 1 : 3 * (K - 1) + 1];
 #pragma unroll
-  for (int i = 0; i < 3 * (K - 1) + 1; ++i) acc_rest[i] = 0.f;
+  for (int i = 0; i < (SINGLE ? 1 : 3 * (K - 1) + 1); ++i) acc_rest[i] = 0.f;
   bool any_view = false;
 
   for (int vi = 0; vi < vt.n_views; ++vi) {
@@ -313,6 +364,47 @@ __global__ __launch_bounds__(256) void k_preprocess_bwd(ViewTable vt, const floa
     }
     if (live) {
       any_view = true;
+      // colour first (its live values do not overlap the geometry's): SH coefficients and the
+      // view direction. The forward recorded which channels were clamped at zero.
+      float dir[3], dist;
+      view_dir(cam, mx, my, mz, dir, dist);
+      float Y[16];
+      sh_eval(deg, dir[0], dir[1], dir[2], Y);
+      const uint32_t on = __float_as_uint(rgb[e].w);
+      float gr[3];
+#pragma unroll
+      for (int ch = 0; ch < 3; ++ch) gr[ch] = ((on >> ch) & 1u) ? G[6 + ch] : 0.f;
+#pragma unroll
+      for (int ch = 0; ch < 3; ++ch) acc_dc[ch] += gr[ch] * Y[0];
+      // view-direction gradient: sum_k (sum_ch dL/draw_ch SH_{k,ch}) grad Y_k. One SH term per
+      // iteration (not unrolled), so the coefficient loads stay in flight one term at a time.
+      float gdir[3] = {0.f, 0.f, 0.f};
+      if constexpr (DEG >= 1) {
+        const float gmax = fmaxf(fabsf(gr[0]), fmaxf(fabsf(gr[1]), fabsf(gr[2])));
+#pragma unroll 1
+        for (int k = 1; k < K; ++k) {
+          float yk, d0, d1, d2;
+          sh_term(k, dir[0], dir[1], dir[2], yk, d0, d1, d2);
+          float sk = 0.f;
+#pragma unroll
+          for (int ch = 0; ch < 3; ++ch) {
+            const int64_t plane = (int64_t)(3 * (k - 1) + ch) * n + g;
+            sk += gr[ch] * sh_rest[plane];
+            if constexpr (SINGLE) {
+              if (out.sh_rest && gmax != 0.f) out.sh_rest[plane] += gr[ch] * yk;
+            } else {
+              acc_rest[3 * (k - 1) + ch] += gr[ch] * yk;
+            }
+          }
+          gdir[0] += sk * d0;
+          gdir[1] += sk * d1;
+          gdir[2] += sk * d2;
+        }
+      }
+      const float dd = gdir[0] * dir[0] + gdir[1] * dir[1] + gdir[2] * dir[2];
+      const float idist = 1.0f / dist;
+      const float gdf[3] = {(gdir[0] - dd * dir[0]) * idist, (gdir[1] - dd * dir[1]) * idist,
+                            (gdir[2] - dd * dir[2]) * idist};
       Splat s;
       splat_decide(cam, mx, my, mz, sx, sy, sz, qw, qx, qy, qz, o, s);
       const float gu = G[0], gv = G[1], ga = G[2], gb = G[3], gc = G[4], go = G[5];
@@ -414,64 +506,6 @@ __global__ __launch_bounds__(256) void k_preprocess_bwd(ViewTable vt, const floa
       acc_q[2] += (gy - dotq * y) * s.inv_q;
       acc_q[3] += (gz - dotq * z) * s.inv_q;
       acc_o += go;
-      // colour: SH coefficients and the view direction
-      float dir[3], dist;
-      view_dir(cam, mx, my, mz, dir, dist);
-      float Y[16];
-      sh_eval(deg, dir[0], dir[1], dir[2], Y);
-      float raw[3];
-      sh_colour_raw(deg, n, g, sh_dc, sh_rest, Y, raw);
-      float gr[3];
-#pragma unroll
-      for (int ch = 0; ch < 3; ++ch) gr[ch] = raw[ch] > 0.f ? G[6 + ch] : 0.f;
-#pragma unroll
-      for (int ch = 0; ch < 3; ++ch) acc_dc[ch] += gr[ch] * Y[0];
-      float gdir[3] = {0.f, 0.f, 0.f};
-      if constexpr (DEG >= 1) {
-        const float X = dir[0], Yy = dir[1], Z = dir[2];
-        // d Y_k / d(x, y, z) for k >= 1, as polynomials in the unnormalised direction
-        float dY[15][3];
-        using Kc = SHConst;
-        dY[0][0] = 0; dY[0][1] = -Kc::c1; dY[0][2] = 0;
-        dY[1][0] = 0; dY[1][1] = 0; dY[1][2] = Kc::c1;
-        dY[2][0] = -Kc::c1; dY[2][1] = 0; dY[2][2] = 0;
-        if constexpr (DEG >= 2) {
-          dY[3][0] = Kc::c2a * Yy; dY[3][1] = Kc::c2a * X; dY[3][2] = 0;
-          dY[4][0] = 0; dY[4][1] = -Kc::c2a * Z; dY[4][2] = -Kc::c2a * Yy;
-          dY[5][0] = -2.f * Kc::c2b * X; dY[5][1] = -2.f * Kc::c2b * Yy; dY[5][2] = 4.f * Kc::c2b * Z;
-          dY[6][0] = -Kc::c2a * Z; dY[6][1] = 0; dY[6][2] = -Kc::c2a * X;
-          dY[7][0] = 2.f * Kc::c2c * X; dY[7][1] = -2.f * Kc::c2c * Yy; dY[7][2] = 0;
-        }
-        if constexpr (DEG >= 3) {
-          const float xx = X * X, yy = Yy * Yy, zz = Z * Z;
-          dY[8][0] = -6.f * Kc::c3a * X * Yy; dY[8][1] = -3.f * Kc::c3a * (xx - yy); dY[8][2] = 0;
-          dY[9][0] = Kc::c3b * Yy * Z; dY[9][1] = Kc::c3b * X * Z; dY[9][2] = Kc::c3b * X * Yy;
-          dY[10][0] = 2.f * Kc::c3c * X * Yy; dY[10][1] = -Kc::c3c * (4.f * zz - xx - 3.f * yy);
-          dY[10][2] = -8.f * Kc::c3c * Yy * Z;
-          dY[11][0] = -6.f * Kc::c3d * X * Z; dY[11][1] = -6.f * Kc::c3d * Yy * Z;
-          dY[11][2] = Kc::c3d * (6.f * zz - 3.f * xx - 3.f * yy);
-          dY[12][0] = -Kc::c3c * (4.f * zz - 3.f * xx - yy); dY[12][1] = 2.f * Kc::c3c * X * Yy;
-          dY[12][2] = -8.f * Kc::c3c * X * Z;
-          dY[13][0] = 2.f * Kc::c3e * X * Z; dY[13][1] = -2.f * Kc::c3e * Yy * Z; dY[13][2] = Kc::c3e * (xx - yy);
-          dY[14][0] = -3.f * Kc::c3a * (xx - yy); dY[14][1] = 6.f * Kc::c3a * X * Yy; dY[14][2] = 0;
-        }
-#pragma unroll
-        for (int k = 1; k < K; ++k) {
-#pragma unroll
-          for (int ch = 0; ch < 3; ++ch) {
-            const float coef = sh_rest[(int64_t)(3 * (k - 1) + ch) * n + g];
-            acc_rest[3 * (k - 1) + ch] += gr[ch] * Y[k];
-            const float gk = gr[ch] * coef;
-            gdir[0] += gk * dY[k - 1][0];
-            gdir[1] += gk * dY[k - 1][1];
-            gdir[2] += gk * dY[k - 1][2];
-          }
-        }
-      }
-      const float dd = gdir[0] * dir[0] + gdir[1] * dir[1] + gdir[2] * dir[2];
-      const float idist = 1.0f / dist;
-      const float gdf[3] = {(gdir[0] - dd * dir[0]) * idist, (gdir[1] - dd * dir[1]) * idist,
-                            (gdir[2] - dd * dir[2]) * idist};
       // mean: R^T dL/dmu_hat + direction path
       acc_m[0] += R[0] * gm0 + R[3] * gm1 + R[6] * gm2 + gdf[0];
       acc_m[1] += R[1] * gm0 + R[4] * gm1 + R[7] * gm2 + gdf[1];
@@ -511,9 +545,11 @@ __global__ __launch_bounds__(256) void k_preprocess_bwd(ViewTable vt, const floa
   if (out.opacity) out.opacity[g] += acc_o;
   if (out.sh_dc)
     for (int i = 0; i < 3; ++i) out.sh_dc[i * n + g] += acc_dc[i];
-  if (out.sh_rest)
+  if constexpr (!SINGLE) {
+    if (out.sh_rest)
 #pragma unroll
-    for (int i = 0; i < 3 * (K - 1); ++i) out.sh_rest[(int64_t)i * n + g] += acc_rest[i];
+      for (int i = 0; i < 3 * (K - 1); ++i) out.sh_rest[(int64_t)i * n + g] += acc_rest[i];
+  }
 }
 
 }  // namespace gs
@@ -560,8 +596,14 @@ hipError_t launch_preprocess_bwd(const ViewTable &vt, const gs_gaussians &g, con
   switch (vt.sh_degree) {
 #define GS_PRE_BWD(D)                                                                                          \
   case D:                                                                                                      \
-    hipLaunchKernelGGL(k_preprocess_bwd<D>, dim3((unsigned)nb), dim3(256), 0, st, vt, g.mean, g.scale, g.rot,  \
-                       g.opacity, g.sh_dc, g.sh_rest, p.n_tiles, g2, po, pose_partial);                        \
+    if (vt.n_views == 1)                                                                                       \
+      hipLaunchKernelGGL((k_preprocess_bwd<D, true>), dim3((unsigned)nb), dim3(256), 0, st, vt, g.mean, g.scale,\
+                         g.rot, g.opacity, g.sh_dc, g.sh_rest, (const float4 *)p.rgb, p.n_tiles, g2, po,         \
+                         pose_partial);                \
+    else                                                                                                       \
+      hipLaunchKernelGGL((k_preprocess_bwd<D, false>), dim3((unsigned)nb), dim3(256), 0, st, vt, g.mean,       \
+                         g.scale, g.rot, g.opacity, g.sh_dc, g.sh_rest, (const float4 *)p.rgb, p.n_tiles, g2,  \
+                         po, pose_partial);                                                                      \
     break;
     GS_PRE_BWD(0)
     GS_PRE_BWD(1)
