@@ -17,7 +17,7 @@ import torch
 from . import raster as R
 from .batch import BatchPlan, ViewSlot
 
-DEFAULT_CANDIDATES = [(8, 64), (8, 128), (16, 64), (16, 128), (16, 256), (32, 128), (32, 256)]
+DEFAULT_CANDIDATES = [(8, 128), (8, 256), (16, 128), (16, 256), (32, 256)]
 
 
 def workload_key(gm: R.GaussianMap, cams, backward: bool) -> str:

@@ -102,26 +102,33 @@ __global__ __launch_bounds__(kItemThreads) void k_items_apply(const uint32_t *__
   }
 }
 
-// ---- shared per-pixel setup ----------------------------------------------------------------
-template <int TW, int TH>
-struct PixelCtx {
-  int vi, wx, wy;
-  bool inside;
-  float px, py;
-  int64_t pi, npx;
+// ---- per-lane pixels -------------------------------------------------------------------------
+// A workgroup of NT lanes covers a TW x TH tile; lane t owns the PPT = TW*TH/NT pixels
+// t, t + NT, t + 2 NT, ... (row-major in the tile), so one wavefront instruction touches a
+// 64-pixel block and a splat's per-pixel terms are summed inside the lane first.
+template <int TW, int TH, int NT>
+struct TileCtx {
+  static constexpr int PPT = TW * TH / NT;
+  int vi, tx, ty;
+  int64_t npx;
+  const ViewCam *cam;
 
-  __device__ __forceinline__ PixelCtx(const ViewTable &vt, uint32_t gt) {
+  __device__ __forceinline__ TileCtx(const ViewTable &vt, uint32_t gt) {
     vi = view_of_tile(vt, gt);
-    const ViewCam &cam = vt.v[vi];
-    const uint32_t lt = gt - cam.tile_base;
-    const int tx = (int)(lt % (uint32_t)cam.tiles_x), ty = (int)(lt / (uint32_t)cam.tiles_x);
-    wx = tx * TW + (int)threadIdx.x % TW;
-    wy = ty * TH + (int)threadIdx.x / TW;
-    inside = wx < cam.w && wy < cam.h;
-    px = (float)(cam.x0 + wx);
-    py = (float)(cam.y0 + wy);
-    npx = (int64_t)cam.w * cam.h;
-    pi = (int64_t)wy * cam.w + wx;
+    cam = &vt.v[vi];
+    const uint32_t lt = gt - cam->tile_base;
+    tx = (int)(lt % (uint32_t)cam->tiles_x);
+    ty = (int)(lt / (uint32_t)cam->tiles_x);
+    npx = (int64_t)cam->w * cam->h;
+  }
+  __device__ __forceinline__ int pidx(int k) const { return (int)threadIdx.x + k * NT; }
+  __device__ __forceinline__ void pixel(int k, bool &inside, float &px, float &py, int64_t &pi) const {
+    const int q = pidx(k);
+    const int wx = tx * TW + q % TW, wy = ty * TH + q / TW;
+    inside = wx < cam->w && wy < cam->h;
+    px = (float)(cam->x0 + wx);
+    py = (float)(cam->y0 + wy);
+    pi = (int64_t)wy * cam->w + wx;
   }
 };
 
@@ -151,58 +158,72 @@ __device__ __forceinline__ void write_pixel(const ViewImg &im, const ViewCam &ca
   if (im.n_contrib) im.n_contrib[pi] = nc;
 }
 
-// Front-to-back over cnt staged splats, continuing the state (T, sums, last, count). A splat
-// with alpha < 1/255 is skipped; the walk stops before a splat that would take T below 1e-4
-// (stopped is then set). Written with selects instead of branches: a skipped splat adds an
-// exact zero, so the sums equal those of the branching walk bit for bit. `done` lanes (or
-// stopped ones) carry their state unchanged; the wavefront leaves once all its lanes stop.
+// Compositing state of one pixel.
+struct PixState {
+  float T, C0, C1, C2, D, O;
+  int32_t last, nc;
+  bool stopped;
+};
+
+// Front-to-back over cnt staged splats for the lane's PPT pixels, continuing each pixel's
+// state. A splat with alpha < 1/255 is skipped; a pixel stops before a splat that would take
+// its T below 1e-4. Selects instead of branches: a skipped splat adds an exact zero, so the
+// sums equal those of a branching walk bit for bit. The wavefront leaves once all its
+// pixels have stopped.
+template <int PPT>
 __device__ __forceinline__ void composite_run(const float4 *s_a, const float4 *s_b, const float4 *s_c, int cnt,
-                                              float px, float py, int pos0, float &T, float &C0, float &C1,
-                                              float &C2, float &D, float &O, int32_t &last, int32_t &nc,
-                                              bool &stopped) {
+                                              const float (&px)[PPT], const float (&py)[PPT], int pos0,
+                                              PixState (&st)[PPT]) {
   for (int j0 = 0; j0 < cnt; j0 += 8) {
-    if (__all(stopped)) break;
+    bool all = true;
+#pragma unroll
+    for (int k = 0; k < PPT; ++k) all = all && st[k].stopped;
+    if (__all(all)) break;
     const int jn = min(cnt, j0 + 8);
-#pragma unroll 8
+#pragma unroll 4
     for (int j = j0; j < jn; ++j) {
       const float4 A = s_a[j], B = s_b[j], Cc = s_c[j];
-      const float power = splat_power(B.x, B.y, B.z, px - A.x, py - A.y);
-      const float alpha = fminf(kAlphaMax, splat_alpha_raw(A.z, power));
-      const float Tn = T * (1.f - alpha);
-      const bool blend = !stopped && alpha >= kAlphaMin;
-      const bool stop = blend && Tn < kTMin;
-      const bool take = blend && !stop;
-      stopped = stopped || stop;
-      const float w = take ? alpha * T : 0.f;
-      C0 += w * Cc.x;
-      C1 += w * Cc.y;
-      C2 += w * Cc.z;
-      D += w * A.w;
-      O += w;
-      T = take ? Tn : T;
-      last = take ? pos0 + j : last;
-      nc += take ? 1 : 0;
+#pragma unroll
+      for (int k = 0; k < PPT; ++k) {
+        PixState &p = st[k];
+        const float power = splat_power(B.x, B.y, B.z, px[k] - A.x, py[k] - A.y);
+        const float alpha = fminf(kAlphaMax, splat_alpha_raw(A.z, power));
+        const float Tn = p.T * (1.f - alpha);
+        const bool blend = !p.stopped && alpha >= kAlphaMin;
+        const bool stop = blend && Tn < kTMin;
+        const bool take = blend && !stop;
+        p.stopped = p.stopped || stop;
+        const float w = take ? alpha * p.T : 0.f;
+        p.C0 += w * Cc.x;
+        p.C1 += w * Cc.y;
+        p.C2 += w * Cc.z;
+        p.D += w * A.w;
+        p.O += w;
+        p.T = take ? Tn : p.T;
+        p.last = take ? pos0 + j : p.last;
+        p.nc += take ? 1 : 0;
+      }
     }
   }
 }
 
 // ---- forward pass 1: every chunk from transmittance 1 ------------------------------------
-template <int TW, int TH, int BD>
-__global__ __launch_bounds__(TW *TH) void k_blend_chunk(ViewTable vt, ImgTable it, const float4 *__restrict__ rec_a,
-                                                        const float4 *__restrict__ rec_b,
-                                                        const float4 *__restrict__ rgb,
-                                                        const uint32_t *__restrict__ vals,
-                                                        const uint32_t *__restrict__ range,
-                                                        const uint2 *__restrict__ items,
-                                                        const uint32_t *__restrict__ n_items,
-                                                        ChunkRec *__restrict__ chunk) {
-  constexpr int NT = TW * TH;
+template <int TW, int TH, int BD, int NT>
+__global__ __launch_bounds__(NT) void k_blend_chunk(ViewTable vt, ImgTable it, const float4 *__restrict__ rec_a,
+                                                    const float4 *__restrict__ rec_b, const float4 *__restrict__ rgb,
+                                                    const uint32_t *__restrict__ vals,
+                                                    const uint32_t *__restrict__ range,
+                                                    const uint2 *__restrict__ items,
+                                                    const uint32_t *__restrict__ n_items,
+                                                    ChunkRec *__restrict__ chunk) {
+  using Ctx = TileCtx<TW, TH, NT>;
+  constexpr int PPT = Ctx::PPT;
   __shared__ float4 s_a[BD], s_b[BD], s_c[BD];
   const uint32_t item = blockIdx.x;
   if (item >= *n_items) return;
   const uint2 tc = items[item];
   const uint32_t gt = tc.x, c = tc.y;
-  const PixelCtx<TW, TH> px(vt, gt);
+  const Ctx tile(vt, gt);
   const uint32_t s0 = range[2 * gt], e0 = range[2 * gt + 1];
   const uint32_t K = n_chunks(e0 - s0, BD);
   const uint32_t cs = s0 + c * BD;
@@ -210,20 +231,29 @@ __global__ __launch_bounds__(TW *TH) void k_blend_chunk(ViewTable vt, ImgTable i
   stage<BD, NT>(vals, cs, cnt, rec_a, rec_b, rgb, s_a, s_b, s_c, nullptr);
   __syncthreads();
 
-  float T = 1.f, C0 = 0.f, C1 = 0.f, C2 = 0.f, D = 0.f, O = 0.f;
-  int32_t last = -1, nc = 0;
-  bool cut = !px.inside;
-  composite_run(s_a, s_b, s_c, cnt, px.px, px.py, 0, T, C0, C1, C2, D, O, last, nc, cut);
-  cut = cut && px.inside;
-  if (!px.inside) return;
-  if (K == 1) {
-    write_pixel(it.v[px.vi], vt.v[px.vi], px.pi, px.npx, C0, C1, C2, D, O, T, last, nc);
-  } else {
-    ChunkRec r;
-    r.c0 = C0; r.c1 = C1; r.c2 = C2; r.d = D; r.o = O; r.t = T;
-    r.info = (uint32_t)(last + 1) | ((uint32_t)nc << 10) | ((uint32_t)cut << 20);
-    r.pad = 0.f;
-    chunk[(int64_t)item * NT + threadIdx.x] = r;
+  float px[PPT], py[PPT];
+  bool inside[PPT];
+  int64_t pi[PPT];
+  PixState st[PPT];
+#pragma unroll
+  for (int k = 0; k < PPT; ++k) {
+    tile.pixel(k, inside[k], px[k], py[k], pi[k]);
+    st[k] = PixState{1.f, 0.f, 0.f, 0.f, 0.f, 0.f, -1, 0, !inside[k]};
+  }
+  composite_run<PPT>(s_a, s_b, s_c, cnt, px, py, 0, st);
+#pragma unroll
+  for (int k = 0; k < PPT; ++k) {
+    if (!inside[k]) continue;
+    const PixState &p = st[k];
+    if (K == 1) {
+      write_pixel(it.v[tile.vi], *tile.cam, pi[k], tile.npx, p.C0, p.C1, p.C2, p.D, p.O, p.T, p.last, p.nc);
+    } else {
+      ChunkRec r;
+      r.c0 = p.C0; r.c1 = p.C1; r.c2 = p.C2; r.d = p.D; r.o = p.O; r.t = p.T;
+      r.info = (uint32_t)(p.last + 1) | ((uint32_t)p.nc << 10) | ((uint32_t)p.stopped << 20);
+      r.pad = 0.f;
+      chunk[(int64_t)item * (TW * TH) + tile.pidx(k)] = r;
+    }
   }
 }
 
@@ -236,76 +266,85 @@ constexpr uint32_t kPending = 1u << 31;
 constexpr uint32_t kAfter = 1u << 30;
 
 template <int TW, int TH, int BD>
-__global__ __launch_bounds__(TW *TH) void k_blend_scan(ViewTable vt, ImgTable it, const uint32_t *__restrict__ range,
-                                                       const uint32_t *__restrict__ item_base,
-                                                       ChunkRec *__restrict__ chunk) {
-  constexpr int NT = TW * TH;
+__global__ __launch_bounds__(TW * TH) void k_blend_scan(ViewTable vt, ImgTable it, const uint32_t *__restrict__ range,
+                                                   const uint32_t *__restrict__ item_base,
+                                                   ChunkRec *__restrict__ chunk) {
+  // one pixel per lane: the per-pixel chain over the chunks is serial, so spread it wide
+  using Ctx = TileCtx<TW, TH, TW * TH>;
+  constexpr int PPT = Ctx::PPT;
   const uint32_t gt = blockIdx.x;
   const uint32_t s0 = range[2 * gt], e0 = range[2 * gt + 1];
   const uint32_t K = n_chunks(e0 - s0, BD);
   if (K == 1) return;  // written by k_blend_chunk
-  const PixelCtx<TW, TH> px(vt, gt);
-  if (!px.inside) return;
-  const ViewCam &cam = vt.v[px.vi];
-  if (K == 0) {
-    write_pixel(it.v[px.vi], cam, px.pi, px.npx, 0.f, 0.f, 0.f, 0.f, 0.f, 1.f, -1, 0);
-    return;
-  }
-  ChunkRec *base = chunk + (int64_t)item_base[gt] * NT + threadIdx.x;
-  float T = 1.f, C0 = 0.f, C1 = 0.f, C2 = 0.f, D = 0.f, O = 0.f;
-  int32_t last = -1, nc = 0;
-  bool finished = false, pending = false;
-  ChunkRec nxt = base[0];
-  for (uint32_t k = 0; k < K; ++k) {
-    const ChunkRec r = nxt;
-    if (k + 1 < K) nxt = base[(int64_t)(k + 1) * NT];  // prefetch the next chunk's partial
-    ChunkRec w;
-    w.o = 0.f;
-    w.pad = 0.f;
-    if (finished || pending) {
-      w.c0 = w.c1 = w.c2 = w.d = 0.f;
-      w.t = T;
-      w.info = kAfter;
-    } else {
-      const int ll = (int)(r.info & 1023u) - 1;
-      const int ncl = (int)((r.info >> 10) & 1023u);
-      const bool cut = (r.info >> 20) & 1u;
-      const float Tafter = T * r.t;
-      if (!cut ? (Tafter >= kTMin) : (k == 0)) {
-        // the whole chunk blends (chunk 0 is exact from T = 1 even when it stops inside)
-        w.c0 = T * r.c0; w.c1 = T * r.c1; w.c2 = T * r.c2; w.d = T * r.d;
-        C0 += w.c0; C1 += w.c1; C2 += w.c2; D += w.d;
-        O += T * r.o;
-        if (ll >= 0) last = (int32_t)(k * BD) + ll;
-        nc += ncl;
-        T = Tafter;
-        w.t = T;
-        w.info = 0u;
-        finished = cut;
-      } else {
-        // the pixel stops inside this chunk: hand the incoming state to k_blend_fix
-        w.c0 = C0; w.c1 = C1; w.c2 = C2; w.d = D; w.o = O; w.t = T;
-        w.info = kPending | (uint32_t)(last + 1);
-        w.pad = __int_as_float(nc);
-        pending = true;
-      }
+  const Ctx tile(vt, gt);
+  const ViewImg &im = it.v[tile.vi];
+#pragma unroll 1
+  for (int k = 0; k < PPT; ++k) {
+    bool inside;
+    float pxf, pyf;
+    int64_t pi;
+    tile.pixel(k, inside, pxf, pyf, pi);
+    if (!inside) continue;
+    if (K == 0) {
+      write_pixel(im, *tile.cam, pi, tile.npx, 0.f, 0.f, 0.f, 0.f, 0.f, 1.f, -1, 0);
+      continue;
     }
-    base[(int64_t)k * NT] = w;
+    ChunkRec *base = chunk + (int64_t)item_base[gt] * (TW * TH) + tile.pidx(k);
+    float T = 1.f, C0 = 0.f, C1 = 0.f, C2 = 0.f, D = 0.f, O = 0.f;
+    int32_t last = -1, nc = 0;
+    bool finished = false, pending = false;
+    ChunkRec nxt = base[0];
+    for (uint32_t q = 0; q < K; ++q) {
+      const ChunkRec r = nxt;
+      if (q + 1 < K) nxt = base[(int64_t)(q + 1) * (TW * TH)];  // prefetch the next chunk's partial
+      ChunkRec w;
+      w.o = 0.f;
+      w.pad = 0.f;
+      if (finished || pending) {
+        w.c0 = w.c1 = w.c2 = w.d = 0.f;
+        w.t = T;
+        w.info = kAfter;
+      } else {
+        const int ll = (int)(r.info & 1023u) - 1;
+        const int ncl = (int)((r.info >> 10) & 1023u);
+        const bool cut = (r.info >> 20) & 1u;
+        const float Tafter = T * r.t;
+        if (!cut ? (Tafter >= kTMin) : (q == 0)) {
+          // the whole chunk blends (chunk 0 is exact from T = 1 even when it stops inside)
+          w.c0 = T * r.c0; w.c1 = T * r.c1; w.c2 = T * r.c2; w.d = T * r.d;
+          C0 += w.c0; C1 += w.c1; C2 += w.c2; D += w.d;
+          O += T * r.o;
+          if (ll >= 0) last = (int32_t)(q * BD) + ll;
+          nc += ncl;
+          T = Tafter;
+          w.t = T;
+          w.info = 0u;
+          finished = cut;
+        } else {
+          // the pixel stops inside this chunk: hand the incoming state to k_blend_fix
+          w.c0 = C0; w.c1 = C1; w.c2 = C2; w.d = D; w.o = O; w.t = T;
+          w.info = kPending | (uint32_t)(last + 1);
+          w.pad = __int_as_float(nc);
+          pending = true;
+        }
+      }
+      base[(int64_t)q * (TW * TH)] = w;
+    }
+    if (!pending) write_pixel(im, *tile.cam, pi, tile.npx, C0, C1, C2, D, O, T, last, nc);
   }
-  if (!pending) write_pixel(it.v[px.vi], cam, px.pi, px.npx, C0, C1, C2, D, O, T, last, nc);
 }
 
 // ---- forward pass 3: exact compositing of each pixel's stop chunk (chunk-parallel) -------
-template <int TW, int TH, int BD>
-__global__ __launch_bounds__(TW *TH) void k_blend_fix(ViewTable vt, ImgTable it, const float4 *__restrict__ rec_a,
-                                                      const float4 *__restrict__ rec_b,
-                                                      const float4 *__restrict__ rgb,
-                                                      const uint32_t *__restrict__ vals,
-                                                      const uint32_t *__restrict__ range,
-                                                      const uint2 *__restrict__ items,
-                                                      const uint32_t *__restrict__ n_items,
-                                                      ChunkRec *__restrict__ chunk) {
-  constexpr int NT = TW * TH;
+template <int TW, int TH, int BD, int NT>
+__global__ __launch_bounds__(NT) void k_blend_fix(ViewTable vt, ImgTable it, const float4 *__restrict__ rec_a,
+                                                  const float4 *__restrict__ rec_b, const float4 *__restrict__ rgb,
+                                                  const uint32_t *__restrict__ vals,
+                                                  const uint32_t *__restrict__ range,
+                                                  const uint2 *__restrict__ items,
+                                                  const uint32_t *__restrict__ n_items,
+                                                  ChunkRec *__restrict__ chunk) {
+  using Ctx = TileCtx<TW, TH, NT>;
+  constexpr int PPT = Ctx::PPT;
   __shared__ float4 s_a[BD], s_b[BD], s_c[BD];
   const uint32_t item = blockIdx.x;
   if (item >= *n_items) return;
@@ -313,65 +352,87 @@ __global__ __launch_bounds__(TW *TH) void k_blend_fix(ViewTable vt, ImgTable it,
   const uint32_t gt = tc.x, c = tc.y;
   const uint32_t s0 = range[2 * gt], e0 = range[2 * gt + 1];
   if (n_chunks(e0 - s0, BD) < 2) return;
-  const PixelCtx<TW, TH> px(vt, gt);
-  ChunkRec *slot = chunk + (int64_t)item * NT + threadIdx.x;
-  ChunkRec r{};
-  if (px.inside) r = *slot;
-  const bool pending = px.inside && (r.info & kPending);
-  if (__syncthreads_count(pending) == 0) return;
+  const Ctx tile(vt, gt);
+  float px[PPT], py[PPT];
+  bool inside[PPT], pending[PPT];
+  int64_t pi[PPT];
+  ChunkRec r[PPT];
+  PixState st[PPT];
+  bool any = false;
+#pragma unroll
+  for (int k = 0; k < PPT; ++k) {
+    tile.pixel(k, inside[k], px[k], py[k], pi[k]);
+    r[k] = ChunkRec{};
+    if (inside[k]) r[k] = chunk[(int64_t)item * (TW * TH) + tile.pidx(k)];
+    pending[k] = inside[k] && (r[k].info & kPending);
+    any = any || pending[k];
+    // composite the chunk's splats only (partial sums start at zero; O and the count carry on)
+    st[k] = PixState{r[k].t, 0.f, 0.f, 0.f, 0.f, r[k].o, (int32_t)(r[k].info & 0x3FFFFFFFu) - 1,
+                     __float_as_int(r[k].pad), !pending[k]};
+  }
+  if (__syncthreads_count(any) == 0) return;
   const uint32_t cs = s0 + c * BD;
   const int cnt = (int)min<uint32_t>(BD, e0 - cs);
   stage<BD, NT>(vals, cs, cnt, rec_a, rec_b, rgb, s_a, s_b, s_c, nullptr);
   __syncthreads();
-  if (!pending) return;
-  float T = r.t, O = r.o;
-  int32_t last = (int32_t)(r.info & 0x3FFFFFFFu) - 1, nc = __float_as_int(r.pad);
-  float a0 = 0.f, a1 = 0.f, a2 = 0.f, ad = 0.f;
-  bool stopped = false;
-  composite_run(s_a, s_b, s_c, cnt, px.px, px.py, (int)(c * BD), T, a0, a1, a2, ad, O, last, nc, stopped);
-  write_pixel(it.v[px.vi], vt.v[px.vi], px.pi, px.npx, r.c0 + a0, r.c1 + a1, r.c2 + a2, r.d + ad, O, T, last, nc);
-  ChunkRec w;
-  w.c0 = a0; w.c1 = a1; w.c2 = a2; w.d = ad; w.o = 0.f; w.t = T; w.info = 0u; w.pad = 0.f;
-  *slot = w;
+  composite_run<PPT>(s_a, s_b, s_c, cnt, px, py, (int)(c * BD), st);
+#pragma unroll
+  for (int k = 0; k < PPT; ++k) {
+    if (!pending[k]) continue;
+    const PixState &p = st[k];
+    write_pixel(it.v[tile.vi], *tile.cam, pi[k], tile.npx, r[k].c0 + p.C0, r[k].c1 + p.C1, r[k].c2 + p.C2,
+                r[k].d + p.D, p.O, p.T, p.last, p.nc);
+    ChunkRec w;
+    w.c0 = p.C0; w.c1 = p.C1; w.c2 = p.C2; w.d = p.D; w.o = 0.f; w.t = p.T; w.info = 0u; w.pad = 0.f;
+    chunk[(int64_t)item * (TW * TH) + tile.pidx(k)] = w;
+  }
 }
 
 // ---- forward pass 4: backward starting state per chunk (suffix sums, per tile) ------------
 // Colour / depth composited behind each chunk, normalised by the transmittance after it.
 template <int TW, int TH, int BD>
-__global__ __launch_bounds__(TW *TH) void k_blend_suffix(ViewTable vt, const uint32_t *__restrict__ range,
-                                                         const uint32_t *__restrict__ item_base,
-                                                         ChunkRec *__restrict__ chunk) {
-  constexpr int NT = TW * TH;
+__global__ __launch_bounds__(TW * TH) void k_blend_suffix(ViewTable vt, const uint32_t *__restrict__ range,
+                                                     const uint32_t *__restrict__ item_base,
+                                                     ChunkRec *__restrict__ chunk) {
+  using Ctx = TileCtx<TW, TH, TW * TH>;
+  constexpr int PPT = Ctx::PPT;
   const uint32_t gt = blockIdx.x;
   const uint32_t K = n_chunks(range[2 * gt + 1] - range[2 * gt], BD);
   if (K < 2) return;
-  const PixelCtx<TW, TH> px(vt, gt);
-  if (!px.inside) return;
-  ChunkRec *base = chunk + (int64_t)item_base[gt] * NT + threadIdx.x;
-  float b0 = 0.f, b1 = 0.f, b2 = 0.f, bd = 0.f;
-  ChunkRec nxt = base[(int64_t)(K - 1) * NT];
-  for (int k = (int)K - 1; k >= 0; --k) {
-    const ChunkRec r = nxt;
-    if (k > 0) nxt = base[(int64_t)(k - 1) * NT];
-    if (r.info & kAfter) continue;
-    const float inv = 1.f / r.t;
-    ChunkRec w;
-    w.c0 = b0 * inv; w.c1 = b1 * inv; w.c2 = b2 * inv; w.d = bd * inv; w.o = 0.f; w.t = r.t; w.info = 0u;
-    w.pad = 0.f;
-    base[(int64_t)k * NT] = w;
-    b0 += r.c0; b1 += r.c1; b2 += r.c2; bd += r.d;
+  const Ctx tile(vt, gt);
+#pragma unroll 1
+  for (int k = 0; k < PPT; ++k) {
+    bool inside;
+    float pxf, pyf;
+    int64_t pi;
+    tile.pixel(k, inside, pxf, pyf, pi);
+    if (!inside) continue;
+    ChunkRec *base = chunk + (int64_t)item_base[gt] * (TW * TH) + tile.pidx(k);
+    float b0 = 0.f, b1 = 0.f, b2 = 0.f, bd = 0.f;
+    ChunkRec nxt = base[(int64_t)(K - 1) * (TW * TH)];
+    for (int q = (int)K - 1; q >= 0; --q) {
+      const ChunkRec r = nxt;
+      if (q > 0) nxt = base[(int64_t)(q - 1) * (TW * TH)];
+      if (r.info & kAfter) continue;
+      const float inv = 1.f / r.t;
+      ChunkRec w;
+      w.c0 = b0 * inv; w.c1 = b1 * inv; w.c2 = b2 * inv; w.d = bd * inv; w.o = 0.f; w.t = r.t; w.info = 0u;
+      w.pad = 0.f;
+      base[(int64_t)q * (TW * TH)] = w;
+      b0 += r.c0; b1 += r.c1; b2 += r.c2; bd += r.d;
+    }
   }
 }
 
 // ---- backward: every chunk back to front ---------------------------------------------------
-// Sum over the wavefront of ten values; the lane q < 10 returns value q's total.
-// Transposed reduction: four row-local DPP exchanges each halve the number of values a lane
-// carries (8, 4, 2, 1 of 16), then two cross-row swaps finish one value per lane.
 template <int CTRL>
 __device__ __forceinline__ float dpp(float v) {
   return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), CTRL, 0xF, 0xF, false));
 }
 
+// Sum over the wavefront of ten values; afterwards lane l holds the total of value l & 15.
+// Transposed reduction: four row-local DPP exchanges each halve the number of values a lane
+// carries (8, 4, 2, 1 of 16), then two cross-row swaps finish one value per lane.
 __device__ __forceinline__ float wave_reduce10(const float (&g)[10], int lane) {
   // stage 1: partner lane i^15 within a 16-lane row (row_mirror); lanes < 8 keep values 0-7
   float v8[8];
@@ -406,33 +467,35 @@ __device__ __forceinline__ float wave_reduce10(const float (&g)[10], int lane) {
   const float keep = lo4 ? v2[0] : v2[1];
   const float send = lo4 ? v2[1] : v2[0];
   float v = keep + dpp<0xB1>(send);
-  // now lane l of each row holds the row sum of value idx(l) where idx = 8*!lo1 + 4*!lo2 + 2*!lo3 + !lo4
   // stages 5-6: add the four rows (permlane swaps between rows 0/1, 2/3, then halves)
   const auto s16 = __builtin_amdgcn_permlane16_swap(__float_as_uint(v), __float_as_uint(v), false, false);
   v = __uint_as_float(s16[0]) + __uint_as_float(s16[1]);
   const auto s32 = __builtin_amdgcn_permlane32_swap(__float_as_uint(v), __float_as_uint(v), false, false);
   v = __uint_as_float(s32[0]) + __uint_as_float(s32[1]);
-  return v;  // lane l holds the total of value index(l & 15)
+  return v;
 }
 
-// value index held by lane l after wave_reduce10 (mirror pairings flip the low bits)
-__device__ __forceinline__ int reduce10_index(int lane) {
-  const int r = lane & 15;
-  return ((r & 8) ? 8 : 0) + ((r & 4) ? 4 : 0) + ((r & 2) ? 2 : 0) + ((r & 1) ? 1 : 0);
-}
+// Backward state of one pixel.
+struct PixGrad {
+  float Tfin, gC0, gC1, gC2, gD, gOb;  // gOb = dL/dO - dL/dC . bg
+  float T, A0, A1, A2, AD;
+  int ll;
+  float px, py;
+};
 
-template <int TW, int TH, int BD>
-__global__ __launch_bounds__(TW *TH) void k_blend_bwd_chunk(ViewTable vt, ImgTable it, GradTable gtab,
-                                                            const float4 *__restrict__ rec_a,
-                                                            const float4 *__restrict__ rec_b,
-                                                            const float4 *__restrict__ rgb,
-                                                            const uint32_t *__restrict__ vals,
-                                                            const uint32_t *__restrict__ range,
-                                                            const uint2 *__restrict__ items,
-                                                            const uint32_t *__restrict__ n_items,
-                                                            const ChunkRec *__restrict__ chunk,
-                                                            float *__restrict__ g2 /*[E][12]*/) {
-  constexpr int NT = TW * TH;
+template <int TW, int TH, int BD, int NT>
+__global__ __launch_bounds__(NT) void k_blend_bwd_chunk(ViewTable vt, ImgTable it, GradTable gtab,
+                                                        const float4 *__restrict__ rec_a,
+                                                        const float4 *__restrict__ rec_b,
+                                                        const float4 *__restrict__ rgb,
+                                                        const uint32_t *__restrict__ vals,
+                                                        const uint32_t *__restrict__ range,
+                                                        const uint2 *__restrict__ items,
+                                                        const uint32_t *__restrict__ n_items,
+                                                        const ChunkRec *__restrict__ chunk,
+                                                        float *__restrict__ g2 /*[E][12]*/) {
+  using Ctx = TileCtx<TW, TH, NT>;
+  constexpr int PPT = Ctx::PPT;
   __shared__ float4 s_a[BD], s_b[BD], s_c[BD];
   __shared__ uint32_t s_e[BD];
   __shared__ int s_max;
@@ -440,92 +503,104 @@ __global__ __launch_bounds__(TW *TH) void k_blend_bwd_chunk(ViewTable vt, ImgTab
   if (item >= *n_items) return;
   const uint2 tc = items[item];
   const uint32_t gt = tc.x, c = tc.y;
-  const PixelCtx<TW, TH> px(vt, gt);
-  const ViewCam &cam = vt.v[px.vi];
+  const Ctx tile(vt, gt);
+  const ViewCam &cam = *tile.cam;
   const uint32_t s0 = range[2 * gt], e0 = range[2 * gt + 1];
   const uint32_t K = n_chunks(e0 - s0, BD);
   const uint32_t cs = s0 + c * BD;
   const int cnt = (int)min<uint32_t>(BD, e0 - cs);
-  const ViewImg &im = it.v[px.vi];
-  const ViewGrad &vg = gtab.v[px.vi];
+  const ViewImg &im = it.v[tile.vi];
+  const ViewGrad &vg = gtab.v[tile.vi];
 
-  float Tfin = 1.f, gC0 = 0.f, gC1 = 0.f, gC2 = 0.f, gD = 0.f, gO = 0.f;
-  int ll = -1;
-  float T = 1.f, A0 = 0.f, A1 = 0.f, A2 = 0.f, AD = 0.f;
-  if (px.inside) {
-    Tfin = im.t_final[px.pi];
-    ll = min(im.last[px.pi] - (int)(c * BD), cnt - 1);
-    gC0 = vg.gC[px.pi];
-    gC1 = vg.gC[px.npx + px.pi];
-    gC2 = vg.gC[2 * px.npx + px.pi];
-    if (vg.gD) gD = vg.gD[px.pi];
-    if (vg.gO) gO = vg.gO[px.pi];
-    if (K == 1) {
-      T = Tfin;
-    } else if (ll >= 0) {
-      const ChunkRec r = chunk[(int64_t)item * NT + threadIdx.x];
-      T = r.t;
-      A0 = r.c0; A1 = r.c1; A2 = r.c2; AD = r.d;
+  PixGrad pg[PPT];
+  int mymax = -1;
+  bool depth_any = false;
+#pragma unroll
+  for (int k = 0; k < PPT; ++k) {
+    PixGrad &p = pg[k];
+    bool inside;
+    int64_t pi;
+    tile.pixel(k, inside, p.px, p.py, pi);
+    p = PixGrad{1.f, 0.f, 0.f, 0.f, 0.f, 0.f, 1.f, 0.f, 0.f, 0.f, 0.f, -1, p.px, p.py};
+    if (inside) {
+      p.Tfin = im.t_final[pi];
+      p.ll = min(im.last[pi] - (int)(c * BD), cnt - 1);
+      p.gC0 = vg.gC[pi];
+      p.gC1 = vg.gC[tile.npx + pi];
+      p.gC2 = vg.gC[2 * tile.npx + pi];
+      if (vg.gD) p.gD = vg.gD[pi];
+      const float gO = vg.gO ? vg.gO[pi] : 0.f;
+      p.gOb = gO - (p.gC0 * cam.bg[0] + p.gC1 * cam.bg[1] + p.gC2 * cam.bg[2]);
+      if (K == 1) {
+        p.T = p.Tfin;
+      } else if (p.ll >= 0) {
+        const ChunkRec r = chunk[(int64_t)item * (TW * TH) + tile.pidx(k)];
+        p.T = r.t;
+        p.A0 = r.c0; p.A1 = r.c1; p.A2 = r.c2; p.AD = r.d;
+      }
     }
+    mymax = max(mymax, p.ll);
+    depth_any = depth_any || p.gD != 0.f;
   }
   if (threadIdx.x == 0) s_max = -1;
   __syncthreads();
-  if (ll >= 0) atomicMax(&s_max, ll);
+  if (mymax >= 0) atomicMax(&s_max, mymax);
   __syncthreads();
   const int maxll = s_max;
   if (maxll < 0) return;  // uniform: no pixel has a contributor in this chunk
   stage<BD, NT>(vals, cs, maxll + 1, rec_a, rec_b, rgb, s_a, s_b, s_c, s_e);
   __syncthreads();
 
-  const float gOb = gO - (gC0 * cam.bg[0] + gC1 * cam.bg[1] + gC2 * cam.bg[2]);
   const int lane = threadIdx.x & 63;
-  const int q = reduce10_index(lane);
-  const bool depth_live = __any(gD != 0.f);
+  const int q = lane & 15;
+  const bool depth_live = __any(depth_any);
   for (int j = maxll; j >= 0; --j) {
     float g[10];
 #pragma unroll
-    for (int k = 0; k < 10; ++k) g[k] = 0.f;
-    bool contrib = false;
-    if (j <= ll) {
-      const float4 A = s_a[j], B = s_b[j];
-      const float dx = px.px - A.x, dy = px.py - A.y;
+    for (int v = 0; v < 10; ++v) g[v] = 0.f;
+    bool contrib_any = false;
+    const float4 A = s_a[j], B = s_b[j], Cc = s_c[j];
+#pragma unroll
+    for (int k = 0; k < PPT; ++k) {
+      PixGrad &p = pg[k];
+      if (j > p.ll) continue;
+      const float dx = p.px - A.x, dy = p.py - A.y;
       const float power = splat_power(B.x, B.y, B.z, dx, dy);
       const float ex = __expf(power);
       const float ar = A.z * ex;  // the same two operations as splat_alpha_raw
       const float alpha = fminf(kAlphaMax, ar);
-      if (alpha >= kAlphaMin) {
-        contrib = true;
-        const float one_m = 1.f - alpha;
-        T = T / one_m;  // transmittance in front of this splat
-        const float w = alpha * T;
-        const float4 Cc = s_c[j];
-        g[6] = gC0 * w;
-        g[7] = gC1 * w;
-        g[8] = gC2 * w;
-        float dLda = gC0 * (Cc.x - A0) + gC1 * (Cc.y - A1) + gC2 * (Cc.z - A2);
-        A0 = alpha * Cc.x + one_m * A0;
-        A1 = alpha * Cc.y + one_m * A1;
-        A2 = alpha * Cc.z + one_m * A2;
-        if (depth_live) {
-          g[9] = gD * w;
-          dLda += gD * (A.w - AD);
-          AD = alpha * A.w + one_m * AD;
-        }
-        dLda = T * dLda + (Tfin / one_m) * gOb;
-        if (ar < kAlphaMax) {
-          g[5] = dLda * ex;
-          const float dp = dLda * ar;
-          g[0] = dp * (B.x * dx + B.y * dy);
-          g[1] = dp * (B.y * dx + B.z * dy);
-          g[2] = -0.5f * dp * dx * dx;
-          g[3] = -dp * dx * dy;
-          g[4] = -0.5f * dp * dy * dy;
-        }
+      if (alpha < kAlphaMin) continue;
+      contrib_any = true;
+      const float one_m = 1.f - alpha;
+      const float inv = __builtin_amdgcn_rcpf(one_m);  // 1 ulp; one_m >= 0.01
+      p.T = p.T * inv;  // transmittance in front of this splat
+      const float w = alpha * p.T;
+      g[6] += p.gC0 * w;
+      g[7] += p.gC1 * w;
+      g[8] += p.gC2 * w;
+      float dLda = p.gC0 * (Cc.x - p.A0) + p.gC1 * (Cc.y - p.A1) + p.gC2 * (Cc.z - p.A2);
+      p.A0 = alpha * Cc.x + one_m * p.A0;
+      p.A1 = alpha * Cc.y + one_m * p.A1;
+      p.A2 = alpha * Cc.z + one_m * p.A2;
+      if (depth_live) {
+        g[9] += p.gD * w;
+        dLda += p.gD * (A.w - p.AD);
+        p.AD = alpha * A.w + one_m * p.AD;
+      }
+      dLda = p.T * dLda + (p.Tfin * inv) * p.gOb;
+      if (ar < kAlphaMax) {
+        g[5] += dLda * ex;
+        const float dp = dLda * ar;
+        g[0] += dp * (B.x * dx + B.y * dy);
+        g[1] += dp * (B.y * dx + B.z * dy);
+        g[2] += -0.5f * dp * dx * dx;
+        g[3] += -dp * dx * dy;
+        g[4] += -0.5f * dp * dy * dy;
       }
     }
-    if (__any(contrib)) {
+    if (__any(contrib_any)) {
       const float tot = wave_reduce10(g, lane);
-      if (lane < 16 && q < 10 && tot != 0.f) unsafeAtomicAdd(&g2[(int64_t)s_e[j] * 12 + q], tot);
+      if (lane < 10 && tot != 0.f) unsafeAtomicAdd(&g2[(int64_t)s_e[j] * 12 + q], tot);
     }
   }
 }
@@ -573,7 +648,7 @@ static BlendState carve_state(void *base, int64_t total_tiles, int64_t cap, int 
   return s;
 }
 
-template <int TW, int TH, int BD>
+template <int TW, int TH, int BD, int NT>
 static hipError_t fwd_impl(const ViewTable &vt, const ImgTable &it, const gs_projected &p, const uint32_t *vals,
                            const uint32_t *range, const BlendState &s, hipStream_t st) {
   const uint32_t T = vt.total_tiles;
@@ -581,12 +656,12 @@ static hipError_t fwd_impl(const ViewTable &vt, const ImgTable &it, const gs_pro
   hipLaunchKernelGGL(k_items_reduce, dim3(nb), dim3(kItemThreads), 0, st, range, T, BD, s.bsum);
   hipLaunchKernelGGL(k_items_scan, dim3(1), dim3(1024), 0, st, s.bsum, nb, s.n_items, s.item_base, T);
   hipLaunchKernelGGL(k_items_apply, dim3(nb), dim3(kItemThreads), 0, st, range, T, BD, s.bsum, s.item_base, s.items);
-  hipLaunchKernelGGL((k_blend_chunk<TW, TH, BD>), dim3((unsigned)s.I), dim3(TW * TH), 0, st, vt, it,
+  hipLaunchKernelGGL((k_blend_chunk<TW, TH, BD, NT>), dim3((unsigned)s.I), dim3(NT), 0, st, vt, it,
                      (const float4 *)p.rec_a, (const float4 *)p.rec_b, (const float4 *)p.rgb, vals, range,
                      (const uint2 *)s.items, (const uint32_t *)s.n_items, s.chunk);
   hipLaunchKernelGGL((k_blend_scan<TW, TH, BD>), dim3(T), dim3(TW * TH), 0, st, vt, it, range,
                      (const uint32_t *)s.item_base, s.chunk);
-  hipLaunchKernelGGL((k_blend_fix<TW, TH, BD>), dim3((unsigned)s.I), dim3(TW * TH), 0, st, vt, it,
+  hipLaunchKernelGGL((k_blend_fix<TW, TH, BD, NT>), dim3((unsigned)s.I), dim3(NT), 0, st, vt, it,
                      (const float4 *)p.rec_a, (const float4 *)p.rec_b, (const float4 *)p.rgb, vals, range,
                      (const uint2 *)s.items, (const uint32_t *)s.n_items, s.chunk);
   hipLaunchKernelGGL((k_blend_suffix<TW, TH, BD>), dim3(T), dim3(TW * TH), 0, st, vt, range,
@@ -594,31 +669,33 @@ static hipError_t fwd_impl(const ViewTable &vt, const ImgTable &it, const gs_pro
   return hipGetLastError();
 }
 
-template <int TW, int TH, int BD>
+template <int TW, int TH, int BD, int NT>
 static hipError_t bwd_impl(const ViewTable &vt, const ImgTable &it, const GradTable &gtab, const gs_projected &p,
                            const uint32_t *vals, const uint32_t *range, const BlendState &s, float *g2,
                            hipStream_t st) {
-  hipLaunchKernelGGL((k_blend_bwd_chunk<TW, TH, BD>), dim3((unsigned)s.I), dim3(TW * TH), 0, st, vt, it, gtab,
+  hipLaunchKernelGGL((k_blend_bwd_chunk<TW, TH, BD, NT>), dim3((unsigned)s.I), dim3(NT), 0, st, vt, it, gtab,
                      (const float4 *)p.rec_a, (const float4 *)p.rec_b, (const float4 *)p.rgb, vals, range,
                      (const uint2 *)s.items, (const uint32_t *)s.n_items, (const ChunkRec *)s.chunk, g2);
   return hipGetLastError();
 }
 
+// Lanes per workgroup by tile size: 8x8 -> 64 (one pixel per lane), 16x16 -> 64 (four pixels
+// per lane, one wavefront per tile), 32x32 -> 256 (four pixels per lane).
 #define GS_BLEND_DISPATCH(FN, ...)                                                             \
   do {                                                                                         \
     const int tw = vt.tile_w;                                                                  \
     if (tw == 8) {                                                                             \
-      if (bd == 64) return FN<8, 8, 64>(__VA_ARGS__);                                          \
-      if (bd == 128) return FN<8, 8, 128>(__VA_ARGS__);                                        \
-      if (bd == 256) return FN<8, 8, 256>(__VA_ARGS__);                                        \
+      if (bd == 64) return FN<8, 8, 64, 64>(__VA_ARGS__);                                      \
+      if (bd == 128) return FN<8, 8, 128, 64>(__VA_ARGS__);                                    \
+      if (bd == 256) return FN<8, 8, 256, 64>(__VA_ARGS__);                                    \
     } else if (tw == 16) {                                                                     \
-      if (bd == 64) return FN<16, 16, 64>(__VA_ARGS__);                                        \
-      if (bd == 128) return FN<16, 16, 128>(__VA_ARGS__);                                      \
-      if (bd == 256) return FN<16, 16, 256>(__VA_ARGS__);                                      \
+      if (bd == 64) return FN<16, 16, 64, 64>(__VA_ARGS__);                                    \
+      if (bd == 128) return FN<16, 16, 128, 64>(__VA_ARGS__);                                  \
+      if (bd == 256) return FN<16, 16, 256, 64>(__VA_ARGS__);                                  \
     } else if (tw == 32) {                                                                     \
-      if (bd == 64) return FN<32, 32, 64>(__VA_ARGS__);                                        \
-      if (bd == 128) return FN<32, 32, 128>(__VA_ARGS__);                                      \
-      if (bd == 256) return FN<32, 32, 256>(__VA_ARGS__);                                      \
+      if (bd == 64) return FN<32, 32, 64, 256>(__VA_ARGS__);                                   \
+      if (bd == 128) return FN<32, 32, 128, 256>(__VA_ARGS__);                                 \
+      if (bd == 256) return FN<32, 32, 256, 256>(__VA_ARGS__);                                 \
     }                                                                                          \
     return hipErrorInvalidValue;                                                               \
   } while (0)

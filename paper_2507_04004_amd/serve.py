@@ -42,7 +42,7 @@ class Request:
 
 
 class RenderServer:
-    def __init__(self, gm: R.GaussianMap, max_batch: int = 16, memory_budget: int = 4 << 30, tile: int = 16,
+    def __init__(self, gm: R.GaussianMap, max_batch: int = 16, memory_budget: int = 4 << 30, tile: int = 8,
                  blend_depth: int = 256, device="cuda"):
         self.gm, self.max_batch, self.budget = gm, max_batch, memory_budget
         self.tile, self.bd, self.device = tile, blend_depth, device
