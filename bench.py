@@ -10,7 +10,8 @@ path before timing.
 One step = the whole hot path on one view with inputs resident in HBM: projection + SH (a1),
 binning with the alpha-max cull and the (tile, depth) sort (a2), compositing (a3) with the
 sparse-LiDAR depth term (a6), the RGB L1 loss, and the backward to every parameter and the
-pose (a4, a5). Gradient buffers are zeroed inside the step (the ABI accumulates).
+pose (a4, a5). The backward writes every gradient element (overwrite mode), so the step needs
+no clearing pass.
 
 Prints ONE JSON line. `value` is fwd+bwd views/s on one GPU.
 """
@@ -52,9 +53,11 @@ def parse():
     ap.add_argument("--latency-calls", type=int, default=200)
     ap.add_argument("--n", type=int, default=1_000_000)
     ap.add_argument("--tile", type=int, default=8)
-    ap.add_argument("--blend-depth", type=int, default=256)
+    ap.add_argument("--blend-depth", type=int, default=128)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-repeats", type=int, default=1)
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run one plain 256 MiB device copy (reference point for HBM byte counters)")
     return ap.parse_args()
 
 
@@ -98,7 +101,7 @@ class PlainStep:
         self.s_img = self.frame.struct()
         self.s_lid_f = self.lidar.struct(self.lidar_loss)
         self.s_lid_b = self.lidar.struct(None)
-        self.s_grads = self.grads.struct(self.scratch)
+        self.s_grads = self.grads.struct(self.scratch, overwrite=True)
         self.p_color = C.c_void_p(self.frame.color.data_ptr())
         self.p_target = C.c_void_p(self.target.data_ptr())
         self.p_dldc = C.c_void_p(self.dLdC.data_ptr())
@@ -121,7 +124,6 @@ class PlainStep:
         st = self.stream()
         self.forward(st)
         N.check(L.gs_loss_l1(self.p_color, self.p_target, self.nval, 1.0, self.p_dldc, self.p_rgbloss, st))
-        self.flat.zero_()
         N.check(L.gs_render_bwd(C.byref(self.gs), C.byref(self.cs), C.byref(self.s_proj), C.byref(self.s_bins),
                                 C.byref(self.s_img), self.p_dldc, None, None, C.byref(self.s_lid_b), self.bd,
                                 C.byref(self.s_grads), st))
@@ -182,6 +184,13 @@ def main():
     ds = (D[pix] / O[pix]).astype(np.float32)
     del tgt
     torch.cuda.empty_cache()
+
+    if args.copy_calibration:
+        src = torch.ones(64 << 20, device=dev)  # 256 MiB read, 256 MiB written
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
 
     log("[bench] building the step")
     ps = PlainStep(R, N, torch, g, cam, pix, target_color, ds, args.tile, args.blend_depth, dev)

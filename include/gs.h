@@ -68,18 +68,20 @@ typedef struct gs_gaussians {
   const float *mean, *scale, *rot, *opacity, *sh_dc, *sh_rest;
 } gs_gaussians;
 
-/* Per-Gaussian splat records written by gs_preprocess (n = number of Gaussians x views):
- *   rec_a [n][4] = (u, v, o, d): projected centre mu', opacity, camera-frame depth;
- *   rec_b [n][4] = (a, b, c, kappa^2): conic Sigma'^-1 = [[a, b], [b, c]] and the squared
- *                  footprint radius 2 ln(255 o);
- *   rgb   [n][4] = (r, g, b, m): view-dependent colour max(0, SH . Y(dir) + 0.5); the bits of
- *                  m (a float holding an integer bit pattern) mark the channels not clamped;
- *   rect  [n][4] int16 inclusive tile rectangle (tx0, ty0, tx1, ty1), -1 when n_tiles = 0;
- *   n_tiles [n]  number of tiles kept after the alpha-max cull;
- *   dkey  [n]    sort key: IEEE bits of d, or 0xFFFFFFFF when n_tiles = 0. */
+/* Per-Gaussian splat records written by gs_preprocess (n = number of Gaussians x views).
+ * card [n][16] (64 B per record, 64-B aligned, so that every later gather of a record
+ * touches one memory line):
+ *   words 0-3   (u, v, o, d): projected centre mu', opacity, camera-frame depth;
+ *   words 4-7   (a, b, c, kappa^2): conic Sigma'^-1 = [[a, b], [b, c]] and the squared
+ *               footprint radius 2 ln(255 o);
+ *   words 8-11  (r, g, b, m): view-dependent colour max(0, SH . Y(dir) + 0.5); the bits of m
+ *               (a float holding an integer bit pattern) mark the channels not clamped;
+ *   words 12-13 int16 inclusive tile rectangle (tx0, ty0, tx1, ty1), -1 when n_tiles = 0;
+ *   word 14     number of tiles kept, word 15 the depth key (copies of the arrays below).
+ * n_tiles [n]  number of tiles kept after the alpha-max cull;
+ * dkey    [n]  sort key: IEEE bits of d, or 0xFFFFFFFF when n_tiles = 0. */
 typedef struct gs_projected {
-  float *rec_a, *rec_b, *rgb;
-  int16_t *rect;
+  float *card;
   uint32_t *n_tiles;
   uint32_t *dkey;
 } gs_projected;
@@ -135,15 +137,19 @@ typedef struct gs_lidar {
   const float *grad_scale;
 } gs_lidar;
 
-/* Gradient outputs, all accumulated (+=), same layouts as gs_gaussians; pose [6] is
- * dL/dxi for the left perturbation T_cw <- Exp(xi) T_cw with xi = (rho, phi), translation
- * first (the manifold derivative after eq:3dgs_jacobi, taken on the world-to-camera pose).
+/* Gradient outputs, same layouts as gs_gaussians; pose [6] is dL/dxi for the left
+ * perturbation T_cw <- Exp(xi) T_cw with xi = (rho, phi), translation first (the manifold
+ * derivative after eq:3dgs_jacobi, taken on the world-to-camera pose).
+ * overwrite = 0: gradients are accumulated (+=) into the outputs;
+ * overwrite = 1: every element of every given output is written (zero where no view
+ *                contributes), so the outputs need no clearing beforehand.
  * scratch: at least gs_grads_scratch_bytes(...) bytes. Any of the parameter pointers may be
  * NULL to skip that output (sh_rest must be given when sh_degree > 0 and sh_dc is given). */
 typedef struct gs_grads {
   float *mean, *scale, *rot, *opacity, *sh_dc, *sh_rest, *pose;
   void *scratch;
   size_t scratch_bytes;
+  int32_t overwrite;
 } gs_grads;
 
 /* Stage a1 — projection, covariance, SH colour, footprint, tile rectangle and alpha-max cull

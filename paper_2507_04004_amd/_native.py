@@ -31,7 +31,7 @@ class Gaussians(C.Structure):
 
 
 class Projected(C.Structure):
-    _fields_ = [(k, vp) for k in ("rec_a", "rec_b", "rgb", "rect", "n_tiles", "dkey")]
+    _fields_ = [(k, vp) for k in ("card", "n_tiles", "dkey")]
 
 
 class Bins(C.Structure):
@@ -51,7 +51,7 @@ class Lidar(C.Structure):
 
 class Grads(C.Structure):
     _fields_ = [(k, vp) for k in ("mean", "scale", "rot", "opacity", "sh_dc", "sh_rest", "pose", "scratch")] + [
-        ("scratch_bytes", C.c_size_t)]
+        ("scratch_bytes", C.c_size_t), ("overwrite", C.c_int32)]
 
 
 class View(C.Structure):

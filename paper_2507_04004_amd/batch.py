@@ -72,11 +72,13 @@ class BatchPlan:
             pass
 
     def run(self, gm: R.GaussianMap, views: list[ViewSlot], fwd=True, bwd=False, grads: R.ParamGrads | None = None,
-            graph=False, grad_scratch=None):
+            graph=False, grad_scratch=None, overwrite=False):
+        """overwrite=False adds the batch's gradients to `grads`; True writes every element."""
         mode = (N.GS_FWD if fwd else 0) | (N.GS_BWD if bwd else 0) | (N.GS_GRAPH if graph else 0)
         arr = (N.View * len(views))(*[v.struct() for v in views])
         gs = gm.struct()
-        gst = grads.struct(torch.empty(0, dtype=torch.uint8, device=self.device)) if grads is not None else None
+        gst = (grads.struct(torch.empty(0, dtype=torch.uint8, device=self.device), overwrite)
+               if grads is not None else None)
         self._keep = (arr, gs, gst)
         st = C.c_void_p(torch.cuda.current_stream().cuda_stream)
         N.check(N.lib().gs_render_batch(self._plan, C.byref(gs), len(views), arr, mode,

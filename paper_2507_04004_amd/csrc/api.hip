@@ -66,15 +66,17 @@ int check_gaussians(const gs_gaussians *g) {
   if (g->n > 0 && (!g->mean || !g->scale || !g->rot || !g->opacity || !g->sh_dc))
     return fail(GS_ERR_INVALID_ARG, "a parameter plane is NULL");
   if (g->n > 0 && g->sh_degree > 0 && !g->sh_rest) return fail(GS_ERR_INVALID_ARG, "sh_rest is NULL at degree > 0");
-  if (g->n > (int64_t)0x7FFFFFFF) return fail(GS_ERR_INVALID_ARG, "n too large");
+  if (g->n >= ((int64_t)1 << 30)) return fail(GS_ERR_INVALID_ARG, "n too large (at most 2^30 - 1 Gaussians)");
   return GS_OK;
 }
 
 // Record arrays may be NULL only when there are no records.
 int check_projected(const gs_projected *p, int64_t n) {
   if (!p) return fail(GS_ERR_INVALID_ARG, "projected records are NULL");
-  if (n > 0 && (!p->rec_a || !p->rec_b || !p->rgb || !p->rect || !p->n_tiles || !p->dkey))
+  if (n > 0 && (!p->card || !p->n_tiles || !p->dkey))
     return fail(GS_ERR_INVALID_ARG, "projected record pointer is NULL");
+  if (n > 0 && (reinterpret_cast<uintptr_t>(p->card) & 63u))
+    return fail(GS_ERR_INVALID_ARG, "splat cards must be 64-byte aligned");
   return GS_OK;
 }
 
@@ -493,19 +495,16 @@ size_t plan_bytes(const gs_batch_plan &p, size_t *offs) {
     offs[i] = o;
     o += a256(bytes);
   };
-  put(0, 16 * E);                                      // rec_a
-  put(1, 16 * E);                                      // rec_b
-  put(2, 16 * E);                                      // rgb
-  put(3, 8 * E);                                       // rect
-  put(4, 4 * E);                                       // n_tiles
-  put(5, 4 * E);                                       // dkey
-  put(6, 4 * std::max<int64_t>(p.cap, 1));             // vals
-  put(7, 8 * std::max<int64_t>(p.max_tiles, 1));       // tile ranges
-  put(8, 16);                                          // num_pairs
-  put(9, gs::bin_scratch_bytes(E, p.cap));             // bin scratch
-  put(10, grads_scratch_bytes_impl(p.n, p.max_views, p.max_pixels));
-  put(11, 12 * std::max<int64_t>(p.max_pixels, 1));   // dC planes
-  put(12, gs::blend_state_bytes(p.max_tiles, p.cap, p.tw, p.th, p.bd));
+  put(0, 64 * E);                                      // splat cards
+  put(1, 4 * E);                                       // n_tiles
+  put(2, 4 * E);                                       // dkey
+  put(3, 4 * std::max<int64_t>(p.cap, 1));             // vals
+  put(4, 8 * std::max<int64_t>(p.max_tiles, 1));       // tile ranges
+  put(5, 16);                                          // num_pairs
+  put(6, gs::bin_scratch_bytes(E, p.cap));             // bin scratch
+  put(7, grads_scratch_bytes_impl(p.n, p.max_views, p.max_pixels));
+  put(8, 12 * std::max<int64_t>(p.max_pixels, 1));    // dC planes
+  put(9, gs::blend_state_bytes(p.max_tiles, p.cap, p.tw, p.th, p.bd));
   return o;
 }
 
@@ -624,7 +623,7 @@ int gs_batch_plan_create(gs_batch_plan **out, int64_t n, int32_t sh_degree, int3
   p->cap = capacity;
   // every view adds at most one partial tile row and column beyond pixels / tile area
   p->max_tiles = max_total_pixels / ((int64_t)tile_w * tile_h) + (int64_t)n_views * (2 * 32768 / tile_w + 1);
-  size_t offs[13];
+  size_t offs[10];
   const size_t bytes = plan_bytes(*p, offs);
   hipError_t e = hipMalloc(&p->block, bytes);
   if (e != hipSuccess) {
@@ -632,19 +631,16 @@ int gs_batch_plan_create(gs_batch_plan **out, int64_t n, int32_t sh_degree, int3
     return hip_fail(e, "plan allocation");
   }
   char *b = (char *)p->block;
-  p->proj.rec_a = (float *)(b + offs[0]);
-  p->proj.rec_b = (float *)(b + offs[1]);
-  p->proj.rgb = (float *)(b + offs[2]);
-  p->proj.rect = (int16_t *)(b + offs[3]);
-  p->proj.n_tiles = (uint32_t *)(b + offs[4]);
-  p->proj.dkey = (uint32_t *)(b + offs[5]);
-  p->vals = (uint32_t *)(b + offs[6]);
-  p->tile_range = (uint32_t *)(b + offs[7]);
-  p->num_pairs = (int64_t *)(b + offs[8]);
-  p->bin_scratch = b + offs[9];
-  p->grad_scratch = b + offs[10];
-  p->dC = (float *)(b + offs[11]);
-  p->blend_state = b + offs[12];
+  p->proj.card = (float *)(b + offs[0]);
+  p->proj.n_tiles = (uint32_t *)(b + offs[1]);
+  p->proj.dkey = (uint32_t *)(b + offs[2]);
+  p->vals = (uint32_t *)(b + offs[3]);
+  p->tile_range = (uint32_t *)(b + offs[4]);
+  p->num_pairs = (int64_t *)(b + offs[5]);
+  p->bin_scratch = b + offs[6];
+  p->grad_scratch = b + offs[7];
+  p->dC = (float *)(b + offs[8]);
+  p->blend_state = b + offs[9];
   *out = p;
   return GS_OK;
 }

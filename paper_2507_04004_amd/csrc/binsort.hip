@@ -176,29 +176,34 @@ __global__ __launch_bounds__(1024) void k_count_scan_bsums(uint32_t *__restrict_
 }
 
 __global__ __launch_bounds__(kScanThreads) void k_emit_pairs(ViewTable vt, const uint32_t *__restrict__ order,
-                                                             int64_t n, const uint32_t *__restrict__ n_tiles,
-                                                             const float4 *__restrict__ rec_a,
-                                                             const float4 *__restrict__ rec_b,
-                                                             const short4 *__restrict__ rect,
+                                                             int64_t n,
+                                                             const Card *__restrict__ card,
                                                              const uint32_t *__restrict__ bsum, int64_t cap,
-                                                             uint32_t *__restrict__ pkey, uint32_t *__restrict__ pval) {
+                                                             uint32_t *__restrict__ pkey, uint32_t *__restrict__ pval,
+                                                             uint32_t *__restrict__ big_e, uint32_t *__restrict__ big_off,
+                                                             uint32_t *__restrict__ big_n) {
   __shared__ uint32_t lds[kScanThreads / 64 + 1];
   const int64_t i = (int64_t)blockIdx.x * kScanChunk + threadIdx.x;
+  // one card gather per record (a single memory line) supplies the count, centre, conic and
+  // rectangle together
   uint32_t e = 0, cnt = 0;
+  float4 A = make_float4(0.f, 0.f, 0.f, 0.f), B = A;
+  uint4 d = make_uint4(0u, 0u, 0u, 0u);
   if (i < n) {
     e = order[i];
-    cnt = n_tiles[e];
+    const Card &cd = card[e];
+    A = cd.a;
+    B = cd.b;
+    d = cd.d;
+    cnt = d.z;
   }
   uint32_t total;
   const uint32_t off = bsum[blockIdx.x] + block_exclusive_scan<kScanThreads>(cnt, lds, total);
-  float4 A = make_float4(0.f, 0.f, 0.f, 0.f), B = A;
   short4 rc = make_short4(0, 0, -1, -1);
   int vi = 0;
   if (cnt) {
     vi = (int)(e / (uint32_t)vt.n);
-    A = rec_a[e];
-    B = rec_b[e];
-    rc = rect[e];
+    rc = make_short4((short)lo_i16(d.x), (short)hi_i16(d.x), (short)lo_i16(d.y), (short)hi_i16(d.y));
   }
   const int area = cnt ? (rc.z - rc.x + 1) * (rc.w - rc.y + 1) : 0;
   // small rectangles: one lane each
@@ -213,24 +218,46 @@ __global__ __launch_bounds__(kScanThreads) void k_emit_pairs(ViewTable vt, const
                        }
                      });
   }
-  // large rectangles: the whole wavefront, one splat at a time
-  uint64_t big = __ballot(cnt && area > kCoopArea);
-  while (big) {
-    const int src = __ffsll((unsigned long long)big) - 1;
-    big &= big - 1;
-    const int bvi = __shfl(vi, src);
-    const ViewCam &cam = vt.v[bvi];
-    const float bu = __shfl(A.x, src), bv = __shfl(A.y, src);
-    const float ba = __shfl(B.x, src), bb = __shfl(B.y, src), bc = __shfl(B.z, src), bk = __shfl(B.w, src);
-    const int x0 = __shfl((int)rc.x, src), y0 = __shfl((int)rc.y, src);
-    const int x1 = __shfl((int)rc.z, src), y1 = __shfl((int)rc.w, src);
-    const uint32_t boff = __shfl(off, src), be = __shfl(e, src);
-    wave_visit_kept_tiles(cam, vt.tile_w, vt.tile_h, bu, bv, ba, bb, bc, bk, x0, y0, x1, y1,
-                          [&](uint32_t lt, uint32_t j) {
+  // large rectangles go to a list that k_emit_big spreads over the whole chip: in depth order
+  // the near (large) splats are neighbours, so visiting them here would leave a few
+  // wavefronts with most of the work
+  const bool is_big = cnt && area > kCoopArea;
+  const uint64_t big = __ballot(is_big);
+  if (big) {
+    const int lane = threadIdx.x & 63;
+    uint32_t base = 0;
+    if (lane == __ffsll((unsigned long long)big) - 1) base = atomicAdd(big_n, (uint32_t)__popcll(big));
+    base = __shfl(base, __ffsll((unsigned long long)big) - 1);
+    if (is_big) {
+      const uint32_t slot = base + (uint32_t)__popcll(big & lanemask_lt());
+      big_e[slot] = e;
+      big_off[slot] = off;
+    }
+  }
+}
+
+// One wavefront per large rectangle (grid-stride over the list): the wavefront tests 64
+// tiles per step and compacts the kept ones with a ballot.
+constexpr int kBigBlocks = 512;
+__global__ __launch_bounds__(kScanThreads) void k_emit_big(ViewTable vt, const Card *__restrict__ card,
+                                                           const uint32_t *__restrict__ big_e,
+                                                           const uint32_t *__restrict__ big_off,
+                                                           const uint32_t *__restrict__ big_n, int64_t cap,
+                                                           uint32_t *__restrict__ pkey, uint32_t *__restrict__ pval) {
+  const uint32_t waves = gridDim.x * (kScanThreads / 64);
+  const uint32_t nbig = *big_n;
+  for (uint32_t it = blockIdx.x * (kScanThreads / 64) + threadIdx.x / 64; it < nbig; it += waves) {
+    const uint32_t e = big_e[it], boff = big_off[it];
+    const Card &cd = card[e];
+    const float4 A = cd.a, B = cd.b;
+    const uint4 d = cd.d;
+    const ViewCam &cam = vt.v[e / (uint32_t)vt.n];
+    wave_visit_kept_tiles(cam, vt.tile_w, vt.tile_h, A.x, A.y, B.x, B.y, B.z, B.w, lo_i16(d.x), hi_i16(d.x),
+                          lo_i16(d.y), hi_i16(d.y), [&](uint32_t lt, uint32_t j) {
                             const int64_t pos = (int64_t)boff + j;
                             if (pos < cap) {
                               pkey[pos] = cam.tile_base + lt;
-                              pval[pos] = be;
+                              pval[pos] = e;
                             }
                           });
   }
@@ -261,6 +288,7 @@ struct BinScratch {
   uint32_t *pk_a, *pv_a, *pk_b, *pv_b;  // pair sort ping-pong [cap]
   uint32_t *hist;                       // [256][max blocks]
   uint32_t *tot;                        // [256]
+  uint32_t *big_n;                      // [1] length of the large-rectangle list
 };
 
 size_t bin_scratch_bytes(int64_t n, int64_t cap) {
@@ -272,6 +300,7 @@ size_t bin_scratch_bytes(int64_t n, int64_t cap) {
   s += 4 * align256(sizeof(uint32_t) * std::max<int64_t>(cap, 1));
   s += align256(sizeof(uint32_t) * kRadixDigits * nb_max);
   s += align256(sizeof(uint32_t) * kRadixDigits);
+  s += align256(16);
   return s;
 }
 
@@ -292,6 +321,7 @@ static BinScratch carve(void *base, int64_t n, int64_t cap) {
   s.pk_a = take(cc); s.pv_a = take(cc); s.pk_b = take(cc); s.pv_b = take(cc);
   s.hist = take(sizeof(uint32_t) * kRadixDigits * nb_max);
   s.tot = take(sizeof(uint32_t) * kRadixDigits);
+  s.big_n = take(16);
   return s;
 }
 
@@ -339,8 +369,12 @@ hipError_t launch_bin_sort(const ViewTable &vt, const gs_projected &p, int64_t n
   hipLaunchKernelGGL(k_count_reduce, dim3((unsigned)nbs), dim3(kScanThreads), 0, st, order, p.n_tiles, n, s.bsum);
   hipLaunchKernelGGL(k_count_scan_bsums, dim3(1), dim3(1024), 0, st, s.bsum, nbs, num_pairs);
   // 3. emission in depth order
-  hipLaunchKernelGGL(k_emit_pairs, dim3((unsigned)nbs), dim3(kScanThreads), 0, st, vt, order, n, p.n_tiles,
-                     (const float4 *)p.rec_a, (const float4 *)p.rec_b, (const short4 *)p.rect, s.bsum, cap, s.pk_a,
+  // the depth keys' ping-pong buffers are free now: they hold the large-rectangle list
+  hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(64), 0, st, s.big_n, 1, 0u);
+  hipLaunchKernelGGL(k_emit_pairs, dim3((unsigned)nbs), dim3(kScanThreads), 0, st, vt, order, n,
+                     (const Card *)p.card, s.bsum, cap, s.pk_a, s.pv_a, s.dk_a, s.dk_b, s.big_n);
+  hipLaunchKernelGGL(k_emit_big, dim3(kBigBlocks), dim3(kScanThreads), 0, st, vt, (const Card *)p.card,
+                     (const uint32_t *)s.dk_a, (const uint32_t *)s.dk_b, (const uint32_t *)s.big_n, cap, s.pk_a,
                      s.pv_a);
   if ((err = hipGetLastError()) != hipSuccess) return err;
   // 4. stable sort by global tile id

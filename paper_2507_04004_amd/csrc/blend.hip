@@ -45,18 +45,52 @@ static_assert(sizeof(ChunkRec) == 32, "chunk record is 32 B");
 __host__ __device__ __forceinline__ uint32_t n_chunks(uint32_t len, int bd) { return (len + bd - 1) / bd; }
 
 // ---- work items: (tile, chunk) pairs --------------------------------------------------------
+// Items are listed tile by tile in a locality order: stripes of kStripe tile rows, column by
+// column inside a stripe, so that consecutive items are spatial neighbours and share splats.
+// Workgroups are dealt to the 8 XCDs round-robin; the launch remaps them so that each XCD
+// takes whole groups of kGroup consecutive items (neighbouring tiles share that XCD's L2),
+// while the groups themselves are dealt round-robin, which keeps the XCDs evenly loaded
+// (the work per image band differs by a large factor).
 constexpr int kItemThreads = 256;
 constexpr int kItemPer = 4;
 constexpr int kItemChunk = kItemThreads * kItemPer;
+constexpr int kStripe = 4;
+constexpr uint32_t kXcds = 8;
+constexpr uint32_t kGroup = 16;
 
-__global__ __launch_bounds__(kItemThreads) void k_items_reduce(const uint32_t *__restrict__ range, uint32_t T, int bd,
-                                                                uint32_t *__restrict__ bsum) {
+// Global tile id at position j of the locality order (a bijection within each view).
+__device__ __forceinline__ uint32_t tile_at(const ViewTable &vt, uint32_t j) {
+  const int vi = view_of_tile(vt, j);
+  const ViewCam &cam = vt.v[vi];
+  const uint32_t s = j - cam.tile_base;
+  const uint32_t tx_n = (uint32_t)cam.tiles_x, ty_n = (uint32_t)cam.tiles_y;
+  const uint32_t stripe = s / (kStripe * tx_n);
+  const uint32_t r = s - stripe * kStripe * tx_n;
+  const uint32_t h = min((uint32_t)kStripe, ty_n - stripe * kStripe);
+  const uint32_t tx = r / h, ty = stripe * kStripe + r % h;
+  return cam.tile_base + ty * tx_n + tx;
+}
+
+// Work item of this workgroup after the XCD remap; false when out of range. Workgroup b runs
+// on XCD b % 8 as its (b / 8)-th workgroup there.
+__device__ __forceinline__ bool item_of_block(const uint32_t *n_items, uint32_t &item) {
+  const uint32_t x = blockIdx.x % kXcds, k = blockIdx.x / kXcds;
+  item = ((k / kGroup) * kXcds + x) * kGroup + k % kGroup;
+  return item < *n_items;
+}
+
+__global__ __launch_bounds__(kItemThreads) void k_items_reduce(ViewTable vt, const uint32_t *__restrict__ range,
+                                                                int bd, uint32_t *__restrict__ bsum) {
   __shared__ uint32_t lds[kItemThreads / 64 + 1];
+  const uint32_t T = vt.total_tiles;
   uint32_t s = 0;
 #pragma unroll
   for (int r = 0; r < kItemPer; ++r) {
-    const uint32_t t = blockIdx.x * kItemChunk + r * kItemThreads + threadIdx.x;
-    if (t < T) s += n_chunks(range[2 * t + 1] - range[2 * t], bd);
+    const uint32_t j = blockIdx.x * kItemChunk + r * kItemThreads + threadIdx.x;
+    if (j < T) {
+      const uint32_t t = tile_at(vt, j);
+      s += n_chunks(range[2 * t + 1] - range[2 * t], bd);
+    }
   }
   uint32_t total;
   block_exclusive_scan<kItemThreads>(s, lds, total);
@@ -82,18 +116,20 @@ __global__ __launch_bounds__(1024) void k_items_scan(uint32_t *__restrict__ bsum
   }
 }
 
-__global__ __launch_bounds__(kItemThreads) void k_items_apply(const uint32_t *__restrict__ range, uint32_t T, int bd,
+__global__ __launch_bounds__(kItemThreads) void k_items_apply(ViewTable vt, const uint32_t *__restrict__ range, int bd,
                                                                const uint32_t *__restrict__ bsum,
                                                                uint32_t *__restrict__ item_base,
                                                                uint2 *__restrict__ items) {
   __shared__ uint32_t lds[kItemThreads / 64 + 1];
+  const uint32_t T = vt.total_tiles;
   uint32_t running = bsum[blockIdx.x];
   for (int r = 0; r < kItemPer; ++r) {
-    const uint32_t t = blockIdx.x * kItemChunk + r * kItemThreads + threadIdx.x;
-    const uint32_t k = t < T ? n_chunks(range[2 * t + 1] - range[2 * t], bd) : 0u;
+    const uint32_t j = blockIdx.x * kItemChunk + r * kItemThreads + threadIdx.x;
+    const uint32_t t = j < T ? tile_at(vt, j) : 0u;
+    const uint32_t k = j < T ? n_chunks(range[2 * t + 1] - range[2 * t], bd) : 0u;
     uint32_t total;
     const uint32_t ex = block_exclusive_scan<kItemThreads>(k, lds, total);
-    if (t < T) {
+    if (j < T) {
       const uint32_t b = running + ex;
       item_base[t] = b;
       for (uint32_t c = 0; c < k; ++c) items[b + c] = make_uint2(t, c);
@@ -134,15 +170,15 @@ struct TileCtx {
 
 template <int BD, int NT>
 __device__ __forceinline__ void stage(const uint32_t *__restrict__ vals, uint32_t start, int cnt,
-                                      const float4 *__restrict__ rec_a, const float4 *__restrict__ rec_b,
-                                      const float4 *__restrict__ rgb, float4 *s_a, float4 *s_b, float4 *s_c,
+                                      const Card *__restrict__ card, float4 *s_a, float4 *s_b, float4 *s_c,
                                       uint32_t *s_e) {
   for (int k = threadIdx.x; k < cnt; k += NT) {
     const uint32_t e = vals[start + k];
     if (s_e) s_e[k] = e;
-    s_a[k] = rec_a[e];
-    s_b[k] = rec_b[e];
-    s_c[k] = rgb[e];
+    const Card &cd = card[e];
+    s_a[k] = cd.a;
+    s_b[k] = cd.b;
+    s_c[k] = cd.c;
   }
 }
 
@@ -209,8 +245,7 @@ __device__ __forceinline__ void composite_run(const float4 *s_a, const float4 *s
 
 // ---- forward pass 1: every chunk from transmittance 1 ------------------------------------
 template <int TW, int TH, int BD, int NT>
-__global__ __launch_bounds__(NT) void k_blend_chunk(ViewTable vt, ImgTable it, const float4 *__restrict__ rec_a,
-                                                    const float4 *__restrict__ rec_b, const float4 *__restrict__ rgb,
+__global__ __launch_bounds__(NT) void k_blend_chunk(ViewTable vt, ImgTable it, const Card *__restrict__ card,
                                                     const uint32_t *__restrict__ vals,
                                                     const uint32_t *__restrict__ range,
                                                     const uint2 *__restrict__ items,
@@ -219,8 +254,8 @@ __global__ __launch_bounds__(NT) void k_blend_chunk(ViewTable vt, ImgTable it, c
   using Ctx = TileCtx<TW, TH, NT>;
   constexpr int PPT = Ctx::PPT;
   __shared__ float4 s_a[BD], s_b[BD], s_c[BD];
-  const uint32_t item = blockIdx.x;
-  if (item >= *n_items) return;
+  uint32_t item;
+  if (!item_of_block(n_items, item)) return;
   const uint2 tc = items[item];
   const uint32_t gt = tc.x, c = tc.y;
   const Ctx tile(vt, gt);
@@ -228,7 +263,7 @@ __global__ __launch_bounds__(NT) void k_blend_chunk(ViewTable vt, ImgTable it, c
   const uint32_t K = n_chunks(e0 - s0, BD);
   const uint32_t cs = s0 + c * BD;
   const int cnt = (int)min<uint32_t>(BD, e0 - cs);
-  stage<BD, NT>(vals, cs, cnt, rec_a, rec_b, rgb, s_a, s_b, s_c, nullptr);
+  stage<BD, NT>(vals, cs, cnt, card, s_a, s_b, s_c, nullptr);
   __syncthreads();
 
   float px[PPT], py[PPT];
@@ -336,8 +371,7 @@ __global__ __launch_bounds__(TW * TH) void k_blend_scan(ViewTable vt, ImgTable i
 
 // ---- forward pass 3: exact compositing of each pixel's stop chunk (chunk-parallel) -------
 template <int TW, int TH, int BD, int NT>
-__global__ __launch_bounds__(NT) void k_blend_fix(ViewTable vt, ImgTable it, const float4 *__restrict__ rec_a,
-                                                  const float4 *__restrict__ rec_b, const float4 *__restrict__ rgb,
+__global__ __launch_bounds__(NT) void k_blend_fix(ViewTable vt, ImgTable it, const Card *__restrict__ card,
                                                   const uint32_t *__restrict__ vals,
                                                   const uint32_t *__restrict__ range,
                                                   const uint2 *__restrict__ items,
@@ -346,8 +380,8 @@ __global__ __launch_bounds__(NT) void k_blend_fix(ViewTable vt, ImgTable it, con
   using Ctx = TileCtx<TW, TH, NT>;
   constexpr int PPT = Ctx::PPT;
   __shared__ float4 s_a[BD], s_b[BD], s_c[BD];
-  const uint32_t item = blockIdx.x;
-  if (item >= *n_items) return;
+  uint32_t item;
+  if (!item_of_block(n_items, item)) return;
   const uint2 tc = items[item];
   const uint32_t gt = tc.x, c = tc.y;
   const uint32_t s0 = range[2 * gt], e0 = range[2 * gt + 1];
@@ -373,7 +407,7 @@ __global__ __launch_bounds__(NT) void k_blend_fix(ViewTable vt, ImgTable it, con
   if (__syncthreads_count(any) == 0) return;
   const uint32_t cs = s0 + c * BD;
   const int cnt = (int)min<uint32_t>(BD, e0 - cs);
-  stage<BD, NT>(vals, cs, cnt, rec_a, rec_b, rgb, s_a, s_b, s_c, nullptr);
+  stage<BD, NT>(vals, cs, cnt, card, s_a, s_b, s_c, nullptr);
   __syncthreads();
   composite_run<PPT>(s_a, s_b, s_c, cnt, px, py, (int)(c * BD), st);
 #pragma unroll
@@ -485,9 +519,7 @@ struct PixGrad {
 
 template <int TW, int TH, int BD, int NT>
 __global__ __launch_bounds__(NT) void k_blend_bwd_chunk(ViewTable vt, ImgTable it, GradTable gtab,
-                                                        const float4 *__restrict__ rec_a,
-                                                        const float4 *__restrict__ rec_b,
-                                                        const float4 *__restrict__ rgb,
+                                                        const Card *__restrict__ card,
                                                         const uint32_t *__restrict__ vals,
                                                         const uint32_t *__restrict__ range,
                                                         const uint2 *__restrict__ items,
@@ -499,8 +531,8 @@ __global__ __launch_bounds__(NT) void k_blend_bwd_chunk(ViewTable vt, ImgTable i
   __shared__ float4 s_a[BD], s_b[BD], s_c[BD];
   __shared__ uint32_t s_e[BD];
   __shared__ int s_max;
-  const uint32_t item = blockIdx.x;
-  if (item >= *n_items) return;
+  uint32_t item;
+  if (!item_of_block(n_items, item)) return;
   const uint2 tc = items[item];
   const uint32_t gt = tc.x, c = tc.y;
   const Ctx tile(vt, gt);
@@ -548,7 +580,7 @@ __global__ __launch_bounds__(NT) void k_blend_bwd_chunk(ViewTable vt, ImgTable i
   __syncthreads();
   const int maxll = s_max;
   if (maxll < 0) return;  // uniform: no pixel has a contributor in this chunk
-  stage<BD, NT>(vals, cs, maxll + 1, rec_a, rec_b, rgb, s_a, s_b, s_c, s_e);
+  stage<BD, NT>(vals, cs, maxll + 1, card, s_a, s_b, s_c, s_e);
   __syncthreads();
 
   const int lane = threadIdx.x & 63;
@@ -608,7 +640,13 @@ __global__ __launch_bounds__(NT) void k_blend_bwd_chunk(ViewTable vt, ImgTable i
 // ---- scratch layout and dispatch -----------------------------------------------------------
 static inline size_t a256(size_t x) { return (x + 255) & ~size_t(255); }
 
-int64_t max_items(int64_t total_tiles, int64_t cap, int bd) { return total_tiles + (cap + bd - 1) / bd + 1; }
+// Upper bound on items, rounded up to whole rounds of the XCD remap (kXcds * kGroup), so the
+// launch of max_items workgroups reaches every item.
+int64_t max_items(int64_t total_tiles, int64_t cap, int bd) {
+  const int64_t m = total_tiles + (cap + bd - 1) / bd + 1;
+  const int64_t r = (int64_t)kXcds * kGroup;
+  return (m + r - 1) / r * r;
+}
 
 size_t blend_state_bytes(int64_t total_tiles, int64_t cap, int tw, int th, int bd) {
   const int64_t T = std::max<int64_t>(total_tiles, 1);
@@ -653,16 +691,16 @@ static hipError_t fwd_impl(const ViewTable &vt, const ImgTable &it, const gs_pro
                            const uint32_t *range, const BlendState &s, hipStream_t st) {
   const uint32_t T = vt.total_tiles;
   const uint32_t nb = (T + kItemChunk - 1) / kItemChunk;
-  hipLaunchKernelGGL(k_items_reduce, dim3(nb), dim3(kItemThreads), 0, st, range, T, BD, s.bsum);
+  hipLaunchKernelGGL(k_items_reduce, dim3(nb), dim3(kItemThreads), 0, st, vt, range, BD, s.bsum);
   hipLaunchKernelGGL(k_items_scan, dim3(1), dim3(1024), 0, st, s.bsum, nb, s.n_items, s.item_base, T);
-  hipLaunchKernelGGL(k_items_apply, dim3(nb), dim3(kItemThreads), 0, st, range, T, BD, s.bsum, s.item_base, s.items);
+  hipLaunchKernelGGL(k_items_apply, dim3(nb), dim3(kItemThreads), 0, st, vt, range, BD, s.bsum, s.item_base, s.items);
   hipLaunchKernelGGL((k_blend_chunk<TW, TH, BD, NT>), dim3((unsigned)s.I), dim3(NT), 0, st, vt, it,
-                     (const float4 *)p.rec_a, (const float4 *)p.rec_b, (const float4 *)p.rgb, vals, range,
+                     (const Card *)p.card, vals, range,
                      (const uint2 *)s.items, (const uint32_t *)s.n_items, s.chunk);
   hipLaunchKernelGGL((k_blend_scan<TW, TH, BD>), dim3(T), dim3(TW * TH), 0, st, vt, it, range,
                      (const uint32_t *)s.item_base, s.chunk);
   hipLaunchKernelGGL((k_blend_fix<TW, TH, BD, NT>), dim3((unsigned)s.I), dim3(NT), 0, st, vt, it,
-                     (const float4 *)p.rec_a, (const float4 *)p.rec_b, (const float4 *)p.rgb, vals, range,
+                     (const Card *)p.card, vals, range,
                      (const uint2 *)s.items, (const uint32_t *)s.n_items, s.chunk);
   hipLaunchKernelGGL((k_blend_suffix<TW, TH, BD>), dim3(T), dim3(TW * TH), 0, st, vt, range,
                      (const uint32_t *)s.item_base, s.chunk);
@@ -674,7 +712,7 @@ static hipError_t bwd_impl(const ViewTable &vt, const ImgTable &it, const GradTa
                            const uint32_t *vals, const uint32_t *range, const BlendState &s, float *g2,
                            hipStream_t st) {
   hipLaunchKernelGGL((k_blend_bwd_chunk<TW, TH, BD, NT>), dim3((unsigned)s.I), dim3(NT), 0, st, vt, it, gtab,
-                     (const float4 *)p.rec_a, (const float4 *)p.rec_b, (const float4 *)p.rgb, vals, range,
+                     (const Card *)p.card, vals, range,
                      (const uint2 *)s.items, (const uint32_t *)s.n_items, (const ChunkRec *)s.chunk, g2);
   return hipGetLastError();
 }

@@ -203,6 +203,40 @@ __device__ __forceinline__ uint32_t wave_visit_kept_tiles(const ViewCam &cam, in
   return done;
 }
 
+// One splat record (64 B, one memory line): centre / opacity / depth, conic / kappa^2,
+// colour / clamp bits, and the tile rectangle (two int16 pairs), tile count and depth key.
+struct alignas(64) Card {
+  float4 a, b, c;
+  uint4 d;
+};
+static_assert(sizeof(Card) == 64, "splat card is 64 B");
+
+__device__ __forceinline__ uint32_t pack_i16x2(int lo, int hi) {
+  return ((uint32_t)lo & 0xFFFFu) | ((uint32_t)hi << 16);
+}
+__device__ __forceinline__ int lo_i16(uint32_t w) { return (int)(int16_t)(w & 0xFFFFu); }
+__device__ __forceinline__ int hi_i16(uint32_t w) { return (int)(int16_t)(w >> 16); }
+
+// Planar [k][n] float arrays through buffer instructions: the descriptor of plane k (base
+// + k n, n floats long) lives in scalar registers and every plane shares one 32-bit lane
+// offset, so a lane holds a single address register however many planes it touches. Out-of-
+// range offsets read 0 and drop stores (hardware range check). Needs n < 2^30.
+struct Planes {
+  uint32_t off, bytes;
+  int64_t n;
+  __device__ __forceinline__ Planes(int64_t n_, uint32_t idx) : off(idx * 4u), bytes((uint32_t)(n_ * 4)), n(n_) {}
+  __device__ __forceinline__ __amdgpu_buffer_rsrc_t rsrc(const float *base, int k) const {
+    return __builtin_amdgcn_make_buffer_rsrc((void *)(base + k * n), (short)0, (int)bytes, 0x00020000);
+  }
+  __device__ __forceinline__ float ld(const float *base, int k) const {
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rsrc(base, k), (int)off, 0, 0));
+  }
+  __device__ __forceinline__ void st(float *base, int k, float v) const {
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), rsrc(base, k), (int)off, 0, 0);
+  }
+  __device__ __forceinline__ void add(float *base, int k, float v) const { st(base, k, ld(base, k) + v); }
+};
+
 // Rectangles with more tiles than this are visited cooperatively by the whole wavefront.
 constexpr int kCoopArea = 32;
 

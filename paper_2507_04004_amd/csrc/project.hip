@@ -157,20 +157,36 @@ __device__ __forceinline__ void sh_eval(int deg, float x, float y, float z, floa
   }
 }
 
-// Colour pre-activation per channel: SH . Y + 0.5 (contraction off, so the clamp decision
-// max(0, .) is identical in the forward and the backward).
-__device__ __forceinline__ void sh_colour_raw(int deg, int64_t n, int64_t g, const float *__restrict__ sh_dc,
-                                              const float *__restrict__ sh_rest, const float *Y, float raw[3]) {
+// Colour pre-activation per channel: SH . Y + 0.5, from coefficients already in registers
+// (dc [3], rest [3 (K-1)] with index 3 (k-1) + channel). Contraction off and one fixed order,
+// so the forward and the backward take the same max(0, .) clamp decision.
+__device__ __forceinline__ void sh_colour_raw_v(int deg, const float *dc, const float *rest, const float *Y,
+                                                float raw[3]) {
 #pragma clang fp contract(off)
   const int K = (deg + 1) * (deg + 1);
 #pragma unroll
-  for (int ch = 0; ch < 3; ++ch) raw[ch] = sh_dc[ch * n + g] * Y[0];
-  for (int k = 1; k < K; ++k) {
+  for (int ch = 0; ch < 3; ++ch) raw[ch] = dc[ch] * Y[0];
 #pragma unroll
-    for (int ch = 0; ch < 3; ++ch) raw[ch] = raw[ch] + sh_rest[(int64_t)(3 * (k - 1) + ch) * n + g] * Y[k];
+  for (int k = 1; k < 16; ++k) {
+    if (k < K) {
+#pragma unroll
+      for (int ch = 0; ch < 3; ++ch) raw[ch] = raw[ch] + rest[3 * (k - 1) + ch] * Y[k];
+    }
   }
 #pragma unroll
   for (int ch = 0; ch < 3; ++ch) raw[ch] = raw[ch] + 0.5f;
+}
+
+// Loads one Gaussian's coefficients (all lanes issue their loads together) and evaluates.
+__device__ __forceinline__ void sh_colour_raw(int deg, const Planes &P, const float *__restrict__ sh_dc,
+                                              const float *__restrict__ sh_rest, const float *Y, float raw[3]) {
+  const int K = (deg + 1) * (deg + 1);
+  float dc[3], rest[45];
+#pragma unroll
+  for (int ch = 0; ch < 3; ++ch) dc[ch] = P.ld(sh_dc, ch);
+#pragma unroll
+  for (int i = 0; i < 45; ++i) rest[i] = i < 3 * (K - 1) ? P.ld(sh_rest, i) : 0.f;
+  sh_colour_raw_v(deg, dc, rest, Y, raw);
 }
 
 __device__ __forceinline__ void view_dir(const ViewCam &cam, float mx, float my, float mz, float dir[3], float &dist) {
@@ -184,21 +200,19 @@ __global__ __launch_bounds__(256) void k_preprocess(ViewTable vt, const float *_
                                                     const float *__restrict__ scale, const float *__restrict__ rot,
                                                     const float *__restrict__ opacity,
                                                     const float *__restrict__ sh_dc,
-                                                    const float *__restrict__ sh_rest, float4 *__restrict__ rec_a,
-                                                    float4 *__restrict__ rec_b, float4 *__restrict__ rgb,
-                                                    short4 *__restrict__ rect, uint32_t *__restrict__ n_tiles,
-                                                    uint32_t *__restrict__ dkey) {
+                                                    const float *__restrict__ sh_rest, Card *__restrict__ card,
+                                                    uint32_t *__restrict__ n_tiles, uint32_t *__restrict__ dkey) {
   const int64_t n = vt.n;
   const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int vi = blockIdx.y;
   const bool in = g < n;  // every lane stays active: the wavefront-wide tile visit below needs all
   const ViewCam &cam = vt.v[vi];
   const int64_t e = (int64_t)vi * n + g;
-  const int64_t gg = in ? g : 0;
-  float mx = mean[gg], my = mean[n + gg], mz = mean[2 * n + gg];
+  const Planes P(n, (uint32_t)(in ? g : 0));
+  float mx = P.ld(mean, 0), my = P.ld(mean, 1), mz = P.ld(mean, 2);
   Splat s;
-  splat_decide(cam, mx, my, mz, scale[gg], scale[n + gg], scale[2 * n + gg], rot[gg], rot[n + gg], rot[2 * n + gg],
-               rot[3 * n + gg], opacity[gg], s);
+  splat_decide(cam, mx, my, mz, P.ld(scale, 0), P.ld(scale, 1), P.ld(scale, 2), P.ld(rot, 0), P.ld(rot, 1),
+               P.ld(rot, 2), P.ld(rot, 3), P.ld(opacity, 0), s);
   s.ok = s.ok && in;
   uint32_t cnt = 0;
   int tx0 = 0, ty0 = 0, tx1 = -1, ty1 = -1;
@@ -230,18 +244,21 @@ __global__ __launch_bounds__(256) void k_preprocess(ViewTable vt, const float *_
     float Y[16];
     sh_eval(vt.sh_degree, dir[0], dir[1], dir[2], Y);
     float raw[3];
-    sh_colour_raw(vt.sh_degree, n, g, sh_dc, sh_rest, Y, raw);
+    sh_colour_raw(vt.sh_degree, P, sh_dc, sh_rest, Y, raw);
     const uint32_t on = (raw[0] > 0.f ? 1u : 0u) | (raw[1] > 0.f ? 2u : 0u) | (raw[2] > 0.f ? 4u : 0u);
     col = make_float4(fmaxf(raw[0], 0.f), fmaxf(raw[1], 0.f), fmaxf(raw[2], 0.f), __uint_as_float(on));
   }
   if (!in) return;
   const bool vis = cnt > 0;
-  rec_a[e] = vis ? make_float4(s.u, s.v, s.o, s.pz) : make_float4(0.f, 0.f, 0.f, 0.f);
-  rec_b[e] = vis ? make_float4(s.a, s.b, s.c, s.kappa2) : make_float4(0.f, 0.f, 0.f, 0.f);
-  rgb[e] = col;
-  rect[e] = vis ? make_short4((short)tx0, (short)ty0, (short)tx1, (short)ty1) : make_short4(-1, -1, -1, -1);
+  const uint32_t key = vis ? __float_as_uint(s.pz) : 0xFFFFFFFFu;
+  Card &cd = card[e];
+  cd.a = vis ? make_float4(s.u, s.v, s.o, s.pz) : make_float4(0.f, 0.f, 0.f, 0.f);
+  cd.b = vis ? make_float4(s.a, s.b, s.c, s.kappa2) : make_float4(0.f, 0.f, 0.f, 0.f);
+  cd.c = col;
+  cd.d = vis ? make_uint4(pack_i16x2(tx0, ty0), pack_i16x2(tx1, ty1), cnt, key)
+             : make_uint4(0xFFFFFFFFu, 0xFFFFFFFFu, 0u, key);
   n_tiles[e] = cnt;
-  dkey[e] = vis ? __float_as_uint(s.pz) : 0xFFFFFFFFu;
+  dkey[e] = key;
 }
 
 // ---------------------------------------------------------------------------------------------
@@ -314,36 +331,133 @@ __device__ __forceinline__ void sh_term(int k, float x, float y, float z, float 
   }
 }
 
-// SINGLE: one view, so SH gradients go straight to memory instead of per-view accumulators.
-template <int DEG, bool SINGLE>
-__global__ __launch_bounds__(256) void k_preprocess_bwd(ViewTable vt, const float *__restrict__ mean,
-                                                        const float *__restrict__ scale,
-                                                        const float *__restrict__ rot,
-                                                        const float *__restrict__ opacity,
-                                                        const float *__restrict__ sh_dc,
-                                                        const float *__restrict__ sh_rest,
-                                                        const float4 *__restrict__ rgb,
-                                                        const uint32_t *__restrict__ n_tiles,
-                                                        const float *__restrict__ g2, ParamGradOut out,
-                                                        float *__restrict__ pose_partial /*[grid][V][6]*/) {
+// Stage a5 runs as two kernels over the Gaussians, each looping over the views:
+//   k_sh_bwd   colour: SH coefficient gradients and the view-direction gradient, which it
+//              leaves in grad2d slots 6-8 (the colour slots it has consumed);
+//   k_geo_bwd  geometry: mean, scale, rotation, opacity and the pose partials.
+// Split this way, the coefficient traffic (48 floats in, 48 out per Gaussian) runs at the
+// occupancy of a light kernel instead of that of the geometry chain rule.
+// OVERWRITE: every output element of the launched range is written (zeros where no view
+// contributes); otherwise the gradients are added to the outputs where some view contributes.
+template <int DEG, bool SINGLE, bool OVERWRITE>
+__global__ __launch_bounds__(256) void k_sh_bwd(ViewTable vt, const float *__restrict__ mean,
+                                                const float *__restrict__ sh_dc, const float *__restrict__ sh_rest,
+                                                const uint32_t *__restrict__ n_tiles, float *__restrict__ g2,
+                                                float *__restrict__ out_dc, float *__restrict__ out_rest) {
+  constexpr int K = (DEG + 1) * (DEG + 1);
+  constexpr int NR = 3 * (K - 1);
+  constexpr int NRA = NR > 0 ? NR : 1;
+  const int64_t n = vt.n;
+  const uint32_t gi = blockIdx.x * blockDim.x + threadIdx.x;
+  if ((int64_t)gi >= n) return;
+  // every plane is addressed by a scalar descriptor and one shared 32-bit lane offset
+  const Planes P(n, gi);
+  const float mx = P.ld(mean, 0), my = P.ld(mean, 1), mz = P.ld(mean, 2);
+  bool any_live = false, loaded = false;
+  float c_dc[3], c_rest[NRA];
+  float acc_dc[3] = {0.f, 0.f, 0.f};
+  float acc_rest[SINGLE ? 1 : NRA];
+#pragma unroll
+  for (int i = 0; i < (SINGLE ? 1 : NRA); ++i) acc_rest[i] = 0.f;
+  for (int vi = 0; vi < vt.n_views; ++vi) {
+    const ViewCam &cam = vt.v[vi];
+    const int64_t e = (int64_t)vi * n + gi;
+    if (n_tiles[e] == 0) continue;
+    const float2 G67 = *reinterpret_cast<const float2 *>(g2 + e * 12 + 6);
+    const float G8 = g2[e * 12 + 8];
+    if (G67.x == 0.f && G67.y == 0.f && G8 == 0.f) continue;
+    any_live = true;
+    if (!loaded) {  // all coefficients at once: one burst of independent loads
+#pragma unroll
+      for (int ch = 0; ch < 3; ++ch) c_dc[ch] = P.ld(sh_dc, ch);
+#pragma unroll
+      for (int i = 0; i < NR; ++i) c_rest[i] = P.ld(sh_rest, i);
+      loaded = true;
+    }
+    float dir[3], dist;
+    view_dir(cam, mx, my, mz, dir, dist);
+    float Y[16];
+    sh_eval(DEG, dir[0], dir[1], dir[2], Y);
+    // the forward's clamp decision, recomputed with the same operations
+    float raw[3];
+    sh_colour_raw_v(DEG, c_dc, c_rest, Y, raw);
+    const float gr[3] = {raw[0] > 0.f ? G67.x : 0.f, raw[1] > 0.f ? G67.y : 0.f, raw[2] > 0.f ? G8 : 0.f};
+#pragma unroll
+    for (int ch = 0; ch < 3; ++ch) acc_dc[ch] += gr[ch] * Y[0];
+    float gdir[3] = {0.f, 0.f, 0.f};
+#pragma unroll
+    for (int k = 1; k < K; ++k) {
+      float yk, d0, d1, d2;
+      sh_term(k, dir[0], dir[1], dir[2], yk, d0, d1, d2);
+      float sk = 0.f;
+#pragma unroll
+      for (int ch = 0; ch < 3; ++ch) {
+        const int i = 3 * (k - 1) + ch;
+        sk += gr[ch] * c_rest[i];
+        if constexpr (SINGLE) {
+          if (out_rest) {
+            if constexpr (OVERWRITE) P.st(out_rest, i, gr[ch] * yk);
+            else P.add(out_rest, i, gr[ch] * yk);
+          }
+        } else {
+          acc_rest[i] += gr[ch] * yk;
+        }
+      }
+      gdir[0] += sk * d0;
+      gdir[1] += sk * d1;
+      gdir[2] += sk * d2;
+    }
+    // d dir / d mean = (I - dir dir^T) / dist
+    const float dd = gdir[0] * dir[0] + gdir[1] * dir[1] + gdir[2] * dir[2];
+    const float idist = 1.0f / dist;
+    float *slot = g2 + e * 12 + 6;
+    slot[0] = (gdir[0] - dd * dir[0]) * idist;
+    slot[1] = (gdir[1] - dd * dir[1]) * idist;
+    slot[2] = (gdir[2] - dd * dir[2]) * idist;
+  }
+  if (out_dc && (OVERWRITE || any_live)) {
+#pragma unroll
+    for (int ch = 0; ch < 3; ++ch) {
+      if constexpr (OVERWRITE) P.st(out_dc, ch, acc_dc[ch]);
+      else P.add(out_dc, ch, acc_dc[ch]);
+    }
+  }
+  if (out_rest && NR > 0) {
+    if constexpr (SINGLE) {
+      if constexpr (OVERWRITE) {
+        if (!any_live)
+#pragma unroll
+          for (int i = 0; i < NR; ++i) P.st(out_rest, i, 0.f);
+      }
+    } else if (OVERWRITE || any_live) {
+#pragma unroll
+      for (int i = 0; i < NR; ++i) {
+        if constexpr (OVERWRITE) P.st(out_rest, i, acc_rest[i]);
+        else P.add(out_rest, i, acc_rest[i]);
+      }
+    }
+  }
+}
+
+template <bool OVERWRITE>
+__global__ __launch_bounds__(256) void k_geo_bwd(ViewTable vt, const float *__restrict__ mean,
+                                                 const float *__restrict__ scale, const float *__restrict__ rot,
+                                                 const float *__restrict__ opacity,
+                                                 const uint32_t *__restrict__ n_tiles, const float *__restrict__ g2,
+                                                 ParamGradOut out, float *__restrict__ pose_partial /*[grid][V][6]*/) {
   __shared__ float red[8];
   const int64_t n = vt.n;
   const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const bool in = g < n;
-  constexpr int deg = DEG;
-  constexpr int K = (DEG + 1) * (DEG + 1);
+  const bool in = g < n;  // every lane stays for the block sums of the pose
+  const Planes P(n, (uint32_t)g);
   float mx = 0, my = 0, mz = 0, sx = 1, sy = 1, sz = 1, qw = 1, qx = 0, qy = 0, qz = 0, o = 0;
   if (in) {
-    mx = mean[g]; my = mean[n + g]; mz = mean[2 * n + g];
-    sx = scale[g]; sy = scale[n + g]; sz = scale[2 * n + g];
-    qw = rot[g]; qx = rot[n + g]; qy = rot[2 * n + g]; qz = rot[3 * n + g];
-    o = opacity[g];
+    mx = P.ld(mean, 0); my = P.ld(mean, 1); mz = P.ld(mean, 2);
+    sx = P.ld(scale, 0); sy = P.ld(scale, 1); sz = P.ld(scale, 2);
+    qw = P.ld(rot, 0); qx = P.ld(rot, 1); qy = P.ld(rot, 2); qz = P.ld(rot, 3);
+    o = P.ld(opacity, 0);
   }
   float acc_m[3] = {0, 0, 0}, acc_s[3] = {0, 0, 0}, acc_q[4] = {0, 0, 0, 0}, acc_o = 0;
-  float acc_dc[3] = {0, 0, 0};
-  float acc_rest[SINGLE ? 1 : 3 * (K - 1) + 1];
-#pragma unroll
-  for (int i = 0; i < (SINGLE ? 1 : 3 * (K - 1) + 1); ++i) acc_rest[i] = 0.f;
   bool any_view = false;
 
   for (int vi = 0; vi < vt.n_views; ++vi) {
@@ -364,47 +478,7 @@ __global__ __launch_bounds__(256) void k_preprocess_bwd(ViewTable vt, const floa
     }
     if (live) {
       any_view = true;
-      // colour first (its live values do not overlap the geometry's): SH coefficients and the
-      // view direction. The forward recorded which channels were clamped at zero.
-      float dir[3], dist;
-      view_dir(cam, mx, my, mz, dir, dist);
-      float Y[16];
-      sh_eval(deg, dir[0], dir[1], dir[2], Y);
-      const uint32_t on = __float_as_uint(rgb[e].w);
-      float gr[3];
-#pragma unroll
-      for (int ch = 0; ch < 3; ++ch) gr[ch] = ((on >> ch) & 1u) ? G[6 + ch] : 0.f;
-#pragma unroll
-      for (int ch = 0; ch < 3; ++ch) acc_dc[ch] += gr[ch] * Y[0];
-      // view-direction gradient: sum_k (sum_ch dL/draw_ch SH_{k,ch}) grad Y_k. One SH term per
-      // iteration (not unrolled), so the coefficient loads stay in flight one term at a time.
-      float gdir[3] = {0.f, 0.f, 0.f};
-      if constexpr (DEG >= 1) {
-        const float gmax = fmaxf(fabsf(gr[0]), fmaxf(fabsf(gr[1]), fabsf(gr[2])));
-#pragma unroll 1
-        for (int k = 1; k < K; ++k) {
-          float yk, d0, d1, d2;
-          sh_term(k, dir[0], dir[1], dir[2], yk, d0, d1, d2);
-          float sk = 0.f;
-#pragma unroll
-          for (int ch = 0; ch < 3; ++ch) {
-            const int64_t plane = (int64_t)(3 * (k - 1) + ch) * n + g;
-            sk += gr[ch] * sh_rest[plane];
-            if constexpr (SINGLE) {
-              if (out.sh_rest && gmax != 0.f) out.sh_rest[plane] += gr[ch] * yk;
-            } else {
-              acc_rest[3 * (k - 1) + ch] += gr[ch] * yk;
-            }
-          }
-          gdir[0] += sk * d0;
-          gdir[1] += sk * d1;
-          gdir[2] += sk * d2;
-        }
-      }
-      const float dd = gdir[0] * dir[0] + gdir[1] * dir[1] + gdir[2] * dir[2];
-      const float idist = 1.0f / dist;
-      const float gdf[3] = {(gdir[0] - dd * dir[0]) * idist, (gdir[1] - dd * dir[1]) * idist,
-                            (gdir[2] - dd * dir[2]) * idist};
+      const float gdf[3] = {G[6], G[7], G[8]};  // direction path, left by k_sh_bwd
       Splat s;
       splat_decide(cam, mx, my, mz, sx, sy, sz, qw, qx, qy, qz, o, s);
       const float gu = G[0], gv = G[1], ga = G[2], gb = G[3], gc = G[4], go = G[5];
@@ -535,21 +609,21 @@ __global__ __launch_bounds__(256) void k_preprocess_bwd(ViewTable vt, const floa
       if (threadIdx.x == 0) pose_partial[((int64_t)blockIdx.x * vt.n_views + vi) * 6 + i] = t;
     }
   }
-  if (!in || !any_view) return;
+  if (!in || (!OVERWRITE && !any_view)) return;
+  auto put = [&](float *base, int i, float v) {
+    if constexpr (OVERWRITE) P.st(base, i, v);
+    else P.add(base, i, v);
+  };
   if (out.mean)
-    for (int i = 0; i < 3; ++i) out.mean[i * n + g] += acc_m[i];
-  if (out.scale)
-    for (int i = 0; i < 3; ++i) out.scale[i * n + g] += acc_s[i];
-  if (out.rot)
-    for (int i = 0; i < 4; ++i) out.rot[i * n + g] += acc_q[i];
-  if (out.opacity) out.opacity[g] += acc_o;
-  if (out.sh_dc)
-    for (int i = 0; i < 3; ++i) out.sh_dc[i * n + g] += acc_dc[i];
-  if constexpr (!SINGLE) {
-    if (out.sh_rest)
 #pragma unroll
-      for (int i = 0; i < 3 * (K - 1); ++i) out.sh_rest[(int64_t)i * n + g] += acc_rest[i];
-  }
+    for (int i = 0; i < 3; ++i) put(out.mean, i, acc_m[i]);
+  if (out.scale)
+#pragma unroll
+    for (int i = 0; i < 3; ++i) put(out.scale, i, acc_s[i]);
+  if (out.rot)
+#pragma unroll
+    for (int i = 0; i < 4; ++i) put(out.rot, i, acc_q[i]);
+  if (out.opacity) put(out.opacity, 0, acc_o);
 }
 
 }  // namespace gs
@@ -561,8 +635,7 @@ hipError_t launch_preprocess(const ViewTable &vt, const gs_gaussians &g, const g
   if (vt.n == 0) return hipSuccess;
   dim3 grid((unsigned)((vt.n + 255) / 256), (unsigned)vt.n_views);
   hipLaunchKernelGGL(k_preprocess, grid, dim3(256), 0, st, vt, g.mean, g.scale, g.rot, g.opacity, g.sh_dc,
-                     g.sh_rest, (float4 *)p.rec_a, (float4 *)p.rec_b, (float4 *)p.rgb, (short4 *)p.rect, p.n_tiles,
-                     p.dkey);
+                     g.sh_rest, (Card *)p.card, p.n_tiles, p.dkey);
   return hipGetLastError();
 }
 
@@ -574,7 +647,8 @@ struct PosePtrs {
   float *p[kMaxViews];
 };
 
-__global__ void k_pose_reduce_tab(const float *__restrict__ partial, int32_t n_blocks, int32_t n_views, PosePtrs out) {
+__global__ void k_pose_reduce_tab(const float *__restrict__ partial, int32_t n_blocks, int32_t n_views, PosePtrs out,
+                                  int32_t overwrite) {
   __shared__ double red[256];
   const int vi = blockIdx.x / 6, i = blockIdx.x % 6;
   double s = 0.0;
@@ -585,40 +659,57 @@ __global__ void k_pose_reduce_tab(const float *__restrict__ partial, int32_t n_b
     if (threadIdx.x < off) red[threadIdx.x] += red[threadIdx.x + off];
     __syncthreads();
   }
-  if (threadIdx.x == 0 && out.p[vi]) out.p[vi][i] += (float)red[0];
+  if (threadIdx.x == 0 && out.p[vi]) {
+    if (overwrite) out.p[vi][i] = (float)red[0];
+    else out.p[vi][i] += (float)red[0];
+  }
 }
 
-hipError_t launch_preprocess_bwd(const ViewTable &vt, const gs_gaussians &g, const gs_projected &p, const float *g2,
+hipError_t launch_preprocess_bwd(const ViewTable &vt, const gs_gaussians &g, const gs_projected &p, float *g2,
                                  const gs_grads &out, float *const *pose_out, float *pose_partial, hipStream_t st) {
   if (vt.n == 0) return hipSuccess;
   const int64_t nb = preprocess_bwd_blocks(vt.n);
-  ParamGradOut po{out.mean, out.scale, out.rot, out.opacity, out.sh_dc, out.sh_rest};
-  switch (vt.sh_degree) {
-#define GS_PRE_BWD(D)                                                                                          \
+  const bool ow = out.overwrite != 0;
+  const bool single = vt.n_views == 1;
+  // colour first: it hands the direction gradient to the geometry kernel through grad2d
+  {
+    switch (vt.sh_degree) {
+#define GS_SH_BWD(D, S, O)                                                                                     \
+  hipLaunchKernelGGL((k_sh_bwd<D, S, O>), dim3((unsigned)nb), dim3(256), 0, st, vt, g.mean, g.sh_dc, g.sh_rest, \
+                     p.n_tiles, g2, out.sh_dc, out.sh_rest)
+#define GS_SH_CASE(D)                                                                                          \
   case D:                                                                                                      \
-    if (vt.n_views == 1)                                                                                       \
-      hipLaunchKernelGGL((k_preprocess_bwd<D, true>), dim3((unsigned)nb), dim3(256), 0, st, vt, g.mean, g.scale,\
-                         g.rot, g.opacity, g.sh_dc, g.sh_rest, (const float4 *)p.rgb, p.n_tiles, g2, po,         \
-                         pose_partial);                \
-    else                                                                                                       \
-      hipLaunchKernelGGL((k_preprocess_bwd<D, false>), dim3((unsigned)nb), dim3(256), 0, st, vt, g.mean,       \
-                         g.scale, g.rot, g.opacity, g.sh_dc, g.sh_rest, (const float4 *)p.rgb, p.n_tiles, g2,  \
-                         po, pose_partial);                                                                      \
+    if (single) {                                                                                              \
+      if (ow) GS_SH_BWD(D, true, true); else GS_SH_BWD(D, true, false);                                        \
+    } else {                                                                                                   \
+      if (ow) GS_SH_BWD(D, false, true); else GS_SH_BWD(D, false, false);                                      \
+    }                                                                                                          \
     break;
-    GS_PRE_BWD(0)
-    GS_PRE_BWD(1)
-    GS_PRE_BWD(2)
-    GS_PRE_BWD(3)
-#undef GS_PRE_BWD
-    default:
-      return hipErrorInvalidValue;
+      GS_SH_CASE(0)
+      GS_SH_CASE(1)
+      GS_SH_CASE(2)
+      GS_SH_CASE(3)
+#undef GS_SH_CASE
+#undef GS_SH_BWD
+      default:
+        return hipErrorInvalidValue;
+    }
+    hipError_t err = hipGetLastError();
+    if (err != hipSuccess) return err;
   }
+  ParamGradOut po{out.mean, out.scale, out.rot, out.opacity, out.sh_dc, out.sh_rest};
+  if (ow)
+    hipLaunchKernelGGL(k_geo_bwd<true>, dim3((unsigned)nb), dim3(256), 0, st, vt, g.mean, g.scale, g.rot, g.opacity,
+                       p.n_tiles, (const float *)g2, po, pose_partial);
+  else
+    hipLaunchKernelGGL(k_geo_bwd<false>, dim3((unsigned)nb), dim3(256), 0, st, vt, g.mean, g.scale, g.rot,
+                       g.opacity, p.n_tiles, (const float *)g2, po, pose_partial);
   hipError_t err = hipGetLastError();
   if (err != hipSuccess) return err;
   PosePtrs pp;
   for (int i = 0; i < kMaxViews; ++i) pp.p[i] = i < vt.n_views ? pose_out[i] : nullptr;
   hipLaunchKernelGGL(k_pose_reduce_tab, dim3((unsigned)(6 * vt.n_views)), dim3(256), 0, st, pose_partial, (int32_t)nb,
-                     vt.n_views, pp);
+                     vt.n_views, pp, (int32_t)ow);
   return hipGetLastError();
 }
 

@@ -81,21 +81,38 @@ def gaussians_struct(mean, scale, rot, opacity, sh_dc, sh_rest, deg) -> N.Gaussi
 
 @dataclasses.dataclass
 class Splats:
-    rec_a: torch.Tensor
-    rec_b: torch.Tensor
-    rgb: torch.Tensor
-    rect: torch.Tensor
+    """Splat records: card [n][16] float32 (64 B each: centre/opacity/depth, conic/kappa^2,
+    colour/clamp bits, tile rectangle/tile count/depth key), n_tiles [n], dkey [n]."""
+    card: torch.Tensor
     n_tiles: torch.Tensor
     dkey: torch.Tensor
 
     @staticmethod
     def empty(n, device) -> "Splats":
-        f = lambda *s: torch.empty(*s, dtype=torch.float32, device=device)
-        return Splats(f(n, 4), f(n, 4), f(n, 4), torch.empty(n, 4, dtype=torch.int16, device=device),
-                      torch.empty(n, dtype=torch.int32, device=device), torch.empty(n, dtype=torch.int32, device=device))
+        card = torch.empty(n, 16, dtype=torch.float32, device=device)
+        if card.data_ptr() % 64:
+            raise RuntimeError("splat cards must be 64-byte aligned")
+        return Splats(card, torch.empty(n, dtype=torch.int32, device=device),
+                      torch.empty(n, dtype=torch.int32, device=device))
+
+    @property
+    def rec_a(self) -> torch.Tensor:
+        return self.card[:, 0:4]
+
+    @property
+    def rec_b(self) -> torch.Tensor:
+        return self.card[:, 4:8]
+
+    @property
+    def rgb(self) -> torch.Tensor:
+        return self.card[:, 8:12]
+
+    @property
+    def rect(self) -> torch.Tensor:
+        return self.card[:, 12:14].contiguous().view(torch.int16)
 
     def struct(self) -> N.Projected:
-        return N.Projected(*[_p(t) for t in (self.rec_a, self.rec_b, self.rgb, self.rect, self.n_tiles, self.dkey)])
+        return N.Projected(_p(self.card), _p(self.n_tiles), _p(self.dkey))
 
 
 @dataclasses.dataclass
@@ -227,10 +244,17 @@ class ParamGrads:
         return ParamGrads(z(gm.mean), z(gm.scale), z(gm.rot), z(gm.opacity), z(gm.sh_dc), z(gm.sh_rest),
                           torch.zeros(6, dtype=torch.float32, device=gm.mean.device))
 
-    def struct(self, scratch: torch.Tensor) -> N.Grads:
+    @staticmethod
+    def empty(gm: GaussianMap) -> "ParamGrads":
+        """Uninitialised outputs, for a backward called with overwrite=True (writes every element)."""
+        e = torch.empty_like
+        return ParamGrads(e(gm.mean), e(gm.scale), e(gm.rot), e(gm.opacity), e(gm.sh_dc), e(gm.sh_rest),
+                          torch.empty(6, dtype=torch.float32, device=gm.mean.device))
+
+    def struct(self, scratch: torch.Tensor, overwrite: bool = False) -> N.Grads:
         rest = self.sh_rest if self.sh_rest.numel() else None
         return N.Grads(_p(self.mean), _p(self.scale), _p(self.rot), _p(self.opacity), _p(self.sh_dc), _p(rest),
-                       _p(self.pose), _p(scratch), scratch.numel())
+                       _p(self.pose), _p(scratch), scratch.numel(), int(bool(overwrite)))
 
 
 def grads_scratch(n: int, pixels: int, device, views: int = 1) -> torch.Tensor:
@@ -239,12 +263,13 @@ def grads_scratch(n: int, pixels: int, device, views: int = 1) -> torch.Tensor:
 
 def render_bwd(gs: N.Gaussians, cs: N.Camera, spl: Splats, bins: TileBins, fr: Frame, dL_dC, dL_dD, dL_dO,
                blend_depth: int, grads: ParamGrads, scratch: torch.Tensor, lidar: LidarHits | None = None,
-               grad_scale: torch.Tensor | None = None) -> ParamGrads:
+               grad_scale: torch.Tensor | None = None, overwrite: bool = False) -> ParamGrads:
+    """overwrite=False adds the gradients to `grads`; overwrite=True writes every element."""
     ls = lidar.struct(None, grad_scale) if lidar is not None and lidar.m > 0 else None
     N.check(N.lib().gs_render_bwd(C.byref(gs), C.byref(cs), C.byref(spl.struct()), C.byref(bins.struct()),
                                   C.byref(fr.struct()), _p(dL_dC), _p(dL_dD), _p(dL_dO),
                                   C.byref(ls) if ls is not None else None, blend_depth,
-                                  C.byref(grads.struct(scratch)), _stream()), "gs_render_bwd")
+                                  C.byref(grads.struct(scratch, overwrite)), _stream()), "gs_render_bwd")
     return grads
 
 
@@ -305,7 +330,7 @@ class GSRender(torch.autograd.Function):
         dev = mean.device
         gs = gaussians_struct(mean, scale, rot, opacity, sh_dc, sh_rest, ctx.deg)
         gm = GaussianMap(mean, scale, rot, opacity, sh_dc, sh_rest, ctx.deg)
-        grads = ParamGrads.zeros(gm)
+        grads = ParamGrads.empty(gm)  # the backward writes every element
         cs = ctx.cs
         gC = torch.zeros_like(ctx.fr.color) if gC is None else gC.contiguous()
         gD = None if gD is None else gD.contiguous()
@@ -316,7 +341,7 @@ class GSRender(torch.autograd.Function):
             scale_t = (torch.ones(1, device=dev) if gL is None else gL.reshape(1).float().contiguous())
         scratch = grads_scratch(gs.n, cs.w * cs.h, dev)
         render_bwd(gs, cs, ctx.spl, ctx.bins, ctx.fr, gC, gD, gO, ctx.settings.blend_depth, grads, scratch,
-                   lidar, scale_t)
+                   lidar, scale_t, overwrite=True)
         gpose = grads.pose if ctx.has_pose else None
         return None, grads.mean, grads.scale, grads.rot, grads.opacity, grads.sh_dc, grads.sh_rest, gpose
 

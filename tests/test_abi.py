@@ -38,9 +38,9 @@ def _cam(**kw):
 
 def test_host_argument_errors():
     L = N.lib()
-    dummy = C.c_void_p(16)  # never dereferenced: validation fails first
+    dummy = C.c_void_p(64)  # never dereferenced: validation fails first
     g = N.Gaussians(10, 0, dummy, dummy, dummy, dummy, dummy, None)
-    proj = N.Projected(*([dummy] * 6))
+    proj = N.Projected(*([dummy] * 3))
     cases = [
         (dict(), dict(sh_degree=5)),
         (dict(w=0), dict()),
@@ -60,6 +60,11 @@ def test_host_argument_errors():
     bins = N.Bins(16, 16, 100, dummy, dummy, dummy, dummy, 1)  # scratch too small
     assert L.gs_bin_sort(C.byref(proj), 10, C.byref(_cam()), C.byref(bins), None) == N.GS_ERR_INVALID_ARG
     assert b"scratch" in L.gs_last_error()
+    # splat cards must sit on 64-byte boundaries (one memory line per record)
+    skew = N.Projected(C.c_void_p(64 + 16), dummy, dummy)
+    bins_ok = N.Bins(16, 16, 100, dummy, dummy, dummy, dummy, 1 << 30)
+    assert L.gs_bin_sort(C.byref(skew), 10, C.byref(_cam()), C.byref(bins_ok), None) == N.GS_ERR_INVALID_ARG
+    assert b"aligned" in L.gs_last_error()
     img = N.Image(*([dummy] * 5))
     bins_ok = N.Bins(16, 16, 100, dummy, dummy, dummy, dummy, 1 << 30)
     assert L.gs_render_fwd(C.byref(proj), 10, C.byref(bins_ok), C.byref(_cam()), 100, None, C.byref(img),

@@ -193,6 +193,42 @@ def test_backward_matches_oracle(case, which):
     assert_grads_close(got, ref)
 
 
+@pytest.mark.parametrize("case", ["street_sh3_posed", "small_sh0"])
+def test_backward_overwrite_and_accumulate(case):
+    """overwrite=1 writes every element (NaN garbage beforehand does not leak through) and
+    matches accumulation into zeros; overwrite=0 adds to what the outputs hold. (Runs are
+    compared to float32 summation-order level: the compositing backward adds its per-splat
+    sums with float atomics.)"""
+    g, cam = CASES[case]()
+    run = GpuRun(g, cam)
+    gC, gD, gO = S.upstream_grads(cam.w * cam.h, seed=13)
+    gC, gD, gO = gC.reshape(3, cam.h, cam.w), gD.reshape(cam.h, cam.w), gO.reshape(cam.h, cam.w)
+    acc = run.backward(gC, gD, gO)
+    junk = R.ParamGrads.empty(run.gm)
+    for t in (junk.mean, junk.scale, junk.rot, junk.opacity, junk.sh_dc, junk.sh_rest, junk.pose):
+        t.fill_(float("nan"))
+    ow = run.backward(gC, gD, gO, overwrite=True, grads=junk)
+    for k in acc:
+        assert np.isfinite(ow[k]).all(), k
+        assert np.array_equal(ow[k] == 0, acc[k] == 0) or k == "pose", k  # untouched Gaussians read 0
+        np.testing.assert_allclose(ow[k], acc[k], rtol=1e-4, atol=1e-6 * max(1.0, np.abs(acc[k]).max(initial=0)),
+                                   err_msg=k)
+    base = R.ParamGrads.zeros(run.gm)
+    rng = np.random.default_rng(3)
+    pre = {}
+    for k in acc:
+        t = getattr(base, k)
+        v = rng.standard_normal(tuple(t.shape)).astype(np.float32)
+        t.copy_(torch.from_numpy(v))
+        pre[k] = v.astype(np.float64)
+    added = run.backward(gC, gD, gO, grads=base)
+    for k in acc:
+        untouched = acc[k] == 0
+        assert np.array_equal(added[k][untouched], pre[k][untouched]), k
+        np.testing.assert_allclose(added[k] - pre[k], acc[k], rtol=1e-4,
+                                   atol=1e-6 * max(1.0, np.abs(acc[k]).max(initial=0)), err_msg=k)
+
+
 def test_lidar_depth_term():
     g, cam, pix = S.config_small(0)
     gp = S.perturb(g, 0.01, seed=1)

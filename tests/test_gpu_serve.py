@@ -47,7 +47,7 @@ def test_served_frames_equal_plain_renders(batched):
     assert stats["requests"] == len(cams) and stats["p99_ms"] >= stats["p50_ms"] > 0
     # every served frame equals the plain single-view render of its camera
     for i, (c, fr) in enumerate(zip(cams, stats["frames"])):
-        ref = GpuRun(g, c).image()
+        ref = GpuRun(g, c, tile=server.tile, blend_depth=server.bd).image()
         for key in ("color", "depth", "alpha", "t_final"):
             assert np.array_equal(getattr(fr, key).cpu().numpy(), ref[key]), (i, key)
     server.close()
