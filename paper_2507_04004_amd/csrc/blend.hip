@@ -176,9 +176,7 @@ __device__ __forceinline__ void stage(const uint32_t *__restrict__ vals, uint32_
     const uint32_t e = vals[start + k];
     if (s_e) s_e[k] = e;
     const Card &cd = card[e];
-    s_a[k] = cd.a;
-    s_b[k] = cd.b;
-    s_c[k] = cd.c;
+    stage_card(cd.a, cd.b, cd.c, s_a[k], s_b[k], s_c[k]);
   }
 }
 
@@ -205,8 +203,8 @@ struct PixState {
 // state. A splat with alpha < 1/255 is skipped; a pixel stops before a splat that would take
 // its T below 1e-4. Selects instead of branches: a skipped splat adds an exact zero, so the
 // sums equal those of a branching walk bit for bit. The wavefront leaves once all its
-// pixels have stopped.
-template <int PPT>
+// pixels have stopped. CNT: also count the contributors (only when that output is wanted).
+template <int PPT, bool CNT>
 __device__ __forceinline__ void composite_run(const float4 *s_a, const float4 *s_b, const float4 *s_c, int cnt,
                                               const float (&px)[PPT], const float (&py)[PPT], int pos0,
                                               PixState (&st)[PPT]) {
@@ -222,8 +220,9 @@ __device__ __forceinline__ void composite_run(const float4 *s_a, const float4 *s
 #pragma unroll
       for (int k = 0; k < PPT; ++k) {
         PixState &p = st[k];
-        const float power = splat_power(B.x, B.y, B.z, px[k] - A.x, py[k] - A.y);
-        const float alpha = fminf(kAlphaMax, splat_alpha_raw(A.z, power));
+        float m, qc;
+        const float p2 = splat_p2(A, B, px[k] - A.x, py[k] - A.y, m, qc);
+        const float alpha = fminf(kAlphaMax, B.y * __builtin_amdgcn_exp2f(p2));
         const float Tn = p.T * (1.f - alpha);
         const bool blend = !p.stopped && alpha >= kAlphaMin;
         const bool stop = blend && Tn < kTMin;
@@ -233,18 +232,18 @@ __device__ __forceinline__ void composite_run(const float4 *s_a, const float4 *s
         p.C0 += w * Cc.x;
         p.C1 += w * Cc.y;
         p.C2 += w * Cc.z;
-        p.D += w * A.w;
+        p.D += w * B.z;
         p.O += w;
         p.T = take ? Tn : p.T;
         p.last = take ? pos0 + j : p.last;
-        p.nc += take ? 1 : 0;
+        if constexpr (CNT) p.nc += take ? 1 : 0;
       }
     }
   }
 }
 
 // ---- forward pass 1: every chunk from transmittance 1 ------------------------------------
-template <int TW, int TH, int BD, int NT>
+template <int TW, int TH, int BD, int NT, bool CNT>
 __global__ __launch_bounds__(NT) void k_blend_chunk(ViewTable vt, ImgTable it, const Card *__restrict__ card,
                                                     const uint32_t *__restrict__ vals,
                                                     const uint32_t *__restrict__ range,
@@ -275,7 +274,7 @@ __global__ __launch_bounds__(NT) void k_blend_chunk(ViewTable vt, ImgTable it, c
     tile.pixel(k, inside[k], px[k], py[k], pi[k]);
     st[k] = PixState{1.f, 0.f, 0.f, 0.f, 0.f, 0.f, -1, 0, !inside[k]};
   }
-  composite_run<PPT>(s_a, s_b, s_c, cnt, px, py, 0, st);
+  composite_run<PPT, CNT>(s_a, s_b, s_c, cnt, px, py, 0, st);
 #pragma unroll
   for (int k = 0; k < PPT; ++k) {
     if (!inside[k]) continue;
@@ -370,7 +369,7 @@ __global__ __launch_bounds__(TW * TH) void k_blend_scan(ViewTable vt, ImgTable i
 }
 
 // ---- forward pass 3: exact compositing of each pixel's stop chunk (chunk-parallel) -------
-template <int TW, int TH, int BD, int NT>
+template <int TW, int TH, int BD, int NT, bool CNT>
 __global__ __launch_bounds__(NT) void k_blend_fix(ViewTable vt, ImgTable it, const Card *__restrict__ card,
                                                   const uint32_t *__restrict__ vals,
                                                   const uint32_t *__restrict__ range,
@@ -409,7 +408,7 @@ __global__ __launch_bounds__(NT) void k_blend_fix(ViewTable vt, ImgTable it, con
   const int cnt = (int)min<uint32_t>(BD, e0 - cs);
   stage<BD, NT>(vals, cs, cnt, card, s_a, s_b, s_c, nullptr);
   __syncthreads();
-  composite_run<PPT>(s_a, s_b, s_c, cnt, px, py, (int)(c * BD), st);
+  composite_run<PPT, CNT>(s_a, s_b, s_c, cnt, px, py, (int)(c * BD), st);
 #pragma unroll
   for (int k = 0; k < PPT; ++k) {
     if (!pending[k]) continue;
@@ -459,9 +458,11 @@ __global__ __launch_bounds__(TW * TH) void k_blend_suffix(ViewTable vt, const ui
 }
 
 // ---- backward: every chunk back to front ---------------------------------------------------
+// Row-local DPP read of a neighbour lane (every pattern used reads inside its own row, so no
+// lane sees the bound value); in this form the compiler folds it into the consuming add.
 template <int CTRL>
 __device__ __forceinline__ float dpp(float v) {
-  return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), CTRL, 0xF, 0xF, false));
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, true));
 }
 
 // Sum over the wavefront of ten values; afterwards lane l holds the total of value l & 15.
@@ -517,6 +518,15 @@ struct PixGrad {
   float px, py;
 };
 
+// Gradient record per splat and view (grad2d, 12 floats), summed over pixels in the units of
+// the staged splat form (the geometry kernel applies the constant factors):
+//   0: sum dp (a' dx + b'/2 dy)      -> dL/du = slot / kA
+//   1: sum dp (b'/2 dx + c' dy)      -> dL/dv = slot / kA
+//   2: sum dp dx^2                   -> dL/da = -slot / 2
+//   3: sum dp dx dy                  -> dL/db = -slot
+//   4: sum dp dy^2                   -> dL/dc = -slot / 2
+//   5: dL/do;  6-8: dL/d(r, g, b);  9: dL/d(depth)
+// with dp = dL/dpower = dL/dalpha * o exp(power) (zero where alpha is clamped at 0.99).
 template <int TW, int TH, int BD, int NT>
 __global__ __launch_bounds__(NT) void k_blend_bwd_chunk(ViewTable vt, ImgTable it, GradTable gtab,
                                                         const Card *__restrict__ card,
@@ -552,8 +562,9 @@ __global__ __launch_bounds__(NT) void k_blend_bwd_chunk(ViewTable vt, ImgTable i
     PixGrad &p = pg[k];
     bool inside;
     int64_t pi;
-    tile.pixel(k, inside, p.px, p.py, pi);
-    p = PixGrad{1.f, 0.f, 0.f, 0.f, 0.f, 0.f, 1.f, 0.f, 0.f, 0.f, 0.f, -1, p.px, p.py};
+    float pxf, pyf;
+    tile.pixel(k, inside, pxf, pyf, pi);
+    p = PixGrad{1.f, 0.f, 0.f, 0.f, 0.f, 0.f, 1.f, 0.f, 0.f, 0.f, 0.f, -1, pxf, pyf};
     if (inside) {
       p.Tfin = im.t_final[pi];
       p.ll = min(im.last[pi] - (int)(c * BD), cnt - 1);
@@ -587,53 +598,58 @@ __global__ __launch_bounds__(NT) void k_blend_bwd_chunk(ViewTable vt, ImgTable i
   const int q = lane & 15;
   const bool depth_live = __any(depth_any);
   for (int j = maxll; j >= 0; --j) {
+    const float4 A = s_a[j], B = s_b[j], Cc = s_c[j];
+    // alpha at every pixel first; a splat no pixel of the wavefront blends costs only this
+    float dxs[PPT], dys[PPT], ms[PPT], qcs[PPT], exs[PPT], ars[PPT];
+    bool act[PPT];
+    bool any = false;
+#pragma unroll
+    for (int k = 0; k < PPT; ++k) {
+      dxs[k] = pg[k].px - A.x;
+      dys[k] = pg[k].py - A.y;
+      const float p2 = splat_p2(A, B, dxs[k], dys[k], ms[k], qcs[k]);
+      exs[k] = __builtin_amdgcn_exp2f(p2);
+      ars[k] = B.y * exs[k];
+      act[k] = j <= pg[k].ll && fminf(kAlphaMax, ars[k]) >= kAlphaMin;
+      any = any || act[k];
+    }
+    if (!__any(any)) continue;
     float g[10];
 #pragma unroll
     for (int v = 0; v < 10; ++v) g[v] = 0.f;
-    bool contrib_any = false;
-    const float4 A = s_a[j], B = s_b[j], Cc = s_c[j];
 #pragma unroll
     for (int k = 0; k < PPT; ++k) {
       PixGrad &p = pg[k];
-      if (j > p.ll) continue;
-      const float dx = p.px - A.x, dy = p.py - A.y;
-      const float power = splat_power(B.x, B.y, B.z, dx, dy);
-      const float ex = __expf(power);
-      const float ar = A.z * ex;  // the same two operations as splat_alpha_raw
-      const float alpha = fminf(kAlphaMax, ar);
-      if (alpha < kAlphaMin) continue;
-      contrib_any = true;
+      const float alpha = fminf(kAlphaMax, ars[k]);
       const float one_m = 1.f - alpha;
       const float inv = __builtin_amdgcn_rcpf(one_m);  // 1 ulp; one_m >= 0.01
-      p.T = p.T * inv;  // transmittance in front of this splat
-      const float w = alpha * p.T;
+      p.T = act[k] ? p.T * inv : p.T;                    // transmittance in front of this splat
+      const float w = act[k] ? alpha * p.T : 0.f;
       g[6] += p.gC0 * w;
       g[7] += p.gC1 * w;
       g[8] += p.gC2 * w;
       float dLda = p.gC0 * (Cc.x - p.A0) + p.gC1 * (Cc.y - p.A1) + p.gC2 * (Cc.z - p.A2);
-      p.A0 = alpha * Cc.x + one_m * p.A0;
-      p.A1 = alpha * Cc.y + one_m * p.A1;
-      p.A2 = alpha * Cc.z + one_m * p.A2;
+      p.A0 = act[k] ? alpha * Cc.x + one_m * p.A0 : p.A0;
+      p.A1 = act[k] ? alpha * Cc.y + one_m * p.A1 : p.A1;
+      p.A2 = act[k] ? alpha * Cc.z + one_m * p.A2 : p.A2;
       if (depth_live) {
         g[9] += p.gD * w;
-        dLda += p.gD * (A.w - p.AD);
-        p.AD = alpha * A.w + one_m * p.AD;
+        dLda += p.gD * (B.z - p.AD);
+        p.AD = act[k] ? alpha * B.z + one_m * p.AD : p.AD;
       }
       dLda = p.T * dLda + (p.Tfin * inv) * p.gOb;
-      if (ar < kAlphaMax) {
-        g[5] += dLda * ex;
-        const float dp = dLda * ar;
-        g[0] += dp * (B.x * dx + B.y * dy);
-        g[1] += dp * (B.y * dx + B.z * dy);
-        g[2] += -0.5f * dp * dx * dx;
-        g[3] += -dp * dx * dy;
-        g[4] += -0.5f * dp * dy * dy;
-      }
+      const float dm = (act[k] && ars[k] < kAlphaMax) ? dLda : 0.f;  // clamped alpha: no power path
+      g[5] += dm * exs[k];
+      const float dp = dm * ars[k];
+      g[0] += dp * fmaf(B.w, dys[k], ms[k]);
+      g[1] += dp * fmaf(B.w, dxs[k], qcs[k]);
+      const float dpx = dp * dxs[k];
+      g[2] += dpx * dxs[k];
+      g[3] += dpx * dys[k];
+      g[4] += (dp * dys[k]) * dys[k];
     }
-    if (__any(contrib_any)) {
-      const float tot = wave_reduce10(g, lane);
-      if (lane < 10 && tot != 0.f) unsafeAtomicAdd(&g2[(int64_t)s_e[j] * 12 + q], tot);
-    }
+    const float tot = wave_reduce10(g, lane);
+    if (lane < 10 && tot != 0.f) unsafeAtomicAdd(&g2[(int64_t)s_e[j] * 12 + q], tot);
   }
 }
 
@@ -686,25 +702,35 @@ static BlendState carve_state(void *base, int64_t total_tiles, int64_t cap, int 
   return s;
 }
 
-template <int TW, int TH, int BD, int NT>
-static hipError_t fwd_impl(const ViewTable &vt, const ImgTable &it, const gs_projected &p, const uint32_t *vals,
-                           const uint32_t *range, const BlendState &s, hipStream_t st) {
+template <int TW, int TH, int BD, int NT, bool CNT>
+static hipError_t fwd_impl_cnt(const ViewTable &vt, const ImgTable &it, const gs_projected &p, const uint32_t *vals,
+                               const uint32_t *range, const BlendState &s, hipStream_t st) {
   const uint32_t T = vt.total_tiles;
   const uint32_t nb = (T + kItemChunk - 1) / kItemChunk;
   hipLaunchKernelGGL(k_items_reduce, dim3(nb), dim3(kItemThreads), 0, st, vt, range, BD, s.bsum);
   hipLaunchKernelGGL(k_items_scan, dim3(1), dim3(1024), 0, st, s.bsum, nb, s.n_items, s.item_base, T);
   hipLaunchKernelGGL(k_items_apply, dim3(nb), dim3(kItemThreads), 0, st, vt, range, BD, s.bsum, s.item_base, s.items);
-  hipLaunchKernelGGL((k_blend_chunk<TW, TH, BD, NT>), dim3((unsigned)s.I), dim3(NT), 0, st, vt, it,
+  hipLaunchKernelGGL((k_blend_chunk<TW, TH, BD, NT, CNT>), dim3((unsigned)s.I), dim3(NT), 0, st, vt, it,
                      (const Card *)p.card, vals, range,
                      (const uint2 *)s.items, (const uint32_t *)s.n_items, s.chunk);
   hipLaunchKernelGGL((k_blend_scan<TW, TH, BD>), dim3(T), dim3(TW * TH), 0, st, vt, it, range,
                      (const uint32_t *)s.item_base, s.chunk);
-  hipLaunchKernelGGL((k_blend_fix<TW, TH, BD, NT>), dim3((unsigned)s.I), dim3(NT), 0, st, vt, it,
+  hipLaunchKernelGGL((k_blend_fix<TW, TH, BD, NT, CNT>), dim3((unsigned)s.I), dim3(NT), 0, st, vt, it,
                      (const Card *)p.card, vals, range,
                      (const uint2 *)s.items, (const uint32_t *)s.n_items, s.chunk);
   hipLaunchKernelGGL((k_blend_suffix<TW, TH, BD>), dim3(T), dim3(TW * TH), 0, st, vt, range,
                      (const uint32_t *)s.item_base, s.chunk);
   return hipGetLastError();
+}
+
+// Contributor counting only when some view asks for that plane.
+template <int TW, int TH, int BD, int NT>
+static hipError_t fwd_impl(const ViewTable &vt, const ImgTable &it, const gs_projected &p, const uint32_t *vals,
+                           const uint32_t *range, const BlendState &s, hipStream_t st) {
+  bool cnt = false;
+  for (int i = 0; i < vt.n_views; ++i) cnt = cnt || it.v[i].n_contrib != nullptr;
+  return cnt ? fwd_impl_cnt<TW, TH, BD, NT, true>(vt, it, p, vals, range, s, st)
+             : fwd_impl_cnt<TW, TH, BD, NT, false>(vt, it, p, vals, range, s, st);
 }
 
 template <int TW, int TH, int BD, int NT>

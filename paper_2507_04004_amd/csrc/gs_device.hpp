@@ -81,16 +81,33 @@ __device__ __forceinline__ int view_of_tile(const ViewTable &vt, uint32_t gt) {
   return v;
 }
 
-// Exponent of a splat at pixel offset (dx, dy): -q/2 with q = a dx^2 + 2 b dx dy + c dy^2,
-// clamped to <= 0 (q >= 0 exactly; the clamp only absorbs rounding). The forward and the
-// backward both call this, with fixed FMA placement, so they take identical decisions.
-__device__ __forceinline__ float splat_power(float a, float b, float c, float dx, float dy) {
-#pragma clang fp contract(off)
-  float q = __builtin_fmaf(a * dx, dx, __builtin_fmaf(c * dy, dy, (2.0f * b) * (dx * dy)));
-  return fminf(-0.5f * q, 0.0f);
+// Compositing form of a splat, staged once per chunk: the conic is pre-scaled so that the
+// exponent comes out in base 2 (alpha = o 2^p, p = log2(e) * (-q/2)) with the -1/2 folded in:
+//   sa = (u, v, a', b'), sb = (c', o, d, b'/2), with a' = kA a, b' = 2 kA b, c' = kA c,
+//   kA = -log2(e) / 2.
+// p = dx (a' dx + b' dy) + c' dy^2, clamped to <= 0 (q >= 0 exactly; the clamp only absorbs
+// rounding). The forward and the backward both evaluate it through splat_p2, with fixed FMA
+// placement, so they take identical alpha decisions.
+constexpr float kA = -0.72134752044448170368f;  // -log2(e) / 2
+
+__device__ __forceinline__ void stage_card(const float4 &A, const float4 &B, const float4 &C, float4 &sa, float4 &sb,
+                                           float4 &sc) {
+  const float bp = (2.0f * kA) * B.y;
+  sa = make_float4(A.x, A.y, kA * B.x, bp);
+  sb = make_float4(kA * B.z, A.z, A.w, 0.5f * bp);
+  sc = C;
 }
 
-__device__ __forceinline__ float splat_alpha_raw(float o, float power) { return o * __expf(power); }
+// Exponent p at pixel offset (dx, dy); also returns a' dx and c' dy for the backward.
+__device__ __forceinline__ float splat_p2(const float4 &sa, const float4 &sb, float dx, float dy, float &m,
+                                          float &qc) {
+#pragma clang fp contract(off)
+  m = sa.z * dx;
+  const float t = fmaf(sa.w, dy, m);
+  qc = sb.x * dy;
+  const float q = qc * dy;
+  return fminf(fmaf(dx, t, q), 0.0f);
+}
 
 // Smallest value of q over the pixel-centre rectangle [xl,xh] x [yl,yh]: zero when the
 // centre lies inside, else the least of the clamped 1-D minima on the facing edges.

@@ -263,7 +263,9 @@ __global__ __launch_bounds__(256) void k_preprocess(ViewTable vt, const float *_
 
 // ---------------------------------------------------------------------------------------------
 // Stage a5: chain rule from the 2D quantities to the parameters and the pose.
-// grad2d records [E][12] (48 B, last two unused): u, v, a, b, c, o, r, g, b, d.
+// grad2d records [E][12] (48 B, last two unused), as the compositing backward leaves them:
+// sums for u, v, a, b, c in its pre-scaled units (see the factors applied below), then
+// dL/do, dL/d(r, g, b), dL/d(depth).
 // ---------------------------------------------------------------------------------------------
 struct ParamGradOut {
   float *mean, *scale, *rot, *opacity, *sh_dc, *sh_rest;
@@ -481,7 +483,9 @@ __global__ __launch_bounds__(256) void k_geo_bwd(ViewTable vt, const float *__re
       const float gdf[3] = {G[6], G[7], G[8]};  // direction path, left by k_sh_bwd
       Splat s;
       splat_decide(cam, mx, my, mz, sx, sy, sz, qw, qx, qy, qz, o, s);
-      const float gu = G[0], gv = G[1], ga = G[2], gb = G[3], gc = G[4], go = G[5];
+      // grad2d slots 0-4 hold the compositing kernel's sums in its pre-scaled units
+      const float gu = G[0] * (1.0f / kA), gv = G[1] * (1.0f / kA);
+      const float ga = -0.5f * G[2], gb = -G[3], gc = -0.5f * G[4], go = G[5];
       const float gd = G[9];
       // conic -> Sigma': G_S = -Q Ghat Q, Ghat = [[ga, gb/2], [gb/2, gc]]
       const float a = s.a, b = s.b, c = s.c;
