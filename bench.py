@@ -29,20 +29,49 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-FP32_PEAK_TFLOPS = 157.3
-# Algorithmic work per unit (see the design notes): bytes for HBM-bound stages, flops for
-# the compositing stages (per alpha evaluation / per contribution).
-BYTES_PRE_PER_N = 12
-BYTES_PRE_PER_V = 224 + 56
-BYTES_BIN_PER_V = 52
-BYTES_BIN_PER_P = 12 + 24
-BYTES_PREBWD_PER_V = 236 + 40 + 236
-FLOPS_FWD_EVAL, FLOPS_FWD_CONTRIB = 13, 13
-FLOPS_BWD_EVAL, FLOPS_BWD_CONTRIB = 13, 50
+# fp32 ceiling of this code: 256 CUs x 64 fp32 lanes per clock x 2 flops (FMA) x 2.4 GHz.
+# (The published 157.3 TFLOP/s counts packed two-wide fp32 instructions, which this build
+# does not emit.)
+FP32_PEAK_TFLOPS = 78.6
+# Algorithmic work per unit: bytes for the memory-bound stages (N Gaussians, V visible, P
+# pairs, T tiles), flops (FMA = 2) per alpha evaluation and per contribution for compositing.
+BYTES_PRE_PER_N, BYTES_PRE_PER_V = 44 + 64 + 8, 192
+BYTES_BIN_PER_N, BYTES_BIN_PER_V, BYTES_BIN_PER_P, BYTES_BIN_PER_T = 4, 64, 4, 8
+BYTES_PREBWD_PER_N, BYTES_PREBWD_PER_V = 12 + 44 + 236 + 8, 192 + 48
+FLOPS_FWD_EVAL, FLOPS_FWD_CONTRIB = 14, 13
+FLOPS_BWD_EVAL, FLOPS_BWD_CONTRIB = 14, 57
 
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
+
+
+def kernel_source_digest() -> str:
+    """Digest of the HIP sources; counter readings are valid only for the sources they came from."""
+    import hashlib
+    d = hashlib.sha256()
+    src = os.path.join(ROOT, "paper_2507_04004_amd", "csrc")
+    for name in sorted(os.listdir(src)):
+        if name.endswith((".hip", ".hpp")):
+            with open(os.path.join(src, name), "rb") as fh:
+                d.update(name.encode() + b"\0" + fh.read())
+    return d.hexdigest()
+
+
+def measured_traffic(kernel: str, tile: int, bd: int):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter readings (FETCH_SIZE
+    and WRITE_SIZE, each scaled by what the counter reads for a plain copy of known size), or
+    None when the readings are missing or were taken on different kernel sources."""
+    path = os.path.join(ROOT, "profiles", "hbm_traffic.json")
+    try:
+        with open(path) as fh:
+            rec = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    if rec.get("source_digest") != kernel_source_digest():
+        return None
+    k = rec.get("kernels", {}).get(f"{kernel}/{tile}x{tile}/{bd}")
+    return None if k is None else int(k["bytes_per_launch"])
 
 
 def parse():
@@ -247,26 +276,36 @@ def main():
     cnt_frame = R.Frame.empty(cam.h, cam.w, dev, count=True)
     R.render_fwd(ps.spl, ps.n, ps.bins, ps.cs, args.blend_depth, dev, out=cnt_frame)
     torch.cuda.synchronize()
+    # evaluations: the forward walks each tile's whole list for every pixel of the tile (every
+    # tile of this scene keeps a pixel below the stop threshold); the backward walks each
+    # pixel's list from its last contributor to the front
+    tr = ps.bins.tile_range.view(-1, 2).long()
+    lens = (tr[:, 1] - tr[:, 0]).cpu().numpy()
+    tx, ty = (cam.w + args.tile - 1) // args.tile, (cam.h + args.tile - 1) // args.tile
+    pw = np.minimum(args.tile, cam.w - np.arange(tx) * args.tile)
+    ph = np.minimum(args.tile, cam.h - np.arange(ty) * args.tile)
+    E_f = int((lens.reshape(ty, tx) * np.outer(ph, pw)).sum())
     E_b = int((cnt_frame.last.long() + 1).sum().item())
     C_n = int(cnt_frame.n_contrib.long().sum().item())
     V = int((ps.spl.n_tiles > 0).sum().item())
     work = {
         "preprocess": ("hbm", BYTES_PRE_PER_N * ps.n + BYTES_PRE_PER_V * V),
-        "bin_sort": ("hbm", BYTES_BIN_PER_V * V + BYTES_BIN_PER_P * P),
-        "preprocess_bwd": ("hbm", BYTES_PREBWD_PER_V * V),
-        "blend_fwd": ("alu", FLOPS_FWD_EVAL * E_b + FLOPS_FWD_CONTRIB * C_n),
+        "bin_sort": ("hbm", BYTES_BIN_PER_N * ps.n + BYTES_BIN_PER_V * V + BYTES_BIN_PER_P * P
+                     + BYTES_BIN_PER_T * tx * ty),
+        "preprocess_bwd": ("hbm", BYTES_PREBWD_PER_N * ps.n + BYTES_PREBWD_PER_V * V),
+        "blend_fwd": ("alu", FLOPS_FWD_EVAL * E_f + FLOPS_FWD_CONTRIB * C_n),
         "blend_bwd": ("alu", FLOPS_BWD_EVAL * E_b + FLOPS_BWD_CONTRIB * C_n),
     }
-    dom = max(stage_ms, key=lambda k: stage_ms[k])
+    # dominant kernel: the compositing backward, one launch per step (its stage events bracket
+    # exactly that launch on the library's stream)
+    dom = "blend_bwd"
     bound, amount = work[dom]
     t_s = stage_ms[dom] * 1e-3
-    if bound == "hbm":
-        achieved, peak, unit = amount / t_s / 1e9, HBM_PEAK_GBS, "GB/s"
-    else:
-        achieved, peak, unit = amount / t_s / 1e12, FP32_PEAK_TFLOPS, "TFLOP/s"
-    roofline = {"bound": bound, "kernel": dom, "achieved": round(achieved, 3), "peak": peak, "unit": unit,
-                "frac": round(achieved / peak, 5), "traffic": None,
-                "avg_launch_ms": round(stage_ms[dom], 4)}
+    achieved, peak, unit = amount / t_s / 1e12, FP32_PEAK_TFLOPS, "TFLOP/s"
+    roofline = {"bound": bound, "kernel": "k_blend_bwd_chunk", "achieved": round(achieved, 3), "peak": peak,
+                "unit": unit, "frac": round(achieved / peak, 5),
+                "traffic": measured_traffic("k_blend_bwd_chunk", args.tile, args.blend_depth),
+                "avg_launch_ms": round(stage_ms[dom], 4), "flops_per_launch": amount}
     per_stage = {}
     for k, (b, amt) in work.items():
         ts = stage_ms[k] * 1e-3
@@ -296,7 +335,7 @@ def main():
         "config": {"workload": "1M-Gaussian street map (SH3), one 1280x720 view, fx=900, 32-beam LiDAR; "
                                "fwd + L1/LiDAR loss + bwd to all parameters and the pose",
                    "n_gaussians": ps.n, "width": cam.w, "height": cam.h, "tile": args.tile,
-                   "blend_depth": args.blend_depth, "visible": V, "pairs": P, "evals_bwd": E_b,
+                   "blend_depth": args.blend_depth, "visible": V, "pairs": P, "evals_fwd": E_f, "evals_bwd": E_b,
                    "contributions": C_n, "lidar_hits": int(pix.size)},
         "render_mpix_s": round(cam.w * cam.h / (statistics.median(rlat) * 1e-3) / 1e6, 2),
         "latency_ms": {"fwd_bwd_p50": round(pct(lat, 0.5), 4), "fwd_bwd_p99": round(pct(lat, 0.99), 4),
