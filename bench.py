@@ -85,6 +85,9 @@ def parse():
     ap.add_argument("--blend-depth", type=int, default=128)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-repeats", type=int, default=1)
+    ap.add_argument("--no-batched", action="store_true", help="skip the 8-keyframe batched measurement")
+    ap.add_argument("--no-serving", action="store_true", help="skip the serving measurement")
+    ap.add_argument("--serve-requests", type=int, default=2000, help="requests per arrival rate")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one plain 256 MiB device copy (reference point for HBM byte counters)")
     return ap.parse_args()
@@ -93,10 +96,10 @@ def parse():
 class PlainStep:
     """Buffers and pre-built C structs for one view; step() enqueues the whole hot path."""
 
-    def __init__(self, R, N, torch, g, cam, pix, target_color, ds, tile, bd, dev):
+    def __init__(self, R, N, torch, gm, cam, pix, target_color, ds, tile, bd, dev):
         self.R, self.N, self.torch = R, N, torch
         self.L = N.lib()
-        self.gm = R.GaussianMap.from_numpy(g, dev)
+        self.gm = gm
         self.cs = R.camera_struct(cam)
         self.gs = self.gm.struct()
         self.n = self.gs.n
@@ -158,6 +161,115 @@ class PlainStep:
                                 C.byref(self.s_grads), st))
 
 
+def lidar_targets(frame, pix):
+    """LiDAR depths D/O of a rendered target at the mask pixels (hits with O = 0 dropped)."""
+    import numpy as np
+    D = frame.depth.flatten().cpu().numpy()
+    O = frame.alpha.flatten().cpu().numpy()
+    keep = O[pix] > 0
+    pix = pix[keep].astype(np.int32)
+    return pix, (D[pix] / O[pix]).astype(np.float32)
+
+
+def timed(torch, fn, reps, warmup):
+    for _ in range(warmup):
+        fn()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(reps)]
+    for a, b in ev:
+        a.record()
+        fn()
+        b.record()
+    torch.cuda.synchronize()
+    return statistics.median(a.elapsed_time(b) for a, b in ev)
+
+
+def measure_batched(R, N, torch, S, g, gm, tile, bd, dev, reps=20):
+    """8 keyframes of the same map (uneven intrinsics and resolutions) per optimisation pass:
+    one graph-captured fwd+bwd batch (tile size and chunk length from the autotuner) against 8
+    sequential plain fwd+bwd calls on the same stream."""
+    from paper_2507_04004_amd.autotune import autotune
+    from paper_2507_04004_amd.batch import BatchPlan, ViewSlot
+    cams = S.keyframe_cameras(8, seed=2)
+    total_px = sum(c.w * c.h for c in cams)
+    gp = R.GaussianMap.from_numpy(S.perturb(g, 0.01, seed=3), dev)
+    # targets and LiDAR depths from the perturbed map (untimed)
+    cap = 8 << 20
+    while True:
+        tplan = BatchPlan(gm.n, gm.sh_degree, 8, total_px, tile, bd, cap, dev)
+        tslots = [ViewSlot.make(c, dev) for c in cams]
+        tplan.run(gp, tslots, fwd=True)
+        need = tplan.num_pairs()
+        tplan.close()
+        if need <= cap:
+            break
+        cap = int(need * 1.25)
+    del gp
+    cap = int(need * 1.25) + 4096
+    targets = [s.frame.color.clone() for s in tslots]
+    lidars = []
+    for k, (c, sl) in enumerate(zip(cams, tslots)):
+        pix, ds = lidar_targets(sl.frame, S.lidar_beams(c, 32, 30.0, 0.32, seed=200 + k))
+        lidars.append((pix, ds))
+    del tslots
+    tile_b, bd_b, timings = autotune(gm, cams, backward=True, candidates=[(8, 128), (8, 256), (16, 128)],
+                                     capacity=cap, reps=3, warmup=1, device=dev, targets=targets)
+    plan = BatchPlan(gm.n, gm.sh_degree, 8, total_px, tile_b, bd_b, cap, dev)
+    slots = [ViewSlot.make(c, dev, backward=True, target=targets[k],
+                           lidar=R.LidarHits(torch.from_numpy(lidars[k][0]).to(dev),
+                                             torch.from_numpy(lidars[k][1]).to(dev), weight=1.0))
+             for k, c in enumerate(cams)]
+    grads = R.ParamGrads.empty(gm)
+    run = lambda: plan.run(gm, slots, fwd=True, bwd=True, grads=grads, graph=True, overwrite=True)
+    ms_b = timed(torch, run, reps, 3)
+    assert plan.num_pairs() <= plan.capacity
+    plan.close()
+    seq = [PlainStep(R, N, torch, gm, c, lidars[k][0], targets[k], lidars[k][1], tile, bd, dev)
+           for k, c in enumerate(cams)]
+
+    def run_seq():
+        for st in seq:
+            st.step()
+    ms_s = timed(torch, run_seq, reps, 3)
+    del seq
+    return {"views": 8, "pixels": total_px, "tile": tile_b, "blend_depth": bd_b,
+            "autotune_ms": {k: round(v, 4) for k, v in timings.items()},
+            "batched_graph_ms": round(ms_b, 4), "batched_views_s": round(8e3 / ms_b, 2),
+            "sequential_plain_ms": round(ms_s, 4), "sequential_views_s": round(8e3 / ms_s, 2),
+            "speedup": round(ms_s / ms_b, 3)}
+
+
+def measure_serving(R, torch, S, tile, bd, dev, n_req, log):
+    """Novel-view serving from a resident 3M-Gaussian map of a 1 km street: Poisson arrivals at
+    0.5 / 0.8 / 1.0 / 1.2 x the one-at-a-time capacity, 640x360 / 1280x720 / 1920x1080 at
+    50/35/15 %, RGB + depth forward; arrival-to-completion latency, batched (up to 16 views
+    per launch) against one-at-a-time FIFO."""
+    import numpy as np
+    from paper_2507_04004_amd.serve import RenderServer, poisson_arrivals, simulate
+    log("[bench] serving: generating the 3M-Gaussian 1 km map")
+    g5 = S.street_map(3_000_000, seed=4, z_range=(-20.0, 1020.0), n_boxes=260, n_clusters=860)
+    gm5 = R.GaussianMap.from_numpy(g5, dev)
+    del g5
+    server = RenderServer(gm5, max_batch=16, memory_budget=8 << 30, tile=tile, blend_depth=bd, device=dev)
+    cams = S.serving_requests(n_req, seed=4)
+    # warm-up, then the one-at-a-time capacity on back-to-back requests
+    simulate(server, cams[:48], np.zeros(48), batched=True)
+    simulate(server, cams[:48], np.zeros(48), batched=False)
+    m = min(n_req, 300)
+    st = simulate(server, cams[:m], np.zeros(m), batched=False)
+    cap_rate = m / (st["busy_frac"] * st["wall_s"])
+    out = {"map_gaussians": gm5.n, "requests_per_rate": n_req, "fifo_capacity_req_s": round(cap_rate, 1), "rates": []}
+    for f in (0.5, 0.8, 1.0, 1.2):
+        arr = poisson_arrivals(n_req, f * cap_rate, seed=int(f * 100))
+        b = simulate(server, cams, arr, batched=True)
+        o = simulate(server, cams, arr, batched=False)
+        out["rates"].append({"load": f, "rate_req_s": round(f * cap_rate, 1),
+                             "batched": {k: round(b[k], 3) for k in ("p50_ms", "p99_ms", "mpix_per_s")},
+                             "fifo": {k: round(o[k], 3) for k in ("p50_ms", "p99_ms", "mpix_per_s")}})
+        log(f"[bench] serving load {f}: batched {out['rates'][-1]['batched']} fifo {out['rates'][-1]['fifo']}")
+    server.close()
+    return out
+
+
 def cpu_baseline(g, cam, gC_np, repeats):
     """The FP64 oracle (as it stands) on the host: one full-view fwd + bwd of the same workload."""
     import numpy as np
@@ -201,7 +313,7 @@ def main():
     # Targets: a perturbed copy rendered once by the same GPU path (untimed).
     log("[bench] rendering targets")
     gp = S.perturb(g, 0.01, seed=3)
-    tgt = PlainStep(R, N, torch, gp, cam, pix, torch.zeros(3, cam.h, cam.w, device=dev),
+    tgt = PlainStep(R, N, torch, R.GaussianMap.from_numpy(gp, dev), cam, pix, torch.zeros(3, cam.h, cam.w, device=dev),
                     np.zeros(pix.size, np.float32), args.tile, args.blend_depth, dev)
     tgt.forward()
     torch.cuda.synchronize()
@@ -222,7 +334,8 @@ def main():
         del src, dst
 
     log("[bench] building the step")
-    ps = PlainStep(R, N, torch, g, cam, pix, target_color, ds, args.tile, args.blend_depth, dev)
+    gm = R.GaussianMap.from_numpy(g, dev)
+    ps = PlainStep(R, N, torch, gm, cam, pix, target_color, ds, args.tile, args.blend_depth, dev)
     for _ in range(args.warmup):
         ps.step()
     torch.cuda.synchronize()
@@ -344,10 +457,20 @@ def main():
         "stages": per_stage,
         "roofline": roofline,
     }
+    gC_cpu = None
+    if not args.no_cpu_baseline:
+        gC_cpu = np.sign(ps.frame.color.cpu().numpy().astype(np.float64) - target_color.cpu().numpy()) / ps.nval
+    if not args.no_batched:
+        log("[bench] batched keyframes")
+        out["batched"] = measure_batched(R, N, torch, S, g, gm, args.tile, args.blend_depth, dev)
+        log(f"[bench] batched {out['batched']}")
+    if not args.no_serving:
+        del ps
+        torch.cuda.empty_cache()
+        out["serving"] = measure_serving(R, torch, S, args.tile, args.blend_depth, dev, args.serve_requests, log)
     if not args.no_cpu_baseline:
         log("[bench] timing the CPU oracle")
-        gC = np.sign(ps.frame.color.cpu().numpy().astype(np.float64) - target_color.cpu().numpy()) / ps.nval
-        out["cpu_baseline"] = cpu_baseline(g, cam, gC, args.cpu_repeats)
+        out["cpu_baseline"] = cpu_baseline(g, cam, gC_cpu, args.cpu_repeats)
     print(json.dumps(out), flush=True)
 
 

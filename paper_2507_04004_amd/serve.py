@@ -47,7 +47,7 @@ class RenderServer:
         self.gm, self.max_batch, self.budget = gm, max_batch, memory_budget
         self.tile, self.bd, self.device = tile, blend_depth, device
         self.pairs_per_pixel = 4.0   # running estimate, refined from completed batches
-        self.plans: dict[tuple[int, int], BatchPlan] = {}
+        self.plans: dict[str, BatchPlan] = {}
 
     def estimate_bytes(self, req: Request) -> int:
         return int(req.pixels * (PIXEL_BYTES + 1.5 * self.pairs_per_pixel * PAIR_BYTES))
@@ -64,16 +64,19 @@ class RenderServer:
         return batch
 
     def _plan(self, views: int, pixels: int, pairs: int) -> BatchPlan:
-        # plans are bucketed by (views, pixel budget) and reused
+        # one plan sized for max_batch views, grown (re-created) only when a batch needs more
+        # pixels or pairs than it holds: its buffers scale with views x map size, so a plan per
+        # batch shape would multiply the device memory
         pix_b = 1 << max(16, math.ceil(math.log2(max(pixels, 1))))
-        key = (views, pix_b)
         cap = max(1 << 20, int(pairs * 1.5))
-        p = self.plans.get(key)
-        if p is None or p.capacity < cap:
+        p = self.plans.get("main")
+        if p is None or p.capacity < cap or p.max_total_pixels < pixels:
             if p is not None:
+                pix_b = max(pix_b, p.max_total_pixels)
+                cap = max(cap, p.capacity)
                 p.close()
-            p = BatchPlan(self.gm.n, self.gm.sh_degree, views, pix_b, self.tile, self.bd, cap, self.device)
-            self.plans[key] = p
+            p = BatchPlan(self.gm.n, self.gm.sh_degree, self.max_batch, pix_b, self.tile, self.bd, cap, self.device)
+            self.plans["main"] = p
         return p
 
     def render(self, batch: list[Request]) -> None:
