@@ -22,8 +22,12 @@ namespace gs {
 constexpr int kRadixBits = 8;
 constexpr int kRadixDigits = 1 << kRadixBits;
 constexpr int kRadixThreads = 256;
-constexpr int kRadixItems = 16;
-constexpr int kRadixChunk = kRadixThreads * kRadixItems;
+// Elements per block: the depth sort (one record per Gaussian and view) uses smaller blocks
+// so that a 1M-record pass still spreads over the whole chip; the pair sort uses larger
+// blocks, whose longer per-digit runs make the stores more contiguous.
+constexpr int kItemsDepth = 4;
+constexpr int kItemsPairs = 8;
+constexpr int kRadixMinChunk = kRadixThreads * kItemsDepth;
 constexpr int kScanThreads = 256;
 constexpr int kScanItems = 1;
 constexpr int kScanChunk = kScanThreads * kScanItems;
@@ -47,6 +51,7 @@ __device__ __forceinline__ uint64_t digit_peers(uint32_t d, bool valid) {
 }
 
 // ---- radix passes --------------------------------------------------------------------------
+template <int ITEMS>
 __global__ __launch_bounds__(kRadixThreads) void k_radix_hist(const uint32_t *__restrict__ keys, int64_t n_static,
                                                               const int64_t *n_dev, int64_t cap, int shift,
                                                               uint32_t *__restrict__ hist, int nblocks) {
@@ -54,11 +59,11 @@ __global__ __launch_bounds__(kRadixThreads) void k_radix_hist(const uint32_t *__
   const int64_t n = live_count(n_static, n_dev, cap);
   h[threadIdx.x] = 0;
   __syncthreads();
-  const int64_t base = (int64_t)blockIdx.x * kRadixChunk;
+  const int64_t base = (int64_t)blockIdx.x * (kRadixThreads * ITEMS);
   if (base < n) {
     const uint64_t lt = lanemask_lt();
 #pragma unroll 4
-    for (int r = 0; r < kRadixItems; ++r) {
+    for (int r = 0; r < ITEMS; ++r) {
       const int64_t i = base + r * kRadixThreads + threadIdx.x;
       const bool valid = i < n;
       const uint32_t d = valid ? (keys[i] >> shift) & (kRadixDigits - 1) : 0u;
@@ -89,6 +94,10 @@ __global__ __launch_bounds__(kRadixThreads) void k_radix_scan(uint32_t *__restri
 }
 
 // Stable scatter. vin == nullptr means the values are the input positions; kout may be null.
+// The block first orders its chunk by digit in LDS (stable: round, then wavefront, then lane
+// rank), then writes each digit's run to consecutive global positions, so the stores leave
+// as contiguous runs instead of one scattered element per lane.
+template <int ITEMS>
 __global__ __launch_bounds__(kRadixThreads) void k_radix_scatter(const uint32_t *__restrict__ kin,
                                                                  const uint32_t *__restrict__ vin,
                                                                  uint32_t *__restrict__ kout,
@@ -97,38 +106,45 @@ __global__ __launch_bounds__(kRadixThreads) void k_radix_scatter(const uint32_t 
                                                                  const uint32_t *__restrict__ hist,
                                                                  const uint32_t *__restrict__ tot, int nblocks) {
   constexpr int NW = kRadixThreads / 64;
-  __shared__ uint32_t s_base[kRadixDigits];
+  constexpr int CHUNK = kRadixThreads * ITEMS;
+  __shared__ uint32_t s_k[CHUNK], s_v[CHUNK];
+  __shared__ uint32_t s_glob[kRadixDigits];  // global start of this block's run of each digit
+  __shared__ uint32_t s_loc[kRadixDigits];   // start of each digit's run inside the block
   __shared__ uint32_t s_run[kRadixDigits];
   __shared__ uint32_t s_wcnt[NW][kRadixDigits];
   __shared__ uint32_t lds[NW + 1];
   const int64_t n = live_count(n_static, n_dev, cap);
-  const int64_t base = (int64_t)blockIdx.x * kRadixChunk;
+  const int64_t base = (int64_t)blockIdx.x * CHUNK;
   if (base >= n) return;  // uniform per block
+  const int cnt = (int)min<int64_t>(CHUNK, n - base);
   const int t = threadIdx.x;
   uint32_t total;
   const uint32_t pre = block_exclusive_scan<kRadixThreads>(tot[t], lds, total);
-  s_base[t] = pre + hist[(int64_t)t * nblocks + blockIdx.x];
+  const uint32_t h0 = hist[(int64_t)t * nblocks + blockIdx.x];
+  const uint32_t h1 = blockIdx.x + 1 < (unsigned)nblocks ? hist[(int64_t)t * nblocks + blockIdx.x + 1] : tot[t];
+  s_glob[t] = pre + h0;
+  const uint32_t loc = block_exclusive_scan<kRadixThreads>(h1 - h0, lds, total);
+  s_loc[t] = loc;
   s_run[t] = 0;
 #pragma unroll
   for (int w = 0; w < NW; ++w) s_wcnt[w][t] = 0;
   __syncthreads();
   const int wave = t >> 6;
   const uint64_t lt = lanemask_lt();
-  for (int r = 0; r < kRadixItems; ++r) {
-    const int64_t i = base + r * kRadixThreads + t;
-    const bool valid = i < n;
-    const uint32_t k = valid ? kin[i] : 0u;
+  for (int r = 0; r < ITEMS; ++r) {
+    const int li = r * kRadixThreads + t;
+    const bool valid = li < cnt;
+    const uint32_t k = valid ? kin[base + li] : 0u;
     const uint32_t d = (k >> shift) & (kRadixDigits - 1);
     const uint64_t peers = digit_peers(d, valid);
     const uint32_t rank = (uint32_t)__popcll(peers & lt);
     if (valid && rank == 0) s_wcnt[wave][d] = (uint32_t)__popcll(peers);
     __syncthreads();
     if (valid) {
-      uint32_t off = s_run[d];
+      uint32_t off = s_loc[d] + s_run[d];
       for (int w = 0; w < wave; ++w) off += s_wcnt[w][d];
-      const uint32_t pos = s_base[d] + off + rank;
-      if (kout) kout[pos] = k;
-      vout[pos] = vin ? vin[i] : (uint32_t)i;
+      s_k[off + rank] = k;
+      s_v[off + rank] = vin ? vin[base + li] : (uint32_t)(base + li);
     }
     __syncthreads();
     uint32_t add = 0;
@@ -139,6 +155,14 @@ __global__ __launch_bounds__(kRadixThreads) void k_radix_scatter(const uint32_t 
     }
     s_run[t] += add;
     __syncthreads();
+  }
+  // the chunk is in digit order in LDS: element j goes to its digit's global run
+  for (int j = t; j < cnt; j += kRadixThreads) {
+    const uint32_t k = s_k[j];
+    const uint32_t d = (k >> shift) & (kRadixDigits - 1);
+    const uint32_t pos = s_glob[d] + (uint32_t)j - s_loc[d];
+    if (kout) kout[pos] = k;
+    vout[pos] = s_v[j];
   }
 }
 
@@ -292,8 +316,8 @@ struct BinScratch {
 };
 
 size_t bin_scratch_bytes(int64_t n, int64_t cap) {
-  const int64_t nb_max = std::max<int64_t>(cdiv(std::max<int64_t>(n, 1), kRadixChunk),
-                                           cdiv(std::max<int64_t>(cap, 1), kRadixChunk));
+  const int64_t nb_max = std::max<int64_t>(cdiv(std::max<int64_t>(n, 1), kRadixMinChunk),
+                                           cdiv(std::max<int64_t>(cap, 1), kRadixMinChunk));
   size_t s = 0;
   s += 4 * align256(sizeof(uint32_t) * std::max<int64_t>(n, 1));
   s += align256(sizeof(uint32_t) * cdiv(std::max<int64_t>(n, 1), kScanChunk));
@@ -305,8 +329,8 @@ size_t bin_scratch_bytes(int64_t n, int64_t cap) {
 }
 
 static BinScratch carve(void *base, int64_t n, int64_t cap) {
-  const int64_t nb_max = std::max<int64_t>(cdiv(std::max<int64_t>(n, 1), kRadixChunk),
-                                           cdiv(std::max<int64_t>(cap, 1), kRadixChunk));
+  const int64_t nb_max = std::max<int64_t>(cdiv(std::max<int64_t>(n, 1), kRadixMinChunk),
+                                           cdiv(std::max<int64_t>(cap, 1), kRadixMinChunk));
   char *p = (char *)base;
   auto take = [&](size_t bytes) {
     char *r = p;
@@ -325,14 +349,16 @@ static BinScratch carve(void *base, int64_t n, int64_t cap) {
   return s;
 }
 
+template <int ITEMS>
 static hipError_t radix_pass(const uint32_t *kin, const uint32_t *vin, uint32_t *kout, uint32_t *vout, int64_t n_static,
                              const int64_t *n_dev, int64_t cap, int shift, const BinScratch &s, hipStream_t st) {
   const int64_t nmax = n_dev ? cap : n_static;
-  const int nb = (int)std::max<int64_t>(cdiv(nmax, kRadixChunk), 1);
-  hipLaunchKernelGGL(k_radix_hist, dim3(nb), dim3(kRadixThreads), 0, st, kin, n_static, n_dev, cap, shift, s.hist, nb);
+  const int nb = (int)std::max<int64_t>(cdiv(nmax, kRadixThreads * ITEMS), 1);
+  hipLaunchKernelGGL(k_radix_hist<ITEMS>, dim3(nb), dim3(kRadixThreads), 0, st, kin, n_static, n_dev, cap, shift,
+                     s.hist, nb);
   hipLaunchKernelGGL(k_radix_scan, dim3(kRadixDigits), dim3(kRadixThreads), 0, st, s.hist, nb, s.tot);
-  hipLaunchKernelGGL(k_radix_scatter, dim3(nb), dim3(kRadixThreads), 0, st, kin, vin, kout, vout, n_static, n_dev, cap,
-                     shift, s.hist, s.tot, nb);
+  hipLaunchKernelGGL(k_radix_scatter<ITEMS>, dim3(nb), dim3(kRadixThreads), 0, st, kin, vin, kout, vout, n_static,
+                     n_dev, cap, shift, s.hist, s.tot, nb);
   return hipGetLastError();
 }
 
@@ -359,7 +385,8 @@ hipError_t launch_bin_sort(const ViewTable &vt, const gs_projected &p, int64_t n
   for (int pass = 0; pass < 4; ++pass) {
     uint32_t *ko = pass == 3 ? nullptr : kb[pass & 1];
     uint32_t *vo = vb[pass & 1];
-    if ((err = radix_pass(kin, vin, ko, vo, n, nullptr, 0, pass * kRadixBits, s, st)) != hipSuccess) return err;
+    if ((err = radix_pass<kItemsDepth>(kin, vin, ko, vo, n, nullptr, 0, pass * kRadixBits, s, st)) != hipSuccess)
+      return err;
     kin = ko;
     vin = vo;
   }
@@ -386,7 +413,9 @@ hipError_t launch_bin_sort(const ViewTable &vt, const gs_projected &p, int64_t n
   for (int pass = 0; pass < passes; ++pass) {
     uint32_t *ko = pkb[pass & 1];
     uint32_t *vo = pass == passes - 1 ? vals : pvb[pass & 1];
-    if ((err = radix_pass(pk, pv, ko, vo, 0, num_pairs, cap, pass * kRadixBits, s, st)) != hipSuccess) return err;
+    if ((err = radix_pass<kItemsPairs>(pk, pv, ko, vo, 0, num_pairs, cap, pass * kRadixBits, s, st)) !=
+        hipSuccess)
+      return err;
     pk = ko;
     pv = vo;
   }
