@@ -465,42 +465,44 @@ __device__ __forceinline__ float dpp(float v) {
   return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, true));
 }
 
-// Sum over the wavefront of ten values; afterwards lane l holds the total of value l & 15.
-// Transposed reduction: four row-local DPP exchanges each halve the number of values a lane
-// carries (8, 4, 2, 1 of 16), then two cross-row swaps finish one value per lane.
+// Sum over the wavefront of ten values. Transposed reduction: four row-local DPP exchanges
+// leave each lane with fewer values (10 -> 5 -> 3 -> 2 -> 1 per lane, the partner lane
+// holding the complementary half), then two cross-row swaps add the four rows. Afterwards
+// lane l holds the total of value reduce10_slot(l) (lanes whose slot is -1 hold nothing).
 __device__ __forceinline__ float wave_reduce10(const float (&g)[10], int lane) {
-  // stage 1: partner lane i^15 within a 16-lane row (row_mirror); lanes < 8 keep values 0-7
-  float v8[8];
-  const bool lo1 = (lane & 8) == 0;
+  // stage 1, partner i^15 in the 16-lane row (row_mirror): bit 3 clear keeps 0-4, set keeps 5-9
+  float v1[5];
+  const bool h3 = (lane & 8) != 0;
 #pragma unroll
-  for (int k = 0; k < 8; ++k) {
-    const float mine = (8 + k < 10) ? g[8 + k] : 0.f;
-    const float keep = lo1 ? g[k] : mine;
-    const float send = lo1 ? mine : g[k];
-    v8[k] = keep + dpp<0x140>(send);
+  for (int m = 0; m < 5; ++m) {
+    const float keep = h3 ? g[5 + m] : g[m];
+    const float send = h3 ? g[m] : g[5 + m];
+    v1[m] = keep + dpp<0x140>(send);
   }
-  // stage 2: partner i^7 within 8 (row_half_mirror); lanes with bit 2 clear keep 0-3
-  float v4[4];
-  const bool lo2 = (lane & 4) == 0;
+  // stage 2, partner i^7 (row_half_mirror): bit 2 clear keeps {0, 1, 2}, set keeps {3, 4}
+  float v2[3];
+  const bool h2 = (lane & 4) != 0;
 #pragma unroll
-  for (int k = 0; k < 4; ++k) {
-    const float keep = lo2 ? v8[k] : v8[4 + k];
-    const float send = lo2 ? v8[4 + k] : v8[k];
-    v4[k] = keep + dpp<0x141>(send);
+  for (int m = 0; m < 3; ++m) {
+    const float hi = m < 2 ? v1[3 + m] : 0.f;
+    const float keep = h2 ? hi : v1[m];
+    const float send = h2 ? v1[m] : hi;
+    v2[m] = keep + dpp<0x141>(send);
   }
-  // stage 3: partner i^2 (quad_perm [2,3,0,1]); bit 1 clear keeps 0-1
-  float v2[2];
-  const bool lo3 = (lane & 2) == 0;
+  // stage 3, partner i^2 (quad_perm [2,3,0,1]): bit 1 clear keeps {0, 1}, set keeps {2}
+  float v3[2];
+  const bool h1 = (lane & 2) != 0;
 #pragma unroll
-  for (int k = 0; k < 2; ++k) {
-    const float keep = lo3 ? v4[k] : v4[2 + k];
-    const float send = lo3 ? v4[2 + k] : v4[k];
-    v2[k] = keep + dpp<0x4E>(send);
+  for (int m = 0; m < 2; ++m) {
+    const float hi = m == 0 ? v2[2] : 0.f;
+    const float keep = h1 ? hi : v2[m];
+    const float send = h1 ? v2[m] : hi;
+    v3[m] = keep + dpp<0x4E>(send);
   }
-  // stage 4: partner i^1 (quad_perm [1,0,3,2]); bit 0 clear keeps 0
-  const bool lo4 = (lane & 1) == 0;
-  const float keep = lo4 ? v2[0] : v2[1];
-  const float send = lo4 ? v2[1] : v2[0];
+  // stage 4, partner i^1 (quad_perm [1,0,3,2]): bit 0 picks one of the two
+  const bool h0 = (lane & 1) != 0;
+  const float keep = h0 ? v3[1] : v3[0];
+  const float send = h0 ? v3[0] : v3[1];
   float v = keep + dpp<0xB1>(send);
   // stages 5-6: add the four rows (permlane swaps between rows 0/1, 2/3, then halves)
   const auto s16 = __builtin_amdgcn_permlane16_swap(__float_as_uint(v), __float_as_uint(v), false, false);
@@ -508,6 +510,13 @@ __device__ __forceinline__ float wave_reduce10(const float (&g)[10], int lane) {
   const auto s32 = __builtin_amdgcn_permlane32_swap(__float_as_uint(v), __float_as_uint(v), false, false);
   v = __uint_as_float(s32[0]) + __uint_as_float(s32[1]);
   return v;
+}
+
+// Which of the ten values lane l (of the first row) holds after wave_reduce10, or -1.
+__device__ __forceinline__ int reduce10_slot(int lane) {
+  const int r = lane & 7;
+  const int loc = r < 3 ? r : (r == 4 ? 3 : (r == 5 ? 4 : -1));
+  return (lane < 16 && loc >= 0) ? ((lane & 8) ? 5 : 0) + loc : -1;
 }
 
 // Backward state of one pixel.
@@ -595,7 +604,7 @@ __global__ __launch_bounds__(NT) void k_blend_bwd_chunk(ViewTable vt, ImgTable i
   __syncthreads();
 
   const int lane = threadIdx.x & 63;
-  const int q = lane & 15;
+  const int slot = reduce10_slot(lane);
   const bool depth_live = __any(depth_any);
   for (int j = maxll; j >= 0; --j) {
     const float4 A = s_a[j], B = s_b[j], Cc = s_c[j];
@@ -620,22 +629,24 @@ __global__ __launch_bounds__(NT) void k_blend_bwd_chunk(ViewTable vt, ImgTable i
 #pragma unroll
     for (int k = 0; k < PPT; ++k) {
       PixGrad &p = pg[k];
-      const float alpha = fminf(kAlphaMax, ars[k]);
+      // a pixel this splat does not reach takes alpha 0: every update below then leaves its
+      // state unchanged exactly (T * 1, 0 * x + 1 * A) and adds zeros
+      const float alpha = act[k] ? fminf(kAlphaMax, ars[k]) : 0.f;
       const float one_m = 1.f - alpha;
-      const float inv = __builtin_amdgcn_rcpf(one_m);  // 1 ulp; one_m >= 0.01
-      p.T = act[k] ? p.T * inv : p.T;                    // transmittance in front of this splat
-      const float w = act[k] ? alpha * p.T : 0.f;
+      const float inv = __builtin_amdgcn_rcpf(one_m);  // 1 ulp; one_m >= 0.01; exactly 1 at alpha 0
+      p.T = p.T * inv;                                  // transmittance in front of this splat
+      const float w = alpha * p.T;
       g[6] += p.gC0 * w;
       g[7] += p.gC1 * w;
       g[8] += p.gC2 * w;
       float dLda = p.gC0 * (Cc.x - p.A0) + p.gC1 * (Cc.y - p.A1) + p.gC2 * (Cc.z - p.A2);
-      p.A0 = act[k] ? alpha * Cc.x + one_m * p.A0 : p.A0;
-      p.A1 = act[k] ? alpha * Cc.y + one_m * p.A1 : p.A1;
-      p.A2 = act[k] ? alpha * Cc.z + one_m * p.A2 : p.A2;
+      p.A0 = alpha * Cc.x + one_m * p.A0;
+      p.A1 = alpha * Cc.y + one_m * p.A1;
+      p.A2 = alpha * Cc.z + one_m * p.A2;
       if (depth_live) {
         g[9] += p.gD * w;
         dLda += p.gD * (B.z - p.AD);
-        p.AD = act[k] ? alpha * B.z + one_m * p.AD : p.AD;
+        p.AD = alpha * B.z + one_m * p.AD;
       }
       dLda = p.T * dLda + (p.Tfin * inv) * p.gOb;
       const float dm = (act[k] && ars[k] < kAlphaMax) ? dLda : 0.f;  // clamped alpha: no power path
@@ -649,7 +660,7 @@ __global__ __launch_bounds__(NT) void k_blend_bwd_chunk(ViewTable vt, ImgTable i
       g[4] += (dp * dys[k]) * dys[k];
     }
     const float tot = wave_reduce10(g, lane);
-    if (lane < 10 && tot != 0.f) unsafeAtomicAdd(&g2[(int64_t)s_e[j] * 12 + q], tot);
+    if (slot >= 0 && tot != 0.f) unsafeAtomicAdd(&g2[(int64_t)s_e[j] * 12 + slot], tot);
   }
 }
 
