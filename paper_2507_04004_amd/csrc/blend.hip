@@ -292,20 +292,24 @@ __global__ __launch_bounds__(NT) void k_blend_chunk(ViewTable vt, ImgTable it, c
 }
 
 // ---- forward pass 2: per multi-chunk tile, chunk partials in order ------------------------
-// Slot flags after this pass: kPending = the pixel stops inside this chunk (slot holds the
-// state before it: colour, depth, opacity, transmittance, last + 1, count in pad); kAfter =
-// the chunk lies behind the pixel's stop. Otherwise the slot holds the chunk's absolute
-// colour / depth and the transmittance after it.
+// Per pixel, over the chunks in order until the pixel stops: a chunk whose product keeps T at
+// or above 1e-4 is accumulated whole (its record then holds the chunk's absolute colour /
+// depth and the transmittance after it); at the chunk where the pixel stops the record gets
+// the incoming state (colour, depth, opacity, T, last + 1, count) flagged kPending, and the
+// item is marked for k_blend_fix. Chunks behind that point are not touched: later passes stop
+// at the pixel's last contributor. Chunk records are loaded kScanBatch at a time, so a long
+// tile's chain costs one memory latency per batch instead of one per chunk.
 constexpr uint32_t kPending = 1u << 31;
-constexpr uint32_t kAfter = 1u << 30;
+constexpr int kScanBatch = 8;
 
 template <int TW, int TH, int BD>
 __global__ __launch_bounds__(TW * TH) void k_blend_scan(ViewTable vt, ImgTable it, const uint32_t *__restrict__ range,
                                                    const uint32_t *__restrict__ item_base,
-                                                   ChunkRec *__restrict__ chunk) {
+                                                   ChunkRec *__restrict__ chunk, uint32_t *__restrict__ need_fix) {
   // one pixel per lane: the per-pixel chain over the chunks is serial, so spread it wide
   using Ctx = TileCtx<TW, TH, TW * TH>;
   constexpr int PPT = Ctx::PPT;
+  constexpr int64_t TT = TW * TH;
   const uint32_t gt = blockIdx.x;
   const uint32_t s0 = range[2 * gt], e0 = range[2 * gt + 1];
   const uint32_t K = n_chunks(e0 - s0, BD);
@@ -323,28 +327,30 @@ __global__ __launch_bounds__(TW * TH) void k_blend_scan(ViewTable vt, ImgTable i
       write_pixel(im, *tile.cam, pi, tile.npx, 0.f, 0.f, 0.f, 0.f, 0.f, 1.f, -1, 0);
       continue;
     }
-    ChunkRec *base = chunk + (int64_t)item_base[gt] * (TW * TH) + tile.pidx(k);
+    const uint32_t ib = item_base[gt];
+    ChunkRec *base = chunk + (int64_t)ib * TT + tile.pidx(k);
     float T = 1.f, C0 = 0.f, C1 = 0.f, C2 = 0.f, D = 0.f, O = 0.f;
     int32_t last = -1, nc = 0;
-    bool finished = false, pending = false;
-    ChunkRec nxt = base[0];
-    for (uint32_t q = 0; q < K; ++q) {
-      const ChunkRec r = nxt;
-      if (q + 1 < K) nxt = base[(int64_t)(q + 1) * (TW * TH)];  // prefetch the next chunk's partial
-      ChunkRec w;
-      w.o = 0.f;
-      w.pad = 0.f;
-      if (finished || pending) {
-        w.c0 = w.c1 = w.c2 = w.d = 0.f;
-        w.t = T;
-        w.info = kAfter;
-      } else {
+    bool done = false, pending = false;
+    for (uint32_t q0 = 0; q0 < K && !done; q0 += kScanBatch) {
+      ChunkRec rb[kScanBatch];
+#pragma unroll
+      for (int i = 0; i < kScanBatch; ++i)
+        if (q0 + i < K) rb[i] = base[(int64_t)(q0 + i) * TT];
+#pragma unroll
+      for (int i = 0; i < kScanBatch; ++i) {
+        const uint32_t q = q0 + i;
+        if (done || q >= K) continue;
+        const ChunkRec &r = rb[i];
         const int ll = (int)(r.info & 1023u) - 1;
         const int ncl = (int)((r.info >> 10) & 1023u);
         const bool cut = (r.info >> 20) & 1u;
         const float Tafter = T * r.t;
-        if (!cut ? (Tafter >= kTMin) : (q == 0)) {
-          // the whole chunk blends (chunk 0 is exact from T = 1 even when it stops inside)
+        ChunkRec w;
+        w.o = 0.f;
+        w.pad = 0.f;
+        if (!cut ? (Tafter >= kTMin) : (T == 1.f)) {
+          // the whole chunk blends (from T = 1 the chunk pass is exact even when it stops inside)
           w.c0 = T * r.c0; w.c1 = T * r.c1; w.c2 = T * r.c2; w.d = T * r.d;
           C0 += w.c0; C1 += w.c1; C2 += w.c2; D += w.d;
           O += T * r.o;
@@ -353,16 +359,17 @@ __global__ __launch_bounds__(TW * TH) void k_blend_scan(ViewTable vt, ImgTable i
           T = Tafter;
           w.t = T;
           w.info = 0u;
-          finished = cut;
+          done = cut;
         } else {
           // the pixel stops inside this chunk: hand the incoming state to k_blend_fix
           w.c0 = C0; w.c1 = C1; w.c2 = C2; w.d = D; w.o = O; w.t = T;
           w.info = kPending | (uint32_t)(last + 1);
           w.pad = __int_as_float(nc);
-          pending = true;
+          pending = done = true;
+          need_fix[ib + q] = 1u;  // every writer stores the same value
         }
+        base[(int64_t)q * TT] = w;
       }
-      base[(int64_t)q * (TW * TH)] = w;
     }
     if (!pending) write_pixel(im, *tile.cam, pi, tile.npx, C0, C1, C2, D, O, T, last, nc);
   }
@@ -375,16 +382,17 @@ __global__ __launch_bounds__(NT) void k_blend_fix(ViewTable vt, ImgTable it, con
                                                   const uint32_t *__restrict__ range,
                                                   const uint2 *__restrict__ items,
                                                   const uint32_t *__restrict__ n_items,
+                                                  const uint32_t *__restrict__ need_fix,
                                                   ChunkRec *__restrict__ chunk) {
   using Ctx = TileCtx<TW, TH, NT>;
   constexpr int PPT = Ctx::PPT;
   __shared__ float4 s_a[BD], s_b[BD], s_c[BD];
   uint32_t item;
   if (!item_of_block(n_items, item)) return;
+  if (!need_fix[item]) return;  // no pixel stops inside this chunk
   const uint2 tc = items[item];
   const uint32_t gt = tc.x, c = tc.y;
   const uint32_t s0 = range[2 * gt], e0 = range[2 * gt + 1];
-  if (n_chunks(e0 - s0, BD) < 2) return;
   const Ctx tile(vt, gt);
   float px[PPT], py[PPT];
   bool inside[PPT], pending[PPT];
@@ -422,17 +430,21 @@ __global__ __launch_bounds__(NT) void k_blend_fix(ViewTable vt, ImgTable it, con
 }
 
 // ---- forward pass 4: backward starting state per chunk (suffix sums, per tile) ------------
-// Colour / depth composited behind each chunk, normalised by the transmittance after it.
+// Colour / depth composited behind each chunk, normalised by the transmittance after it, for
+// the chunks up to the one holding the pixel's last contributor (the backward reads no
+// other). Records are loaded kScanBatch at a time.
 template <int TW, int TH, int BD>
-__global__ __launch_bounds__(TW * TH) void k_blend_suffix(ViewTable vt, const uint32_t *__restrict__ range,
+__global__ __launch_bounds__(TW * TH) void k_blend_suffix(ViewTable vt, ImgTable it, const uint32_t *__restrict__ range,
                                                      const uint32_t *__restrict__ item_base,
                                                      ChunkRec *__restrict__ chunk) {
   using Ctx = TileCtx<TW, TH, TW * TH>;
   constexpr int PPT = Ctx::PPT;
+  constexpr int64_t TT = TW * TH;
   const uint32_t gt = blockIdx.x;
   const uint32_t K = n_chunks(range[2 * gt + 1] - range[2 * gt], BD);
   if (K < 2) return;
   const Ctx tile(vt, gt);
+  const ViewImg &im = it.v[tile.vi];
 #pragma unroll 1
   for (int k = 0; k < PPT; ++k) {
     bool inside;
@@ -440,19 +452,27 @@ __global__ __launch_bounds__(TW * TH) void k_blend_suffix(ViewTable vt, const ui
     int64_t pi;
     tile.pixel(k, inside, pxf, pyf, pi);
     if (!inside) continue;
-    ChunkRec *base = chunk + (int64_t)item_base[gt] * (TW * TH) + tile.pidx(k);
+    const int last = im.last[pi];
+    if (last < 0) continue;
+    ChunkRec *base = chunk + (int64_t)item_base[gt] * TT + tile.pidx(k);
     float b0 = 0.f, b1 = 0.f, b2 = 0.f, bd = 0.f;
-    ChunkRec nxt = base[(int64_t)(K - 1) * (TW * TH)];
-    for (int q = (int)K - 1; q >= 0; --q) {
-      const ChunkRec r = nxt;
-      if (q > 0) nxt = base[(int64_t)(q - 1) * (TW * TH)];
-      if (r.info & kAfter) continue;
-      const float inv = 1.f / r.t;
-      ChunkRec w;
-      w.c0 = b0 * inv; w.c1 = b1 * inv; w.c2 = b2 * inv; w.d = bd * inv; w.o = 0.f; w.t = r.t; w.info = 0u;
-      w.pad = 0.f;
-      base[(int64_t)q * (TW * TH)] = w;
-      b0 += r.c0; b1 += r.c1; b2 += r.c2; bd += r.d;
+    for (int q0 = last / BD; q0 >= 0; q0 -= kScanBatch) {
+      ChunkRec rb[kScanBatch];
+#pragma unroll
+      for (int i = 0; i < kScanBatch; ++i)
+        if (q0 - i >= 0) rb[i] = base[(int64_t)(q0 - i) * TT];
+#pragma unroll
+      for (int i = 0; i < kScanBatch; ++i) {
+        const int q = q0 - i;
+        if (q < 0) continue;
+        const ChunkRec &r = rb[i];
+        const float inv = 1.f / r.t;
+        ChunkRec w;
+        w.c0 = b0 * inv; w.c1 = b1 * inv; w.c2 = b2 * inv; w.d = bd * inv; w.o = 0.f; w.t = r.t; w.info = 0u;
+        w.pad = 0.f;
+        base[(int64_t)q * TT] = w;
+        b0 += r.c0; b1 += r.c1; b2 += r.c2; bd += r.d;
+      }
     }
   }
 }
@@ -683,6 +703,7 @@ size_t blend_state_bytes(int64_t total_tiles, int64_t cap, int tw, int th, int b
   s += a256(4 * ((T + kItemChunk - 1) / kItemChunk + 1));          // block sums
   s += a256(16);                                                    // n_items
   s += a256(sizeof(ChunkRec) * (size_t)I * tw * th);                // chunk records
+  s += a256(4 * (size_t)I);                                         // fix-needed flags
   return s;
 }
 
@@ -692,6 +713,7 @@ struct BlendState {
   uint32_t *bsum;
   uint32_t *n_items;
   ChunkRec *chunk;
+  uint32_t *need_fix;
   int64_t I;
 };
 
@@ -709,7 +731,8 @@ static BlendState carve_state(void *base, int64_t total_tiles, int64_t cap, int 
   s.n_items = (uint32_t *)p;
   p += a256(16);
   s.chunk = (ChunkRec *)p;
-  (void)tw; (void)th;
+  p += a256(sizeof(ChunkRec) * (size_t)s.I * tw * th);
+  s.need_fix = (uint32_t *)p;
   return s;
 }
 
@@ -724,12 +747,14 @@ static hipError_t fwd_impl_cnt(const ViewTable &vt, const ImgTable &it, const gs
   hipLaunchKernelGGL((k_blend_chunk<TW, TH, BD, NT, CNT>), dim3((unsigned)s.I), dim3(NT), 0, st, vt, it,
                      (const Card *)p.card, vals, range,
                      (const uint2 *)s.items, (const uint32_t *)s.n_items, s.chunk);
+  hipError_t err = fill_u32(s.need_fix, s.I, 0u, st);
+  if (err != hipSuccess) return err;
   hipLaunchKernelGGL((k_blend_scan<TW, TH, BD>), dim3(T), dim3(TW * TH), 0, st, vt, it, range,
-                     (const uint32_t *)s.item_base, s.chunk);
+                     (const uint32_t *)s.item_base, s.chunk, s.need_fix);
   hipLaunchKernelGGL((k_blend_fix<TW, TH, BD, NT, CNT>), dim3((unsigned)s.I), dim3(NT), 0, st, vt, it,
                      (const Card *)p.card, vals, range,
-                     (const uint2 *)s.items, (const uint32_t *)s.n_items, s.chunk);
-  hipLaunchKernelGGL((k_blend_suffix<TW, TH, BD>), dim3(T), dim3(TW * TH), 0, st, vt, range,
+                     (const uint2 *)s.items, (const uint32_t *)s.n_items, (const uint32_t *)s.need_fix, s.chunk);
+  hipLaunchKernelGGL((k_blend_suffix<TW, TH, BD>), dim3(T), dim3(TW * TH), 0, st, vt, it, range,
                      (const uint32_t *)s.item_base, s.chunk);
   return hipGetLastError();
 }
