@@ -119,9 +119,11 @@ int make_table(const gs_camera *cams, int nv, int64_t n, int deg, int tw, int th
   return GS_OK;
 }
 
-// Backward scratch layout: grad2d [E][12] | pose partials [blocks][V][6] | gD, gO maps [pixels].
+// Backward scratch layout: grad2d [E][12] | pose partials [blocks][V][6] | gD, gO maps [pixels]
+// | view-direction gradients [E] (float4).
 struct GradScratch {
   float *g2, *pose_partial, *mapD, *mapO;
+  float4 *gdir;
 };
 
 size_t grads_scratch_bytes_impl(int64_t n, int nv, int64_t pixels) {
@@ -129,6 +131,7 @@ size_t grads_scratch_bytes_impl(int64_t n, int nv, int64_t pixels) {
   size_t s = a256(sizeof(float) * 12 * E);
   s += a256(sizeof(float) * 6 * nv * std::max<int64_t>(gs::preprocess_bwd_blocks(n), 1));
   s += 2 * a256(sizeof(float) * std::max<int64_t>(pixels, 1));
+  s += a256(sizeof(float4) * E);
   return s;
 }
 
@@ -143,6 +146,8 @@ GradScratch carve_grads(void *base, int64_t n, int nv, int64_t pixels) {
   s.mapD = (float *)p;
   p += a256(sizeof(float) * std::max<int64_t>(pixels, 1));
   s.mapO = (float *)p;
+  p += a256(sizeof(float) * std::max<int64_t>(pixels, 1));
+  s.gdir = (float4 *)p;
   return s;
 }
 
@@ -200,7 +205,8 @@ int enqueue_backward(const gs::ViewTable &vt, const gs_gaussians &g, const gs_pr
   float *pose_out[gs::kMaxViews] = {};
   for (int i = 0; i < nv; ++i) pose_out[i] = io[i].pose;
   gs::profile_begin(GS_STAGE_PREPROCESS_BWD, st);
-  GS_TRY_HIP(gs::launch_preprocess_bwd(vt, g, p, s.g2, out, pose_out, s.pose_partial, st), "preprocess backward");
+  GS_TRY_HIP(gs::launch_preprocess_bwd(vt, g, p, s.g2, s.gdir, out, pose_out, s.pose_partial, st),
+             "preprocess backward");
   gs::profile_end(GS_STAGE_PREPROCESS_BWD, st);
   return GS_OK;
 }

@@ -20,7 +20,8 @@ void profile_begin(int stage, hipStream_t st);
 void profile_end(int stage, hipStream_t st);
 
 hipError_t launch_preprocess(const ViewTable &vt, const gs_gaussians &g, const gs_projected &p, hipStream_t st);
-hipError_t launch_preprocess_bwd(const ViewTable &vt, const gs_gaussians &g, const gs_projected &p, float *g2,
+hipError_t launch_preprocess_bwd(const ViewTable &vt, const gs_gaussians &g, const gs_projected &p, const float *g2,
+                                 float4 *gdir,
                                  const gs_grads &out, float *const *pose_out, float *pose_partial, hipStream_t st);
 int64_t preprocess_bwd_blocks(int64_t n);
 

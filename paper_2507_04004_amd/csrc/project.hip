@@ -335,7 +335,7 @@ __device__ __forceinline__ void sh_term(int k, float x, float y, float z, float 
 
 // Stage a5 runs as two kernels over the Gaussians, each looping over the views:
 //   k_sh_bwd   colour: SH coefficient gradients and the view-direction gradient, which it
-//              leaves in grad2d slots 6-8 (the colour slots it has consumed);
+//              leaves in a compact [E] float4 array;
 //   k_geo_bwd  geometry: mean, scale, rotation, opacity and the pose partials.
 // Split this way, the coefficient traffic (48 floats in, 48 out per Gaussian) runs at the
 // occupancy of a light kernel instead of that of the geometry chain rule.
@@ -344,8 +344,9 @@ __device__ __forceinline__ void sh_term(int k, float x, float y, float z, float 
 template <int DEG, bool SINGLE, bool OVERWRITE>
 __global__ __launch_bounds__(256) void k_sh_bwd(ViewTable vt, const float *__restrict__ mean,
                                                 const float *__restrict__ sh_dc, const float *__restrict__ sh_rest,
-                                                const uint32_t *__restrict__ n_tiles, float *__restrict__ g2,
-                                                float *__restrict__ out_dc, float *__restrict__ out_rest) {
+                                                const uint32_t *__restrict__ n_tiles, const float *__restrict__ g2,
+                                                float4 *__restrict__ gdir, float *__restrict__ out_dc,
+                                                float *__restrict__ out_rest) {
   constexpr int K = (DEG + 1) * (DEG + 1);
   constexpr int NR = 3 * (K - 1);
   constexpr int NRA = NR > 0 ? NR : 1;
@@ -364,10 +365,18 @@ __global__ __launch_bounds__(256) void k_sh_bwd(ViewTable vt, const float *__res
   for (int vi = 0; vi < vt.n_views; ++vi) {
     const ViewCam &cam = vt.v[vi];
     const int64_t e = (int64_t)vi * n + gi;
-    if (n_tiles[e] == 0) continue;
-    const float2 G67 = *reinterpret_cast<const float2 *>(g2 + e * 12 + 6);
-    const float G8 = g2[e * 12 + 8];
-    if (G67.x == 0.f && G67.y == 0.f && G8 == 0.f) continue;
+    bool live = n_tiles[e] > 0;
+    float2 G67 = make_float2(0.f, 0.f);
+    float G8 = 0.f;
+    if (live) {
+      G67 = *reinterpret_cast<const float2 *>(g2 + e * 12 + 6);
+      G8 = g2[e * 12 + 8];
+      live = G67.x != 0.f || G67.y != 0.f || G8 != 0.f;
+    }
+    if (!live) {
+      gdir[e] = make_float4(0.f, 0.f, 0.f, 0.f);
+      continue;
+    }
     any_live = true;
     if (!loaded) {  // all coefficients at once: one burst of independent loads
 #pragma unroll
@@ -386,7 +395,7 @@ __global__ __launch_bounds__(256) void k_sh_bwd(ViewTable vt, const float *__res
     const float gr[3] = {raw[0] > 0.f ? G67.x : 0.f, raw[1] > 0.f ? G67.y : 0.f, raw[2] > 0.f ? G8 : 0.f};
 #pragma unroll
     for (int ch = 0; ch < 3; ++ch) acc_dc[ch] += gr[ch] * Y[0];
-    float gdir[3] = {0.f, 0.f, 0.f};
+    float gd[3] = {0.f, 0.f, 0.f};
 #pragma unroll
     for (int k = 1; k < K; ++k) {
       float yk, d0, d1, d2;
@@ -405,17 +414,15 @@ __global__ __launch_bounds__(256) void k_sh_bwd(ViewTable vt, const float *__res
           acc_rest[i] += gr[ch] * yk;
         }
       }
-      gdir[0] += sk * d0;
-      gdir[1] += sk * d1;
-      gdir[2] += sk * d2;
+      gd[0] += sk * d0;
+      gd[1] += sk * d1;
+      gd[2] += sk * d2;
     }
     // d dir / d mean = (I - dir dir^T) / dist
-    const float dd = gdir[0] * dir[0] + gdir[1] * dir[1] + gdir[2] * dir[2];
+    const float dd = gd[0] * dir[0] + gd[1] * dir[1] + gd[2] * dir[2];
     const float idist = 1.0f / dist;
-    float *slot = g2 + e * 12 + 6;
-    slot[0] = (gdir[0] - dd * dir[0]) * idist;
-    slot[1] = (gdir[1] - dd * dir[1]) * idist;
-    slot[2] = (gdir[2] - dd * dir[2]) * idist;
+    gdir[e] = make_float4((gd[0] - dd * dir[0]) * idist, (gd[1] - dd * dir[1]) * idist,
+                          (gd[2] - dd * dir[2]) * idist, 0.f);
   }
   if (out_dc && (OVERWRITE || any_live)) {
 #pragma unroll
@@ -446,7 +453,8 @@ __global__ __launch_bounds__(256) void k_geo_bwd(ViewTable vt, const float *__re
                                                  const float *__restrict__ scale, const float *__restrict__ rot,
                                                  const float *__restrict__ opacity,
                                                  const uint32_t *__restrict__ n_tiles, const float *__restrict__ g2,
-                                                 ParamGradOut out, float *__restrict__ pose_partial /*[grid][V][6]*/) {
+                                                 const float4 *__restrict__ gdir, ParamGradOut out,
+                                                 float *__restrict__ pose_partial /*[grid][V][6]*/) {
   __shared__ float red[8];
   const int64_t n = vt.n;
   const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -480,7 +488,8 @@ __global__ __launch_bounds__(256) void k_geo_bwd(ViewTable vt, const float *__re
     }
     if (live) {
       any_view = true;
-      const float gdf[3] = {G[6], G[7], G[8]};  // direction path, left by k_sh_bwd
+      const float4 gv4 = gdir[e];  // view-direction path, left by k_sh_bwd
+      const float gdf[3] = {gv4.x, gv4.y, gv4.z};
       Splat s;
       splat_decide(cam, mx, my, mz, sx, sy, sz, qw, qx, qy, qz, o, s);
       // grad2d slots 0-4 hold the compositing kernel's sums in its pre-scaled units
@@ -669,18 +678,19 @@ __global__ void k_pose_reduce_tab(const float *__restrict__ partial, int32_t n_b
   }
 }
 
-hipError_t launch_preprocess_bwd(const ViewTable &vt, const gs_gaussians &g, const gs_projected &p, float *g2,
-                                 const gs_grads &out, float *const *pose_out, float *pose_partial, hipStream_t st) {
+hipError_t launch_preprocess_bwd(const ViewTable &vt, const gs_gaussians &g, const gs_projected &p, const float *g2,
+                                 float4 *gdir, const gs_grads &out, float *const *pose_out, float *pose_partial,
+                                 hipStream_t st) {
   if (vt.n == 0) return hipSuccess;
   const int64_t nb = preprocess_bwd_blocks(vt.n);
   const bool ow = out.overwrite != 0;
   const bool single = vt.n_views == 1;
-  // colour first: it hands the direction gradient to the geometry kernel through grad2d
+  // colour first: it hands the view-direction gradient to the geometry kernel
   {
     switch (vt.sh_degree) {
 #define GS_SH_BWD(D, S, O)                                                                                     \
   hipLaunchKernelGGL((k_sh_bwd<D, S, O>), dim3((unsigned)nb), dim3(256), 0, st, vt, g.mean, g.sh_dc, g.sh_rest, \
-                     p.n_tiles, g2, out.sh_dc, out.sh_rest)
+                     p.n_tiles, g2, gdir, out.sh_dc, out.sh_rest)
 #define GS_SH_CASE(D)                                                                                          \
   case D:                                                                                                      \
     if (single) {                                                                                              \
@@ -704,10 +714,10 @@ hipError_t launch_preprocess_bwd(const ViewTable &vt, const gs_gaussians &g, con
   ParamGradOut po{out.mean, out.scale, out.rot, out.opacity, out.sh_dc, out.sh_rest};
   if (ow)
     hipLaunchKernelGGL(k_geo_bwd<true>, dim3((unsigned)nb), dim3(256), 0, st, vt, g.mean, g.scale, g.rot, g.opacity,
-                       p.n_tiles, (const float *)g2, po, pose_partial);
+                       p.n_tiles, g2, (const float4 *)gdir, po, pose_partial);
   else
     hipLaunchKernelGGL(k_geo_bwd<false>, dim3((unsigned)nb), dim3(256), 0, st, vt, g.mean, g.scale, g.rot,
-                       g.opacity, p.n_tiles, (const float *)g2, po, pose_partial);
+                       g.opacity, p.n_tiles, g2, (const float4 *)gdir, po, pose_partial);
   hipError_t err = hipGetLastError();
   if (err != hipSuccess) return err;
   PosePtrs pp;

@@ -74,15 +74,29 @@ __global__ void k_zero_f32(float *p, int64_t n) {
   if (i < n) p[i] = 0.f;
 }
 
+// vec: every pointer is 16-B aligned, so the bulk goes through float4 accesses
 __global__ __launch_bounds__(256) void k_loss_l1(const float *__restrict__ c, const float *__restrict__ t, int64_t n,
-                                                 float weight, float *__restrict__ dldc, float *__restrict__ loss) {
+                                                 float weight, float *__restrict__ dldc, float *__restrict__ loss,
+                                                 int vec) {
   __shared__ float red[4];
   const float inv = weight / (float)n;
+  auto sgn = [inv](float r) { return r > 0.f ? inv : (r < 0.f ? -inv : 0.f); };
   float s = 0.f;
-  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
+  // four elements per lane and step (16-B loads and stores), then the tail
+  const int64_t n4 = vec ? n / 4 : 0;
+  const float4 *c4 = reinterpret_cast<const float4 *>(c), *t4 = reinterpret_cast<const float4 *>(t);
+  float4 *d4 = reinterpret_cast<float4 *>(dldc);
+  const int64_t stride = (int64_t)gridDim.x * 256;
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n4; i += stride) {
+    const float4 a = c4[i], b = t4[i];
+    const float r0 = a.x - b.x, r1 = a.y - b.y, r2 = a.z - b.z, r3 = a.w - b.w;
+    s += (fabsf(r0) + fabsf(r1)) + (fabsf(r2) + fabsf(r3));
+    if (dldc) d4[i] = make_float4(sgn(r0), sgn(r1), sgn(r2), sgn(r3));
+  }
+  for (int64_t i = 4 * n4 + (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += stride) {
     const float r = c[i] - t[i];
     s += fabsf(r);
-    if (dldc) dldc[i] = (r > 0.f ? inv : (r < 0.f ? -inv : 0.f));
+    if (dldc) dldc[i] = sgn(r);
   }
   s = wave_sum(s);
   if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
@@ -118,10 +132,12 @@ hipError_t zero_f32(float *p, int64_t n, hipStream_t st) {
 hipError_t launch_loss_l1(const float *c, const float *t, int64_t n, float weight, float *dldc, float *loss,
                           hipStream_t st) {
   if (loss) hipLaunchKernelGGL(k_zero_f32, dim3(1), dim3(64), 0, st, loss, (int64_t)1);
-  const int64_t blocks = std::min<int64_t>((n + 255) / 256, 512);  // few blocks: one atomic each
+  const int vec = ((reinterpret_cast<uintptr_t>(c) | reinterpret_cast<uintptr_t>(t) |
+                    reinterpret_cast<uintptr_t>(dldc)) & 15u) == 0;
+  const int64_t blocks = std::min<int64_t>((n / 4 + 255) / 256 + 1, 1024);  // one atomic per block
   if (n > 0)
     hipLaunchKernelGGL(k_loss_l1, dim3((unsigned)std::max<int64_t>(blocks, 1)), dim3(256), 0, st, c, t, n, weight,
-                       dldc, loss);
+                       dldc, loss, vec);
   return hipGetLastError();
 }
 
