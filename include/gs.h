@@ -77,7 +77,9 @@ typedef struct gs_gaussians {
  *   words 8-11  (r, g, b, m): view-dependent colour max(0, SH . Y(dir) + 0.5); the bits of m
  *               (a float holding an integer bit pattern) mark the channels not clamped;
  *   words 12-13 int16 inclusive tile rectangle (tx0, ty0, tx1, ty1), -1 when n_tiles = 0;
- *   word 14     number of tiles kept, word 15 the depth key (copies of the arrays below).
+ *   word 14     number of tiles kept (copy of n_tiles below);
+ *   word 15     for rectangles of at most 32 tiles, bit t set when the t-th tile of the
+ *               rectangle (row-major) passed the cull; 0 for larger rectangles.
  * n_tiles [n]  number of tiles kept after the alpha-max cull;
  * dkey    [n]  sort key: IEEE bits of d, or 0xFFFFFFFF when n_tiles = 0. */
 typedef struct gs_projected {

@@ -230,17 +230,22 @@ __global__ __launch_bounds__(kScanThreads) void k_emit_pairs(ViewTable vt, const
     rc = make_short4((short)lo_i16(d.x), (short)hi_i16(d.x), (short)lo_i16(d.y), (short)hi_i16(d.y));
   }
   const int area = cnt ? (rc.z - rc.x + 1) * (rc.w - rc.y + 1) : 0;
-  // small rectangles: one lane each
+  // small rectangles: one lane each, walking the kept-tile mask the projection stage stored
   if (cnt && area <= kCoopArea) {
     const ViewCam &cam = vt.v[vi];
-    visit_kept_tiles(cam, vt.tile_w, vt.tile_h, A.x, A.y, B.x, B.y, B.z, B.w, rc.x, rc.y, rc.z, rc.w,
-                     [&](uint32_t lt, uint32_t j) {
-                       const int64_t pos = (int64_t)off + j;
-                       if (pos < cap) {
-                         pkey[pos] = cam.tile_base + lt;
-                         pval[pos] = e;
-                       }
-                     });
+    const int rw = rc.z - rc.x + 1;
+    const float inv_rw = 1.0f / (float)rw;  // exact row for t < 32: (t + 1/2) / rw is never near an integer
+    uint32_t mask = d.w;
+    for (uint32_t j = 0; mask; ++j, mask &= mask - 1) {
+      const int t = __ffs(mask) - 1;
+      const int r = (int)(((float)t + 0.5f) * inv_rw);
+      const uint32_t lt = (uint32_t)((rc.y + r) * cam.tiles_x + rc.x + (t - r * rw));
+      const int64_t pos = (int64_t)off + j;
+      if (pos < cap) {
+        pkey[pos] = cam.tile_base + lt;
+        pval[pos] = e;
+      }
+    }
   }
   // large rectangles go to a list that k_emit_big spreads over the whole chip: in depth order
   // the near (large) splats are neighbours, so visiting them here would leave a few
@@ -277,7 +282,7 @@ __global__ __launch_bounds__(kScanThreads) void k_emit_big(ViewTable vt, const C
     const uint4 d = cd.d;
     const ViewCam &cam = vt.v[e / (uint32_t)vt.n];
     wave_visit_kept_tiles(cam, vt.tile_w, vt.tile_h, A.x, A.y, B.x, B.y, B.z, B.w, lo_i16(d.x), hi_i16(d.x),
-                          lo_i16(d.y), hi_i16(d.y), [&](uint32_t lt, uint32_t j) {
+                          lo_i16(d.y), hi_i16(d.y), [&](uint32_t lt, uint32_t j, uint32_t) {
                             const int64_t pos = (int64_t)boff + j;
                             if (pos < cap) {
                               pkey[pos] = cam.tile_base + lt;

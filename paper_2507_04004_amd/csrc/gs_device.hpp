@@ -137,22 +137,23 @@ __device__ __forceinline__ float rect_qmin(float u, float v, float a, float b, f
   return best;
 }
 
-// Kept tiles of a splat, in row-major order over its rectangle. Visitor gets the local tile id.
+// Kept tiles of a splat, in row-major order over its rectangle. The visitor gets the local
+// tile id, the rank among kept tiles and the tile's row-major index inside the rectangle.
 template <typename F>
 __device__ __forceinline__ uint32_t visit_kept_tiles(const ViewCam &cam, int tw, int th, float u, float v, float a,
                                                      float b, float c, float kappa2, int tx0, int ty0, int tx1,
                                                      int ty1, F &&f) {
-  uint32_t cnt = 0;
+  uint32_t cnt = 0, t = 0;
   const int xend = cam.x0 + cam.w - 1, yend = cam.y0 + cam.h - 1;
   for (int ty = ty0; ty <= ty1; ++ty) {
     const int ya = cam.y0 + ty * th;
     const int yb = min(ya + th - 1, yend);
-    for (int tx = tx0; tx <= tx1; ++tx) {
+    for (int tx = tx0; tx <= tx1; ++tx, ++t) {
       const int xa = cam.x0 + tx * tw;
       const int xb = min(xa + tw - 1, xend);
       float q = rect_qmin(u, v, a, b, c, (float)xa, (float)xb, (float)ya, (float)yb);
       if (q <= kappa2) {
-        f((uint32_t)(ty * cam.tiles_x + tx), cnt);
+        f((uint32_t)(ty * cam.tiles_x + tx), cnt, t);
         ++cnt;
       }
     }
@@ -214,7 +215,7 @@ __device__ __forceinline__ uint32_t wave_visit_kept_tiles(const ViewCam &cam, in
       keep = rect_qmin(u, v, a, b, c, (float)xa, (float)xb, (float)ya, (float)yb) <= kappa2;
     }
     const uint64_t m = __ballot(keep);
-    if (keep) f((uint32_t)(ty * cam.tiles_x + tx), done + (uint32_t)__popcll(m & lt));
+    if (keep) f((uint32_t)(ty * cam.tiles_x + tx), done + (uint32_t)__popcll(m & lt), (uint32_t)t);
     done += (uint32_t)__popcll(m);
   }
   return done;
@@ -222,6 +223,9 @@ __device__ __forceinline__ uint32_t wave_visit_kept_tiles(const ViewCam &cam, in
 
 // One splat record (64 B, one memory line): centre / opacity / depth, conic / kappa^2,
 // colour / clamp bits, and the tile rectangle (two int16 pairs), tile count and depth key.
+// d = (tx0 | ty0 << 16, tx1 | ty1 << 16, kept tile count, kept-tile mask): for rectangles of
+// at most kCoopArea tiles the mask has bit t set when the t-th tile of the rectangle
+// (row-major) passed the cull, so pair emission needs no second cull test; 0 otherwise.
 struct alignas(64) Card {
   float4 a, b, c;
   uint4 d;

@@ -223,9 +223,10 @@ __global__ __launch_bounds__(256) void k_preprocess(ViewTable vt, const float *_
     ty1 = (s.py1 - cam.y0) / vt.tile_h;
   }
   const int area = s.ok ? (tx1 - tx0 + 1) * (ty1 - ty0 + 1) : 0;
+  uint32_t kept_mask = 0;  // kCoopArea <= 32: one bit per tile of the rectangle
   if (s.ok && area <= kCoopArea)
     cnt = visit_kept_tiles(cam, vt.tile_w, vt.tile_h, s.u, s.v, s.a, s.b, s.c, s.kappa2, tx0, ty0, tx1, ty1,
-                           [](uint32_t, uint32_t) {});
+                           [&](uint32_t, uint32_t, uint32_t t) { kept_mask |= 1u << t; });
   // large rectangles are counted by the whole wavefront, one splat at a time
   uint64_t big = __ballot(s.ok && area > kCoopArea);
   while (big) {
@@ -234,7 +235,7 @@ __global__ __launch_bounds__(256) void k_preprocess(ViewTable vt, const float *_
     const uint32_t c = wave_visit_kept_tiles(
         cam, vt.tile_w, vt.tile_h, __shfl(s.u, src), __shfl(s.v, src), __shfl(s.a, src), __shfl(s.b, src),
         __shfl(s.c, src), __shfl(s.kappa2, src), __shfl(tx0, src), __shfl(ty0, src), __shfl(tx1, src),
-        __shfl(ty1, src), [](uint32_t, uint32_t) {});
+        __shfl(ty1, src), [](uint32_t, uint32_t, uint32_t) {});
     if ((int)(threadIdx.x & 63) == src) cnt = c;
   }
   float4 col = make_float4(0.f, 0.f, 0.f, 0.f);
@@ -255,8 +256,8 @@ __global__ __launch_bounds__(256) void k_preprocess(ViewTable vt, const float *_
   cd.a = vis ? make_float4(s.u, s.v, s.o, s.pz) : make_float4(0.f, 0.f, 0.f, 0.f);
   cd.b = vis ? make_float4(s.a, s.b, s.c, s.kappa2) : make_float4(0.f, 0.f, 0.f, 0.f);
   cd.c = col;
-  cd.d = vis ? make_uint4(pack_i16x2(tx0, ty0), pack_i16x2(tx1, ty1), cnt, key)
-             : make_uint4(0xFFFFFFFFu, 0xFFFFFFFFu, 0u, key);
+  cd.d = vis ? make_uint4(pack_i16x2(tx0, ty0), pack_i16x2(tx1, ty1), cnt, kept_mask)
+             : make_uint4(0xFFFFFFFFu, 0xFFFFFFFFu, 0u, 0u);
   n_tiles[e] = cnt;
   dkey[e] = key;
 }
