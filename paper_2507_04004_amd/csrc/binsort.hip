@@ -31,6 +31,7 @@ constexpr int kRadixMinChunk = kRadixThreads * kItemsDepth;
 constexpr int kScanThreads = 256;
 constexpr int kScanItems = 1;
 constexpr int kScanChunk = kScanThreads * kScanItems;
+constexpr int kEmitStage = 4096;  // pairs staged in LDS per emission block (32 KB)
 
 __device__ __forceinline__ int64_t live_count(int64_t n_static, const int64_t *n_dev, int64_t cap) {
   if (!n_dev) return n_static;
@@ -207,6 +208,7 @@ __global__ __launch_bounds__(kScanThreads) void k_emit_pairs(ViewTable vt, const
                                                              uint32_t *__restrict__ big_e, uint32_t *__restrict__ big_off,
                                                              uint32_t *__restrict__ big_n) {
   __shared__ uint32_t lds[kScanThreads / 64 + 1];
+  __shared__ uint32_t s_key[kEmitStage], s_val[kEmitStage];
   const int64_t i = (int64_t)blockIdx.x * kScanChunk + threadIdx.x;
   // one card gather per record (a single memory line) supplies the count, centre, conic and
   // rectangle together
@@ -222,7 +224,12 @@ __global__ __launch_bounds__(kScanThreads) void k_emit_pairs(ViewTable vt, const
     cnt = d.z;
   }
   uint32_t total;
-  const uint32_t off = bsum[blockIdx.x] + block_exclusive_scan<kScanThreads>(cnt, lds, total);
+  const uint32_t blk0 = bsum[blockIdx.x];
+  const uint32_t off = blk0 + block_exclusive_scan<kScanThreads>(cnt, lds, total);
+  // the block's pairs occupy one contiguous output range: stage it in LDS and store it as
+  // whole lines (the ranges of large rectangles are left as holes, which k_emit_big fills
+  // later in stream order)
+  const bool staged = total <= (uint32_t)kEmitStage;
   short4 rc = make_short4(0, 0, -1, -1);
   int vi = 0;
   if (cnt) {
@@ -240,10 +247,25 @@ __global__ __launch_bounds__(kScanThreads) void k_emit_pairs(ViewTable vt, const
       const int t = __ffs(mask) - 1;
       const int r = (int)(((float)t + 0.5f) * inv_rw);
       const uint32_t lt = (uint32_t)((rc.y + r) * cam.tiles_x + rc.x + (t - r * rw));
-      const int64_t pos = (int64_t)off + j;
+      if (staged) {
+        s_key[off - blk0 + j] = cam.tile_base + lt;
+        s_val[off - blk0 + j] = e;
+      } else {
+        const int64_t pos = (int64_t)off + j;
+        if (pos < cap) {
+          pkey[pos] = cam.tile_base + lt;
+          pval[pos] = e;
+        }
+      }
+    }
+  }
+  if (staged) {
+    __syncthreads();
+    for (uint32_t k = threadIdx.x; k < total; k += kScanThreads) {
+      const int64_t pos = (int64_t)blk0 + k;
       if (pos < cap) {
-        pkey[pos] = cam.tile_base + lt;
-        pval[pos] = e;
+        pkey[pos] = s_key[k];
+        pval[pos] = s_val[k];
       }
     }
   }
