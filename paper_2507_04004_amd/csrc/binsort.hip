@@ -168,10 +168,15 @@ __global__ __launch_bounds__(kRadixThreads) void k_radix_scatter(const uint32_t 
 }
 
 // ---- pair counts, scan, emission -----------------------------------------------------------
+// Also clears the tile ranges (an empty tile keeps [0, 0)).
 __global__ __launch_bounds__(kScanThreads) void k_count_reduce(const uint32_t *__restrict__ order,
                                                                const uint32_t *__restrict__ n_tiles, int64_t n,
-                                                               uint32_t *__restrict__ bsum) {
+                                                               uint32_t *__restrict__ bsum,
+                                                               uint32_t *__restrict__ tile_range, int64_t n_range) {
   __shared__ uint32_t lds[kScanThreads / 64 + 1];
+  for (int64_t i = (int64_t)blockIdx.x * kScanThreads + threadIdx.x; i < n_range;
+       i += (int64_t)gridDim.x * kScanThreads)
+    tile_range[i] = 0u;
   const int64_t base = (int64_t)blockIdx.x * kScanChunk;
   uint32_t s = 0;
 #pragma unroll
@@ -185,8 +190,10 @@ __global__ __launch_bounds__(kScanThreads) void k_count_reduce(const uint32_t *_
 }
 
 // Single workgroup: exclusive scan of the block sums; total pair count (int64) to *num_pairs.
+// Also clears the length of the large-rectangle list that the emission appends to.
 __global__ __launch_bounds__(1024) void k_count_scan_bsums(uint32_t *__restrict__ bsum, int64_t nb,
-                                                           int64_t *__restrict__ num_pairs) {
+                                                           int64_t *__restrict__ num_pairs,
+                                                           uint32_t *__restrict__ big_n) {
   __shared__ uint32_t lds[1024 / 64 + 1];
   uint64_t running = 0;
   for (int64_t base = 0; base < nb; base += 1024) {
@@ -197,7 +204,10 @@ __global__ __launch_bounds__(1024) void k_count_scan_bsums(uint32_t *__restrict_
     if (i < nb) bsum[i] = (uint32_t)(running + ex);
     running += total;
   }
-  if (threadIdx.x == 0) *num_pairs = (int64_t)running;
+  if (threadIdx.x == 0) {
+    *num_pairs = (int64_t)running;
+    *big_n = 0u;
+  }
 }
 
 __global__ __launch_bounds__(kScanThreads) void k_emit_pairs(ViewTable vt, const uint32_t *__restrict__ order,
@@ -400,8 +410,8 @@ hipError_t launch_bin_sort(const ViewTable &vt, const gs_projected &p, int64_t n
                            uint32_t *tile_range, int64_t *num_pairs, void *scratch, hipStream_t st) {
   BinScratch s = carve(scratch, n, cap);
   hipError_t err;
-  if ((err = fill_u32(tile_range, 2 * (int64_t)vt.total_tiles, 0u, st)) != hipSuccess) return err;
   if (n == 0) {
+    if ((err = fill_u32(tile_range, 2 * (int64_t)vt.total_tiles, 0u, st)) != hipSuccess) return err;
     hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(64), 0, st, (uint32_t *)num_pairs, 2, 0u);
     return hipGetLastError();
   }
@@ -420,11 +430,11 @@ hipError_t launch_bin_sort(const ViewTable &vt, const gs_projected &p, int64_t n
   const uint32_t *order = vin;  // == s.dv_b
   // 2. exclusive scan of tile counts in depth order; total -> num_pairs
   const int64_t nbs = cdiv(n, kScanChunk);
-  hipLaunchKernelGGL(k_count_reduce, dim3((unsigned)nbs), dim3(kScanThreads), 0, st, order, p.n_tiles, n, s.bsum);
-  hipLaunchKernelGGL(k_count_scan_bsums, dim3(1), dim3(1024), 0, st, s.bsum, nbs, num_pairs);
+  hipLaunchKernelGGL(k_count_reduce, dim3((unsigned)nbs), dim3(kScanThreads), 0, st, order, p.n_tiles, n, s.bsum,
+                     tile_range, 2 * (int64_t)vt.total_tiles);
+  hipLaunchKernelGGL(k_count_scan_bsums, dim3(1), dim3(1024), 0, st, s.bsum, nbs, num_pairs, s.big_n);
   // 3. emission in depth order
   // the depth keys' ping-pong buffers are free now: they hold the large-rectangle list
-  hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(64), 0, st, s.big_n, 1, 0u);
   hipLaunchKernelGGL(k_emit_pairs, dim3((unsigned)nbs), dim3(kScanThreads), 0, st, vt, order, n,
                      (const Card *)p.card, s.bsum, cap, s.pk_a, s.pv_a, s.dk_a, s.dk_b, s.big_n);
   hipLaunchKernelGGL(k_emit_big, dim3(kBigBlocks), dim3(kScanThreads), 0, st, vt, (const Card *)p.card,

@@ -119,7 +119,8 @@ __global__ __launch_bounds__(1024) void k_items_scan(uint32_t *__restrict__ bsum
 __global__ __launch_bounds__(kItemThreads) void k_items_apply(ViewTable vt, const uint32_t *__restrict__ range, int bd,
                                                                const uint32_t *__restrict__ bsum,
                                                                uint32_t *__restrict__ item_base,
-                                                               uint2 *__restrict__ items) {
+                                                               uint2 *__restrict__ items,
+                                                               uint32_t *__restrict__ need_fix) {
   __shared__ uint32_t lds[kItemThreads / 64 + 1];
   const uint32_t T = vt.total_tiles;
   uint32_t running = bsum[blockIdx.x];
@@ -132,7 +133,10 @@ __global__ __launch_bounds__(kItemThreads) void k_items_apply(ViewTable vt, cons
     if (j < T) {
       const uint32_t b = running + ex;
       item_base[t] = b;
-      for (uint32_t c = 0; c < k; ++c) items[b + c] = make_uint2(t, c);
+      for (uint32_t c = 0; c < k; ++c) {
+        items[b + c] = make_uint2(t, c);
+        need_fix[b + c] = 0u;  // set again by k_blend_scan where a pixel stops inside
+      }
     }
     running += total;
   }
@@ -743,12 +747,11 @@ static hipError_t fwd_impl_cnt(const ViewTable &vt, const ImgTable &it, const gs
   const uint32_t nb = (T + kItemChunk - 1) / kItemChunk;
   hipLaunchKernelGGL(k_items_reduce, dim3(nb), dim3(kItemThreads), 0, st, vt, range, BD, s.bsum);
   hipLaunchKernelGGL(k_items_scan, dim3(1), dim3(1024), 0, st, s.bsum, nb, s.n_items, s.item_base, T);
-  hipLaunchKernelGGL(k_items_apply, dim3(nb), dim3(kItemThreads), 0, st, vt, range, BD, s.bsum, s.item_base, s.items);
+  hipLaunchKernelGGL(k_items_apply, dim3(nb), dim3(kItemThreads), 0, st, vt, range, BD, s.bsum, s.item_base, s.items,
+                     s.need_fix);
   hipLaunchKernelGGL((k_blend_chunk<TW, TH, BD, NT, CNT>), dim3((unsigned)s.I), dim3(NT), 0, st, vt, it,
                      (const Card *)p.card, vals, range,
                      (const uint2 *)s.items, (const uint32_t *)s.n_items, s.chunk);
-  hipError_t err = fill_u32(s.need_fix, s.I, 0u, st);
-  if (err != hipSuccess) return err;
   hipLaunchKernelGGL((k_blend_scan<TW, TH, BD>), dim3(T), dim3(TW * TH), 0, st, vt, it, range,
                      (const uint32_t *)s.item_base, s.chunk, s.need_fix);
   hipLaunchKernelGGL((k_blend_fix<TW, TH, BD, NT, CNT>), dim3((unsigned)s.I), dim3(NT), 0, st, vt, it,
