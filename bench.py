@@ -25,6 +25,8 @@ import statistics
 import sys
 import time
 
+import numpy as np
+
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
@@ -86,6 +88,7 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-repeats", type=int, default=1)
     ap.add_argument("--no-batched", action="store_true", help="skip the 8-keyframe batched measurement")
+    ap.add_argument("--no-small", action="store_true", help="skip the two small single-view configurations")
     ap.add_argument("--no-serving", action="store_true", help="skip the serving measurement")
     ap.add_argument("--serve-requests", type=int, default=2000, help="requests per arrival rate")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -163,7 +166,6 @@ class PlainStep:
 
 def lidar_targets(frame, pix):
     """LiDAR depths D/O of a rendered target at the mask pixels (hits with O = 0 dropped)."""
-    import numpy as np
     D = frame.depth.flatten().cpu().numpy()
     O = frame.alpha.flatten().cpu().numpy()
     keep = O[pix] > 0
@@ -181,6 +183,28 @@ def timed(torch, fn, reps, warmup):
         b.record()
     torch.cuda.synchronize()
     return statistics.median(a.elapsed_time(b) for a, b in ev)
+
+
+def measure_small_configs(R, N, torch, S, tile, bd, dev, reps=50):
+    """The two plain single-view configurations beside the headline view: 2,000 Gaussians at
+    128x96 (SH 0, 16-row LiDAR mask) and 100k Gaussians at 640x512 (SH 3, 32-beam mask), each
+    one full fwd + L1/LiDAR loss + bwd step with inputs resident."""
+    out = {}
+    for name, (g, cam, pix) in (("small_2k_128x96", S.config_small(0)), ("street_100k_640x512", S.config_street_view(1))):
+        gp = S.perturb(g, 0.01, seed=3)
+        tgt = PlainStep(R, N, torch, R.GaussianMap.from_numpy(gp, dev), cam, pix,
+                        torch.zeros(3, cam.h, cam.w, device=dev), np.zeros(pix.size, np.float32), tile, bd, dev)
+        tgt.forward()
+        torch.cuda.synchronize()
+        target = tgt.frame.color.clone()
+        hits, ds = lidar_targets(tgt.frame, pix)
+        del tgt
+        st = PlainStep(R, N, torch, R.GaussianMap.from_numpy(g, dev), cam, hits, target, ds, tile, bd, dev)
+        ms = timed(torch, st.step, reps, 5)
+        out[name] = {"gaussians": int(g.n), "pixels": int(cam.w * cam.h), "ms_per_step": round(ms, 4),
+                     "views_s": round(1e3 / ms, 1)}
+        del st
+    return out
 
 
 def measure_batched(R, N, torch, S, g, gm, tile, bd, dev, reps=20):
@@ -460,6 +484,9 @@ def main():
     gC_cpu = None
     if not args.no_cpu_baseline:
         gC_cpu = np.sign(ps.frame.color.cpu().numpy().astype(np.float64) - target_color.cpu().numpy()) / ps.nval
+    if not args.no_small:
+        log("[bench] small configurations")
+        out["small_configs"] = measure_small_configs(R, N, torch, S, args.tile, args.blend_depth, dev)
     if not args.no_batched:
         log("[bench] batched keyframes")
         out["batched"] = measure_batched(R, N, torch, S, g, gm, args.tile, args.blend_depth, dev)
