@@ -27,11 +27,23 @@ constexpr int kRadixThreads = 256;
 // blocks, whose longer per-digit runs make the stores more contiguous.
 constexpr int kItemsDepth = 4;
 constexpr int kItemsPairs = 8;
-constexpr int kRadixMinChunk = kRadixThreads * kItemsDepth;
+constexpr int kRadixMinChunk = kRadixThreads * (kItemsDepth < kItemsPairs ? kItemsDepth : kItemsPairs);
 constexpr int kScanThreads = 256;
 constexpr int kScanItems = 1;
 constexpr int kScanChunk = kScanThreads * kScanItems;
 constexpr int kEmitStage = 4096;  // pairs staged in LDS per emission block (32 KB)
+
+// Workgroups are dealt to the 8 XCDs round-robin. A radix pass gives each XCD groups of
+// kChunkGroup consecutive chunks, so the histogram lines and the digit runs that neighbouring
+// chunks share are completed inside one L2 instead of being written back in pieces by eight.
+// The launch is rounded up to whole rounds (kChunkRound); workgroups past the last chunk exit.
+constexpr int kXcdCount = 8;
+constexpr int kChunkGroup = 16;
+constexpr int kChunkRound = kXcdCount * kChunkGroup;
+__device__ __forceinline__ int chunk_of_block() {
+  const int x = (int)blockIdx.x % kXcdCount, k = (int)blockIdx.x / kXcdCount;
+  return ((k / kChunkGroup) * kXcdCount + x) * kChunkGroup + k % kChunkGroup;
+}
 
 __device__ __forceinline__ int64_t live_count(int64_t n_static, const int64_t *n_dev, int64_t cap) {
   if (!n_dev) return n_static;
@@ -55,40 +67,60 @@ __device__ __forceinline__ uint64_t digit_peers(uint32_t d, bool valid) {
 template <int ITEMS>
 __global__ __launch_bounds__(kRadixThreads) void k_radix_hist(const uint32_t *__restrict__ keys, int64_t n_static,
                                                               const int64_t *n_dev, int64_t cap, int shift,
-                                                              uint32_t *__restrict__ hist, int nblocks) {
+                                                              uint32_t *__restrict__ hist, int nblocks, int stride) {
   __shared__ uint32_t h[kRadixDigits];
+  const int chunk = chunk_of_block();
+  if (chunk >= nblocks) return;  // uniform per block
   const int64_t n = live_count(n_static, n_dev, cap);
   h[threadIdx.x] = 0;
   __syncthreads();
-  const int64_t base = (int64_t)blockIdx.x * (kRadixThreads * ITEMS);
+  const int64_t base = (int64_t)chunk * (kRadixThreads * ITEMS);
   if (base < n) {
-    const uint64_t lt = lanemask_lt();
-#pragma unroll 4
+    // every key of the block is requested before the first is ranked
+    uint32_t kr[ITEMS];
+#pragma unroll
     for (int r = 0; r < ITEMS; ++r) {
       const int64_t i = base + r * kRadixThreads + threadIdx.x;
-      const bool valid = i < n;
-      const uint32_t d = valid ? (keys[i] >> shift) & (kRadixDigits - 1) : 0u;
+      kr[r] = i < n ? keys[i] : 0u;
+    }
+    const uint64_t lt = lanemask_lt();
+#pragma unroll
+    for (int r = 0; r < ITEMS; ++r) {
+      const bool valid = base + r * kRadixThreads + threadIdx.x < n;
+      const uint32_t d = (kr[r] >> shift) & (kRadixDigits - 1);
       const uint64_t peers = digit_peers(d, valid);
       if (valid && (peers & lt) == 0) atomicAdd(&h[d], (uint32_t)__popcll(peers));
     }
   }
   __syncthreads();
-  hist[(int64_t)threadIdx.x * nblocks + blockIdx.x] = h[threadIdx.x];
+  hist[(int64_t)threadIdx.x * stride + chunk] = h[threadIdx.x];
 }
 
-// One workgroup per digit: exclusive scan of that digit's counts over the blocks, in place;
-// the digit total goes to tot[digit].
-__global__ __launch_bounds__(kRadixThreads) void k_radix_scan(uint32_t *__restrict__ hist, int nblocks,
+// One workgroup per digit: exclusive scan of that digit's counts over the chunks, in place;
+// the digit total goes to tot[digit]. Each thread owns kScanRun consecutive counts, so a row
+// of up to kRadixThreads * kScanRun blocks takes a single block-wide scan.
+constexpr int kScanRun = 16;
+__global__ __launch_bounds__(kRadixThreads) void k_radix_scan(uint32_t *__restrict__ hist, int nblocks, int stride,
                                                               uint32_t *__restrict__ tot) {
   __shared__ uint32_t lds[kRadixThreads / 64 + 1];
-  uint32_t *row = hist + (int64_t)blockIdx.x * nblocks;
+  uint32_t *row = hist + (int64_t)blockIdx.x * stride;
   uint32_t running = 0;
-  for (int base = 0; base < nblocks; base += kRadixThreads) {
-    const int i = base + threadIdx.x;
-    const uint32_t v = i < nblocks ? row[i] : 0u;
+  for (int base = 0; base < nblocks; base += kRadixThreads * kScanRun) {
+    const int i0 = base + threadIdx.x * kScanRun;
+    uint32_t v[kScanRun];
+    uint32_t sum = 0;
+#pragma unroll
+    for (int j = 0; j < kScanRun; ++j) {
+      v[j] = i0 + j < nblocks ? row[i0 + j] : 0u;
+      sum += v[j];
+    }
     uint32_t total;
-    const uint32_t ex = block_exclusive_scan<kRadixThreads>(v, lds, total);
-    if (i < nblocks) row[i] = running + ex;
+    uint32_t ex = running + block_exclusive_scan<kRadixThreads>(sum, lds, total);
+#pragma unroll
+    for (int j = 0; j < kScanRun; ++j) {
+      if (i0 + j < nblocks) row[i0 + j] = ex;
+      ex += v[j];
+    }
     running += total;
   }
   if (threadIdx.x == 0) tot[blockIdx.x] = running;
@@ -105,7 +137,8 @@ __global__ __launch_bounds__(kRadixThreads) void k_radix_scatter(const uint32_t 
                                                                  uint32_t *__restrict__ vout, int64_t n_static,
                                                                  const int64_t *n_dev, int64_t cap, int shift,
                                                                  const uint32_t *__restrict__ hist,
-                                                                 const uint32_t *__restrict__ tot, int nblocks) {
+                                                                 const uint32_t *__restrict__ tot, int nblocks,
+                                                                 int stride) {
   constexpr int NW = kRadixThreads / 64;
   constexpr int CHUNK = kRadixThreads * ITEMS;
   __shared__ uint32_t s_k[CHUNK], s_v[CHUNK];
@@ -114,15 +147,25 @@ __global__ __launch_bounds__(kRadixThreads) void k_radix_scatter(const uint32_t 
   __shared__ uint32_t s_run[kRadixDigits];
   __shared__ uint32_t s_wcnt[NW][kRadixDigits];
   __shared__ uint32_t lds[NW + 1];
+  const int chunk = chunk_of_block();
+  if (chunk >= nblocks) return;  // uniform per block
   const int64_t n = live_count(n_static, n_dev, cap);
-  const int64_t base = (int64_t)blockIdx.x * CHUNK;
+  const int64_t base = (int64_t)chunk * CHUNK;
   if (base >= n) return;  // uniform per block
   const int cnt = (int)min<int64_t>(CHUNK, n - base);
   const int t = threadIdx.x;
+  // the block's keys and values are requested before the digit offsets are computed
+  uint32_t kr[ITEMS], vr[ITEMS];
+#pragma unroll
+  for (int r = 0; r < ITEMS; ++r) {
+    const int li = r * kRadixThreads + t;
+    kr[r] = li < cnt ? kin[base + li] : 0u;
+    vr[r] = li < cnt ? (vin ? vin[base + li] : (uint32_t)(base + li)) : 0u;
+  }
   uint32_t total;
   const uint32_t pre = block_exclusive_scan<kRadixThreads>(tot[t], lds, total);
-  const uint32_t h0 = hist[(int64_t)t * nblocks + blockIdx.x];
-  const uint32_t h1 = blockIdx.x + 1 < (unsigned)nblocks ? hist[(int64_t)t * nblocks + blockIdx.x + 1] : tot[t];
+  const uint32_t h0 = hist[(int64_t)t * stride + chunk];
+  const uint32_t h1 = chunk + 1 < nblocks ? hist[(int64_t)t * stride + chunk + 1] : tot[t];
   s_glob[t] = pre + h0;
   const uint32_t loc = block_exclusive_scan<kRadixThreads>(h1 - h0, lds, total);
   s_loc[t] = loc;
@@ -132,10 +175,11 @@ __global__ __launch_bounds__(kRadixThreads) void k_radix_scatter(const uint32_t 
   __syncthreads();
   const int wave = t >> 6;
   const uint64_t lt = lanemask_lt();
+#pragma unroll
   for (int r = 0; r < ITEMS; ++r) {
     const int li = r * kRadixThreads + t;
     const bool valid = li < cnt;
-    const uint32_t k = valid ? kin[base + li] : 0u;
+    const uint32_t k = kr[r];
     const uint32_t d = (k >> shift) & (kRadixDigits - 1);
     const uint64_t peers = digit_peers(d, valid);
     const uint32_t rank = (uint32_t)__popcll(peers & lt);
@@ -145,7 +189,7 @@ __global__ __launch_bounds__(kRadixThreads) void k_radix_scatter(const uint32_t 
       uint32_t off = s_loc[d] + s_run[d];
       for (int w = 0; w < wave; ++w) off += s_wcnt[w][d];
       s_k[off + rank] = k;
-      s_v[off + rank] = vin ? vin[base + li] : (uint32_t)(base + li);
+      s_v[off + rank] = vr[r];
     }
     __syncthreads();
     uint32_t add = 0;
@@ -341,20 +385,22 @@ __global__ void k_tile_ranges(const uint32_t *__restrict__ keys, const int64_t *
 
 // ---- host-side orchestration ---------------------------------------------------------------
 static inline int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
+static inline int64_t round_up(int64_t a, int64_t b) { return cdiv(a, b) * b; }
 static inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
 struct BinScratch {
   uint32_t *dk_a, *dv_a, *dk_b, *dv_b;  // depth sort ping-pong [n]
   uint32_t *bsum;                       // [ceil(n / kScanChunk)]
   uint32_t *pk_a, *pv_a, *pk_b, *pv_b;  // pair sort ping-pong [cap]
-  uint32_t *hist;                       // [256][max blocks]
+  uint32_t *hist;                       // [256][row stride: chunks rounded to kChunkRound]
   uint32_t *tot;                        // [256]
   uint32_t *big_n;                      // [1] length of the large-rectangle list
 };
 
 size_t bin_scratch_bytes(int64_t n, int64_t cap) {
-  const int64_t nb_max = std::max<int64_t>(cdiv(std::max<int64_t>(n, 1), kRadixMinChunk),
-                                           cdiv(std::max<int64_t>(cap, 1), kRadixMinChunk));
+  const int64_t nb_max = round_up(std::max<int64_t>(cdiv(std::max<int64_t>(n, 1), kRadixMinChunk),
+                                                    cdiv(std::max<int64_t>(cap, 1), kRadixMinChunk)),
+                                   kChunkRound);
   size_t s = 0;
   s += 4 * align256(sizeof(uint32_t) * std::max<int64_t>(n, 1));
   s += align256(sizeof(uint32_t) * cdiv(std::max<int64_t>(n, 1), kScanChunk));
@@ -366,8 +412,9 @@ size_t bin_scratch_bytes(int64_t n, int64_t cap) {
 }
 
 static BinScratch carve(void *base, int64_t n, int64_t cap) {
-  const int64_t nb_max = std::max<int64_t>(cdiv(std::max<int64_t>(n, 1), kRadixMinChunk),
-                                           cdiv(std::max<int64_t>(cap, 1), kRadixMinChunk));
+  const int64_t nb_max = round_up(std::max<int64_t>(cdiv(std::max<int64_t>(n, 1), kRadixMinChunk),
+                                                    cdiv(std::max<int64_t>(cap, 1), kRadixMinChunk)),
+                                   kChunkRound);
   char *p = (char *)base;
   auto take = [&](size_t bytes) {
     char *r = p;
@@ -391,11 +438,12 @@ static hipError_t radix_pass(const uint32_t *kin, const uint32_t *vin, uint32_t 
                              const int64_t *n_dev, int64_t cap, int shift, const BinScratch &s, hipStream_t st) {
   const int64_t nmax = n_dev ? cap : n_static;
   const int nb = (int)std::max<int64_t>(cdiv(nmax, kRadixThreads * ITEMS), 1);
-  hipLaunchKernelGGL(k_radix_hist<ITEMS>, dim3(nb), dim3(kRadixThreads), 0, st, kin, n_static, n_dev, cap, shift,
-                     s.hist, nb);
-  hipLaunchKernelGGL(k_radix_scan, dim3(kRadixDigits), dim3(kRadixThreads), 0, st, s.hist, nb, s.tot);
-  hipLaunchKernelGGL(k_radix_scatter<ITEMS>, dim3(nb), dim3(kRadixThreads), 0, st, kin, vin, kout, vout, n_static,
-                     n_dev, cap, shift, s.hist, s.tot, nb);
+  const int grid = (int)round_up(nb, kChunkRound);  // also the histogram's row stride
+  hipLaunchKernelGGL(k_radix_hist<ITEMS>, dim3(grid), dim3(kRadixThreads), 0, st, kin, n_static, n_dev, cap, shift,
+                     s.hist, nb, grid);
+  hipLaunchKernelGGL(k_radix_scan, dim3(kRadixDigits), dim3(kRadixThreads), 0, st, s.hist, nb, grid, s.tot);
+  hipLaunchKernelGGL(k_radix_scatter<ITEMS>, dim3(grid), dim3(kRadixThreads), 0, st, kin, vin, kout, vout, n_static,
+                     n_dev, cap, shift, s.hist, s.tot, nb, grid);
   return hipGetLastError();
 }
 
