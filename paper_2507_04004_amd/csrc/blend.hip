@@ -51,8 +51,8 @@ __host__ __device__ __forceinline__ uint32_t n_chunks(uint32_t len, int bd) { re
 // takes whole groups of kGroup consecutive items (neighbouring tiles share that XCD's L2),
 // while the groups themselves are dealt round-robin, which keeps the XCDs evenly loaded
 // (the work per image band differs by a large factor).
-constexpr int kItemThreads = 256;
-constexpr int kItemPer = 4;
+constexpr int kItemThreads = 64;  // one wavefront per 64 tiles: the item pass spreads over the chip
+constexpr int kItemPer = 1;
 constexpr int kItemChunk = kItemThreads * kItemPer;
 constexpr int kStripe = 4;
 constexpr uint32_t kXcds = 8;

@@ -211,7 +211,9 @@ def test_backward_overwrite_and_accumulate(case):
     for k in acc:
         assert np.isfinite(ow[k]).all(), k
         assert np.array_equal(ow[k] == 0, acc[k] == 0) or k == "pose", k  # untouched Gaussians read 0
-        np.testing.assert_allclose(ow[k], acc[k], rtol=1e-4, atol=1e-6 * max(1.0, np.abs(acc[k]).max(initial=0)),
+        # atomics add per-tile sums that cancel: reordering them moves an element by up to a
+        # few 1e-6 of the largest one
+        np.testing.assert_allclose(ow[k], acc[k], rtol=1e-4, atol=1e-5 * max(1.0, np.abs(acc[k]).max(initial=0)),
                                    err_msg=k)
     base = R.ParamGrads.zeros(run.gm)
     rng = np.random.default_rng(3)
@@ -226,7 +228,7 @@ def test_backward_overwrite_and_accumulate(case):
         untouched = acc[k] == 0
         assert np.array_equal(added[k][untouched], pre[k][untouched]), k
         np.testing.assert_allclose(added[k] - pre[k], acc[k], rtol=1e-4,
-                                   atol=1e-6 * max(1.0, np.abs(acc[k]).max(initial=0)), err_msg=k)
+                                   atol=1e-5 * max(1.0, np.abs(acc[k]).max(initial=0)), err_msg=k)
 
 
 def test_lidar_depth_term():
