@@ -489,58 +489,65 @@ __device__ __forceinline__ float dpp(float v) {
   return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, true));
 }
 
-// Sum over the wavefront of ten values. Transposed reduction: four row-local DPP exchanges
-// leave each lane with fewer values (10 -> 5 -> 3 -> 2 -> 1 per lane, the partner lane
-// holding the complementary half), then two cross-row swaps add the four rows. Afterwards
-// lane l holds the total of value reduce10_slot(l) (lanes whose slot is -1 hold nothing).
-__device__ __forceinline__ float wave_reduce10(const float (&g)[10], int lane) {
-  // stage 1, partner i^15 in the 16-lane row (row_mirror): bit 3 clear keeps 0-4, set keeps 5-9
-  float v1[5];
-  const bool h3 = (lane & 8) != 0;
-#pragma unroll
-  for (int m = 0; m < 5; ++m) {
-    const float keep = h3 ? g[5 + m] : g[m];
-    const float send = h3 ? g[m] : g[5 + m];
-    v1[m] = keep + dpp<0x140>(send);
-  }
-  // stage 2, partner i^7 (row_half_mirror): bit 2 clear keeps {0, 1, 2}, set keeps {3, 4}
-  float v2[3];
-  const bool h2 = (lane & 4) != 0;
-#pragma unroll
-  for (int m = 0; m < 3; ++m) {
-    const float hi = m < 2 ? v1[3 + m] : 0.f;
-    const float keep = h2 ? hi : v1[m];
-    const float send = h2 ? v1[m] : hi;
-    v2[m] = keep + dpp<0x141>(send);
-  }
-  // stage 3, partner i^2 (quad_perm [2,3,0,1]): bit 1 clear keeps {0, 1}, set keeps {2}
-  float v3[2];
-  const bool h1 = (lane & 2) != 0;
-#pragma unroll
-  for (int m = 0; m < 2; ++m) {
-    const float hi = m == 0 ? v2[2] : 0.f;
-    const float keep = h1 ? hi : v2[m];
-    const float send = h1 ? v2[m] : hi;
-    v3[m] = keep + dpp<0x4E>(send);
-  }
-  // stage 4, partner i^1 (quad_perm [1,0,3,2]): bit 0 picks one of the two
-  const bool h0 = (lane & 1) != 0;
-  const float keep = h0 ? v3[1] : v3[0];
-  const float send = h0 ? v3[0] : v3[1];
-  float v = keep + dpp<0xB1>(send);
-  // stages 5-6: add the four rows (permlane swaps between rows 0/1, 2/3, then halves)
-  const auto s16 = __builtin_amdgcn_permlane16_swap(__float_as_uint(v), __float_as_uint(v), false, false);
-  v = __uint_as_float(s16[0]) + __uint_as_float(s16[1]);
-  const auto s32 = __builtin_amdgcn_permlane32_swap(__float_as_uint(v), __float_as_uint(v), false, false);
-  v = __uint_as_float(s32[0]) + __uint_as_float(s32[1]);
+// Sum over the wavefront of ten values, transposed so that no lane selects are needed where
+// the lane split falls on a DPP bank (4-lane group) boundary:
+//   1. row_mirror pairs lane i with 15 - i (bit 3 differs). Two DPP adds per output, each
+//      writing half of the banks: lanes with bit 3 clear keep slots 0-4, the others 5-9.
+//   2. row_half_mirror pairs i with 7 - i (bit 2 differs): bit 2 clear keeps the first three
+//      of its five slots, set keeps the last two (its third output is 0).
+//   3. permlane16 swaps add row pairs (0+1, 2+3) of two outputs in one register, and of the
+//      third in another; a permlane32 swap adds the halves: row 0 then holds output 0, row 1
+//      output 1, rows 2 and 3 output 2, each summed over the four rows.
+//   4. two quad DPP adds sum the four lanes of a quad (bits 0 and 1).
+// Afterwards lane l holds the total of value reduce10_slot(l) (-1: nothing to store).
+// The DPP sources are written by ordinary VALU code just before each block, hence the two
+// wait states (s_nop 1) that a DPP read of a freshly written register needs.
+__device__ __forceinline__ float wave_reduce10(const float (&g)[10]) {
+  float a0, a1, a2, a3, a4;
+  asm volatile(
+      "s_nop 1\n"
+      "v_add_f32_dpp %0, %5, %5 row_mirror row_mask:0xf bank_mask:0x3\n"
+      "v_add_f32_dpp %0, %10, %10 row_mirror row_mask:0xf bank_mask:0xc\n"
+      "v_add_f32_dpp %1, %6, %6 row_mirror row_mask:0xf bank_mask:0x3\n"
+      "v_add_f32_dpp %1, %11, %11 row_mirror row_mask:0xf bank_mask:0xc\n"
+      "v_add_f32_dpp %2, %7, %7 row_mirror row_mask:0xf bank_mask:0x3\n"
+      "v_add_f32_dpp %2, %12, %12 row_mirror row_mask:0xf bank_mask:0xc\n"
+      "v_add_f32_dpp %3, %8, %8 row_mirror row_mask:0xf bank_mask:0x3\n"
+      "v_add_f32_dpp %3, %13, %13 row_mirror row_mask:0xf bank_mask:0xc\n"
+      "v_add_f32_dpp %4, %9, %9 row_mirror row_mask:0xf bank_mask:0x3\n"
+      "v_add_f32_dpp %4, %14, %14 row_mirror row_mask:0xf bank_mask:0xc"
+      : "=&v"(a0), "=&v"(a1), "=&v"(a2), "=&v"(a3), "=&v"(a4)
+      : "v"(g[0]), "v"(g[1]), "v"(g[2]), "v"(g[3]), "v"(g[4]), "v"(g[5]), "v"(g[6]), "v"(g[7]), "v"(g[8]),
+        "v"(g[9]));
+  float b0, b1, b2;
+  asm volatile(
+      "s_nop 1\n"
+      "v_mov_b32 %2, 0\n"
+      "v_add_f32_dpp %0, %3, %3 row_half_mirror row_mask:0xf bank_mask:0x5\n"
+      "v_add_f32_dpp %0, %6, %6 row_half_mirror row_mask:0xf bank_mask:0xa\n"
+      "v_add_f32_dpp %1, %4, %4 row_half_mirror row_mask:0xf bank_mask:0x5\n"
+      "v_add_f32_dpp %1, %7, %7 row_half_mirror row_mask:0xf bank_mask:0xa\n"
+      "v_add_f32_dpp %2, %5, %5 row_half_mirror row_mask:0xf bank_mask:0x5"
+      : "=&v"(b0), "=&v"(b1), "=&v"(b2)
+      : "v"(a0), "v"(a1), "v"(a2), "v"(a3), "v"(a4));
+  const auto p01 = __builtin_amdgcn_permlane16_swap(__float_as_uint(b0), __float_as_uint(b1), false, false);
+  const float r01 = __uint_as_float(p01[0]) + __uint_as_float(p01[1]);
+  const auto p22 = __builtin_amdgcn_permlane16_swap(__float_as_uint(b2), __float_as_uint(b2), false, false);
+  const float r22 = __uint_as_float(p22[0]) + __uint_as_float(p22[1]);
+  const auto q = __builtin_amdgcn_permlane32_swap(__float_as_uint(r01), __float_as_uint(r22), false, false);
+  float v = __uint_as_float(q[0]) + __uint_as_float(q[1]);
+  v += dpp<0xB1>(v);  // quad_perm [1,0,3,2]
+  v += dpp<0x4E>(v);  // quad_perm [2,3,0,1]
   return v;
 }
 
-// Which of the ten values lane l (of the first row) holds after wave_reduce10, or -1.
+// Which of the ten values lane l holds after wave_reduce10, or -1 (one lane per quad; bits 3-2
+// pick the slot group {0-2, 3-4, 5-7, 8-9}, the row the member of the group).
 __device__ __forceinline__ int reduce10_slot(int lane) {
-  const int r = lane & 7;
-  const int loc = r < 3 ? r : (r == 4 ? 3 : (r == 5 ? 4 : -1));
-  return (lane < 16 && loc >= 0) ? ((lane & 8) ? 5 : 0) + loc : -1;
+  const int grp = (lane >> 2) & 3, row = lane >> 4;
+  const int base = grp == 0 ? 0 : (grp == 1 ? 3 : (grp == 2 ? 5 : 8));
+  const bool ok = (lane & 3) == 0 && (row < 2 || (row == 2 && (grp & 1) == 0));
+  return ok ? base + row : -1;
 }
 
 // Backward state of one pixel.
@@ -622,7 +629,7 @@ __global__ __launch_bounds__(NT) void k_blend_bwd_chunk(ViewTable vt, ImgTable i
   __syncthreads();
   if (mymax >= 0) atomicMax(&s_max, mymax);
   __syncthreads();
-  const int maxll = s_max;
+  const int maxll = __builtin_amdgcn_readfirstlane(s_max);  // uniform: the splat loop runs on scalar registers
   if (maxll < 0) return;  // uniform: no pixel has a contributor in this chunk
   stage<BD, NT>(vals, cs, maxll + 1, card, s_a, s_b, s_c, s_e);
   __syncthreads();
@@ -683,7 +690,7 @@ __global__ __launch_bounds__(NT) void k_blend_bwd_chunk(ViewTable vt, ImgTable i
       g[3] += dpx * dys[k];
       g[4] += (dp * dys[k]) * dys[k];
     }
-    const float tot = wave_reduce10(g, lane);
+    const float tot = wave_reduce10(g);
     if (slot >= 0 && tot != 0.f) unsafeAtomicAdd(&g2[(int64_t)s_e[j] * 12 + slot], tot);
   }
 }
