@@ -172,6 +172,9 @@ struct TileCtx {
   }
 };
 
+// Splats per compositing group (the unit of the early exit and of the last-index bookkeeping).
+constexpr int kGroupLen = 8;
+
 template <int BD, int NT>
 __device__ __forceinline__ void stage(const uint32_t *__restrict__ vals, uint32_t start, int cnt,
                                       const Card *__restrict__ card, float4 *s_a, float4 *s_b, float4 *s_c,
@@ -181,6 +184,15 @@ __device__ __forceinline__ void stage(const uint32_t *__restrict__ vals, uint32_
     if (s_e) s_e[k] = e;
     const Card &cd = card[e];
     stage_card(cd.a, cd.b, cd.c, s_a[k], s_b[k], s_c[k]);
+  }
+  // up to the next multiple of kGroupLen: records of opacity 0 (alpha 0, never blended), so
+  // the compositing loop runs whole groups
+  const int padded = min(BD, (cnt + kGroupLen - 1) / kGroupLen * kGroupLen);
+  for (int k = cnt + (int)threadIdx.x; k < padded; k += NT) {
+    const float4 z = make_float4(0.f, 0.f, 0.f, 0.f);
+    s_a[k] = z;
+    s_b[k] = z;
+    s_c[k] = z;
   }
 }
 
@@ -197,10 +209,13 @@ __device__ __forceinline__ void write_pixel(const ViewImg &im, const ViewCam &ca
 }
 
 // Compositing state of one pixel.
+// The last blended position is lastg + lastr: lastg is the start of the group that holds it,
+// lastr its offset inside the group (a constant per unrolled step).
 struct PixState {
   float T, C0, C1, C2, D, O;
-  int32_t last, nc;
+  int32_t lastg, lastr, nc;
   bool stopped;
+  __device__ __forceinline__ int32_t last() const { return lastg + lastr; }
 };
 
 // Front-to-back over cnt staged splats for the lane's PPT pixels, continuing each pixel's
@@ -208,41 +223,50 @@ struct PixState {
 // its T below 1e-4. Selects instead of branches: a skipped splat adds an exact zero, so the
 // sums equal those of a branching walk bit for bit. The wavefront leaves once all its
 // pixels have stopped. CNT: also count the contributors (only when that output is wanted).
+// The staged list is padded to whole groups of kGroupLen (by stage).
 template <int PPT, bool CNT>
 __device__ __forceinline__ void composite_run(const float4 *s_a, const float4 *s_b, const float4 *s_c, int cnt,
                                               const float (&px)[PPT], const float (&py)[PPT], int pos0,
                                               PixState (&st)[PPT]) {
-  for (int j0 = 0; j0 < cnt; j0 += 8) {
+  for (int j0 = 0; j0 < cnt; j0 += kGroupLen) {
     bool all = true;
 #pragma unroll
     for (int k = 0; k < PPT; ++k) all = all && st[k].stopped;
     if (__all(all)) break;
-    const int jn = min(cnt, j0 + 8);
-#pragma unroll 4
-    for (int j = j0; j < jn; ++j) {
+    bool took[PPT];
+#pragma unroll
+    for (int k = 0; k < PPT; ++k) took[k] = false;
+#pragma unroll
+    for (int u = 0; u < kGroupLen; ++u) {
+      const int j = j0 + u;
       const float4 A = s_a[j], B = s_b[j], Cc = s_c[j];
 #pragma unroll
       for (int k = 0; k < PPT; ++k) {
         PixState &p = st[k];
         float m, qc;
         const float p2 = splat_p2(A, B, px[k] - A.x, py[k] - A.y, m, qc);
-        const float alpha = fminf(kAlphaMax, B.y * __builtin_amdgcn_exp2f(p2));
-        const float Tn = p.T * (1.f - alpha);
-        const bool blend = !p.stopped && alpha >= kAlphaMin;
-        const bool stop = blend && Tn < kTMin;
-        const bool take = blend && !stop;
-        p.stopped = p.stopped || stop;
-        const float w = take ? alpha * p.T : 0.f;
+        const float alpha = fminf(kAlphaMax, B.y * splat_e2(p2));
+        const float wt = alpha * p.T;  // the weight, and T's decrement: T (1 - alpha) = T - alpha T
+        const float Tn = p.T - wt;
+        // take = !stopped && alpha_ok && !low, written through the updated stop flag so that
+        // the one compare of Tn serves both (its negation falls on a lane mask)
+        const bool alpha_ok = alpha >= kAlphaMin;
+        p.stopped = p.stopped || (alpha_ok && Tn < kTMin);
+        const bool take = alpha_ok && !p.stopped;
+        const float w = take ? wt : 0.f;
         p.C0 += w * Cc.x;
         p.C1 += w * Cc.y;
         p.C2 += w * Cc.z;
         p.D += w * B.z;
         p.O += w;
         p.T = take ? Tn : p.T;
-        p.last = take ? pos0 + j : p.last;
+        p.lastr = take ? u : p.lastr;
+        took[k] = took[k] || take;
         if constexpr (CNT) p.nc += take ? 1 : 0;
       }
     }
+#pragma unroll
+    for (int k = 0; k < PPT; ++k) st[k].lastg = took[k] ? pos0 + j0 : st[k].lastg;
   }
 }
 
@@ -276,7 +300,7 @@ __global__ __launch_bounds__(NT) void k_blend_chunk(ViewTable vt, ImgTable it, c
 #pragma unroll
   for (int k = 0; k < PPT; ++k) {
     tile.pixel(k, inside[k], px[k], py[k], pi[k]);
-    st[k] = PixState{1.f, 0.f, 0.f, 0.f, 0.f, 0.f, -1, 0, !inside[k]};
+    st[k] = PixState{1.f, 0.f, 0.f, 0.f, 0.f, 0.f, -1, 0, 0, !inside[k]};
   }
   composite_run<PPT, CNT>(s_a, s_b, s_c, cnt, px, py, 0, st);
 #pragma unroll
@@ -284,11 +308,11 @@ __global__ __launch_bounds__(NT) void k_blend_chunk(ViewTable vt, ImgTable it, c
     if (!inside[k]) continue;
     const PixState &p = st[k];
     if (K == 1) {
-      write_pixel(it.v[tile.vi], *tile.cam, pi[k], tile.npx, p.C0, p.C1, p.C2, p.D, p.O, p.T, p.last, p.nc);
+      write_pixel(it.v[tile.vi], *tile.cam, pi[k], tile.npx, p.C0, p.C1, p.C2, p.D, p.O, p.T, p.last(), p.nc);
     } else {
       ChunkRec r;
       r.c0 = p.C0; r.c1 = p.C1; r.c2 = p.C2; r.d = p.D; r.o = p.O; r.t = p.T;
-      r.info = (uint32_t)(p.last + 1) | ((uint32_t)p.nc << 10) | ((uint32_t)p.stopped << 20);
+      r.info = (uint32_t)(p.last() + 1) | ((uint32_t)p.nc << 10) | ((uint32_t)p.stopped << 20);
       r.pad = 0.f;
       chunk[(int64_t)item * (TW * TH) + tile.pidx(k)] = r;
     }
@@ -412,7 +436,7 @@ __global__ __launch_bounds__(NT) void k_blend_fix(ViewTable vt, ImgTable it, con
     pending[k] = inside[k] && (r[k].info & kPending);
     any = any || pending[k];
     // composite the chunk's splats only (partial sums start at zero; O and the count carry on)
-    st[k] = PixState{r[k].t, 0.f, 0.f, 0.f, 0.f, r[k].o, (int32_t)(r[k].info & 0x3FFFFFFFu) - 1,
+    st[k] = PixState{r[k].t, 0.f, 0.f, 0.f, 0.f, r[k].o, (int32_t)(r[k].info & 0x3FFFFFFFu) - 1, 0,
                      __float_as_int(r[k].pad), !pending[k]};
   }
   if (__syncthreads_count(any) == 0) return;
@@ -426,7 +450,7 @@ __global__ __launch_bounds__(NT) void k_blend_fix(ViewTable vt, ImgTable it, con
     if (!pending[k]) continue;
     const PixState &p = st[k];
     write_pixel(it.v[tile.vi], *tile.cam, pi[k], tile.npx, r[k].c0 + p.C0, r[k].c1 + p.C1, r[k].c2 + p.C2,
-                r[k].d + p.D, p.O, p.T, p.last, p.nc);
+                r[k].d + p.D, p.O, p.T, p.last(), p.nc);
     ChunkRec w;
     w.c0 = p.C0; w.c1 = p.C1; w.c2 = p.C2; w.d = p.D; w.o = 0.f; w.t = p.T; w.info = 0u; w.pad = 0.f;
     chunk[(int64_t)item * (TW * TH) + tile.pidx(k)] = w;
@@ -648,7 +672,7 @@ __global__ __launch_bounds__(NT) void k_blend_bwd_chunk(ViewTable vt, ImgTable i
       dxs[k] = pg[k].px - A.x;
       dys[k] = pg[k].py - A.y;
       const float p2 = splat_p2(A, B, dxs[k], dys[k], ms[k], qcs[k]);
-      exs[k] = __builtin_amdgcn_exp2f(p2);
+      exs[k] = splat_e2(p2);
       ars[k] = B.y * exs[k];
       act[k] = j <= pg[k].ll && fminf(kAlphaMax, ars[k]) >= kAlphaMin;
       any = any || act[k];

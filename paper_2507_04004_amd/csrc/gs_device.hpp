@@ -85,9 +85,10 @@ __device__ __forceinline__ int view_of_tile(const ViewTable &vt, uint32_t gt) {
 // exponent comes out in base 2 (alpha = o 2^p, p = log2(e) * (-q/2)) with the -1/2 folded in:
 //   sa = (u, v, a', b'), sb = (c', o, d, b'/2), with a' = kA a, b' = 2 kA b, c' = kA c,
 //   kA = -log2(e) / 2.
-// p = dx (a' dx + b' dy) + c' dy^2, clamped to <= 0 (q >= 0 exactly; the clamp only absorbs
-// rounding). The forward and the backward both evaluate it through splat_p2, with fixed FMA
-// placement, so they take identical alpha decisions.
+// p = dx (a' dx + b' dy) + c' dy^2 <= 0 in exact arithmetic; splat_e2 returns 2^p clamped to
+// at most 1, which equals 2^min(p, 0) and so absorbs the rounding that can leave p slightly
+// positive. The forward and the backward both evaluate it through splat_p2 and splat_e2,
+// with fixed FMA placement, so they take identical alpha decisions.
 constexpr float kA = -0.72134752044448170368f;  // -log2(e) / 2
 
 __device__ __forceinline__ void stage_card(const float4 &A, const float4 &B, const float4 &C, float4 &sa, float4 &sb,
@@ -106,7 +107,12 @@ __device__ __forceinline__ float splat_p2(const float4 &sa, const float4 &sb, fl
   const float t = fmaf(sa.w, dy, m);
   qc = sb.x * dy;
   const float q = qc * dy;
-  return fminf(fmaf(dx, t, q), 0.0f);
+  return fmaf(dx, t, q);
+}
+
+// 2^p clamped to [0, 1] (the median with 0 and 1 becomes the clamp bit of the exp instruction).
+__device__ __forceinline__ float splat_e2(float p) {
+  return __builtin_amdgcn_fmed3f(__builtin_amdgcn_exp2f(p), 0.0f, 1.0f);
 }
 
 // Smallest value of q over the pixel-centre rectangle [xl,xh] x [yl,yh]: zero when the
