@@ -218,56 +218,68 @@ struct PixState {
   __device__ __forceinline__ int32_t last() const { return lastg + lastr; }
 };
 
-// Front-to-back over cnt staged splats for the lane's PPT pixels, continuing each pixel's
-// state. A splat with alpha < 1/255 is skipped; a pixel stops before a splat that would take
-// its T below 1e-4. Selects instead of branches: a skipped splat adds an exact zero, so the
-// sums equal those of a branching walk bit for bit. The wavefront leaves once all its
-// pixels have stopped. CNT: also count the contributors (only when that output is wanted).
-// The staged list is padded to whole groups of kGroupLen (by stage).
+// One staged splat over the lane's PPT pixels, continuing each pixel's state; u is the
+// splat's offset inside its group. A splat with alpha < 1/255 is skipped; a pixel stops
+// before a splat that would take its T below 1e-4. Selects instead of branches: a skipped
+// splat adds an exact zero, so the sums equal those of a branching walk bit for bit.
+// CNT: also count the contributors (only when that output is wanted).
 template <int PPT, bool CNT>
-__device__ __forceinline__ void composite_run(const float4 *s_a, const float4 *s_b, const float4 *s_c, int cnt,
+__device__ __forceinline__ void composite_splat(const float4 &A, const float4 &B, const float4 &Cc, int u,
+                                                const float (&px)[PPT], const float (&py)[PPT],
+                                                PixState (&st)[PPT], bool (&took)[PPT]) {
+#pragma unroll
+  for (int k = 0; k < PPT; ++k) {
+    PixState &p = st[k];
+    float m, qc;
+    const float p2 = splat_p2(A, B, px[k] - A.x, py[k] - A.y, m, qc);
+    const float alpha = fminf(kAlphaMax, B.y * splat_e2(p2));
+    const float wt = alpha * p.T;  // the weight, and T's decrement: T (1 - alpha) = T - alpha T
+    const float Tn = p.T - wt;
+    // take = !stopped && alpha_ok && !low, written through the updated stop flag so that the
+    // one compare of Tn serves both (its negation falls on a lane mask)
+    const bool alpha_ok = alpha >= kAlphaMin;
+    p.stopped = p.stopped || (alpha_ok && Tn < kTMin);
+    const bool take = alpha_ok && !p.stopped;
+    const float w = take ? wt : 0.f;
+    p.C0 += w * Cc.x;
+    p.C1 += w * Cc.y;
+    p.C2 += w * Cc.z;
+    p.D += w * B.z;
+    p.O += w;
+    p.T = take ? Tn : p.T;
+    p.lastr = take ? u : p.lastr;
+    took[k] = took[k] || take;
+    if constexpr (CNT) p.nc += take ? 1 : 0;
+  }
+}
+
+template <int PPT>
+__device__ __forceinline__ bool all_stopped(const PixState (&st)[PPT]) {
+  bool all = true;
+#pragma unroll
+  for (int k = 0; k < PPT; ++k) all = all && st[k].stopped;
+  return __all(all);
+}
+
+// Front-to-back over cnt staged splats (padded to whole groups of kGroupLen by the staging)
+// for the lane's PPT pixels; positions are pos0 + index. Returns false once every pixel of
+// the wavefront has stopped (the walk then ends early).
+template <int PPT, bool CNT, int G = kGroupLen>
+__device__ __forceinline__ bool composite_run(const float4 *s_a, const float4 *s_b, const float4 *s_c, int cnt,
                                               const float (&px)[PPT], const float (&py)[PPT], int pos0,
                                               PixState (&st)[PPT]) {
-  for (int j0 = 0; j0 < cnt; j0 += kGroupLen) {
-    bool all = true;
-#pragma unroll
-    for (int k = 0; k < PPT; ++k) all = all && st[k].stopped;
-    if (__all(all)) break;
+  static_assert(kGroupLen % G == 0, "groups must tile the padding");
+  for (int j0 = 0; j0 < cnt; j0 += G) {
+    if (all_stopped(st)) return false;
     bool took[PPT];
 #pragma unroll
     for (int k = 0; k < PPT; ++k) took[k] = false;
 #pragma unroll
-    for (int u = 0; u < kGroupLen; ++u) {
-      const int j = j0 + u;
-      const float4 A = s_a[j], B = s_b[j], Cc = s_c[j];
-#pragma unroll
-      for (int k = 0; k < PPT; ++k) {
-        PixState &p = st[k];
-        float m, qc;
-        const float p2 = splat_p2(A, B, px[k] - A.x, py[k] - A.y, m, qc);
-        const float alpha = fminf(kAlphaMax, B.y * splat_e2(p2));
-        const float wt = alpha * p.T;  // the weight, and T's decrement: T (1 - alpha) = T - alpha T
-        const float Tn = p.T - wt;
-        // take = !stopped && alpha_ok && !low, written through the updated stop flag so that
-        // the one compare of Tn serves both (its negation falls on a lane mask)
-        const bool alpha_ok = alpha >= kAlphaMin;
-        p.stopped = p.stopped || (alpha_ok && Tn < kTMin);
-        const bool take = alpha_ok && !p.stopped;
-        const float w = take ? wt : 0.f;
-        p.C0 += w * Cc.x;
-        p.C1 += w * Cc.y;
-        p.C2 += w * Cc.z;
-        p.D += w * B.z;
-        p.O += w;
-        p.T = take ? Tn : p.T;
-        p.lastr = take ? u : p.lastr;
-        took[k] = took[k] || take;
-        if constexpr (CNT) p.nc += take ? 1 : 0;
-      }
-    }
+    for (int u = 0; u < G; ++u) composite_splat<PPT, CNT>(s_a[j0 + u], s_b[j0 + u], s_c[j0 + u], u, px, py, st, took);
 #pragma unroll
     for (int k = 0; k < PPT; ++k) st[k].lastg = took[k] ? pos0 + j0 : st[k].lastg;
   }
+  return true;
 }
 
 // ---- forward pass 1: every chunk from transmittance 1 ------------------------------------
@@ -454,6 +466,137 @@ __global__ __launch_bounds__(NT) void k_blend_fix(ViewTable vt, ImgTable it, con
     ChunkRec w;
     w.c0 = p.C0; w.c1 = p.C1; w.c2 = p.C2; w.d = p.D; w.o = 0.f; w.t = p.T; w.info = 0u; w.pad = 0.f;
     chunk[(int64_t)item * (TW * TH) + tile.pidx(k)] = w;
+  }
+}
+
+// ---- forward passes 1 and 3 for 8x8 tiles: two work items per wavefront ----------------
+// With one pixel per lane the broadcast LDS reads of the staged splats (40 B per splat and
+// lane) bound the compositing loop. Here lanes 0-31 take item 2p and lanes 32-63 item 2p + 1,
+// two pixels each (rows 0-3 and 4-7 of the 8x8 tile): one LDS instruction delivers a splat of
+// each item and every lane uses it for two pixels, which halves the LDS bytes per
+// evaluation. Each chunk is staged in sub-chunks of kSub splats (the LDS footprint of a
+// one-item workgroup); the half with fewer splats runs over opacity-0 padding. The second
+// half's arrays start 16 B further into the banks, so the two addresses of a read differ in
+// bank.
+constexpr int kSub = 64;
+constexpr int kPairGroup = 8;  // splats per unrolled group in the two-item loop
+constexpr int kHalfStride = kSub + 1;  // float4 entries per half in the staging arrays
+
+// Pair of items of this workgroup after the XCD remap; false when neither exists.
+__device__ __forceinline__ bool pair_of_block(const uint32_t *n_items, uint32_t &pair) {
+  const uint32_t x = blockIdx.x % kXcds, k = blockIdx.x / kXcds;
+  pair = ((k / kGroup) * kXcds + x) * kGroup + k % kGroup;
+  return 2 * pair < *n_items;
+}
+
+// One half-wavefront's item: its tile, chunk and the lane's two pixels.
+template <int BD>
+struct HalfItem {
+  bool valid;
+  uint32_t item, gt, c, K, cs;
+  int cnt, vi;
+  const ViewCam *cam;
+  int64_t npx;
+  bool inside[2];
+  float px[2], py[2];
+  int64_t pi[2];
+  int q[2];  // row-major pixel index in the tile
+
+  __device__ __forceinline__ HalfItem(const ViewTable &vt, const uint2 *items, const uint32_t *range, uint32_t nI,
+                                      uint32_t it, int hl) {
+    item = it;
+    valid = it < nI;
+    const uint2 tc = valid ? items[it] : make_uint2(0u, 0u);
+    gt = tc.x;
+    c = tc.y;
+    const uint32_t s0 = valid ? range[2 * gt] : 0u, e0 = valid ? range[2 * gt + 1] : 0u;
+    K = n_chunks(e0 - s0, BD);
+    cs = s0 + c * BD;
+    cnt = valid ? (int)min<uint32_t>(BD, e0 - cs) : 0;
+    vi = view_of_tile(vt, gt);
+    cam = &vt.v[vi];
+    npx = (int64_t)cam->w * cam->h;
+    const uint32_t lt = gt - cam->tile_base;
+    const int tx = (int)(lt % (uint32_t)cam->tiles_x), ty = (int)(lt / (uint32_t)cam->tiles_x);
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+      q[k] = hl + 32 * k;
+      const int wx = tx * 8 + (q[k] & 7), wy = ty * 8 + (q[k] >> 3);
+      inside[k] = valid && wx < cam->w && wy < cam->h;
+      px[k] = (float)(cam->x0 + wx);
+      py[k] = (float)(cam->y0 + wy);
+      pi[k] = (int64_t)wy * cam->w + wx;
+    }
+  }
+};
+
+// Stage splats [base, base + kSub) of the half's chunk (zero records past cnt) into its half
+// of the arrays; 32 lanes, two splats each.
+__device__ __forceinline__ void stage_half(const uint32_t *__restrict__ vals, const Card *__restrict__ card,
+                                           uint32_t cs, int cnt, int base, int hl, float4 *a, float4 *b, float4 *cc) {
+#pragma unroll
+  for (int r = 0; r < 2; ++r) {
+    const int kk = hl + 32 * r;
+    float4 sa = make_float4(0.f, 0.f, 0.f, 0.f), sb = sa, sc = sa;
+    if (base + kk < cnt) {
+      const Card &cd = card[vals[cs + base + kk]];
+      stage_card(cd.a, cd.b, cd.c, sa, sb, sc);
+    }
+    a[kk] = sa;
+    b[kk] = sb;
+    cc[kk] = sc;
+  }
+}
+
+// Both halves over their chunks, sub-chunk by sub-chunk; positions are relative to the chunk
+// start. Leaves early once every pixel of the wavefront has stopped.
+template <int BD, bool CNT>
+__device__ __forceinline__ void composite_pair(const uint32_t *__restrict__ vals, const Card *__restrict__ card,
+                                               const HalfItem<BD> &hi, int hl, float4 *s_a, float4 *s_b, float4 *s_c,
+                                               PixState (&st)[2]) {
+  const int h = (int)threadIdx.x >> 5;
+  float4 *a = s_a + h * kHalfStride, *b = s_b + h * kHalfStride, *cc = s_c + h * kHalfStride;
+  const int n_max = max(__builtin_amdgcn_readlane(hi.cnt, 0), __builtin_amdgcn_readlane(hi.cnt, 32));
+#pragma unroll 1
+  for (int base = 0; base < n_max; base += kSub) {
+    if (all_stopped(st)) return;
+    __syncthreads();  // the previous sub-chunk's reads are done
+    stage_half(vals, card, hi.cs, hi.cnt, base, hl, a, b, cc);
+    __syncthreads();
+    const int len = min(kSub, n_max - base);
+    if (!composite_run<2, CNT, kPairGroup>(a, b, cc, len, hi.px, hi.py, base, st)) return;
+  }
+}
+
+template <int BD, bool CNT>
+__global__ __launch_bounds__(64) void k_blend_chunk_pair(ViewTable vt, ImgTable it, const Card *__restrict__ card,
+                                                         const uint32_t *__restrict__ vals,
+                                                         const uint32_t *__restrict__ range,
+                                                         const uint2 *__restrict__ items,
+                                                         const uint32_t *__restrict__ n_items,
+                                                         ChunkRec *__restrict__ chunk) {
+  __shared__ float4 s_a[2 * kHalfStride], s_b[2 * kHalfStride], s_c[2 * kHalfStride];
+  uint32_t pair;
+  if (!pair_of_block(n_items, pair)) return;
+  const int hl = (int)threadIdx.x & 31;
+  const HalfItem<BD> hi(vt, items, range, *n_items, 2 * pair + (threadIdx.x >> 5), hl);
+  PixState st[2];
+#pragma unroll
+  for (int k = 0; k < 2; ++k) st[k] = PixState{1.f, 0.f, 0.f, 0.f, 0.f, 0.f, -1, 0, 0, !hi.inside[k]};
+  composite_pair<BD, CNT>(vals, card, hi, hl, s_a, s_b, s_c, st);
+#pragma unroll
+  for (int k = 0; k < 2; ++k) {
+    if (!hi.inside[k]) continue;
+    const PixState &p = st[k];
+    if (hi.K == 1) {
+      write_pixel(it.v[hi.vi], *hi.cam, hi.pi[k], hi.npx, p.C0, p.C1, p.C2, p.D, p.O, p.T, p.last(), p.nc);
+    } else {
+      ChunkRec r;
+      r.c0 = p.C0; r.c1 = p.C1; r.c2 = p.C2; r.d = p.D; r.o = p.O; r.t = p.T;
+      r.info = (uint32_t)(p.last() + 1) | ((uint32_t)p.nc << 10) | ((uint32_t)p.stopped << 20);
+      r.pad = 0.f;
+      chunk[(int64_t)hi.item * 64 + hi.q[k]] = r;
+    }
   }
 }
 
@@ -780,9 +923,17 @@ static hipError_t fwd_impl_cnt(const ViewTable &vt, const ImgTable &it, const gs
   hipLaunchKernelGGL(k_items_scan, dim3(1), dim3(1024), 0, st, s.bsum, nb, s.n_items, s.item_base, T);
   hipLaunchKernelGGL(k_items_apply, dim3(nb), dim3(kItemThreads), 0, st, vt, range, BD, s.bsum, s.item_base, s.items,
                      s.need_fix);
-  hipLaunchKernelGGL((k_blend_chunk<TW, TH, BD, NT, CNT>), dim3((unsigned)s.I), dim3(NT), 0, st, vt, it,
-                     (const Card *)p.card, vals, range,
-                     (const uint2 *)s.items, (const uint32_t *)s.n_items, s.chunk);
+  // 8x8 tiles: two items per wavefront (rounded up to whole rounds of the XCD remap)
+  constexpr bool kPair = TW == 8 && TH == 8;
+  const int64_t r = (int64_t)kXcds * kGroup;
+  const unsigned pairs = (unsigned)(((s.I + 1) / 2 + r - 1) / r * r);
+  if constexpr (kPair)
+    hipLaunchKernelGGL((k_blend_chunk_pair<BD, CNT>), dim3(pairs), dim3(64), 0, st, vt, it, (const Card *)p.card,
+                       vals, range, (const uint2 *)s.items, (const uint32_t *)s.n_items, s.chunk);
+  else
+    hipLaunchKernelGGL((k_blend_chunk<TW, TH, BD, NT, CNT>), dim3((unsigned)s.I), dim3(NT), 0, st, vt, it,
+                       (const Card *)p.card, vals, range,
+                       (const uint2 *)s.items, (const uint32_t *)s.n_items, s.chunk);
   hipLaunchKernelGGL((k_blend_scan<TW, TH, BD>), dim3(T), dim3(TW * TH), 0, st, vt, it, range,
                      (const uint32_t *)s.item_base, s.chunk, s.need_fix);
   hipLaunchKernelGGL((k_blend_fix<TW, TH, BD, NT, CNT>), dim3((unsigned)s.I), dim3(NT), 0, st, vt, it,
