@@ -357,6 +357,70 @@ __global__ __launch_bounds__(256) void k_sh_bwd(ViewTable vt, const float *__res
   // every plane is addressed by a scalar descriptor and one shared 32-bit lane offset
   const Planes P(n, gi);
   const float mx = P.ld(mean, 0), my = P.ld(mean, 1), mz = P.ld(mean, 2);
+  if constexpr (SINGLE && OVERWRITE) {
+    // One view, every plane written. All lanes run the body (a lane without a contribution
+    // with zero weights and a fixed direction, its coefficients not loaded), so each plane
+    // leaves the wavefront as one full-width store instead of a store of the contributing
+    // lanes now and one of zeros later, which the L2 could write back in pieces.
+    const ViewCam &cam = vt.v[0];
+    bool live = n_tiles[gi] > 0;
+    float2 G67 = make_float2(0.f, 0.f);
+    float G8 = 0.f;
+    if (live) {
+      G67 = *reinterpret_cast<const float2 *>(g2 + (int64_t)gi * 12 + 6);
+      G8 = g2[(int64_t)gi * 12 + 8];
+      live = G67.x != 0.f || G67.y != 0.f || G8 != 0.f;
+    }
+    float c_dc[3] = {0.f, 0.f, 0.f}, c_rest[NRA];
+#pragma unroll
+    for (int i = 0; i < NRA; ++i) c_rest[i] = 0.f;
+    if (live) {
+#pragma unroll
+      for (int ch = 0; ch < 3; ++ch) c_dc[ch] = P.ld(sh_dc, ch);
+#pragma unroll
+      for (int i = 0; i < NR; ++i) c_rest[i] = P.ld(sh_rest, i);
+    }
+    float dir[3], dist;
+    view_dir(cam, mx, my, mz, dir, dist);
+    if (!live) {
+      dir[0] = 0.f;
+      dir[1] = 0.f;
+      dir[2] = 1.f;
+      dist = 1.f;
+    }
+    float Y[16];
+    sh_eval(DEG, dir[0], dir[1], dir[2], Y);
+    float raw[3];
+    sh_colour_raw_v(DEG, c_dc, c_rest, Y, raw);
+    const float gr[3] = {live && raw[0] > 0.f ? G67.x : 0.f, live && raw[1] > 0.f ? G67.y : 0.f,
+                         live && raw[2] > 0.f ? G8 : 0.f};
+    if (out_dc) {
+#pragma unroll
+      for (int ch = 0; ch < 3; ++ch) P.st(out_dc, ch, gr[ch] * Y[0]);
+    }
+    float gd[3] = {0.f, 0.f, 0.f};
+#pragma unroll
+    for (int k = 1; k < K; ++k) {
+      float yk, d0, d1, d2;
+      sh_term(k, dir[0], dir[1], dir[2], yk, d0, d1, d2);
+      float sk = 0.f;
+#pragma unroll
+      for (int ch = 0; ch < 3; ++ch) {
+        const int i = 3 * (k - 1) + ch;
+        sk += gr[ch] * c_rest[i];
+        if (out_rest) P.st(out_rest, i, gr[ch] * yk);
+      }
+      gd[0] += sk * d0;
+      gd[1] += sk * d1;
+      gd[2] += sk * d2;
+    }
+    const float dd = gd[0] * dir[0] + gd[1] * dir[1] + gd[2] * dir[2];
+    const float idist = 1.0f / dist;
+    gdir[gi] = live ? make_float4((gd[0] - dd * dir[0]) * idist, (gd[1] - dd * dir[1]) * idist,
+                                  (gd[2] - dd * dir[2]) * idist, 0.f)
+                    : make_float4(0.f, 0.f, 0.f, 0.f);
+    return;
+  }
   bool any_live = false, loaded = false;
   float c_dc[3], c_rest[NRA];
   float acc_dc[3] = {0.f, 0.f, 0.f};

@@ -74,6 +74,8 @@ __global__ void k_zero_f32(float *p, int64_t n) {
   if (i < n) p[i] = 0.f;
 }
 
+constexpr int kLossUnroll = 4;
+
 // vec: every pointer is 16-B aligned, so the bulk goes through float4 accesses
 __global__ __launch_bounds__(256) void k_loss_l1(const float *__restrict__ c, const float *__restrict__ t, int64_t n,
                                                  float weight, float *__restrict__ dldc, float *__restrict__ loss,
@@ -87,11 +89,26 @@ __global__ __launch_bounds__(256) void k_loss_l1(const float *__restrict__ c, co
   const float4 *c4 = reinterpret_cast<const float4 *>(c), *t4 = reinterpret_cast<const float4 *>(t);
   float4 *d4 = reinterpret_cast<float4 *>(dldc);
   const int64_t stride = (int64_t)gridDim.x * 256;
-  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n4; i += stride) {
-    const float4 a = c4[i], b = t4[i];
-    const float r0 = a.x - b.x, r1 = a.y - b.y, r2 = a.z - b.z, r3 = a.w - b.w;
-    s += (fabsf(r0) + fabsf(r1)) + (fabsf(r2) + fabsf(r3));
-    if (dldc) d4[i] = make_float4(sgn(r0), sgn(r1), sgn(r2), sgn(r3));
+  // kLossUnroll float4 per lane and step, all requested before the first is used
+  for (int64_t i0 = (int64_t)blockIdx.x * (256 * kLossUnroll) + threadIdx.x; i0 < n4; i0 += stride * kLossUnroll) {
+    float4 a[kLossUnroll], b[kLossUnroll];
+#pragma unroll
+    for (int u = 0; u < kLossUnroll; ++u) {
+      const int64_t i = i0 + u * 256;
+      if (i < n4) {
+        a[u] = c4[i];
+        b[u] = t4[i];
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < kLossUnroll; ++u) {
+      const int64_t i = i0 + u * 256;
+      if (i < n4) {
+        const float r0 = a[u].x - b[u].x, r1 = a[u].y - b[u].y, r2 = a[u].z - b[u].z, r3 = a[u].w - b[u].w;
+        s += (fabsf(r0) + fabsf(r1)) + (fabsf(r2) + fabsf(r3));
+        if (dldc) d4[i] = make_float4(sgn(r0), sgn(r1), sgn(r2), sgn(r3));
+      }
+    }
   }
   for (int64_t i = 4 * n4 + (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += stride) {
     const float r = c[i] - t[i];
@@ -134,7 +151,8 @@ hipError_t launch_loss_l1(const float *c, const float *t, int64_t n, float weigh
   if (loss) hipLaunchKernelGGL(k_zero_f32, dim3(1), dim3(64), 0, st, loss, (int64_t)1);
   const int vec = ((reinterpret_cast<uintptr_t>(c) | reinterpret_cast<uintptr_t>(t) |
                     reinterpret_cast<uintptr_t>(dldc)) & 15u) == 0;
-  const int64_t blocks = std::min<int64_t>((n / 4 + 255) / 256 + 1, 1024);  // one atomic per block
+  // one atomic per block; a block covers 256 * kLossUnroll float4 per step
+  const int64_t blocks = std::min<int64_t>((n / 4 + 256 * kLossUnroll - 1) / (256 * kLossUnroll) + 1, 1024);
   if (n > 0)
     hipLaunchKernelGGL(k_loss_l1, dim3((unsigned)std::max<int64_t>(blocks, 1)), dim3(256), 0, st, c, t, n, weight,
                        dldc, loss, vec);
