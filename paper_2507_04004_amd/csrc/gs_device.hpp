@@ -143,30 +143,6 @@ __device__ __forceinline__ float rect_qmin(float u, float v, float a, float b, f
   return best;
 }
 
-// Kept tiles of a splat, in row-major order over its rectangle. The visitor gets the local
-// tile id, the rank among kept tiles and the tile's row-major index inside the rectangle.
-template <typename F>
-__device__ __forceinline__ uint32_t visit_kept_tiles(const ViewCam &cam, int tw, int th, float u, float v, float a,
-                                                     float b, float c, float kappa2, int tx0, int ty0, int tx1,
-                                                     int ty1, F &&f) {
-  uint32_t cnt = 0, t = 0;
-  const int xend = cam.x0 + cam.w - 1, yend = cam.y0 + cam.h - 1;
-  for (int ty = ty0; ty <= ty1; ++ty) {
-    const int ya = cam.y0 + ty * th;
-    const int yb = min(ya + th - 1, yend);
-    for (int tx = tx0; tx <= tx1; ++tx, ++t) {
-      const int xa = cam.x0 + tx * tw;
-      const int xb = min(xa + tw - 1, xend);
-      float q = rect_qmin(u, v, a, b, c, (float)xa, (float)xb, (float)ya, (float)yb);
-      if (q <= kappa2) {
-        f((uint32_t)(ty * cam.tiles_x + tx), cnt, t);
-        ++cnt;
-      }
-    }
-  }
-  return cnt;
-}
-
 __device__ __forceinline__ uint64_t lanemask_lt() {
   const int lane = threadIdx.x & 63;
   return lane ? (~0ull >> (64 - lane)) : 0ull;

@@ -196,6 +196,73 @@ __device__ __forceinline__ void view_dir(const ViewCam &cam, float mx, float my,
   dir[0] = dx * inv; dir[1] = dy * inv; dir[2] = dz * inv;
 }
 
+// Kept-tile masks of the small rectangles (at most kCoopArea tiles) of a wavefront, with its
+// cull tests dealt out flat over the lanes. Lane order fixes the test numbering: record r owns
+// tests [P_r, P_r + area_r), P the exclusive prefix of the areas. In a round of 64 tests a lane
+// finds its record as the latest record that starts at or before it (head marks in LDS and a
+// max-scan over the lanes; record ids grow with the test number), or the record carried over
+// from the previous round. Each test is rect_qmin of the record's centre and conic over the
+// tile's pixel-centre rectangle against kappa^2, the same call a walk over each record's own
+// rectangle would make, so the masks do not depend on how the tests are dealt out.
+__device__ __forceinline__ uint32_t small_rect_masks(const ViewCam &cam, int tw, int th, const Splat &s, bool small,
+                                                     int area, int tx0, int ty0, int rw) {
+  __shared__ float4 s_p0[256], s_p1[256];
+  __shared__ int s_p2[256], s_head[256];
+  const int lane = (int)threadIdx.x & 63, wb = (int)threadIdx.x & ~63;
+  const int na = small ? area : 0;
+  int incl = na;
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) {
+    const int t = __shfl_up(incl, off);
+    if (lane >= off) incl += t;
+  }
+  const int P = incl - na;
+  const int total = __shfl(incl, 63);
+  if (total == 0) return 0u;  // uniform
+  s_p0[threadIdx.x] = make_float4(s.u, s.v, s.a, s.b);
+  s_p1[threadIdx.x] = make_float4(s.c, s.kappa2, small ? 1.0f / (float)rw : 0.f, (float)rw);
+  s_p2[threadIdx.x] = (int)pack_i16x2(tx0, ty0);
+  const int xend = cam.x0 + cam.w - 1, yend = cam.y0 + cam.h - 1;
+  uint32_t mask = 0u;
+  int carry = -1;
+  for (int T0 = 0; T0 < total; T0 += 64) {
+    s_head[threadIdx.x] = -1;
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    if (na > 0 && P >= T0 && P < T0 + 64) s_head[wb + P - T0] = lane;
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    int r = s_head[threadIdx.x];
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+      const int t = __shfl_up(r, off);
+      if (lane >= off) r = max(r, t);
+    }
+    if (r < 0) r = carry;
+    carry = __shfl(r, 63);
+    const int T = T0 + lane;
+    // every lane takes part (a lane shuffle reads nothing from a lane that is switched off)
+    const int pr = __shfl(P, max(r, 0));
+    bool keep = false;
+    if (T < total) {
+      const float4 p0 = s_p0[wb + r], p1 = s_p1[wb + r];
+      const int t = T - pr;
+      const int rwr = (int)p1.w;
+      const int row = (int)(((float)t + 0.5f) * p1.z);  // exact for t < 32: (t + 1/2) / rw is never near an integer
+      const int txy = s_p2[wb + r];
+      const int tx = lo_i16((uint32_t)txy) + (t - row * rwr), ty = hi_i16((uint32_t)txy) + row;
+      const int xa = cam.x0 + tx * tw, ya = cam.y0 + ty * th;
+      const int xb = min(xa + tw - 1, xend), yb = min(ya + th - 1, yend);
+      keep = rect_qmin(p0.x, p0.y, p0.z, p0.w, p1.x, (float)xa, (float)xb, (float)ya, (float)yb) <= p1.y;
+    }
+    const uint64_t m = __ballot(keep);
+    const int lo = max(P, T0), hi = min(P + na, T0 + 64);
+    if (lo < hi) mask |= (uint32_t)((m >> (lo - T0)) & ((1ull << (hi - lo)) - 1ull)) << (lo - P);
+  }
+  return mask;
+}
+
 __global__ __launch_bounds__(256) void k_preprocess(ViewTable vt, const float *__restrict__ mean,
                                                     const float *__restrict__ scale, const float *__restrict__ rot,
                                                     const float *__restrict__ opacity,
@@ -223,10 +290,13 @@ __global__ __launch_bounds__(256) void k_preprocess(ViewTable vt, const float *_
     ty1 = (s.py1 - cam.y0) / vt.tile_h;
   }
   const int area = s.ok ? (tx1 - tx0 + 1) * (ty1 - ty0 + 1) : 0;
-  uint32_t kept_mask = 0;  // kCoopArea <= 32: one bit per tile of the rectangle
-  if (s.ok && area <= kCoopArea)
-    cnt = visit_kept_tiles(cam, vt.tile_w, vt.tile_h, s.u, s.v, s.a, s.b, s.c, s.kappa2, tx0, ty0, tx1, ty1,
-                           [&](uint32_t, uint32_t, uint32_t t) { kept_mask |= 1u << t; });
+  // Small rectangles: the wavefront's tile tests are dealt out flat (test k of the wavefront,
+  // counted over its records in lane order, runs in lane k % 64 of round k / 64), so a
+  // wavefront spends rounds on its total number of tests instead of on its largest rectangle.
+  // Each record's lane collects its tests' results from the round ballots.
+  const uint32_t kept_mask = small_rect_masks(cam, vt.tile_w, vt.tile_h, s, s.ok && area <= kCoopArea, area, tx0,
+                                              ty0, tx1 - tx0 + 1);
+  if (s.ok && area <= kCoopArea) cnt = (uint32_t)__popc(kept_mask);
   // large rectangles are counted by the whole wavefront, one splat at a time
   uint64_t big = __ballot(s.ok && area > kCoopArea);
   while (big) {
