@@ -373,14 +373,31 @@ __global__ void k_fill_u32(uint32_t *__restrict__ p, int64_t n, uint32_t v) {
   if (i < n) p[i] = v;
 }
 
+// Four consecutive sorted keys per thread (one 16-B load and the two neighbours): a tile's
+// range starts where the key differs from the one before and ends where it differs from the
+// one after. keys must be 16-B aligned.
 __global__ void k_tile_ranges(const uint32_t *__restrict__ keys, const int64_t *num_pairs, int64_t cap,
                               uint32_t *__restrict__ range) {
   const int64_t n = live_count(0, num_pairs, cap);
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  const uint32_t k = keys[i];
-  if (i == 0 || keys[i - 1] != k) range[2 * (int64_t)k] = (uint32_t)i;
-  if (i == n - 1 || keys[i + 1] != k) range[2 * (int64_t)k + 1] = (uint32_t)(i + 1);
+  const int64_t i0 = 4 * ((int64_t)blockIdx.x * blockDim.x + threadIdx.x);
+  if (i0 >= n) return;
+  uint32_t k[6];  // keys i0 - 1 .. i0 + 4
+  if (i0 + 4 <= n) {
+    const uint4 q = *reinterpret_cast<const uint4 *>(keys + i0);
+    k[1] = q.x; k[2] = q.y; k[3] = q.z; k[4] = q.w;
+  } else {
+#pragma unroll
+    for (int u = 0; u < 4; ++u) k[1 + u] = i0 + u < n ? keys[i0 + u] : 0xFFFFFFFFu;
+  }
+  k[0] = i0 > 0 ? keys[i0 - 1] : 0xFFFFFFFFu;
+  k[5] = i0 + 4 < n ? keys[i0 + 4] : 0xFFFFFFFFu;
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    const int64_t i = i0 + u;
+    if (i >= n) break;
+    if (i == 0 || k[u] != k[u + 1]) range[2 * (int64_t)k[u + 1]] = (uint32_t)i;
+    if (i == n - 1 || k[u + 2] != k[u + 1]) range[2 * (int64_t)k[u + 1] + 1] = (uint32_t)(i + 1);
+  }
 }
 
 // ---- host-side orchestration ---------------------------------------------------------------
@@ -505,7 +522,7 @@ hipError_t launch_bin_sort(const ViewTable &vt, const gs_projected &p, int64_t n
     pv = vo;
   }
   // 5. tile ranges
-  hipLaunchKernelGGL(k_tile_ranges, dim3((unsigned)cdiv(std::max<int64_t>(cap, 1), 256)), dim3(256), 0, st, pk,
+  hipLaunchKernelGGL(k_tile_ranges, dim3((unsigned)cdiv(std::max<int64_t>(cap, 1), 1024)), dim3(256), 0, st, pk,
                      num_pairs, cap, tile_range);
   return hipGetLastError();
 }

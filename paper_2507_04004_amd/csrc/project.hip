@@ -342,18 +342,27 @@ struct ParamGradOut {
   float *mean, *scale, *rot, *opacity, *sh_dc, *sh_rest;
 };
 
+// Six block sums at once in a fixed order (deterministic): the same xor butterfly in every
+// wave for all six values, then the waves' partials in wave order. Thread t < 6 finds sum t
+// in lds[24 + t] on return; lds holds 4 * 6 + 6 floats.
 template <int NT>
-__device__ __forceinline__ float block_sum_det(float v, float *lds) {
-  // wave butterfly (fixed pattern) then the waves in index order: deterministic
-  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+__device__ __forceinline__ void block_sum6_det(float (&v)[6], float *lds) {
+  static_assert(NT == 256, "four waves");
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1)
+#pragma unroll
+    for (int i = 0; i < 6; ++i) v[i] += __shfl_xor(v[i], off);
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  __syncthreads();  // lds may still be read from the previous call
+  if (lane < 6) {
+    float x = v[0];
+#pragma unroll
+    for (int i = 1; i < 6; ++i) x = lane == i ? v[i] : x;
+    lds[wave * 6 + lane] = x;
+  }
   __syncthreads();
-  if (lane == 0) lds[wave] = v;
-  __syncthreads();
-  float s = 0.f;
-  if (threadIdx.x == 0)
-    for (int w = 0; w < NT / 64; ++w) s += lds[w];
-  return s;  // valid in thread 0
+  if (threadIdx.x < 6) lds[24 + threadIdx.x] = ((lds[threadIdx.x] + lds[6 + threadIdx.x]) + lds[12 + threadIdx.x]) +
+                                               lds[18 + threadIdx.x];
 }
 
 // One real SH basis function Y_k (1 <= k <= 15) and its gradient as a polynomial of the
@@ -590,7 +599,7 @@ __global__ __launch_bounds__(256) void k_geo_bwd(ViewTable vt, const float *__re
                                                  const uint32_t *__restrict__ n_tiles, const float *__restrict__ g2,
                                                  const float4 *__restrict__ gdir, ParamGradOut out,
                                                  float *__restrict__ pose_partial /*[grid][V][6]*/) {
-  __shared__ float red[8];
+  __shared__ float red[32];
   const int64_t n = vt.n;
   const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const bool in = g < n;  // every lane stays for the block sums of the pose
@@ -751,11 +760,8 @@ __global__ __launch_bounds__(256) void k_geo_bwd(ViewTable vt, const float *__re
       pose[5] += N[0][1] - N[1][0];
     }
     // deterministic per-block partial of the pose gradient for this view
-#pragma unroll 1
-    for (int i = 0; i < 6; ++i) {
-      float t = block_sum_det<256>(pose[i], red);
-      if (threadIdx.x == 0) pose_partial[((int64_t)blockIdx.x * vt.n_views + vi) * 6 + i] = t;
-    }
+    block_sum6_det<256>(pose, red);
+    if (threadIdx.x < 6) pose_partial[((int64_t)blockIdx.x * vt.n_views + vi) * 6 + threadIdx.x] = red[24 + threadIdx.x];
   }
   if (!in || (!OVERWRITE && !any_view)) return;
   auto put = [&](float *base, int i, float v) {
