@@ -244,6 +244,48 @@ int gs_profile_enable(uint32_t stage_mask, int32_t max_records);
 int gs_profile_read(int32_t stage, double *total_ms, int32_t *count);
 void gs_profile_disable(void);
 
+/* Sparse Adam (Sec. "Additional Strategies", a): one Adam step (first and second moment
+ * estimates with bias correction) on the Gaussians the rendering reached. A Gaussian whose
+ * tile count is zero in every view of `visible` keeps its parameters and moments; the step
+ * number is shared by all. Groups are sets of k SoA planes of n values:
+ *   param          [k][n] raw parameter (updated in place)
+ *   exp_avg        [k][n] first moment, exp_avg_sq [k][n] second moment (updated in place)
+ *   grad           [k][n] gradient w.r.t. the value the renderer reads: act(param)
+ *   act_out        [k][n] act(param) written for the updated Gaussians (act != GS_ACT_NONE;
+ *                  may be NULL), e.g. the scale / opacity planes of gs_gaussians
+ *   act            GS_ACT_NONE: the renderer reads param; GS_ACT_EXP: exp(param) (log-scale);
+ *                  GS_ACT_SIGMOID: 1 / (1 + exp(-param)) (opacity logit)
+ *   lr             learning rate of the group
+ * The raw gradient is grad * d act / d param at the values before the step. For step t >= 1
+ * the caller passes bias1 = 1 - beta1^t and bias2 = 1 - beta2^t; an element moves by
+ * lr / bias1 * m / (sqrt(v) / sqrt(bias2) + eps).
+ * visible: tile counts [n_views][n] (gs_projected.n_tiles of each view), or NULL for all.
+ * The stores of the 64 consecutive Gaussians of a wavefront that holds an updated one are
+ * full width: the others of that wavefront rewrite their unchanged param / moment values.
+ * Errors: GS_ERR_INVALID_ARG for n < 0 or n >= 2^30, n_groups outside [0, GS_ADAM_MAX_GROUPS],
+ * n_views outside [1, GS_MAX_VIEWS] with visible set, k < 0, a NULL plane of a group with
+ * k > 0, an unknown act, or betas / eps / lr / bias terms out of range (betas in [0, 1),
+ * eps >= 0, bias terms in (0, 1], lr finite). */
+#define GS_ACT_NONE 0
+#define GS_ACT_EXP 1
+#define GS_ACT_SIGMOID 2
+#define GS_ADAM_MAX_GROUPS 8
+typedef struct {
+  float *param, *exp_avg, *exp_avg_sq;
+  const float *grad;
+  float *act_out;
+  int32_t k, act;
+  float lr;
+} gs_adam_group;
+typedef struct {
+  int64_t n;
+  int32_t n_groups, n_views;
+  const uint32_t *visible; /* [n_views][n] or NULL */
+  float beta1, beta2, eps, bias1, bias2;
+  gs_adam_group group[GS_ADAM_MAX_GROUPS];
+} gs_adam;
+int gs_adam_sparse(const gs_adam *a, gs_stream_t stream);
+
 /* Thread-local text of the last error of this thread. */
 const char *gs_last_error(void);
 

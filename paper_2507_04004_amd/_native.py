@@ -59,6 +59,21 @@ class View(C.Structure):
                 ("target", vp), ("rgb_weight", C.c_float), ("rgb_loss_out", vp), ("pose_grad", vp)]
 
 
+GS_ACT_NONE, GS_ACT_EXP, GS_ACT_SIGMOID = 0, 1, 2
+GS_ADAM_MAX_GROUPS = 8
+
+
+class AdamGroup(C.Structure):
+    _fields_ = [("param", vp), ("exp_avg", vp), ("exp_avg_sq", vp), ("grad", vp), ("act_out", vp),
+                ("k", C.c_int32), ("act", C.c_int32), ("lr", C.c_float)]
+
+
+class Adam(C.Structure):
+    _fields_ = [("n", C.c_int64), ("n_groups", C.c_int32), ("n_views", C.c_int32), ("visible", vp),
+                ("beta1", C.c_float), ("beta2", C.c_float), ("eps", C.c_float), ("bias1", C.c_float),
+                ("bias2", C.c_float), ("group", AdamGroup * GS_ADAM_MAX_GROUPS)]
+
+
 class GSError(RuntimeError):
     pass
 
@@ -66,6 +81,7 @@ class GSError(RuntimeError):
 _lib = None
 
 EXPORTS = ["gs_preprocess", "gs_bin_sort", "gs_render_fwd", "gs_render_bwd", "gs_render_batch", "gs_loss_l1",
+           "gs_adam_sparse",
            "gs_bins_scratch_bytes", "gs_image_state_bytes", "gs_grads_scratch_bytes", "gs_batch_plan_create", "gs_batch_plan_destroy",
            "gs_batch_num_pairs", "gs_batch_capacity", "gs_camera_left_update", "gs_last_error",
            "gs_profile_enable", "gs_profile_read", "gs_profile_disable"]
@@ -87,6 +103,7 @@ def lib():
     L.gs_render_bwd.argtypes = [P(Gaussians), P(Camera), P(Projected), P(Bins), P(Image), vp, vp, vp, P(Lidar),
                                 C.c_int32, P(Grads), vp]
     L.gs_loss_l1.argtypes = [vp, vp, C.c_int64, C.c_float, vp, vp, vp]
+    L.gs_adam_sparse.argtypes = [P(Adam), vp]
     L.gs_bins_scratch_bytes.argtypes = [C.c_int64, C.c_int64, C.c_int64]
     L.gs_bins_scratch_bytes.restype = C.c_size_t
     L.gs_image_state_bytes.argtypes = [C.c_int64, C.c_int64, C.c_int32, C.c_int32, C.c_int32]

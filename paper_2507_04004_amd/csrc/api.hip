@@ -457,6 +457,43 @@ int gs_camera_left_update(const gs_camera *in, const float xi[6], gs_camera *out
   return GS_OK;
 }
 
+int gs_adam_sparse(const gs_adam *a, gs_stream_t stream) {
+  if (!a) return fail(GS_ERR_INVALID_ARG, "adam arguments are NULL");
+  if (a->n < 0 || a->n >= (int64_t(1) << 30)) return fail(GS_ERR_INVALID_ARG, "n must be in [0, 2^30)");
+  if (a->n_groups < 0 || a->n_groups > GS_ADAM_MAX_GROUPS)
+    return fail(GS_ERR_INVALID_ARG, "n_groups must be in [0, %d]", GS_ADAM_MAX_GROUPS);
+  if (a->visible && (a->n_views < 1 || a->n_views > GS_MAX_VIEWS))
+    return fail(GS_ERR_INVALID_ARG, "n_views must be in [1, %d]", GS_MAX_VIEWS);
+  if (!(a->beta1 >= 0.f && a->beta1 < 1.f) || !(a->beta2 >= 0.f && a->beta2 < 1.f))
+    return fail(GS_ERR_INVALID_ARG, "betas must be in [0, 1)");
+  if (!(a->eps >= 0.f) || !std::isfinite(a->eps)) return fail(GS_ERR_INVALID_ARG, "eps must be finite and >= 0");
+  if (!(a->bias1 > 0.f && a->bias1 <= 1.f) || !(a->bias2 > 0.f && a->bias2 <= 1.f))
+    return fail(GS_ERR_INVALID_ARG, "bias terms must be in (0, 1]");
+  gs::AdamArgs d{};
+  d.n = a->n;
+  d.n_groups = a->n_groups;
+  d.n_views = a->visible ? a->n_views : 0;
+  d.visible = a->visible;
+  d.beta1 = a->beta1;
+  d.beta2 = a->beta2;
+  d.eps = a->eps;
+  d.sqrt_bias2 = (float)std::sqrt((double)a->bias2);
+  for (int i = 0; i < a->n_groups; ++i) {
+    const gs_adam_group &G = a->group[i];
+    if (G.k < 0) return fail(GS_ERR_INVALID_ARG, "group %d: k < 0", i);
+    if (G.act != GS_ACT_NONE && G.act != GS_ACT_EXP && G.act != GS_ACT_SIGMOID)
+      return fail(GS_ERR_INVALID_ARG, "group %d: unknown activation %d", i, G.act);
+    if (G.k > 0 && a->n > 0 && (!G.param || !G.exp_avg || !G.exp_avg_sq || !G.grad))
+      return fail(GS_ERR_INVALID_ARG, "group %d: a plane is NULL", i);
+    if (!std::isfinite(G.lr)) return fail(GS_ERR_INVALID_ARG, "group %d: lr is not finite", i);
+    d.group[i] = gs::AdamGroupDev{G.param, G.exp_avg, G.exp_avg_sq, G.grad,
+                                  G.act == GS_ACT_NONE ? nullptr : G.act_out, G.k, G.act,
+                                  (float)((double)G.lr / (double)a->bias1)};
+  }
+  GS_TRY_HIP(gs::launch_adam_sparse(d, (hipStream_t)stream), "sparse adam");
+  return GS_OK;
+}
+
 int gs_loss_l1(const float *color, const float *target, int64_t n_values, float weight, float *dL_dC, float *loss_out,
                gs_stream_t stream) {
   if (n_values < 0) return fail(GS_ERR_INVALID_ARG, "n_values < 0");

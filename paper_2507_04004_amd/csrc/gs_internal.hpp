@@ -43,4 +43,21 @@ hipError_t zero_f32(float *p, int64_t n, hipStream_t st);
 hipError_t launch_loss_l1(const float *c, const float *t, int64_t n, float weight, float *dldc, float *loss,
                           hipStream_t st);
 
+// Sparse Adam: the validated gs_adam with the bias terms folded (step_size = lr / bias1).
+struct AdamGroupDev {
+  float *param, *exp_avg, *exp_avg_sq;
+  const float *grad;
+  float *act_out;
+  int32_t k, act;
+  float step_size;
+};
+struct AdamArgs {
+  int64_t n;
+  int32_t n_groups, n_views;
+  const uint32_t *visible;
+  float beta1, beta2, eps, sqrt_bias2;
+  AdamGroupDev group[GS_ADAM_MAX_GROUPS];
+};
+hipError_t launch_adam_sparse(const AdamArgs &a, hipStream_t st);
+
 }  // namespace gs

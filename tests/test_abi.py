@@ -118,3 +118,33 @@ def test_camera_left_update_is_se3_exponential(xi):
     np.testing.assert_allclose(np.array(out.R_cw).reshape(3, 3), dR @ R0f, atol=2e-7)
     np.testing.assert_allclose(np.array(out.t_cw), dR @ t0f + dt, atol=1e-6)
     assert out.w == cam.w and math.isclose(out.fx, cam.fx)
+
+
+def test_adam_argument_errors():
+    L = N.lib()
+    dummy = C.c_void_p(64)  # never dereferenced: validation fails first
+
+    def adam(**kw):
+        a = N.Adam()
+        a.n, a.n_groups, a.n_views, a.visible = 10, 1, 1, None
+        a.beta1, a.beta2, a.eps, a.bias1, a.bias2 = 0.9, 0.999, 1e-15, 0.1, 0.001
+        a.group[0] = N.AdamGroup(dummy, dummy, dummy, dummy, None, 3, N.GS_ACT_NONE, 1e-3)
+        for k, v in kw.items():
+            setattr(a, k, v)
+        return a
+
+    bad = [dict(n=-1), dict(n=1 << 30), dict(n_groups=9), dict(n_groups=-1), dict(beta1=1.0), dict(beta2=-0.1),
+           dict(eps=-1.0), dict(bias1=0.0), dict(bias2=1.5), dict(visible=dummy, n_views=0),
+           dict(visible=dummy, n_views=17)]
+    for kw in bad:
+        assert L.gs_adam_sparse(C.byref(adam(**kw)), None) == N.GS_ERR_INVALID_ARG, kw
+    a = adam()
+    a.group[0] = N.AdamGroup(dummy, None, dummy, dummy, None, 3, N.GS_ACT_NONE, 1e-3)  # NULL moment plane
+    assert L.gs_adam_sparse(C.byref(a), None) == N.GS_ERR_INVALID_ARG
+    a.group[0] = N.AdamGroup(dummy, dummy, dummy, dummy, None, 3, 7, 1e-3)  # unknown activation
+    assert L.gs_adam_sparse(C.byref(a), None) == N.GS_ERR_INVALID_ARG
+    a.group[0] = N.AdamGroup(dummy, dummy, dummy, dummy, None, 3, N.GS_ACT_NONE, float("inf"))
+    assert L.gs_adam_sparse(C.byref(a), None) == N.GS_ERR_INVALID_ARG
+    # no groups or no Gaussians: nothing to launch, success without a GPU
+    assert L.gs_adam_sparse(C.byref(adam(n_groups=0)), None) == N.GS_OK
+    assert L.gs_adam_sparse(C.byref(adam(n=0)), None) == N.GS_OK
