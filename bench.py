@@ -13,6 +13,10 @@ sparse-LiDAR depth term (a6), the RGB L1 loss, and the backward to every paramet
 pose (a4, a5). The backward writes every gradient element (overwrite mode), so the step needs
 no clearing pass.
 
+Besides the headline figure the line carries the roofline of the dominant kernel, the two
+small configurations, the batched 8-keyframe pass, the sparse Adam step over the reached
+Gaussians (`sparse_adam`), novel-view serving, and the float64 CPU oracle as a baseline.
+
 Prints ONE JSON line. `value` is fwd+bwd views/s on one GPU.
 """
 from __future__ import annotations
@@ -90,6 +94,7 @@ def parse():
     ap.add_argument("--no-batched", action="store_true", help="skip the 8-keyframe batched measurement")
     ap.add_argument("--no-small", action="store_true", help="skip the two small single-view configurations")
     ap.add_argument("--no-serving", action="store_true", help="skip the serving measurement")
+    ap.add_argument("--no-adam", action="store_true", help="skip the sparse Adam measurement")
     ap.add_argument("--serve-requests", type=int, default=2000, help="requests per arrival rate")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one plain 256 MiB device copy (reference point for HBM byte counters)")
@@ -294,6 +299,39 @@ def measure_serving(R, torch, S, tile, bd, dev, n_req, log):
     return out
 
 
+def measure_sparse_adam(R, torch, S, ps, tile, dev, reps=20):
+    """Sparse Adam (gs_adam_sparse) on the 1M map with the benchmark's last gradients: over the
+    Gaussians the headline view reached, those a centred 256x192 window reached, and all of them.
+    Algorithmic bytes per updated Gaussian: 16 B read and 12 B written per parameter plane (param,
+    both moments, gradient) plus the 4 renderer planes written back (scale, opacity), and the
+    tile counts read per Gaussian and view."""
+    from paper_2507_04004_amd.adam import SparseAdam
+    opt = SparseAdam(ps.gm)
+    n = ps.n
+    planes = sum(raw.numel() // n for raw, *_ in opt.groups)
+    win = S.headline_camera().window(512, 264, 256, 192)
+    spl_w = R.preprocess(ps.gs, R.camera_struct(win), tile, dev)
+    cases = (("headline_view", ps.spl.n_tiles.view(1, -1)), ("window_256x192", spl_w.n_tiles.view(1, -1)),
+             ("all", None))
+    out = {"gaussians": n, "planes": planes}
+    for name, vis in cases:
+        for _ in range(3):
+            opt.step(ps.grads, vis)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record()
+        for _ in range(reps):
+            opt.step(ps.grads, vis)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        reached = n if vis is None else int((vis > 0).any(0).sum().item())
+        nbytes = reached * (planes * 28 + 4 * 4) + (0 if vis is None else 4 * n * vis.shape[0])
+        out[name] = {"reached": reached, "ms": round(ms, 4), "GB/s": round(nbytes / (ms * 1e-3) / 1e9, 1),
+                     "frac_hbm": round(nbytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+    return out
+
+
 def cpu_baseline(g, cam, gC_np, repeats):
     """The FP64 oracle (as it stands) on the host: one full-view fwd + bwd of the same workload."""
     import numpy as np
@@ -491,6 +529,10 @@ def main():
         log("[bench] batched keyframes")
         out["batched"] = measure_batched(R, N, torch, S, g, gm, args.tile, args.blend_depth, dev)
         log(f"[bench] batched {out['batched']}")
+    if not args.no_adam:
+        log("[bench] sparse Adam")
+        out["sparse_adam"] = measure_sparse_adam(R, torch, S, ps, args.tile, dev)
+        log(f"[bench] sparse Adam {out['sparse_adam']}")
     if not args.no_serving:
         del ps
         torch.cuda.empty_cache()
