@@ -244,6 +244,21 @@ int gs_profile_enable(uint32_t stage_mask, int32_t max_records);
 int gs_profile_read(int32_t stage, double *total_ms, int32_t *count);
 void gs_profile_disable(void);
 
+/* D-SSIM term of the photometric tracking loss (eq:tracking_loss; the D-SSIM term of the
+ * original 3DGS loss; efficient separable SSIM, Sec. "Additional Strategies", c):
+ *   loss = weight * (1 - mean SSIM) over the channels x h x w values,
+ * SSIM per channel from local means / variances / covariance under an 11x11 Gaussian window
+ * (sigma 1.5, weights summing to one), zero outside the image, C1 = 0.01^2, C2 = 0.03^2.
+ * color, target [channels][h][w] fp32 device planes. dL_dC (may be NULL) is ACCUMULATED (+=)
+ * with d loss / d color, so it composes with gs_loss_l1, which overwrites it. loss_out [1]
+ * (may be NULL) is overwritten. scratch: device, at least gs_dssim_scratch_bytes (3 floats
+ * per value). Errors: GS_ERR_INVALID_ARG for negative sizes, more than 64 channels, h or w above
+ * 32768 or 2^31 values, NULL images with
+ * a non-empty size, a non-finite weight or short scratch. */
+size_t gs_dssim_scratch_bytes(int32_t channels, int32_t h, int32_t w);
+int gs_loss_dssim(const float *color, const float *target, int32_t channels, int32_t h, int32_t w, float weight,
+                  float *dL_dC, float *loss_out, void *scratch, size_t scratch_bytes, gs_stream_t stream);
+
 /* Sparse Adam (Sec. "Additional Strategies", a): one Adam step (first and second moment
  * estimates with bias correction) on the Gaussians the rendering reached. A Gaussian whose
  * tile count is zero in every view of `visible` keeps its parameters and moments; the step

@@ -81,7 +81,7 @@ class GSError(RuntimeError):
 _lib = None
 
 EXPORTS = ["gs_preprocess", "gs_bin_sort", "gs_render_fwd", "gs_render_bwd", "gs_render_batch", "gs_loss_l1",
-           "gs_adam_sparse",
+           "gs_adam_sparse", "gs_loss_dssim", "gs_dssim_scratch_bytes",
            "gs_bins_scratch_bytes", "gs_image_state_bytes", "gs_grads_scratch_bytes", "gs_batch_plan_create", "gs_batch_plan_destroy",
            "gs_batch_num_pairs", "gs_batch_capacity", "gs_camera_left_update", "gs_last_error",
            "gs_profile_enable", "gs_profile_read", "gs_profile_disable"]
@@ -104,6 +104,9 @@ def lib():
                                 C.c_int32, P(Grads), vp]
     L.gs_loss_l1.argtypes = [vp, vp, C.c_int64, C.c_float, vp, vp, vp]
     L.gs_adam_sparse.argtypes = [P(Adam), vp]
+    L.gs_dssim_scratch_bytes.argtypes = [C.c_int32, C.c_int32, C.c_int32]
+    L.gs_dssim_scratch_bytes.restype = C.c_size_t
+    L.gs_loss_dssim.argtypes = [vp, vp, C.c_int32, C.c_int32, C.c_int32, C.c_float, vp, vp, vp, C.c_size_t, vp]
     L.gs_bins_scratch_bytes.argtypes = [C.c_int64, C.c_int64, C.c_int64]
     L.gs_bins_scratch_bytes.restype = C.c_size_t
     L.gs_image_state_bytes.argtypes = [C.c_int64, C.c_int64, C.c_int32, C.c_int32, C.c_int32]

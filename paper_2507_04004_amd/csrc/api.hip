@@ -457,6 +457,27 @@ int gs_camera_left_update(const gs_camera *in, const float xi[6], gs_camera *out
   return GS_OK;
 }
 
+size_t gs_dssim_scratch_bytes(int32_t channels, int32_t h, int32_t w) {
+  if (channels < 0 || h < 0 || w < 0) return 0;
+  return gs::dssim_scratch_bytes(channels, h, w);
+}
+
+int gs_loss_dssim(const float *color, const float *target, int32_t channels, int32_t h, int32_t w, float weight,
+                  float *dL_dC, float *loss_out, void *scratch, size_t scratch_bytes, gs_stream_t stream) {
+  if (channels < 0 || h < 0 || w < 0) return fail(GS_ERR_INVALID_ARG, "image size must be non-negative");
+  if ((int64_t)channels * h * w >= (int64_t(1) << 31) || channels > 64 || h > 32768 || w > 32768)
+    return fail(GS_ERR_INVALID_ARG, "image too large (at most 64 channels of 32768 x 32768, 2^31 values)");
+  const int64_t n = (int64_t)channels * h * w;
+  if (n > 0 && (!color || !target)) return fail(GS_ERR_INVALID_ARG, "color / target is NULL");
+  if (!std::isfinite(weight)) return fail(GS_ERR_INVALID_ARG, "weight is not finite");
+  if (n > 0 && (!scratch || scratch_bytes < gs::dssim_scratch_bytes(channels, h, w)))
+    return fail(GS_ERR_INVALID_ARG, "scratch must hold gs_dssim_scratch_bytes bytes");
+  GS_TRY_HIP(gs::launch_dssim(color, target, channels, h, w, weight, dL_dC, loss_out, (float *)scratch,
+                              (hipStream_t)stream),
+             "d-ssim");
+  return GS_OK;
+}
+
 int gs_adam_sparse(const gs_adam *a, gs_stream_t stream) {
   if (!a) return fail(GS_ERR_INVALID_ARG, "adam arguments are NULL");
   if (a->n < 0 || a->n >= (int64_t(1) << 30)) return fail(GS_ERR_INVALID_ARG, "n must be in [0, 2^30)");

@@ -60,4 +60,8 @@ struct AdamArgs {
 };
 hipError_t launch_adam_sparse(const AdamArgs &a, hipStream_t st);
 
+size_t dssim_scratch_bytes(int c, int h, int w);
+hipError_t launch_dssim(const float *x, const float *y, int c, int h, int w, float weight, float *dldc, float *loss,
+                        float *scratch, hipStream_t st);
+
 }  // namespace gs

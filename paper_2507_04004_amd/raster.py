@@ -285,6 +285,20 @@ def loss_l1(color: torch.Tensor, target: torch.Tensor, weight: float = 1.0, dL_d
 
 # ---- autograd --------------------------------------------------------------------------------
 
+def loss_dssim(color: torch.Tensor, target: torch.Tensor, weight: float = 1.0,
+               dL_dC: torch.Tensor | None = None, loss: torch.Tensor | None = None,
+               scratch: torch.Tensor | None = None) -> torch.Tensor:
+    """weight * (1 - mean SSIM) of [c][h][w] images; adds its gradient to dL_dC when given."""
+    c, h, w = (int(v) for v in color.shape)
+    loss = loss if loss is not None else torch.empty(1, dtype=torch.float32, device=color.device)
+    nb = N.lib().gs_dssim_scratch_bytes(c, h, w)
+    if scratch is None or scratch.numel() < nb:
+        scratch = torch.empty(max(nb, 1), dtype=torch.uint8, device=color.device)
+    N.check(N.lib().gs_loss_dssim(_p(color), _p(target), c, h, w, float(weight), _p(dL_dC), _p(loss), _p(scratch),
+                                  scratch.numel(), _stream()), "gs_loss_dssim")
+    return loss
+
+
 @dataclasses.dataclass
 class RenderSettings:
     camera: object                  # scenes.Camera-like

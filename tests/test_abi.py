@@ -148,3 +148,20 @@ def test_adam_argument_errors():
     # no groups or no Gaussians: nothing to launch, success without a GPU
     assert L.gs_adam_sparse(C.byref(adam(n_groups=0)), None) == N.GS_OK
     assert L.gs_adam_sparse(C.byref(adam(n=0)), None) == N.GS_OK
+
+
+def test_dssim_argument_errors():
+    L = N.lib()
+    dummy = C.c_void_p(64)  # never dereferenced: validation fails first
+    nb = L.gs_dssim_scratch_bytes(3, 20, 30)
+    assert nb == 3 * 4 * 3 * 20 * 30 and L.gs_dssim_scratch_bytes(-1, 2, 2) == 0
+
+    def call(c=3, h=20, w=30, color=dummy, target=dummy, weight=0.5, scratch=dummy, nbytes=nb):
+        return L.gs_loss_dssim(color, target, c, h, w, weight, dummy, dummy, scratch, nbytes, None)
+
+    bad = [dict(c=-1), dict(h=-2), dict(w=-3), dict(c=65), dict(h=40000), dict(w=32769), dict(color=None),
+           dict(target=None), dict(weight=float("nan")), dict(weight=float("inf")), dict(scratch=None),
+           dict(nbytes=nb - 1)]
+    for kw in bad:
+        assert call(**kw) == N.GS_ERR_INVALID_ARG, kw
+        assert L.gs_last_error()
