@@ -259,6 +259,56 @@ size_t gs_dssim_scratch_bytes(int32_t channels, int32_t h, int32_t w);
 int gs_loss_dssim(const float *color, const float *target, int32_t channels, int32_t h, int32_t w, float weight,
                   float *dL_dC, float *loss_out, void *scratch, size_t scratch_bytes, gs_stream_t stream);
 
+/* ---- Photometric tracking (camera factor option 2) ------------------------------------ */
+
+/* The pose loop of Sec. "Camera Factor (Option 2)": with the map frozen, `iters` (N_t = 30 in
+ * the paper's setup) iterations, each of which renders the view at the current pose,
+ * evaluates eq:tracking_loss
+ *   L = l1_weight * mean |C_hat - C| + ssim_weight * D-SSIM(C_hat, C)   (1/2 and 1/2)
+ * (the two terms as gs_loss_l1 and gs_loss_dssim), differentiates it to the pose tangent
+ * xi = (rho, phi) of the left perturbation T_cw <- Exp(xi) T_cw (as gs_render_bwd, with no
+ * Gaussian gradient written), and applies an Adam step delta (step sizes lr_rho for the
+ * translation, lr_phi for the rotation; moments and bias correction run over the iterations)
+ * as T_cw <- Exp(delta) T_cw. The result is the refined pose T~ of eq:map_optimize_pose. */
+typedef struct gs_track_params {
+  int32_t iters;
+  float l1_weight, ssim_weight;
+  float lr_rho, lr_phi;
+  float beta1, beta2, eps; /* betas in [0, 1), eps > 0 */
+  uint32_t flags;          /* GS_GRAPH: capture the iterations into a hipGraph, replayed while
+                              every argument but the starting pose is unchanged */
+} gs_track_params;
+
+typedef struct gs_track_plan gs_track_plan;
+
+/* A plan owns every buffer of the loop for maps of up to n Gaussians at up to the given
+ * degree and windows of up to max_pixels: splat records, tile lists of `capacity` pairs,
+ * image planes, gradient maps, scratch and the pose state. Allocates device memory. */
+int gs_track_plan_create(gs_track_plan **plan, int64_t n, int32_t sh_degree, int64_t max_pixels, int32_t tile_w,
+                         int32_t tile_h, int32_t blend_depth, int64_t capacity);
+void gs_track_plan_destroy(gs_track_plan *plan);
+int64_t gs_track_capacity(const gs_track_plan *plan);
+
+/* Runs the loop from the pose in `cam` against target [3][h][w] (window-sized, device).
+ * pose_out [12] (device): the refined world-to-camera pose, R_cw row-major then t_cw.
+ * trace (device, may be NULL): [iters][20] floats per iteration: the pose rendered (12, as
+ * pose_out), dL/dxi at that pose (6), the L1 term and the D-SSIM term. The pose is kept in
+ * float64 on the device between iterations and rounded to float32 for each render.
+ * Asynchronous; no host synchronisation inside the loop. */
+int gs_track_pose(gs_track_plan *plan, const gs_gaussians *g, const gs_camera *cam, const float *target,
+                  const gs_track_params *params, float *pose_out, float *trace, gs_stream_t stream);
+
+/* Largest pair count of the last gs_track_pose over its iterations, copied to *required
+ * after the work queued on `stream` (synchronises it). Above gs_track_capacity, some
+ * iterations rendered clamped tile lists: re-create the plan bigger and run again. */
+int gs_track_required_pairs(const gs_track_plan *plan, int64_t *required, gs_stream_t stream);
+
+/* Host helper: the factor residual of eq:map_optimize_pose, r = Log(T_wc(t) T~_wc^-1) on
+ * camera-to-world poses, from the predicted and refined world-to-camera poses (each R_cw
+ * row-major then t_cw, as pose_out). r = (rho, phi), float64, closed-form SE(3) logarithm
+ * (rotation angles below pi). */
+int gs_pose_residual(const float pred_cw[12], const float refined_cw[12], double r[6]);
+
 /* Sparse Adam (Sec. "Additional Strategies", a): one Adam step (first and second moment
  * estimates with bias correction) on the Gaussians the rendering reached. A Gaussian whose
  * tile count is zero in every view of `visible` keeps its parameters and moments; the step

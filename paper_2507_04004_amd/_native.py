@@ -74,6 +74,15 @@ class Adam(C.Structure):
                 ("bias2", C.c_float), ("group", AdamGroup * GS_ADAM_MAX_GROUPS)]
 
 
+class TrackParams(C.Structure):
+    _fields_ = [("iters", C.c_int32), ("l1_weight", C.c_float), ("ssim_weight", C.c_float), ("lr_rho", C.c_float),
+                ("lr_phi", C.c_float), ("beta1", C.c_float), ("beta2", C.c_float), ("eps", C.c_float),
+                ("flags", C.c_uint32)]
+
+
+TRACK_TRACE_STRIDE = 20
+
+
 class GSError(RuntimeError):
     pass
 
@@ -81,7 +90,9 @@ class GSError(RuntimeError):
 _lib = None
 
 EXPORTS = ["gs_preprocess", "gs_bin_sort", "gs_render_fwd", "gs_render_bwd", "gs_render_batch", "gs_loss_l1",
-           "gs_adam_sparse", "gs_loss_dssim", "gs_dssim_scratch_bytes",
+           "gs_adam_sparse", "gs_loss_dssim", "gs_dssim_scratch_bytes", "gs_track_plan_create",
+           "gs_track_plan_destroy", "gs_track_capacity", "gs_track_pose", "gs_track_required_pairs",
+           "gs_pose_residual",
            "gs_bins_scratch_bytes", "gs_image_state_bytes", "gs_grads_scratch_bytes", "gs_batch_plan_create", "gs_batch_plan_destroy",
            "gs_batch_num_pairs", "gs_batch_capacity", "gs_camera_left_update", "gs_last_error",
            "gs_profile_enable", "gs_profile_read", "gs_profile_disable"]
@@ -122,6 +133,15 @@ def lib():
     L.gs_batch_capacity.argtypes = [vp]
     L.gs_batch_capacity.restype = C.c_int64
     L.gs_camera_left_update.argtypes = [P(Camera), P(C.c_float * 6), P(Camera)]
+    L.gs_track_plan_create.argtypes = [P(vp), C.c_int64, C.c_int32, C.c_int64, C.c_int32, C.c_int32, C.c_int32,
+                                       C.c_int64]
+    L.gs_track_plan_destroy.argtypes = [vp]
+    L.gs_track_plan_destroy.restype = None
+    L.gs_track_capacity.argtypes = [vp]
+    L.gs_track_capacity.restype = C.c_int64
+    L.gs_track_pose.argtypes = [vp, P(Gaussians), P(Camera), vp, P(TrackParams), vp, vp, vp]
+    L.gs_track_required_pairs.argtypes = [vp, P(C.c_int64), vp]
+    L.gs_pose_residual.argtypes = [P(C.c_float * 12), P(C.c_float * 12), P(C.c_double * 6)]
     L.gs_profile_enable.argtypes = [C.c_uint32, C.c_int32]
     L.gs_profile_read.argtypes = [C.c_int32, P(C.c_double), P(C.c_int32)]
     L.gs_profile_disable.argtypes = []

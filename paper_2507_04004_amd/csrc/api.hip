@@ -781,3 +781,310 @@ int gs_render_batch(gs_batch_plan *p, const gs_gaussians *g, int32_t n_views, co
 }
 
 }  // extern "C"
+
+// =============================================================================================
+// Tracking plan: the photometric pose loop (eq:tracking_loss) on one view, map frozen.
+// =============================================================================================
+struct gs_track_plan {
+  int64_t n = 0;
+  int32_t deg = 0, tw = 16, th = 16, bd = 256;
+  int64_t max_pixels = 0, cap = 0, max_tiles = 0;
+  void *block = nullptr;
+  gs_projected proj{};
+  uint32_t *vals = nullptr, *tile_range = nullptr;
+  int64_t *num_pairs = nullptr;
+  void *bin_scratch = nullptr, *grad_scratch = nullptr, *blend_state = nullptr;
+  float *dC = nullptr, *color = nullptr, *depth = nullptr, *alpha = nullptr, *t_final = nullptr;
+  int32_t *last = nullptr;
+  float *ssim_scratch = nullptr;
+  gs::TrackState *state = nullptr;
+  hipStream_t capture_stream = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  std::vector<unsigned char> signature;
+};
+
+namespace {
+
+size_t track_bytes(const gs_track_plan &p, size_t *offs) {
+  const int64_t n = std::max<int64_t>(p.n, 1), px = std::max<int64_t>(p.max_pixels, 1);
+  size_t o = 0;
+  auto put = [&](int i, size_t bytes) {
+    offs[i] = o;
+    o += a256(bytes);
+  };
+  put(0, 64 * n);                                   // splat cards
+  put(1, 4 * n);                                    // n_tiles
+  put(2, 4 * n);                                    // dkey
+  put(3, 4 * std::max<int64_t>(p.cap, 1));          // vals
+  put(4, 8 * std::max<int64_t>(p.max_tiles, 1));    // tile ranges
+  put(5, 16);                                       // num_pairs
+  put(6, gs::bin_scratch_bytes(n, p.cap));          // bin scratch
+  put(7, grads_scratch_bytes_impl(p.n, 1, px));     // backward scratch
+  put(8, gs::blend_state_bytes(p.max_tiles, p.cap, p.tw, p.th, p.bd));
+  put(9, 12 * px);                                  // dL/dC
+  put(10, 12 * px);                                 // colour
+  put(11, 4 * px);                                  // depth
+  put(12, 4 * px);                                  // opacity
+  put(13, 4 * px);                                  // final transmittance
+  put(14, 4 * px);                                  // last contributor
+  put(15, 36 * px);                                 // D-SSIM derivative maps (3 per value)
+  put(16, sizeof(gs::TrackState));
+  return o;
+}
+
+int check_track_params(const gs_track_params *q) {
+  if (!q) return fail(GS_ERR_INVALID_ARG, "tracking parameters are NULL");
+  if (q->iters < 1 || q->iters > 1000) return fail(GS_ERR_INVALID_ARG, "iters must be in [1, 1000]");
+  const float f[] = {q->l1_weight, q->ssim_weight, q->lr_rho, q->lr_phi};
+  for (float v : f)
+    if (!std::isfinite(v) || v < 0.f) return fail(GS_ERR_INVALID_ARG, "weights and step sizes must be finite, >= 0");
+  if (!(q->beta1 >= 0.f && q->beta1 < 1.f) || !(q->beta2 >= 0.f && q->beta2 < 1.f))
+    return fail(GS_ERR_INVALID_ARG, "betas must be in [0, 1)");
+  if (!(q->eps > 0.f) || !std::isfinite(q->eps)) return fail(GS_ERR_INVALID_ARG, "eps must be finite and > 0");
+  if (q->flags & ~(uint32_t)GS_GRAPH) return fail(GS_ERR_INVALID_ARG, "unknown flags");
+  return GS_OK;
+}
+
+// The iterations (everything after the state set-up), enqueued on `st`.
+int enqueue_track(gs_track_plan *p, const gs_gaussians *g, const gs_camera *cam, const float *target,
+                  const gs_track_params *q, float *pose_out, float *trace, hipStream_t st) {
+  gs::ViewTable vt;
+  int rc = make_table(cam, 1, g->n, g->sh_degree, p->tw, p->th, vt);
+  if (rc) return rc;
+  vt.pose_dev = p->state->pose;
+  const int h = cam->h, w = cam->w;
+  const int64_t px = (int64_t)w * h;
+  if (gs::dssim_scratch_bytes(3, h, w) > (size_t)36 * p->max_pixels) return fail(GS_ERR_INVALID_ARG, "d-ssim scratch");
+  gs::ImgTable it{};
+  it.v[0] = {p->color, p->depth, p->alpha, p->t_final, p->last, nullptr};
+  gs_image img{p->color, p->depth, p->alpha, p->t_final, p->last, nullptr, p->blend_state, 0};
+  ViewIO io{};
+  io.img = img;
+  io.dC = p->dC;
+  io.pose = p->state->grad;
+  gs_grads none{};
+  none.overwrite = 1;
+  const GradScratch s = carve_grads(p->grad_scratch, g->n, 1, px);
+  gs::TrackStepArgs a{};
+  for (int i = 0; i < 3; ++i) {
+    a.lr[i] = q->lr_rho;
+    a.lr[3 + i] = q->lr_phi;
+  }
+  a.beta1 = q->beta1;
+  a.beta2 = q->beta2;
+  a.eps = q->eps;
+  for (int k = 1; k <= q->iters; ++k) {
+    gs::profile_begin(GS_STAGE_PREPROCESS, st);
+    GS_TRY_HIP(gs::launch_preprocess(vt, *g, p->proj, st), "track preprocess");
+    gs::profile_end(GS_STAGE_PREPROCESS, st);
+    gs::profile_begin(GS_STAGE_BIN_SORT, st);
+    GS_TRY_HIP(gs::launch_bin_sort(vt, p->proj, g->n, p->cap, p->vals, p->tile_range, p->num_pairs, p->bin_scratch,
+                                   st),
+               "track bin/sort");
+    gs::profile_end(GS_STAGE_BIN_SORT, st);
+    gs::profile_begin(GS_STAGE_BLEND_FWD, st);
+    GS_TRY_HIP(gs::launch_blend_fwd(p->bd, vt, it, p->proj, p->vals, p->tile_range, p->blend_state, p->cap, st),
+               "track blend forward");
+    gs::profile_end(GS_STAGE_BLEND_FWD, st);
+    GS_TRY_HIP(gs::launch_loss_l1(p->color, target, 3 * px, q->l1_weight, p->dC, &p->state->loss[0], st),
+               "track l1 loss");
+    GS_TRY_HIP(gs::launch_dssim(p->color, target, 3, h, w, q->ssim_weight, p->dC, &p->state->loss[1], p->ssim_scratch,
+                                st),
+               "track d-ssim");
+    rc = enqueue_backward(vt, *g, p->proj, p->vals, p->tile_range, p->blend_state, p->cap, &io, p->bd, none, s, st);
+    if (rc) return rc;
+    a.k = k;
+    a.bias1 = 1.0 - std::pow((double)q->beta1, k);
+    a.bias2 = 1.0 - std::pow((double)q->beta2, k);
+    GS_TRY_HIP(gs::launch_track_step(p->state, a, p->num_pairs, trace, k == q->iters ? pose_out : nullptr, st),
+               "track pose step");
+  }
+  return GS_OK;
+}
+
+// SE(3) logarithm (inverse of the closed-form exponential) for rotation angles below pi.
+void se3_log(const double R[9], const double t[3], double xi[6]) {
+  const double c = std::min(1.0, std::max(-1.0, (R[0] + R[4] + R[8] - 1.0) / 2.0));
+  const double th = std::acos(c);
+  const double w[3] = {R[7] - R[5], R[2] - R[6], R[3] - R[1]};  // vee(R - R^T)
+  const double f = th < 1e-5 ? 0.5 + th * th / 12.0 : th / (2.0 * std::sin(th));
+  const double phi[3] = {f * w[0], f * w[1], f * w[2]};
+  const double P[9] = {0, -phi[2], phi[1], phi[2], 0, -phi[0], -phi[1], phi[0], 0};
+  const double t2 = phi[0] * phi[0] + phi[1] * phi[1] + phi[2] * phi[2], tn = std::sqrt(t2);
+  // V^-1 = I - P/2 + D P^2
+  const double D = tn < 1e-5 ? 1.0 / 12.0 + t2 / 720.0
+                             : (1.0 - tn * std::sin(tn) / (2.0 * (1.0 - std::cos(tn)))) / t2;
+  for (int i = 0; i < 3; ++i) {
+    double s = t[i];
+    for (int l = 0; l < 3; ++l) {
+      double p2 = 0.0;
+      for (int m = 0; m < 3; ++m) p2 += P[3 * i + m] * P[3 * m + l];
+      s += (-0.5 * P[3 * i + l] + D * p2) * t[l];
+    }
+    xi[i] = s;
+    xi[3 + i] = phi[i];
+  }
+}
+
+}  // namespace
+
+extern "C" {
+
+int gs_track_plan_create(gs_track_plan **out, int64_t n, int32_t sh_degree, int64_t max_pixels, int32_t tile_w,
+                         int32_t tile_h, int32_t blend_depth, int64_t capacity) {
+  if (!out) return fail(GS_ERR_INVALID_ARG, "plan out-pointer is NULL");
+  *out = nullptr;
+  if (n < 0 || n > 0x7FFFFFFF || sh_degree < 0 || sh_degree > 3) return fail(GS_ERR_INVALID_ARG, "bad n or degree");
+  if (!tile_ok(tile_w, tile_h)) return fail(GS_ERR_INVALID_ARG, "tile size must be 8x8, 16x16 or 32x32");
+  if (!depth_ok(blend_depth)) return fail(GS_ERR_INVALID_ARG, "blend_depth must be 64, 128 or 256");
+  if (max_pixels <= 0 || max_pixels > 0x7FFFFFFF || capacity <= 0 || capacity > 0xFFFFFFFFll)
+    return fail(GS_ERR_INVALID_ARG, "bad pixel budget or capacity");
+  gs_track_plan *p = new gs_track_plan();
+  p->n = n;
+  p->deg = sh_degree;
+  p->tw = tile_w;
+  p->th = tile_h;
+  p->bd = blend_depth;
+  p->max_pixels = max_pixels;
+  p->cap = capacity;
+  p->max_tiles = max_pixels / ((int64_t)tile_w * tile_h) + (2 * 32768 / tile_w + 1);
+  size_t offs[17];
+  const size_t bytes = track_bytes(*p, offs);
+  hipError_t e = hipMalloc(&p->block, bytes);
+  if (e != hipSuccess) {
+    delete p;
+    return hip_fail(e, "tracking plan allocation");
+  }
+  char *b = (char *)p->block;
+  p->proj.card = (float *)(b + offs[0]);
+  p->proj.n_tiles = (uint32_t *)(b + offs[1]);
+  p->proj.dkey = (uint32_t *)(b + offs[2]);
+  p->vals = (uint32_t *)(b + offs[3]);
+  p->tile_range = (uint32_t *)(b + offs[4]);
+  p->num_pairs = (int64_t *)(b + offs[5]);
+  p->bin_scratch = b + offs[6];
+  p->grad_scratch = b + offs[7];
+  p->blend_state = b + offs[8];
+  p->dC = (float *)(b + offs[9]);
+  p->color = (float *)(b + offs[10]);
+  p->depth = (float *)(b + offs[11]);
+  p->alpha = (float *)(b + offs[12]);
+  p->t_final = (float *)(b + offs[13]);
+  p->last = (int32_t *)(b + offs[14]);
+  p->ssim_scratch = (float *)(b + offs[15]);
+  p->state = (gs::TrackState *)(b + offs[16]);
+  *out = p;
+  return GS_OK;
+}
+
+void gs_track_plan_destroy(gs_track_plan *p) {
+  if (!p) return;
+  if (p->exec) (void)hipGraphExecDestroy(p->exec);
+  if (p->graph) (void)hipGraphDestroy(p->graph);
+  if (p->capture_stream) (void)hipStreamDestroy(p->capture_stream);
+  if (p->block) (void)hipFree(p->block);
+  delete p;
+}
+
+int64_t gs_track_capacity(const gs_track_plan *p) { return p ? p->cap : 0; }
+
+int gs_track_required_pairs(const gs_track_plan *p, int64_t *required, gs_stream_t stream) {
+  if (!p || !required) return fail(GS_ERR_INVALID_ARG, "NULL argument");
+  GS_TRY_HIP(hipMemcpyAsync(required, &p->state->max_pairs, sizeof(int64_t), hipMemcpyDeviceToHost,
+                            (hipStream_t)stream),
+             "copy pair count");
+  GS_TRY_HIP(hipStreamSynchronize((hipStream_t)stream), "stream synchronize");
+  return GS_OK;
+}
+
+int gs_track_pose(gs_track_plan *p, const gs_gaussians *g, const gs_camera *cam, const float *target,
+                  const gs_track_params *q, float *pose_out, float *trace, gs_stream_t stream) {
+  if (!p) return fail(GS_ERR_INVALID_ARG, "plan is NULL");
+  int rc;
+  if ((rc = check_gaussians(g)) || (rc = check_camera(cam)) || (rc = check_track_params(q))) return rc;
+  if (g->n > p->n) return fail(GS_ERR_INVALID_ARG, "map has more Gaussians than the plan");
+  if (g->sh_degree > p->deg) return fail(GS_ERR_INVALID_ARG, "SH degree above the plan's");
+  if ((int64_t)cam->w * cam->h > p->max_pixels) return fail(GS_ERR_INVALID_ARG, "window exceeds the plan's pixels");
+  if (cam->w > 32768 || cam->h > 32768) return fail(GS_ERR_INVALID_ARG, "window above 32768 pixels a side");
+  if ((int64_t)((cam->w + p->tw - 1) / p->tw) * ((cam->h + p->th - 1) / p->th) > p->max_tiles)
+    return fail(GS_ERR_INVALID_ARG, "window needs more tiles than the plan holds");
+  if (!target || !pose_out) return fail(GS_ERR_INVALID_ARG, "target / pose_out is NULL");
+  hipStream_t st = (hipStream_t)stream;
+  gs::TrackPose p0;
+  for (int i = 0; i < 9; ++i) p0.R[i] = cam->R_cw[i];
+  for (int i = 0; i < 3; ++i) p0.t[i] = cam->t_cw[i];
+  GS_TRY_HIP(gs::launch_track_init(p->state, p0, st), "track init");
+  if (!(q->flags & GS_GRAPH)) return enqueue_track(p, g, cam, target, q, pose_out, trace, st);
+  // The graph bakes in every argument but the starting pose, which the init above sets.
+  gs_camera key = *cam;
+  std::memset(key.R_cw, 0, sizeof key.R_cw);
+  std::memset(key.t_cw, 0, sizeof key.t_cw);
+  std::vector<unsigned char> sig;
+  auto add = [&](const void *src, size_t bytes) {
+    const unsigned char *c = (const unsigned char *)src;
+    sig.insert(sig.end(), c, c + bytes);
+  };
+  add(g, sizeof *g);
+  add(&key, sizeof key);
+  add(&target, sizeof target);
+  add(q, sizeof *q);
+  add(&pose_out, sizeof pose_out);
+  add(&trace, sizeof trace);
+  if (!p->exec || sig != p->signature) {
+    if (p->exec) {
+      (void)hipGraphExecDestroy(p->exec);
+      p->exec = nullptr;
+    }
+    if (p->graph) {
+      (void)hipGraphDestroy(p->graph);
+      p->graph = nullptr;
+    }
+    if (!p->capture_stream)
+      GS_TRY_HIP(hipStreamCreateWithFlags(&p->capture_stream, hipStreamNonBlocking), "capture stream");
+    hipStream_t cs = p->capture_stream;
+    GS_TRY_HIP(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal), "begin capture");
+    rc = enqueue_track(p, g, cam, target, q, pose_out, trace, cs);
+    hipGraph_t graph = nullptr;
+    hipError_t e = hipStreamEndCapture(cs, &graph);
+    if (rc) {
+      if (graph) (void)hipGraphDestroy(graph);
+      return rc;
+    }
+    if (e != hipSuccess) return hip_fail(e, "end capture");
+    e = hipGraphInstantiate(&p->exec, graph, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+      (void)hipGraphDestroy(graph);
+      return hip_fail(e, "graph instantiate");
+    }
+    p->graph = graph;
+    p->signature.swap(sig);
+  }
+  GS_TRY_HIP(hipGraphLaunch(p->exec, st), "graph launch");
+  return GS_OK;
+}
+
+int gs_pose_residual(const float pred_cw[12], const float refined_cw[12], double r[6]) {
+  if (!pred_cw || !refined_cw || !r) return fail(GS_ERR_INVALID_ARG, "NULL argument");
+  for (int i = 0; i < 12; ++i)
+    if (!std::isfinite(pred_cw[i]) || !std::isfinite(refined_cw[i]))
+      return fail(GS_ERR_INVALID_ARG, "pose is not finite");
+  // camera-to-world T_wc = T_cw^-1, so T_wc(t) T~_wc^-1 = T_cw(t)^-1 T~_cw:
+  //   R = Rp^T Rr,  t = Rp^T (tr - tp)
+  const float *Rp = pred_cw, *tp = pred_cw + 9, *Rr = refined_cw, *tr = refined_cw + 9;
+  double R[9], t[3];
+  for (int i = 0; i < 3; ++i) {
+    for (int j = 0; j < 3; ++j) {
+      double s = 0.0;
+      for (int l = 0; l < 3; ++l) s += (double)Rp[3 * l + i] * (double)Rr[3 * l + j];
+      R[3 * i + j] = s;
+    }
+    double s = 0.0;
+    for (int l = 0; l < 3; ++l) s += (double)Rp[3 * l + i] * ((double)tr[l] - (double)tp[l]);
+    t[i] = s;
+  }
+  se3_log(R, t, r);
+  return GS_OK;
+}
+
+}  // extern "C"

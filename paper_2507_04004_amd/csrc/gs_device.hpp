@@ -38,8 +38,32 @@ struct ViewTable {
   int64_t n;             // Gaussians per view
   uint32_t total_tiles;  // sum of tiles over views
   uint32_t pad;
+  // Device-resident pose of view 0 (one view only): R_cw row-major (9), t_cw (3), camera
+  // centre (3). When set, the kernels that use the pose read it here instead of from v[0],
+  // so a pose updated on the device between launches needs no host round trip.
+  const float *pose_dev;
   ViewCam v[kMaxViews];
 };
+
+// The camera of view vi. DP (device pose): view 0 with its pose from vt.pose_dev, built in
+// `tmp`; otherwise the table entry itself.
+template <bool DP>
+__device__ __forceinline__ const ViewCam &view_cam(const ViewTable &vt, int vi, ViewCam &tmp) {
+  if constexpr (!DP) {
+    return vt.v[vi];
+  } else {
+    tmp = vt.v[0];
+    const float *p = vt.pose_dev;
+#pragma unroll
+    for (int i = 0; i < 9; ++i) tmp.R[i] = p[i];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      tmp.t[i] = p[9 + i];
+      tmp.cw[i] = p[12 + i];
+    }
+    return tmp;
+  }
+}
 
 struct ViewImg {
   float *color, *depth, *alpha, *t_final;

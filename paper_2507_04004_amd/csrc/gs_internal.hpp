@@ -64,4 +64,28 @@ size_t dssim_scratch_bytes(int c, int h, int w);
 hipError_t launch_dssim(const float *x, const float *y, int c, int h, int w, float weight, float *dldc, float *loss,
                         float *scratch, hipStream_t st);
 
+// Tracking loop state in device memory: float64 master pose and Adam moments, the float32
+// pose the projection kernels read (R 9, t 3, centre 3, pad), and the per-iteration
+// gradient and loss terms written by the backward and the loss kernels.
+struct TrackState {
+  double R[9], t[3];
+  double m[6], v[6];
+  int64_t max_pairs;  // largest pair count seen over the iterations
+  float pose[16];
+  float grad[6];
+  float loss[2];  // L1 term, D-SSIM term
+};
+struct TrackPose {
+  double R[9], t[3];
+};
+struct TrackStepArgs {
+  double lr[6];
+  double beta1, beta2, eps, bias1, bias2;  // bias = 1 - beta^k
+  int32_t k;
+};
+constexpr int kTrackTraceStride = 20;  // pose (12), gradient (6), L1 term, D-SSIM term
+hipError_t launch_track_init(TrackState *s, const TrackPose &p0, hipStream_t st);
+hipError_t launch_track_step(TrackState *s, const TrackStepArgs &a, const int64_t *num_pairs, float *trace,
+                             float *pose_out, hipStream_t st);
+
 }  // namespace gs

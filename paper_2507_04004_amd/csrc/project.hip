@@ -263,6 +263,7 @@ __device__ __forceinline__ uint32_t small_rect_masks(const ViewCam &cam, int tw,
   return mask;
 }
 
+template <bool DP>
 __global__ __launch_bounds__(256) void k_preprocess(ViewTable vt, const float *__restrict__ mean,
                                                     const float *__restrict__ scale, const float *__restrict__ rot,
                                                     const float *__restrict__ opacity,
@@ -273,7 +274,8 @@ __global__ __launch_bounds__(256) void k_preprocess(ViewTable vt, const float *_
   const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int vi = blockIdx.y;
   const bool in = g < n;  // every lane stays active: the wavefront-wide tile visit below needs all
-  const ViewCam &cam = vt.v[vi];
+  ViewCam tmp;
+  const ViewCam &cam = view_cam<DP>(vt, vi, tmp);
   const int64_t e = (int64_t)vi * n + g;
   const Planes P(n, (uint32_t)(in ? g : 0));
   float mx = P.ld(mean, 0), my = P.ld(mean, 1), mz = P.ld(mean, 2);
@@ -421,7 +423,7 @@ __device__ __forceinline__ void sh_term(int k, float x, float y, float z, float 
 // occupancy of a light kernel instead of that of the geometry chain rule.
 // OVERWRITE: every output element of the launched range is written (zeros where no view
 // contributes); otherwise the gradients are added to the outputs where some view contributes.
-template <int DEG, bool SINGLE, bool OVERWRITE>
+template <int DEG, bool SINGLE, bool OVERWRITE, bool DP>
 __global__ __launch_bounds__(256) void k_sh_bwd(ViewTable vt, const float *__restrict__ mean,
                                                 const float *__restrict__ sh_dc, const float *__restrict__ sh_rest,
                                                 const uint32_t *__restrict__ n_tiles, const float *__restrict__ g2,
@@ -441,7 +443,8 @@ __global__ __launch_bounds__(256) void k_sh_bwd(ViewTable vt, const float *__res
     // with zero weights and a fixed direction, its coefficients not loaded), so each plane
     // leaves the wavefront as one full-width store instead of a store of the contributing
     // lanes now and one of zeros later, which the L2 could write back in pieces.
-    const ViewCam &cam = vt.v[0];
+    ViewCam tmp;
+    const ViewCam &cam = view_cam<DP>(vt, 0, tmp);
     bool live = n_tiles[gi] > 0;
     float2 G67 = make_float2(0.f, 0.f);
     float G8 = 0.f;
@@ -507,7 +510,8 @@ __global__ __launch_bounds__(256) void k_sh_bwd(ViewTable vt, const float *__res
 #pragma unroll
   for (int i = 0; i < (SINGLE ? 1 : NRA); ++i) acc_rest[i] = 0.f;
   for (int vi = 0; vi < vt.n_views; ++vi) {
-    const ViewCam &cam = vt.v[vi];
+    ViewCam tmp;
+    const ViewCam &cam = view_cam<DP>(vt, vi, tmp);
     const int64_t e = (int64_t)vi * n + gi;
     bool live = n_tiles[e] > 0;
     float2 G67 = make_float2(0.f, 0.f);
@@ -592,7 +596,7 @@ __global__ __launch_bounds__(256) void k_sh_bwd(ViewTable vt, const float *__res
   }
 }
 
-template <bool OVERWRITE>
+template <bool OVERWRITE, bool DP>
 __global__ __launch_bounds__(256) void k_geo_bwd(ViewTable vt, const float *__restrict__ mean,
                                                  const float *__restrict__ scale, const float *__restrict__ rot,
                                                  const float *__restrict__ opacity,
@@ -615,7 +619,8 @@ __global__ __launch_bounds__(256) void k_geo_bwd(ViewTable vt, const float *__re
   bool any_view = false;
 
   for (int vi = 0; vi < vt.n_views; ++vi) {
-    const ViewCam &cam = vt.v[vi];
+    ViewCam tmp;
+    const ViewCam &cam = view_cam<DP>(vt, vi, tmp);
     const int64_t e = (int64_t)vi * n + g;
     float pose[6] = {0, 0, 0, 0, 0, 0};
     bool live = in && n_tiles[e] > 0;
@@ -787,9 +792,14 @@ namespace gs {
 
 hipError_t launch_preprocess(const ViewTable &vt, const gs_gaussians &g, const gs_projected &p, hipStream_t st) {
   if (vt.n == 0) return hipSuccess;
+  if (vt.pose_dev && vt.n_views != 1) return hipErrorInvalidValue;  // a device pose is view 0's alone
   dim3 grid((unsigned)((vt.n + 255) / 256), (unsigned)vt.n_views);
-  hipLaunchKernelGGL(k_preprocess, grid, dim3(256), 0, st, vt, g.mean, g.scale, g.rot, g.opacity, g.sh_dc,
-                     g.sh_rest, (Card *)p.card, p.n_tiles, p.dkey);
+  if (vt.pose_dev)
+    hipLaunchKernelGGL(k_preprocess<true>, grid, dim3(256), 0, st, vt, g.mean, g.scale, g.rot, g.opacity, g.sh_dc,
+                       g.sh_rest, (Card *)p.card, p.n_tiles, p.dkey);
+  else
+    hipLaunchKernelGGL(k_preprocess<false>, grid, dim3(256), 0, st, vt, g.mean, g.scale, g.rot, g.opacity, g.sh_dc,
+                       g.sh_rest, (Card *)p.card, p.n_tiles, p.dkey);
   return hipGetLastError();
 }
 
@@ -823,21 +833,24 @@ hipError_t launch_preprocess_bwd(const ViewTable &vt, const gs_gaussians &g, con
                                  float4 *gdir, const gs_grads &out, float *const *pose_out, float *pose_partial,
                                  hipStream_t st) {
   if (vt.n == 0) return hipSuccess;
+  if (vt.pose_dev && vt.n_views != 1) return hipErrorInvalidValue;
   const int64_t nb = preprocess_bwd_blocks(vt.n);
   const bool ow = out.overwrite != 0;
   const bool single = vt.n_views == 1;
   // colour first: it hands the view-direction gradient to the geometry kernel
   {
     switch (vt.sh_degree) {
-#define GS_SH_BWD(D, S, O)                                                                                     \
-  hipLaunchKernelGGL((k_sh_bwd<D, S, O>), dim3((unsigned)nb), dim3(256), 0, st, vt, g.mean, g.sh_dc, g.sh_rest, \
-                     p.n_tiles, g2, gdir, out.sh_dc, out.sh_rest)
+#define GS_SH_BWD(D, S, O, DP)                                                                                 \
+  hipLaunchKernelGGL((k_sh_bwd<D, S, O, DP>), dim3((unsigned)nb), dim3(256), 0, st, vt, g.mean, g.sh_dc,         \
+                     g.sh_rest, p.n_tiles, g2, gdir, out.sh_dc, out.sh_rest)
 #define GS_SH_CASE(D)                                                                                          \
   case D:                                                                                                      \
-    if (single) {                                                                                              \
-      if (ow) GS_SH_BWD(D, true, true); else GS_SH_BWD(D, true, false);                                        \
+    if (vt.pose_dev) {                                                                                         \
+      if (ow) GS_SH_BWD(D, true, true, true); else GS_SH_BWD(D, true, false, true);                            \
+    } else if (single) {                                                                                       \
+      if (ow) GS_SH_BWD(D, true, true, false); else GS_SH_BWD(D, true, false, false);                          \
     } else {                                                                                                   \
-      if (ow) GS_SH_BWD(D, false, true); else GS_SH_BWD(D, false, false);                                      \
+      if (ow) GS_SH_BWD(D, false, true, false); else GS_SH_BWD(D, false, false, false);                        \
     }                                                                                                          \
     break;
       GS_SH_CASE(0)
@@ -853,12 +866,15 @@ hipError_t launch_preprocess_bwd(const ViewTable &vt, const gs_gaussians &g, con
     if (err != hipSuccess) return err;
   }
   ParamGradOut po{out.mean, out.scale, out.rot, out.opacity, out.sh_dc, out.sh_rest};
-  if (ow)
-    hipLaunchKernelGGL(k_geo_bwd<true>, dim3((unsigned)nb), dim3(256), 0, st, vt, g.mean, g.scale, g.rot, g.opacity,
-                       p.n_tiles, g2, (const float4 *)gdir, po, pose_partial);
-  else
-    hipLaunchKernelGGL(k_geo_bwd<false>, dim3((unsigned)nb), dim3(256), 0, st, vt, g.mean, g.scale, g.rot,
-                       g.opacity, p.n_tiles, g2, (const float4 *)gdir, po, pose_partial);
+#define GS_GEO_BWD(O, DP)                                                                                       \
+  hipLaunchKernelGGL((k_geo_bwd<O, DP>), dim3((unsigned)nb), dim3(256), 0, st, vt, g.mean, g.scale, g.rot,        \
+                     g.opacity, p.n_tiles, g2, (const float4 *)gdir, po, pose_partial)
+  if (vt.pose_dev) {
+    if (ow) GS_GEO_BWD(true, true); else GS_GEO_BWD(false, true);
+  } else {
+    if (ow) GS_GEO_BWD(true, false); else GS_GEO_BWD(false, false);
+  }
+#undef GS_GEO_BWD
   hipError_t err = hipGetLastError();
   if (err != hipSuccess) return err;
   PosePtrs pp;

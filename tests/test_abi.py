@@ -165,3 +165,36 @@ def test_dssim_argument_errors():
     for kw in bad:
         assert call(**kw) == N.GS_ERR_INVALID_ARG, kw
         assert L.gs_last_error()
+
+
+def test_pose_residual_matches_oracle():
+    """gs_pose_residual (host) against the oracle's Log(T_wc(t) T~_wc^-1)."""
+    from oracle import track as OT
+    from paper_2507_04004_amd import track as T
+    rng = np.random.default_rng(7)
+    for scale in (1e-7, 1e-3, 0.05, 0.5):
+        Ra, ta = OT.se3_exp(rng.normal(0, 1, 6))
+        Rb, tb = OT.left_update(Ra, ta, rng.normal(0, scale, 6))
+        pa = np.r_[Ra.ravel(), ta].astype(np.float32).astype(np.float64)
+        pb = np.r_[Rb.ravel(), tb].astype(np.float32).astype(np.float64)
+        RA, tA, RB, tB = pa[:9].reshape(3, 3), pa[9:], pb[:9].reshape(3, 3), pb[9:]
+        want = OT.pose_residual(RA.T, -RA.T @ tA, RB.T, -RB.T @ tB)  # camera-to-world inputs
+        np.testing.assert_allclose(T.pose_residual(pa, pb), want, atol=1e-6)
+    assert np.abs(T.pose_residual(pa, pa)).max() < 1e-6
+
+
+def test_track_argument_errors():
+    L = N.lib()
+    plan = C.c_void_p()
+    bad = [dict(n=-1), dict(sh_degree=4), dict(max_pixels=0), dict(tile=12), dict(blend_depth=100), dict(capacity=0)]
+    for kw in bad:
+        a = {**dict(n=10, sh_degree=0, max_pixels=100, tile=8, blend_depth=128, capacity=100), **kw}
+        rc = L.gs_track_plan_create(C.byref(plan), a["n"], a["sh_degree"], a["max_pixels"], a["tile"], a["tile"],
+                                    a["blend_depth"], a["capacity"])
+        assert rc == N.GS_ERR_INVALID_ARG, kw
+    q = N.TrackParams(30, 0.5, 0.5, 1e-3, 3e-3, 0.9, 0.999, 1e-8, 0)
+    assert L.gs_track_pose(None, None, None, None, C.byref(q), None, None, None) == N.GS_ERR_INVALID_ARG
+    r = (C.c_double * 6)()
+    assert L.gs_pose_residual(None, None, C.byref(r)) == N.GS_ERR_INVALID_ARG
+    nan = (C.c_float * 12)(*([float("nan")] + [0.0] * 11))
+    assert L.gs_pose_residual(C.byref(nan), C.byref(nan), C.byref(r)) == N.GS_ERR_INVALID_ARG
