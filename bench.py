@@ -15,7 +15,8 @@ no clearing pass.
 
 Besides the headline figure the line carries the roofline of the dominant kernel, the two
 small configurations, the batched 8-keyframe pass, the sparse Adam step over the reached
-Gaussians (`sparse_adam`), novel-view serving, and the float64 CPU oracle as a baseline.
+Gaussians (`sparse_adam`), the photometric tracking loop on a 2M-Gaussian map (`tracking`),
+novel-view serving, and the float64 CPU oracle as a baseline.
 
 Prints ONE JSON line. `value` is fwd+bwd views/s on one GPU.
 """
@@ -95,6 +96,10 @@ def parse():
     ap.add_argument("--no-small", action="store_true", help="skip the two small single-view configurations")
     ap.add_argument("--no-serving", action="store_true", help="skip the serving measurement")
     ap.add_argument("--no-adam", action="store_true", help="skip the sparse Adam measurement")
+    ap.add_argument("--no-tracking", action="store_true", help="skip the photometric tracking measurement")
+    ap.add_argument("--tracking-only", action="store_true",
+                    help="run only the photometric tracking measurement (for profiling it alone)")
+    ap.add_argument("--tracking-frames", type=int, default=10)
     ap.add_argument("--serve-requests", type=int, default=2000, help="requests per arrival rate")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one plain 256 MiB device copy (reference point for HBM byte counters)")
@@ -332,6 +337,81 @@ def measure_sparse_adam(R, torch, S, ps, tile, dev, reps=20):
     return out
 
 
+def measure_tracking(R, torch, S, tile, bd, dev, n=2_000_000, frames=10):
+    """Photometric tracking (camera factor option 2): N_t = 30 pose iterations per frame, map
+    frozen, on a 2M-Gaussian street map at 1280x720. Each frame starts from the true pose moved
+    by a seeded perturbation (~5 cm, ~0.3 deg) and refines it against the image rendered at the
+    true pose (rendered once, untimed). Timed: `frames` calls of the captured loop, no host
+    synchronisation between them. Also the D-SSIM kernels alone on a 3x720x1280 image pair,
+    against HBM: algorithmic bytes per value 20 in the forward (two images read, three
+    derivative maps written) and 28 in the backward (three maps and two images read, dL/dC
+    read and written)."""
+    import numpy as np
+    from paper_2507_04004_amd import track as T
+    g = S.street_map(n, seed=6)
+    cam = S.headline_camera()
+    gm = R.GaussianMap.from_numpy(g, dev)
+    cs = R.camera_struct(cam)
+    spl = R.preprocess(gm.struct(), cs, tile, dev)
+    bins = R.bin_sort_fit(spl, gm.n, cs, tile, dev)
+    fr = R.render_fwd(spl, gm.n, bins, cs, bd, dev)
+    target = fr.color.clone()
+    del spl, bins, fr
+    rng = np.random.default_rng(8)
+    starts = []
+    for _ in range(frames):
+        starts.append(R.camera_left_update(cs, np.r_[rng.normal(0, 0.03, 3), rng.normal(0, 0.003, 3)]))
+    trk = T.PoseTracker(gm, cam.w * cam.h, tile=tile, blend_depth=bd, device=dev)
+    out = {"n_gaussians": gm.n, "width": cam.w, "height": cam.h, "iters": T.DEFAULTS["iters"], "frames": frames}
+    for graph in (True, False):
+        trk.track(starts[0], target, graph=graph, check=True)  # capture / warm up, pair check
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record()
+        for st in starts:
+            trk.track(st, target, graph=graph, check=False)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / frames
+        key = "graph" if graph else "eager"
+        out[key] = {"ms_per_frame": round(ms, 3), "frames_s": round(1e3 / ms, 2),
+                    "iters_s": round(1e3 * T.DEFAULTS["iters"] / ms, 1)}
+    res = trk.track(starts[-1], target, graph=True, trace=True, check=True)
+    tr = res.trace.double().cpu().numpy()
+    out["pairs_max"] = res.pairs
+    out["loss_first_last"] = [round(float(tr[0, 18] + tr[0, 19]), 5), round(float(tr[-1, 18] + tr[-1, 19]), 5)]
+
+    true_pose = np.r_[np.asarray(cs.R_cw[:]), np.asarray(cs.t_cw[:])]
+
+    def err(pose):
+        d = T.pose_residual(true_pose, pose)
+        return [round(float(np.linalg.norm(d[:3])), 5), round(float(np.linalg.norm(d[3:])), 6)]
+    out["pose_error_m_rad"] = {"start": err(tr[0, :12]), "end": err(res.pose.double().cpu().numpy())}
+    trk.close()
+    # D-SSIM kernels alone
+    x = target.contiguous()
+    y = torch.roll(target, shifts=(3, 5), dims=(1, 2)).contiguous()
+    dC = torch.zeros_like(x)
+    loss = torch.empty(1, device=dev)
+    scratch = torch.empty(R.N.lib().gs_dssim_scratch_bytes(3, cam.h, cam.w), dtype=torch.uint8, device=dev)
+    for _ in range(3):
+        R.loss_dssim(x, y, 0.5, dC, loss, scratch)
+    reps = 50
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        R.loss_dssim(x, y, 0.5, dC, loss, scratch)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    nbytes = 48 * x.numel()
+    out["dssim"] = {"values": x.numel(), "ms": round(ms, 4), "GB/s": round(nbytes / (ms * 1e-3) / 1e9, 1),
+                    "frac_hbm": round(nbytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+    del gm, target, x, y, dC, scratch
+    torch.cuda.empty_cache()
+    return out
+
+
 def cpu_baseline(g, cam, gC_np, repeats):
     """The FP64 oracle (as it stands) on the host: one full-view fwd + bwd of the same workload."""
     import numpy as np
@@ -367,6 +447,11 @@ def main():
         print(json.dumps({"error": "no GPU visible"}), flush=True)
         sys.exit(1)
     dev = "cuda:0"
+    if args.tracking_only:
+        log("[bench] photometric tracking only")
+        print(json.dumps({"tracking": measure_tracking(R, torch, S, args.tile, args.blend_depth, dev,
+                                                       frames=args.tracking_frames)}), flush=True)
+        return
     log("[bench] generating the 1M-Gaussian street map")
     g = S.street_map(args.n, seed=2)
     cam = S.headline_camera()
@@ -533,6 +618,10 @@ def main():
         log("[bench] sparse Adam")
         out["sparse_adam"] = measure_sparse_adam(R, torch, S, ps, args.tile, dev)
         log(f"[bench] sparse Adam {out['sparse_adam']}")
+    if not args.no_tracking:
+        log("[bench] photometric tracking")
+        out["tracking"] = measure_tracking(R, torch, S, args.tile, args.blend_depth, dev, frames=args.tracking_frames)
+        log(f"[bench] tracking {out['tracking']}")
     if not args.no_serving:
         del ps
         torch.cuda.empty_cache()

@@ -828,7 +828,7 @@ size_t track_bytes(const gs_track_plan &p, size_t *offs) {
   put(12, 4 * px);                                  // opacity
   put(13, 4 * px);                                  // final transmittance
   put(14, 4 * px);                                  // last contributor
-  put(15, 36 * px);                                 // D-SSIM derivative maps (3 per value)
+  put(15, gs::dssim_scratch_bound(px));             // D-SSIM derivative maps and partial sums
   put(16, sizeof(gs::TrackState));
   return o;
 }
@@ -855,7 +855,8 @@ int enqueue_track(gs_track_plan *p, const gs_gaussians *g, const gs_camera *cam,
   vt.pose_dev = p->state->pose;
   const int h = cam->h, w = cam->w;
   const int64_t px = (int64_t)w * h;
-  if (gs::dssim_scratch_bytes(3, h, w) > (size_t)36 * p->max_pixels) return fail(GS_ERR_INVALID_ARG, "d-ssim scratch");
+  if (gs::dssim_scratch_bytes(3, h, w) > gs::dssim_scratch_bound(p->max_pixels))
+    return fail(GS_ERR_INVALID_ARG, "d-ssim scratch");
   gs::ImgTable it{};
   it.v[0] = {p->color, p->depth, p->alpha, p->t_final, p->last, nullptr};
   gs_image img{p->color, p->depth, p->alpha, p->t_final, p->last, nullptr, p->blend_state, 0};

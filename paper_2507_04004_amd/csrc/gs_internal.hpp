@@ -61,6 +61,7 @@ struct AdamArgs {
 hipError_t launch_adam_sparse(const AdamArgs &a, hipStream_t st);
 
 size_t dssim_scratch_bytes(int c, int h, int w);
+size_t dssim_scratch_bound(int64_t pixels);  // three channels, any window of at most `pixels`
 hipError_t launch_dssim(const float *x, const float *y, int c, int h, int w, float weight, float *dldc, float *loss,
                         float *scratch, hipStream_t st);
 

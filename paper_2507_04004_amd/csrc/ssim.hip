@@ -10,7 +10,8 @@
 // Forward: the five filtered maps give S; with g = -weight / (c h w) the kernel writes, per
 // pixel, the derivatives of g S w.r.t. the three maps that depend on x:
 //   d mu_x = g (2 mu_y (S/A - S/B) + 2 mu_x (S/D - S/C)),  d E[x^2] = -g S/D,  d E[xy] = 2 g S/B
-// (mu_x enters A, B through s_xy, C and D through s_x^2), and adds g S to the loss.
+// (mu_x enters A, B through s_xy, C and D through s_x^2), and one partial sum of S per
+// workgroup; the loss weight + g sum S is then summed in a fixed order (deterministic).
 // Backward: the window is symmetric, so the adjoint of each filtering is the same filtering:
 //   dL/dx = G * d mu_x + 2 x (G * d E[x^2]) + y (G * d E[xy]).
 #include <cmath>
@@ -40,7 +41,7 @@ __device__ __forceinline__ void load_halo(const float *__restrict__ src, int h, 
 __global__ __launch_bounds__(256) void k_dssim_fwd(const float *__restrict__ x, const float *__restrict__ y, int h,
                                                    int w, SsimWeights sw, float g, float *__restrict__ dmu,
                                                    float *__restrict__ dxx, float *__restrict__ dxy,
-                                                   float *__restrict__ loss) {
+                                                   float *__restrict__ partial) {
   __shared__ float sx[kSsimW * kSsimH], sy[kSsimW * kSsimH];
   __shared__ float hs[5][kSsimH * kSsimTX];
   __shared__ float red[4];
@@ -91,12 +92,28 @@ __global__ __launch_bounds__(256) void k_dssim_fwd(const float *__restrict__ x, 
     dxx[p] = -g * (S / D);
     dxy[p] = 2.f * g * (S / B);
   }
-  // the block's g * sum S into the loss (which starts at weight)
+  // the block's sum of S, reduced in a fixed order by k_dssim_loss
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) part += __shfl_xor(part, off);
   if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = part;
   __syncthreads();
-  if (threadIdx.x == 0 && loss) atomicAdd(loss, g * ((red[0] + red[1]) + (red[2] + red[3])));
+  if (threadIdx.x == 0)
+    partial[((int64_t)blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x] = (red[0] + red[1]) + (red[2] + red[3]);
+}
+
+// loss = weight + g * sum of the block partials (float64, fixed order): deterministic.
+__global__ __launch_bounds__(256) void k_dssim_loss(const float *__restrict__ partial, int64_t nb, float weight,
+                                                    double g, float *__restrict__ loss) {
+  __shared__ double red[256];
+  double s = 0.0;
+  for (int64_t b = threadIdx.x; b < nb; b += 256) s += (double)partial[b];
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int off = 128; off > 0; off >>= 1) {
+    if (threadIdx.x < off) red[threadIdx.x] += red[threadIdx.x + off];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *loss = (float)((double)weight + g * red[0]);
 }
 
 __global__ __launch_bounds__(256) void k_dssim_bwd(const float *__restrict__ x, const float *__restrict__ y, int h,
@@ -146,7 +163,22 @@ __global__ __launch_bounds__(256) void k_dssim_bwd(const float *__restrict__ x, 
 
 __global__ void k_set_f32(float *p, float v) { *p = v; }
 
-size_t dssim_scratch_bytes(int c, int h, int w) { return 3 * sizeof(float) * (size_t)c * h * w; }
+namespace {
+int64_t dssim_blocks(int c, int h, int w) {
+  return (int64_t)c * ((w + kSsimTX - 1) / kSsimTX) * ((h + kSsimTY - 1) / kSsimTY);
+}
+}  // namespace
+
+// three derivative maps per value, then one partial sum per workgroup
+size_t dssim_scratch_bytes(int c, int h, int w) {
+  return 3 * sizeof(float) * (size_t)c * h * w + sizeof(float) * (size_t)dssim_blocks(c, h, w);
+}
+
+// Enough for any window of at most `pixels` pixels and sides up to 32768, three channels.
+size_t dssim_scratch_bound(int64_t pixels) {
+  const int64_t blocks = pixels / (kSsimTX * kSsimTY) + 32768 / kSsimTX + 32768 / kSsimTY + 1;
+  return 3 * sizeof(float) * 3 * (size_t)pixels + sizeof(float) * 3 * (size_t)blocks;
+}
 
 hipError_t launch_dssim(const float *x, const float *y, int c, int h, int w, float weight, float *dldc, float *loss,
                         float *scratch, hipStream_t st) {
@@ -159,12 +191,17 @@ hipError_t launch_dssim(const float *x, const float *y, int c, int h, int w, flo
   }
   for (int t = 0; t <= 2 * kSsimR; ++t) sw.w[t] = (float)(wd[t] / tot);
   const int64_t n = (int64_t)c * h * w;
-  if (loss) hipLaunchKernelGGL(k_set_f32, dim3(1), dim3(1), 0, st, loss, weight);
-  if (n == 0) return hipGetLastError();
-  const float g = (float)(-(double)weight / (double)n);
-  float *dmu = scratch, *dxx = scratch + n, *dxy = scratch + 2 * n;
+  if (n == 0) {
+    if (loss) hipLaunchKernelGGL(k_set_f32, dim3(1), dim3(1), 0, st, loss, weight);
+    return hipGetLastError();
+  }
+  const double gd = -(double)weight / (double)n;
+  const float g = (float)gd;
+  float *dmu = scratch, *dxx = scratch + n, *dxy = scratch + 2 * n, *partial = scratch + 3 * n;
   const dim3 grid((unsigned)((w + kSsimTX - 1) / kSsimTX), (unsigned)((h + kSsimTY - 1) / kSsimTY), (unsigned)c);
-  hipLaunchKernelGGL(k_dssim_fwd, grid, dim3(256), 0, st, x, y, h, w, sw, g, dmu, dxx, dxy, loss);
+  hipLaunchKernelGGL(k_dssim_fwd, grid, dim3(256), 0, st, x, y, h, w, sw, g, dmu, dxx, dxy, partial);
+  if (loss)
+    hipLaunchKernelGGL(k_dssim_loss, dim3(1), dim3(256), 0, st, partial, dssim_blocks(c, h, w), weight, gd, loss);
   if (dldc) hipLaunchKernelGGL(k_dssim_bwd, grid, dim3(256), 0, st, x, y, h, w, sw, dmu, dxx, dxy, dldc);
   return hipGetLastError();
 }

@@ -61,3 +61,18 @@ def test_dssim_identical_images_and_loss_only():
     l2 = R.loss_dssim(torch.from_numpy(x2).to(DEV), torch.from_numpy(y2).to(DEV), weight=2.0)
     torch.cuda.synchronize()
     assert abs(float(l2.item()) - O.dssim(x2.astype(np.float64), y2.astype(np.float64), 2.0)[0]) <= 2e-5
+
+
+def test_dssim_is_deterministic():
+    """The loss is summed in a fixed order and the gradient has no atomics: repeated calls agree
+    bit for bit."""
+    x, y = _pair(3, 360, 640, seed=9)
+    xt, yt = torch.from_numpy(x).to(DEV), torch.from_numpy(y).to(DEV)
+    outs = []
+    for _ in range(3):
+        d = torch.zeros_like(xt)
+        loss = R.loss_dssim(xt, yt, weight=0.5, dL_dC=d)
+        torch.cuda.synchronize()
+        outs.append((loss.cpu().numpy().copy(), d.cpu().numpy()))
+    for l, d in outs[1:]:
+        assert np.array_equal(l, outs[0][0]) and np.array_equal(d, outs[0][1])
