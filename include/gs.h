@@ -309,6 +309,46 @@ int gs_track_required_pairs(const gs_track_plan *plan, int64_t *required, gs_str
  * (rotation angles below pi). */
 int gs_pose_residual(const float pred_cw[12], const float refined_cw[12], double r[6]);
 
+/* ---- Map initialization and expansion ------------------------------------------------- */
+
+/* Colourised points of a keyframe: xyz [3][n] world coordinates, rgb [3][n] in [0, 1]. */
+typedef struct gs_points {
+  int64_t n;
+  const float *xyz, *rgb;
+} gs_points;
+
+/* Writable Gaussian planes, layouts as gs_gaussians (stride n). */
+typedef struct gs_gaussians_out {
+  int64_t n;
+  int32_t sh_degree;
+  float *mean, *scale, *rot, *opacity, *sh_dc, *sh_rest;
+} gs_gaussians_out;
+
+size_t gs_expand_scratch_bytes(int64_t n_points);
+
+/* Selection of Sec. "Expansion of Gaussian Map": a point is selected when it lies beyond the
+ * near plane (camera-frame z > 0.2), its nearest pixel centre floor(fx x/z + cx + 1/2),
+ * floor(fy y/z + cy + 1/2) lies in the render window, and the rendered opacity there
+ * (eq:rendered_opacity; `opacity` is the window plane [h][w] of gs_render_fwd) is below tau
+ * (0.99 in the paper's setup). opacity = NULL is the initialization of Sec. "Initialization of
+ * Gaussian Map": every point beyond the near plane is selected. The decision is taken in
+ * float32 with the projection's operation order. count_out [1] (device int64) receives the
+ * number selected; scratch (device, gs_expand_scratch_bytes(n)) keeps the decisions for
+ * gs_expand_write. rgb may be NULL here. */
+int gs_expand_select(const gs_points *pts, const gs_camera *cam, const float *opacity, float tau,
+                     int64_t *count_out, void *scratch, size_t scratch_bytes, gs_stream_t stream);
+
+/* The grown map: out->n = old n + added, where added is the count gs_expand_select produced
+ * (read back by the caller to size `out`); a smaller `added` keeps the first `added` selected
+ * points. The existing Gaussians (old_map, may be NULL for none) are copied first, then one
+ * Gaussian per selected point in point order: mean = xyz, scale = (z / fx)(1, 1, 1) with z the
+ * point's camera-frame depth, rotation (1, 0, 0, 0), opacity 0.1, sh_dc = (rgb - 1/2) / Y_0
+ * with Y_0 = 1 / (2 sqrt(pi)), sh_rest = 0. out->sh_degree must equal the old map's; the
+ * planes of `out` must not overlap the old map's. pts, cam and scratch as given to
+ * gs_expand_select. */
+int gs_expand_write(const gs_points *pts, const gs_camera *cam, const gs_gaussians *old_map, int64_t added,
+                    const void *scratch, size_t scratch_bytes, const gs_gaussians_out *out, gs_stream_t stream);
+
 /* Sparse Adam (Sec. "Additional Strategies", a): one Adam step (first and second moment
  * estimates with bias correction) on the Gaussians the rendering reached. A Gaussian whose
  * tile count is zero in every view of `visible` keeps its parameters and moments; the step

@@ -83,6 +83,15 @@ class TrackParams(C.Structure):
 TRACK_TRACE_STRIDE = 20
 
 
+class Points(C.Structure):
+    _fields_ = [("n", C.c_int64), ("xyz", vp), ("rgb", vp)]
+
+
+class GaussiansOut(C.Structure):
+    _fields_ = [("n", C.c_int64), ("sh_degree", C.c_int32)] + [
+        (k, vp) for k in ("mean", "scale", "rot", "opacity", "sh_dc", "sh_rest")]
+
+
 class GSError(RuntimeError):
     pass
 
@@ -92,7 +101,7 @@ _lib = None
 EXPORTS = ["gs_preprocess", "gs_bin_sort", "gs_render_fwd", "gs_render_bwd", "gs_render_batch", "gs_loss_l1",
            "gs_adam_sparse", "gs_loss_dssim", "gs_dssim_scratch_bytes", "gs_track_plan_create",
            "gs_track_plan_destroy", "gs_track_capacity", "gs_track_pose", "gs_track_required_pairs",
-           "gs_pose_residual",
+           "gs_pose_residual", "gs_expand_scratch_bytes", "gs_expand_select", "gs_expand_write",
            "gs_bins_scratch_bytes", "gs_image_state_bytes", "gs_grads_scratch_bytes", "gs_batch_plan_create", "gs_batch_plan_destroy",
            "gs_batch_num_pairs", "gs_batch_capacity", "gs_camera_left_update", "gs_last_error",
            "gs_profile_enable", "gs_profile_read", "gs_profile_disable"]
@@ -142,6 +151,10 @@ def lib():
     L.gs_track_pose.argtypes = [vp, P(Gaussians), P(Camera), vp, P(TrackParams), vp, vp, vp]
     L.gs_track_required_pairs.argtypes = [vp, P(C.c_int64), vp]
     L.gs_pose_residual.argtypes = [P(C.c_float * 12), P(C.c_float * 12), P(C.c_double * 6)]
+    L.gs_expand_scratch_bytes.argtypes = [C.c_int64]
+    L.gs_expand_scratch_bytes.restype = C.c_size_t
+    L.gs_expand_select.argtypes = [P(Points), P(Camera), vp, C.c_float, vp, vp, C.c_size_t, vp]
+    L.gs_expand_write.argtypes = [P(Points), P(Camera), P(Gaussians), C.c_int64, vp, C.c_size_t, P(GaussiansOut), vp]
     L.gs_profile_enable.argtypes = [C.c_uint32, C.c_int32]
     L.gs_profile_read.argtypes = [C.c_int32, P(C.c_double), P(C.c_int32)]
     L.gs_profile_disable.argtypes = []

@@ -15,7 +15,7 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 OUT_DIR = os.path.join(PKG, "_lib")
 LIB = os.path.join(OUT_DIR, "libgs.so")
-SOURCES = ["project.hip", "binsort.hip", "blend.hip", "raster.hip", "adam.hip", "ssim.hip", "track.hip", "api.hip"]
+SOURCES = ["project.hip", "binsort.hip", "blend.hip", "raster.hip", "adam.hip", "ssim.hip", "track.hip", "expand.hip", "api.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-fPIC", "-std=c++17", "-munsafe-fp-atomics",

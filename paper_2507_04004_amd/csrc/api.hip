@@ -1089,3 +1089,112 @@ int gs_pose_residual(const float pred_cw[12], const float refined_cw[12], double
 }
 
 }  // extern "C"
+
+// =============================================================================================
+// Map initialization and expansion.
+// =============================================================================================
+namespace {
+
+gs::ExpandArgs expand_args(const gs_points *pts, const gs_camera *cam, const float *opacity, float tau) {
+  gs::ExpandArgs a{};
+  a.xyz = pts->xyz;
+  a.rgb = pts->rgb;
+  a.n = pts->n;
+  for (int i = 0; i < 9; ++i) a.R[i] = cam->R_cw[i];
+  for (int i = 0; i < 3; ++i) a.t[i] = cam->t_cw[i];
+  a.fx = cam->fx;
+  a.fy = cam->fy;
+  a.cx = cam->cx;
+  a.cy = cam->cy;
+  a.x0 = cam->x0;
+  a.y0 = cam->y0;
+  a.w = cam->w;
+  a.h = cam->h;
+  a.opacity = opacity;
+  a.tau = tau;
+  return a;
+}
+
+int check_points(const gs_points *p) {
+  if (!p) return fail(GS_ERR_INVALID_ARG, "points are NULL");
+  if (p->n < 0 || p->n >= (int64_t(1) << 31)) return fail(GS_ERR_INVALID_ARG, "point count must be in [0, 2^31)");
+  if (p->n > 0 && !p->xyz) return fail(GS_ERR_INVALID_ARG, "xyz is NULL");
+  return GS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t gs_expand_scratch_bytes(int64_t n_points) {
+  if (n_points < 0) return 0;
+  return gs::expand_scratch_bytes(n_points);
+}
+
+int gs_expand_select(const gs_points *pts, const gs_camera *cam, const float *opacity, float tau, int64_t *count_out,
+                     void *scratch, size_t scratch_bytes, gs_stream_t stream) {
+  int rc;
+  if ((rc = check_points(pts)) || (rc = check_camera(cam))) return rc;
+  if (!std::isfinite(tau)) return fail(GS_ERR_INVALID_ARG, "tau is not finite");
+  if (!count_out) return fail(GS_ERR_INVALID_ARG, "count_out is NULL");
+  if (!scratch || scratch_bytes < gs::expand_scratch_bytes(pts->n))
+    return fail(GS_ERR_INVALID_ARG, "scratch must hold gs_expand_scratch_bytes bytes");
+  GS_TRY_HIP(gs::launch_expand_select(expand_args(pts, cam, opacity, tau), scratch, count_out, (hipStream_t)stream),
+             "expand select");
+  return GS_OK;
+}
+
+int gs_expand_write(const gs_points *pts, const gs_camera *cam, const gs_gaussians *old_map, int64_t added,
+                    const void *scratch, size_t scratch_bytes, const gs_gaussians_out *out, gs_stream_t stream) {
+  int rc;
+  if ((rc = check_points(pts)) || (rc = check_camera(cam))) return rc;
+  if (!out) return fail(GS_ERR_INVALID_ARG, "out is NULL");
+  if (added < 0 || added > pts->n) return fail(GS_ERR_INVALID_ARG, "added must be in [0, n_points]");
+  if (added > 0 && !pts->rgb) return fail(GS_ERR_INVALID_ARG, "rgb is NULL");
+  if (!scratch || scratch_bytes < gs::expand_scratch_bytes(pts->n))
+    return fail(GS_ERR_INVALID_ARG, "scratch must hold gs_expand_scratch_bytes bytes");
+  const int64_t n_old = old_map ? old_map->n : 0;
+  if (old_map && (rc = check_gaussians(old_map))) return rc;
+  if (out->sh_degree < 0 || out->sh_degree > 3) return fail(GS_ERR_INVALID_ARG, "out sh_degree must be 0..3");
+  if (old_map && old_map->sh_degree != out->sh_degree) return fail(GS_ERR_INVALID_ARG, "SH degrees differ");
+  if (out->n != n_old + added) return fail(GS_ERR_INVALID_ARG, "out->n must be old n + added");
+  if (out->n >= ((int64_t)1 << 30)) return fail(GS_ERR_INVALID_ARG, "grown map too large (at most 2^30 - 1)");
+  const int k_rest = 3 * ((out->sh_degree + 1) * (out->sh_degree + 1) - 1);
+  if (out->n > 0 && (!out->mean || !out->scale || !out->rot || !out->opacity || !out->sh_dc ||
+                     (k_rest > 0 && !out->sh_rest)))
+    return fail(GS_ERR_INVALID_ARG, "an output plane is NULL");
+  gs::ExpandOut o{};
+  o.n = out->n;
+  o.n_old = n_old;
+  o.added = added;
+  o.k_rest = k_rest;
+  o.mean = out->mean;
+  o.scale = out->scale;
+  o.rot = out->rot;
+  o.opacity = out->opacity;
+  o.sh_dc = out->sh_dc;
+  o.sh_rest = out->sh_rest;
+  gs::PlaneCopy pc{};
+  int np = 0;
+  if (n_old > 0) {
+    auto group = [&](const float *src, float *dst, int k) {
+      for (int i = 0; i < k; ++i) {
+        pc.src[np] = src;
+        pc.dst[np] = dst;
+        pc.plane[np] = i;
+        ++np;
+      }
+    };
+    group(old_map->mean, out->mean, 3);
+    group(old_map->scale, out->scale, 3);
+    group(old_map->rot, out->rot, 4);
+    group(old_map->opacity, out->opacity, 1);
+    group(old_map->sh_dc, out->sh_dc, 3);
+    if (k_rest > 0) group(old_map->sh_rest, out->sh_rest, k_rest);
+  }
+  GS_TRY_HIP(gs::launch_expand_write(expand_args(pts, cam, nullptr, 0.f), scratch, o, pc, np, (hipStream_t)stream),
+             "expand write");
+  return GS_OK;
+}
+
+}  // extern "C"

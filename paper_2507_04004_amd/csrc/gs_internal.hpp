@@ -84,6 +84,33 @@ struct TrackStepArgs {
   double beta1, beta2, eps, bias1, bias2;  // bias = 1 - beta^k
   int32_t k;
 };
+// Map initialization / expansion.
+struct ExpandArgs {
+  const float *xyz, *rgb;  // [3][n]
+  int64_t n;
+  float R[9], t[3];
+  float fx, fy, cx, cy;
+  int32_t x0, y0, w, h;
+  const float *opacity;  // window plane, or null (initialization: no mask)
+  float tau;
+};
+struct ExpandOut {
+  int64_t n, n_old, added;
+  int32_t k_rest;
+  float *mean, *scale, *rot, *opacity, *sh_dc, *sh_rest;
+};
+constexpr int kMaxPlanes = 59;  // 3 + 3 + 4 + 1 + 3 + 45
+struct PlaneCopy {
+  const float *src[kMaxPlanes];
+  float *dst[kMaxPlanes];
+  int64_t plane[kMaxPlanes];  // plane index within its group
+};
+int64_t expand_blocks(int64_t n);
+size_t expand_scratch_bytes(int64_t n);
+hipError_t launch_expand_select(const ExpandArgs &a, void *scratch, int64_t *total, hipStream_t st);
+hipError_t launch_expand_write(const ExpandArgs &a, const void *scratch, const ExpandOut &o, const PlaneCopy &pc,
+                               int n_planes, hipStream_t st);
+
 constexpr int kTrackTraceStride = 20;  // pose (12), gradient (6), L1 term, D-SSIM term
 hipError_t launch_track_init(TrackState *s, const TrackPose &p0, hipStream_t st);
 hipError_t launch_track_step(TrackState *s, const TrackStepArgs &a, const int64_t *num_pairs, float *trace,

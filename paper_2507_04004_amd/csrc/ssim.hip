@@ -29,27 +29,76 @@ struct SsimWeights {
   float w[2 * kSsimR + 1];
 };
 
-// Zero-padded loads of one channel's tile and halo into LDS.
-__device__ __forceinline__ void load_halo(const float *__restrict__ src, int h, int w, int x0, int y0, float *dst) {
-  for (int k = threadIdx.x; k < kSsimW * kSsimH; k += 256) {
+// Tile of this workgroup. Workgroups are dealt to the 8 XCDs round-robin by launch index;
+// the remap gives each XCD one contiguous run of tiles (whole rows of tiles), so the halo a
+// tile shares with its neighbours is read once into that XCD's L2 instead of into several.
+// The grid is rounded up to a multiple of 8; indices past the last tile return.
+constexpr int kSsimXcds = 8;
+struct SsimTile {
+  int tx, ty, c;
+  int64_t id;
+};
+__device__ __forceinline__ bool ssim_tile(int nbx, int nby, int nbc, SsimTile &t) {
+  const int64_t total = (int64_t)nbx * nby * nbc;
+  const int64_t per = (total + kSsimXcds - 1) / kSsimXcds;
+  const int64_t b = blockIdx.x;
+  t.id = (b % kSsimXcds) * per + b / kSsimXcds;
+  if (t.id >= total) return false;
+  t.c = (int)(t.id / ((int64_t)nbx * nby));
+  const int64_t r = t.id - (int64_t)t.c * nbx * nby;
+  t.ty = (int)(r / nbx);
+  t.tx = (int)(r - (int64_t)t.ty * nbx);
+  return true;
+}
+
+// Zero-padded loads of a tile and its halo from M planes into LDS. Every load of the
+// workgroup is issued before the first LDS store, so the wait is one memory latency.
+constexpr int kHaloElems = kSsimW * kSsimH;
+constexpr int kHaloIters = (kHaloElems + 255) / 256;
+template <int M>
+__device__ __forceinline__ void load_halo(const float *const (&src)[M], int h, int w, int x0, int y0,
+                                          float *const (&dst)[M]) {
+  float v[M][kHaloIters];
+  int64_t off[kHaloIters];
+  bool ok[kHaloIters];
+#pragma unroll
+  for (int i = 0; i < kHaloIters; ++i) {
+    const int k = threadIdx.x + 256 * i;
     const int ly = k / kSsimW, lx = k - ly * kSsimW;
     const int gy = y0 + ly - kSsimR, gx = x0 + lx - kSsimR;
-    dst[k] = (gy >= 0 && gy < h && gx >= 0 && gx < w) ? src[(int64_t)gy * w + gx] : 0.f;
+    ok[i] = k < kHaloElems && gy >= 0 && gy < h && gx >= 0 && gx < w;
+    off[i] = ok[i] ? (int64_t)gy * w + gx : 0;
   }
+#pragma unroll
+  for (int m = 0; m < M; ++m)
+#pragma unroll
+    for (int i = 0; i < kHaloIters; ++i) v[m][i] = ok[i] ? src[m][off[i]] : 0.f;
+#pragma unroll
+  for (int m = 0; m < M; ++m)
+#pragma unroll
+    for (int i = 0; i < kHaloIters; ++i) {
+      const int k = threadIdx.x + 256 * i;
+      if (k < kHaloElems) dst[m][k] = v[m][i];
+    }
 }
 
 __global__ __launch_bounds__(256) void k_dssim_fwd(const float *__restrict__ x, const float *__restrict__ y, int h,
-                                                   int w, SsimWeights sw, float g, float *__restrict__ dmu,
-                                                   float *__restrict__ dxx, float *__restrict__ dxy,
-                                                   float *__restrict__ partial) {
+                                                   int w, int nbx, int nby, int nbc, SsimWeights sw, float g,
+                                                   float *__restrict__ dmu, float *__restrict__ dxx,
+                                                   float *__restrict__ dxy, float *__restrict__ partial) {
   __shared__ float sx[kSsimW * kSsimH], sy[kSsimW * kSsimH];
   __shared__ float hs[5][kSsimH * kSsimTX];
   __shared__ float red[4];
-  const int c = blockIdx.z;
+  SsimTile tile;
+  if (!ssim_tile(nbx, nby, nbc, tile)) return;  // whole workgroup, before any barrier
+  const int c = tile.c;
   const int64_t plane = (int64_t)h * w;
-  const int x0 = blockIdx.x * kSsimTX, y0 = blockIdx.y * kSsimTY;
-  load_halo(x + c * plane, h, w, x0, y0, sx);
-  load_halo(y + c * plane, h, w, x0, y0, sy);
+  const int x0 = tile.tx * kSsimTX, y0 = tile.ty * kSsimTY;
+  {
+    const float *const src[2] = {x + c * plane, y + c * plane};
+    float *const dst[2] = {sx, sy};
+    load_halo<2>(src, h, w, x0, y0, dst);
+  }
   __syncthreads();
   // rows: every halo row, the tile's columns
   for (int k = threadIdx.x; k < kSsimH * kSsimTX; k += 256) {
@@ -97,8 +146,7 @@ __global__ __launch_bounds__(256) void k_dssim_fwd(const float *__restrict__ x, 
   for (int off = 32; off > 0; off >>= 1) part += __shfl_xor(part, off);
   if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = part;
   __syncthreads();
-  if (threadIdx.x == 0)
-    partial[((int64_t)blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x] = (red[0] + red[1]) + (red[2] + red[3]);
+  if (threadIdx.x == 0) partial[tile.id] = (red[0] + red[1]) + (red[2] + red[3]);
 }
 
 // loss = weight + g * sum of the block partials (float64, fixed order): deterministic.
@@ -106,6 +154,7 @@ __global__ __launch_bounds__(256) void k_dssim_loss(const float *__restrict__ pa
                                                     double g, float *__restrict__ loss) {
   __shared__ double red[256];
   double s = 0.0;
+#pragma unroll 8
   for (int64_t b = threadIdx.x; b < nb; b += 256) s += (double)partial[b];
   red[threadIdx.x] = s;
   __syncthreads();
@@ -117,17 +166,21 @@ __global__ __launch_bounds__(256) void k_dssim_loss(const float *__restrict__ pa
 }
 
 __global__ __launch_bounds__(256) void k_dssim_bwd(const float *__restrict__ x, const float *__restrict__ y, int h,
-                                                   int w, SsimWeights sw, const float *__restrict__ dmu,
-                                                   const float *__restrict__ dxx, const float *__restrict__ dxy,
-                                                   float *__restrict__ dldc) {
+                                                   int w, int nbx, int nby, int nbc, SsimWeights sw,
+                                                   const float *__restrict__ dmu, const float *__restrict__ dxx,
+                                                   const float *__restrict__ dxy, float *__restrict__ dldc) {
   __shared__ float s0[kSsimW * kSsimH], s1[kSsimW * kSsimH], s2[kSsimW * kSsimH];
   __shared__ float hs[3][kSsimH * kSsimTX];
-  const int c = blockIdx.z;
+  SsimTile tile;
+  if (!ssim_tile(nbx, nby, nbc, tile)) return;
+  const int c = tile.c;
   const int64_t plane = (int64_t)h * w;
-  const int x0 = blockIdx.x * kSsimTX, y0 = blockIdx.y * kSsimTY;
-  load_halo(dmu + c * plane, h, w, x0, y0, s0);
-  load_halo(dxx + c * plane, h, w, x0, y0, s1);
-  load_halo(dxy + c * plane, h, w, x0, y0, s2);
+  const int x0 = tile.tx * kSsimTX, y0 = tile.ty * kSsimTY;
+  {
+    const float *const src[3] = {dmu + c * plane, dxx + c * plane, dxy + c * plane};
+    float *const dst[3] = {s0, s1, s2};
+    load_halo<3>(src, h, w, x0, y0, dst);
+  }
   __syncthreads();
   for (int k = threadIdx.x; k < kSsimH * kSsimTX; k += 256) {
     const int r = k / kSsimTX, col = k - r * kSsimTX;
@@ -198,11 +251,13 @@ hipError_t launch_dssim(const float *x, const float *y, int c, int h, int w, flo
   const double gd = -(double)weight / (double)n;
   const float g = (float)gd;
   float *dmu = scratch, *dxx = scratch + n, *dxy = scratch + 2 * n, *partial = scratch + 3 * n;
-  const dim3 grid((unsigned)((w + kSsimTX - 1) / kSsimTX), (unsigned)((h + kSsimTY - 1) / kSsimTY), (unsigned)c);
-  hipLaunchKernelGGL(k_dssim_fwd, grid, dim3(256), 0, st, x, y, h, w, sw, g, dmu, dxx, dxy, partial);
-  if (loss)
-    hipLaunchKernelGGL(k_dssim_loss, dim3(1), dim3(256), 0, st, partial, dssim_blocks(c, h, w), weight, gd, loss);
-  if (dldc) hipLaunchKernelGGL(k_dssim_bwd, grid, dim3(256), 0, st, x, y, h, w, sw, dmu, dxx, dxy, dldc);
+  const int nbx = (w + kSsimTX - 1) / kSsimTX, nby = (h + kSsimTY - 1) / kSsimTY;
+  const int64_t nb = dssim_blocks(c, h, w);
+  const dim3 grid((unsigned)((nb + kSsimXcds - 1) / kSsimXcds * kSsimXcds));
+  hipLaunchKernelGGL(k_dssim_fwd, grid, dim3(256), 0, st, x, y, h, w, nbx, nby, c, sw, g, dmu, dxx, dxy, partial);
+  if (loss) hipLaunchKernelGGL(k_dssim_loss, dim3(1), dim3(256), 0, st, partial, nb, weight, gd, loss);
+  if (dldc)
+    hipLaunchKernelGGL(k_dssim_bwd, grid, dim3(256), 0, st, x, y, h, w, nbx, nby, c, sw, dmu, dxx, dxy, dldc);
   return hipGetLastError();
 }
 
