@@ -15,8 +15,9 @@ no clearing pass.
 
 Besides the headline figure the line carries the roofline of the dominant kernel, the two
 small configurations, the batched 8-keyframe pass, the sparse Adam step over the reached
-Gaussians (`sparse_adam`), the photometric tracking loop on a 2M-Gaussian map (`tracking`),
-novel-view serving, and the float64 CPU oracle as a baseline.
+Gaussians (`sparse_adam`), map expansion at the headline keyframe (`expansion`), the
+photometric tracking loop on a 2M-Gaussian map (`tracking`), novel-view serving, and the
+float64 CPU oracle as a baseline.
 
 Prints ONE JSON line. `value` is fwd+bwd views/s on one GPU.
 """
@@ -97,6 +98,7 @@ def parse():
     ap.add_argument("--no-serving", action="store_true", help="skip the serving measurement")
     ap.add_argument("--no-adam", action="store_true", help="skip the sparse Adam measurement")
     ap.add_argument("--no-tracking", action="store_true", help="skip the photometric tracking measurement")
+    ap.add_argument("--no-expansion", action="store_true", help="skip the map expansion measurement")
     ap.add_argument("--tracking-only", action="store_true",
                     help="run only the photometric tracking measurement (for profiling it alone)")
     ap.add_argument("--tracking-frames", type=int, default=10)
@@ -412,6 +414,73 @@ def measure_tracking(R, torch, S, tile, bd, dev, n=2_000_000, frames=10):
     return out
 
 
+def measure_expansion(R, N, torch, S, ps, dev, n_pts=1_000_000, reps=10):
+    """Map expansion at the headline keyframe: 1M colourised points (the means of a second street
+    map, seeded, with random colours) tested against the rendered opacity of the headline view
+    (O < 0.99), and the 1M-Gaussian map grown by the selected points. Algorithmic bytes: the
+    selection reads 12 B of position per point and 4 B of opacity per point inside the window;
+    the write copies the existing map (236 B per Gaussian, read and written) and writes 236 B per
+    new Gaussian from 24 B of point data."""
+    import numpy as np
+    gp = S.street_map(n_pts, seed=11)
+    rng = np.random.default_rng(12)
+    xyz = torch.from_numpy(np.ascontiguousarray(gp.mean, np.float32)).to(dev)
+    rgb = torch.from_numpy(rng.uniform(0, 1, (3, n_pts)).astype(np.float32)).to(dev)
+    del gp
+    pts = N.Points(n_pts, R._p(xyz), R._p(rgb))
+    scratch = torch.empty(N.lib().gs_expand_scratch_bytes(n_pts), dtype=torch.uint8, device=dev)
+    count = torch.zeros(1, dtype=torch.int64, device=dev)
+    alpha = ps.frame.alpha
+    st = R._stream()
+
+    def select():
+        N.check(N.lib().gs_expand_select(C.byref(pts), C.byref(ps.cs), R._p(alpha), 0.99, R._p(count),
+                                         R._p(scratch), scratch.numel(), st), "gs_expand_select")
+    select()
+    added = int(count.item())
+    gm = ps.gm
+    m = gm.n + added
+    e = lambda *shape: torch.empty(*shape, dtype=torch.float32, device=dev)
+    new = R.GaussianMap(e(3, m), e(3, m), e(4, m), e(m), e(3, m), e(45, m), 3)
+    out = N.GaussiansOut(m, 3, R._p(new.mean), R._p(new.scale), R._p(new.rot), R._p(new.opacity), R._p(new.sh_dc),
+                         R._p(new.sh_rest))
+    old = gm.struct()
+
+    def write():
+        N.check(N.lib().gs_expand_write(C.byref(pts), C.byref(ps.cs), C.byref(old), added, R._p(scratch),
+                                        scratch.numel(), C.byref(out), st), "gs_expand_write")
+
+    def timed_ms(fn):
+        fn()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps
+    t_sel, t_wr = timed_ms(select), timed_ms(write)
+    # points whose pixel falls inside the window (the opacity gathers), counted on the host
+    Rm = np.asarray(ps.cs.R_cw[:], np.float64).reshape(3, 3)
+    pc = Rm @ xyz.double().cpu().numpy() + np.asarray(ps.cs.t_cw[:], np.float64)[:, None]
+    with np.errstate(divide="ignore", invalid="ignore"):
+        u = ps.cs.fx * pc[0] / pc[2] + ps.cs.cx
+        v = ps.cs.fy * pc[1] / pc[2] + ps.cs.cy
+    inwin = int(((pc[2] > 0.2) & (u > -0.5) & (u < ps.cs.w - 0.5) & (v > -0.5) & (v < ps.cs.h - 0.5)).sum())
+    b_sel = 12 * n_pts + 4 * inwin
+    b_wr = 2 * 236 * gm.n + (236 + 24) * added
+    res = {"points": n_pts, "in_window": inwin, "added": added, "map_before": gm.n,
+           "select": {"ms": round(t_sel, 4), "GB/s": round(b_sel / (t_sel * 1e-3) / 1e9, 1),
+                      "frac_hbm": round(b_sel / (t_sel * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                      "points_s": round(n_pts / (t_sel * 1e-3), 0)},
+           "write": {"ms": round(t_wr, 4), "GB/s": round(b_wr / (t_wr * 1e-3) / 1e9, 1),
+                     "frac_hbm": round(b_wr / (t_wr * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}}
+    del new, xyz, rgb, scratch
+    torch.cuda.empty_cache()
+    return res
+
+
 def cpu_baseline(g, cam, gC_np, repeats):
     """The FP64 oracle (as it stands) on the host: one full-view fwd + bwd of the same workload."""
     import numpy as np
@@ -618,6 +687,10 @@ def main():
         log("[bench] sparse Adam")
         out["sparse_adam"] = measure_sparse_adam(R, torch, S, ps, args.tile, dev)
         log(f"[bench] sparse Adam {out['sparse_adam']}")
+    if not args.no_expansion:
+        log("[bench] map expansion")
+        out["expansion"] = measure_expansion(R, N, torch, S, ps, dev)
+        log(f"[bench] expansion {out['expansion']}")
     if not args.no_tracking:
         log("[bench] photometric tracking")
         out["tracking"] = measure_tracking(R, torch, S, args.tile, args.blend_depth, dev, frames=args.tracking_frames)

@@ -102,23 +102,27 @@ __global__ __launch_bounds__(1024) void k_expand_scan(const uint32_t *__restrict
 __global__ __launch_bounds__(kExpThreads) void k_expand_write(ExpandArgs a, const uint64_t *__restrict__ masks,
                                                                const uint32_t *__restrict__ offsets,
                                                                ExpandOut o) {
-  __shared__ uint32_t pre[kExpPer * kExpWaves];
+  constexpr int kMasks = kExpPer * kExpWaves;
+  __shared__ uint32_t pre[kMasks];
   const int64_t blk = blockIdx.x;
-  if (threadIdx.x == 0) {
-    uint32_t s = offsets[blk];
-    for (int k = 0; k < kExpPer * kExpWaves; ++k) {
-      pre[k] = s;
-      s += (uint32_t)__popcll(masks[blk * (kExpPer * kExpWaves) + k]);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  if (wave == 0) {  // exclusive scan of the 16 mask popcounts across lanes
+    const uint32_t c = lane < kMasks ? (uint32_t)__popcll(masks[blk * kMasks + lane]) : 0u;
+    uint32_t incl = c;
+#pragma unroll
+    for (int off = 1; off < kMasks; off <<= 1) {
+      const uint32_t t = __shfl_up(incl, off);
+      if (lane >= off) incl += t;
     }
+    if (lane < kMasks) pre[lane] = offsets[blk] + incl - c;
   }
   __syncthreads();
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const uint64_t below = lane ? (~0ull >> (64 - lane)) : 0ull;
   const int64_t N = o.n;
 #pragma unroll
   for (int j = 0; j < kExpPer; ++j) {
     const int k = j * kExpWaves + wave;
-    const uint64_t m = masks[blk * (kExpPer * kExpWaves) + k];
+    const uint64_t m = masks[blk * kMasks + k];
     if (!((m >> lane) & 1ull)) continue;
     const int64_t rank = (int64_t)pre[k] + __popcll(m & below);
     if (rank >= o.added) continue;
@@ -145,19 +149,20 @@ __global__ __launch_bounds__(kExpThreads) void k_expand_write(ExpandArgs a, cons
   }
 }
 
-// Copy of the existing planes into the grown map: plane p, elements [0, n_old).
+// Copy of the existing planes into the grown map: plane p, elements [0, n_old). Each
+// workgroup moves 1024 consecutive elements, every load and store a contiguous wavefront run
+// (the plane strides differ, so the runs are not 16-byte aligned in general).
 __global__ __launch_bounds__(256) void k_copy_planes(PlaneCopy pc, int64_t n_old, int64_t n_new) {
   const int p = blockIdx.y;
-  const float *src = pc.src[p];
-  float *dst = pc.dst[p];
-  const int64_t plane = pc.plane[p];
-  const int64_t i0 = ((int64_t)blockIdx.x * 256 + threadIdx.x) * 4;
+  const float *src = pc.src[p] + pc.plane[p] * n_old;
+  float *dst = pc.dst[p] + pc.plane[p] * n_new;
+  const int64_t i0 = (int64_t)blockIdx.x * 1024 + threadIdx.x;
   float v[4];
 #pragma unroll
-  for (int k = 0; k < 4; ++k) v[k] = i0 + k < n_old ? src[plane * n_old + i0 + k] : 0.f;
+  for (int k = 0; k < 4; ++k) v[k] = i0 + 256 * k < n_old ? src[i0 + 256 * k] : 0.f;
 #pragma unroll
   for (int k = 0; k < 4; ++k)
-    if (i0 + k < n_old) dst[plane * n_new + i0 + k] = v[k];
+    if (i0 + 256 * k < n_old) dst[i0 + 256 * k] = v[k];
 }
 
 int64_t expand_blocks(int64_t n) { return (n + kExpBlockPts - 1) / kExpBlockPts; }
