@@ -1174,24 +1174,29 @@ int gs_expand_write(const gs_points *pts, const gs_camera *cam, const gs_gaussia
   o.opacity = out->opacity;
   o.sh_dc = out->sh_dc;
   o.sh_rest = out->sh_rest;
+  // every plane of the grown map: the existing part copied (when there is one), the new
+  // part of the constant planes filled with its initial value
   gs::PlaneCopy pc{};
   int np = 0;
-  if (n_old > 0) {
-    auto group = [&](const float *src, float *dst, int k) {
-      for (int i = 0; i < k; ++i) {
-        pc.src[np] = src;
-        pc.dst[np] = dst;
-        pc.plane[np] = i;
-        ++np;
-      }
-    };
-    group(old_map->mean, out->mean, 3);
-    group(old_map->scale, out->scale, 3);
-    group(old_map->rot, out->rot, 4);
-    group(old_map->opacity, out->opacity, 1);
-    group(old_map->sh_dc, out->sh_dc, 3);
-    if (k_rest > 0) group(old_map->sh_rest, out->sh_rest, k_rest);
-  }
+  const bool has_old = n_old > 0;
+  auto group = [&](const float *src, float *dst, int k, bool constant, const float *fill) {
+    for (int i = 0; i < k; ++i) {
+      pc.src[np] = has_old ? src : nullptr;
+      pc.dst[np] = dst;
+      pc.plane[np] = i;
+      pc.constant[np] = constant ? 1 : 0;
+      pc.fill[np] = constant ? fill[i] : 0.f;
+      ++np;
+    }
+  };
+  const float rot0[4] = {1.f, 0.f, 0.f, 0.f}, opa0[1] = {0.1f}, zero[1] = {0.f};
+  static const float zeros[45] = {};
+  group(has_old ? old_map->mean : nullptr, out->mean, 3, false, zero);
+  group(has_old ? old_map->scale : nullptr, out->scale, 3, false, zero);
+  group(has_old ? old_map->rot : nullptr, out->rot, 4, true, rot0);
+  group(has_old ? old_map->opacity : nullptr, out->opacity, 1, true, opa0);
+  group(has_old ? old_map->sh_dc : nullptr, out->sh_dc, 3, false, zero);
+  if (k_rest > 0) group(has_old ? old_map->sh_rest : nullptr, out->sh_rest, k_rest, true, zeros);
   GS_TRY_HIP(gs::launch_expand_write(expand_args(pts, cam, nullptr, 0.f), scratch, o, pc, np, (hipStream_t)stream),
              "expand write");
   return GS_OK;

@@ -9,8 +9,10 @@
 // order, and stores the wavefront ballots of its decisions (a bitmask, 1 bit per point) and
 // its count. A single-workgroup scan turns the counts into output offsets and the total.
 // Writing (second pass, after the caller has sized the grown map): each selected point's
-// position is its workgroup offset plus the popcount of the mask bits before it. The existing
-// Gaussians are copied plane by plane into the grown map, whose planes have a larger stride.
+// position is its workgroup offset plus the popcount of the mask bits before it; it writes the
+// per-point planes (mean, scale, DC). The existing Gaussians are copied plane by plane into the
+// grown map, whose planes have a larger stride, by the same kernel that fills the new range of
+// the constant planes (rotation, opacity, higher SH).
 #include <algorithm>
 #include <cmath>
 
@@ -140,29 +142,31 @@ __global__ __launch_bounds__(kExpThreads) void k_expand_write(ExpandArgs a, cons
       o.scale[c * N + d] = s;
       o.sh_dc[c * N + d] = (a.rgb[c * a.n + i] - 0.5f) / kY0;
     }
-    o.rot[d] = 1.f;
-    o.rot[N + d] = 0.f;
-    o.rot[2 * N + d] = 0.f;
-    o.rot[3 * N + d] = 0.f;
-    o.opacity[d] = 0.1f;
-    for (int r = 0; r < o.k_rest; ++r) o.sh_rest[r * N + d] = 0.f;
+    // rotation, opacity and higher SH are constant planes, filled by k_copy_planes
   }
 }
 
-// Copy of the existing planes into the grown map: plane p, elements [0, n_old). Each
-// workgroup moves 1024 consecutive elements, every load and store a contiguous wavefront run
-// (the plane strides differ, so the runs are not 16-byte aligned in general).
+// Plane p of the grown map: elements [0, n_old) copied from the existing map, and on the
+// constant planes (rotation, opacity, higher SH) the new elements [n_old, n_new) set to the
+// initial value. Each workgroup moves 1024 consecutive elements, every load and store a
+// contiguous wavefront run (the plane strides differ, so the runs are not 16-byte aligned in
+// general); writing the constant planes here keeps those stores full-width.
 __global__ __launch_bounds__(256) void k_copy_planes(PlaneCopy pc, int64_t n_old, int64_t n_new) {
   const int p = blockIdx.y;
-  const float *src = pc.src[p] + pc.plane[p] * n_old;
+  const float *src = pc.src[p] ? pc.src[p] + pc.plane[p] * n_old : nullptr;
   float *dst = pc.dst[p] + pc.plane[p] * n_new;
+  const int64_t end = pc.constant[p] ? n_new : n_old;
+  const float fill = pc.fill[p];
   const int64_t i0 = (int64_t)blockIdx.x * 1024 + threadIdx.x;
   float v[4];
 #pragma unroll
-  for (int k = 0; k < 4; ++k) v[k] = i0 + 256 * k < n_old ? src[i0 + 256 * k] : 0.f;
+  for (int k = 0; k < 4; ++k) {
+    const int64_t i = i0 + 256 * k;
+    v[k] = i < n_old ? src[i] : fill;
+  }
 #pragma unroll
   for (int k = 0; k < 4; ++k)
-    if (i0 + 256 * k < n_old) dst[i0 + 256 * k] = v[k];
+    if (i0 + 256 * k < end) dst[i0 + 256 * k] = v[k];
 }
 
 int64_t expand_blocks(int64_t n) { return (n + kExpBlockPts - 1) / kExpBlockPts; }
@@ -194,8 +198,8 @@ hipError_t launch_expand_write(const ExpandArgs &a, const void *scratch, const E
   uint64_t *masks;
   uint32_t *counts, *offsets;
   carve(const_cast<void *>(scratch), a.n, masks, counts, offsets);
-  if (o.n_old > 0 && n_planes > 0) {
-    const dim3 grid((unsigned)((o.n_old + 1023) / 1024), (unsigned)n_planes);
+  if (o.n > 0 && n_planes > 0) {
+    const dim3 grid((unsigned)((o.n + 1023) / 1024), (unsigned)n_planes);
     hipLaunchKernelGGL(k_copy_planes, grid, dim3(256), 0, st, pc, o.n_old, o.n);
   }
   const int64_t nb = expand_blocks(a.n);

@@ -101,9 +101,11 @@ struct ExpandOut {
 };
 constexpr int kMaxPlanes = 59;  // 3 + 3 + 4 + 1 + 3 + 45
 struct PlaneCopy {
-  const float *src[kMaxPlanes];
+  const float *src[kMaxPlanes];  // null when there is no existing map
   float *dst[kMaxPlanes];
   int64_t plane[kMaxPlanes];  // plane index within its group
+  float fill[kMaxPlanes];     // value of the new Gaussians on a constant plane
+  int32_t constant[kMaxPlanes];
 };
 int64_t expand_blocks(int64_t n);
 size_t expand_scratch_bytes(int64_t n);
