@@ -6,6 +6,8 @@ Gaussian street map seen by the 1280x720 headline camera, 8x8 tiles, chunk lengt
 - compositing: colour, depth, opacity and transmittance at 600 seeded pixels equal the float64
   brute-force oracle (every Gaussian, no tiles) within 1e-4 where the oracle flags no marginal
   decision;
+- expansion: the benchmark's 1M keyframe points against the oracle's opacity of the view,
+  selection bit-exact and the grown map as in the small expansion tests;
 - backward: the gradient of a seeded linear functional of the image w.r.t. the pose, and
   w.r.t. the means / opacities of the Gaussians that reach a 160x120 window, equal the float64
   oracle on that window within 2e-3 relative.
@@ -85,3 +87,35 @@ def test_fullsize_window_gradients(headline):
     print(f"[fullsize] window gradients: pose {e_pose:.2e} mean {e_mean:.2e} opacity {e_opa:.2e} "
           f"({live.size} Gaussians)", flush=True)
     assert e_pose <= GRAD_RTOL and e_mean <= GRAD_RTOL and e_opa <= GRAD_RTOL
+
+
+def test_fullsize_expansion(headline):
+    """The benchmark's expansion workload: 1M keyframe points against the oracle's opacity of
+    the headline view (tau 0.99); selection bit-exact, values as in the small expansion tests."""
+    import torch
+    from oracle import expand as OE
+    from paper_2507_04004_amd import expand as X
+    from paper_2507_04004_amd import raster as R
+    g, cam = headline
+    print("[fullsize] oracle opacity of the headline view", flush=True)
+    O = oracle.render(g, cam, tile=TILE)["alpha"].astype(np.float32)
+    pts = S.street_map(1_000_000, seed=11).mean.astype(np.float32)
+    rgb = np.random.default_rng(12).uniform(0, 1, (3, pts.shape[1])).astype(np.float32)
+    gm = R.GaussianMap.from_numpy(g, "cuda:0")
+    new, added = X.expand_map(gm, torch.from_numpy(pts).to("cuda:0"), torch.from_numpy(rgb).to("cuda:0"), cam,
+                              torch.from_numpy(O).to("cuda:0"), 0.99, device="cuda:0")
+    torch.cuda.synchronize()
+    sel = OE.select(pts, cam, O, 0.99)
+    print(f"[fullsize] expansion: {added} added (oracle {int(sel.sum())}) of {pts.shape[1]}", flush=True)
+    assert added == int(sel.sum()) > 1000
+    ref = OE.new_gaussians(pts, rgb, cam, sel, 3)
+    n = g.n
+    for k in ("mean", "scale", "rot", "opacity", "sh_dc", "sh_rest"):
+        got = getattr(new, k).cpu().numpy().reshape(-1, n + added)
+        np.testing.assert_array_equal(got[:, :n], getattr(g, k).reshape(-1, n), err_msg=k)
+        tail = got[:, n:].astype(np.float64)
+        if k in ("scale", "sh_dc"):
+            np.testing.assert_allclose(tail, ref[k].reshape(tail.shape), rtol=1e-6, atol=1e-6, err_msg=k)
+        else:
+            np.testing.assert_array_equal(tail, np.float32(ref[k]).reshape(tail.shape).astype(np.float64),
+                                          err_msg=k)

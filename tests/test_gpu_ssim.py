@@ -1,6 +1,6 @@
 """D-SSIM term (needs an MI355X): gs_loss_dssim against the float64 oracle, for ragged tile
-edges, images smaller than the window, one channel and a 640x360 colour image; the gradient
-is accumulated onto what dL_dC held.
+edges, images smaller than the window, one channel, and 640x360 and 1280x720 colour images (the
+tracking loop's size); the gradient is accumulated onto what dL_dC held.
 
 Tolerances from the arithmetic: every filtered statistic is a float32 sum of 121 weighted terms
 (relative error ~1e-6 of the largest term), and the derivative maps subtract such ratios, so
@@ -28,7 +28,7 @@ def _pair(c, h, w, seed):
     return x.astype(np.float32), y.astype(np.float32)
 
 
-@pytest.mark.parametrize("shape", [(3, 50, 77), (1, 7, 5), (3, 16, 32), (2, 33, 129), (3, 360, 640)])
+@pytest.mark.parametrize("shape", [(3, 50, 77), (1, 7, 5), (3, 16, 32), (2, 33, 129), (3, 360, 640), (3, 720, 1280)])
 def test_dssim_matches_oracle(shape):
     c, h, w = shape
     print(f"[dssim] shape={shape}", flush=True)
