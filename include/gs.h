@@ -252,7 +252,7 @@ void gs_profile_disable(void);
  * color, target [channels][h][w] fp32 device planes. dL_dC (may be NULL) is ACCUMULATED (+=)
  * with d loss / d color, so it composes with gs_loss_l1, which overwrites it. loss_out [1]
  * (may be NULL) is overwritten, summed in a fixed order (deterministic). scratch: device, at
- * least gs_dssim_scratch_bytes (3 floats per value and one per 32x16 tile of each channel). Errors: GS_ERR_INVALID_ARG for negative sizes, more than 64 channels, h or w above
+ * least gs_dssim_scratch_bytes (3 floats per value and one per 32x32 tile of each channel). Errors: GS_ERR_INVALID_ARG for negative sizes, more than 64 channels, h or w above
  * 32768 or 2^31 values, NULL images with
  * a non-empty size, a non-finite weight or short scratch. */
 size_t gs_dssim_scratch_bytes(int32_t channels, int32_t h, int32_t w);

@@ -5,7 +5,8 @@
 //   S = A B / (C D),  A = 2 mu_x mu_y + C1,  B = 2 s_xy + C2,  C = mu_x^2 + mu_y^2 + C1,
 //   D = s_x^2 + s_y^2 + C2,  with mu = G*x, s_x^2 = G*x^2 - mu_x^2, s_xy = G*(x y) - mu_x mu_y.
 // The window is separable (efficient SSIM, Sec. "Additional Strategies", c): each workgroup
-// stages a 32x16 tile of one channel plus a 5-pixel halo in LDS and filters rows, then columns.
+// stages a 32x32 tile of one channel plus a 5-pixel halo in LDS and filters rows, then columns;
+// in both passes a lane computes 4 consecutive outputs from 14 inputs held in registers.
 //
 // Forward: the five filtered maps give S; with g = -weight / (c h w) the kernel writes, per
 // pixel, the derivatives of g S w.r.t. the three maps that depend on x:
@@ -20,9 +21,13 @@
 
 namespace gs {
 
-constexpr int kSsimR = 5;               // window radius
-constexpr int kSsimTX = 32, kSsimTY = 16;  // output tile
-constexpr int kSsimW = kSsimTX + 2 * kSsimR, kSsimH = kSsimTY + 2 * kSsimR;
+constexpr int kSsimR = 5;                  // window radius
+constexpr int kSsimTX = 32, kSsimTY = 32;  // output tile
+constexpr int kSsimW = kSsimTX + 2 * kSsimR, kSsimH = kSsimTY + 2 * kSsimR;  // tile + halo (42 x 42)
+constexpr int kSsimLW = 44;               // LDS row stride of the halo tile (16-byte rows)
+constexpr int kSeg = 4;                   // outputs per lane and pass (register sliding)
+constexpr int kSegIn = kSeg + 2 * kSsimR; // 14 inputs per segment
+constexpr int kRowJobs = kSsimH * (kSsimTX / kSeg);  // 42 rows x 8 segments
 constexpr float kC1 = 0.01f * 0.01f, kC2 = 0.03f * 0.03f;
 
 struct SsimWeights {
@@ -51,8 +56,9 @@ __device__ __forceinline__ bool ssim_tile(int nbx, int nby, int nbc, SsimTile &t
   return true;
 }
 
-// Zero-padded loads of a tile and its halo from M planes into LDS. Every load of the
-// workgroup is issued before the first LDS store, so the wait is one memory latency.
+// Zero-padded loads of a tile and its halo from M planes into LDS (rows of kSsimLW floats).
+// Every load of the workgroup is issued before the first LDS store, so the wait is one
+// memory latency.
 constexpr int kHaloElems = kSsimW * kSsimH;
 constexpr int kHaloIters = (kHaloElems + 255) / 256;
 template <int M>
@@ -61,6 +67,7 @@ __device__ __forceinline__ void load_halo(const float *const (&src)[M], int h, i
   float v[M][kHaloIters];
   int64_t off[kHaloIters];
   bool ok[kHaloIters];
+  int lo[kHaloIters];
 #pragma unroll
   for (int i = 0; i < kHaloIters; ++i) {
     const int k = threadIdx.x + 256 * i;
@@ -68,6 +75,7 @@ __device__ __forceinline__ void load_halo(const float *const (&src)[M], int h, i
     const int gy = y0 + ly - kSsimR, gx = x0 + lx - kSsimR;
     ok[i] = k < kHaloElems && gy >= 0 && gy < h && gx >= 0 && gx < w;
     off[i] = ok[i] ? (int64_t)gy * w + gx : 0;
+    lo[i] = ly * kSsimLW + lx;
   }
 #pragma unroll
   for (int m = 0; m < M; ++m)
@@ -76,18 +84,25 @@ __device__ __forceinline__ void load_halo(const float *const (&src)[M], int h, i
 #pragma unroll
   for (int m = 0; m < M; ++m)
 #pragma unroll
-    for (int i = 0; i < kHaloIters; ++i) {
-      const int k = threadIdx.x + 256 * i;
-      if (k < kHaloElems) dst[m][k] = v[m][i];
-    }
+    for (int i = 0; i < kHaloIters; ++i)
+      if (threadIdx.x + 256 * i < kHaloElems) dst[m][lo[i]] = v[m][i];
+}
+
+// The 14 inputs of a row segment (16-byte LDS reads; the last two values are unused).
+__device__ __forceinline__ void row_inputs(const float *row, float (&u)[16]) {
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const float4 f = reinterpret_cast<const float4 *>(row)[q];
+    u[4 * q] = f.x; u[4 * q + 1] = f.y; u[4 * q + 2] = f.z; u[4 * q + 3] = f.w;
+  }
 }
 
 __global__ __launch_bounds__(256) void k_dssim_fwd(const float *__restrict__ x, const float *__restrict__ y, int h,
                                                    int w, int nbx, int nby, int nbc, SsimWeights sw, float g,
                                                    float *__restrict__ dmu, float *__restrict__ dxx,
                                                    float *__restrict__ dxy, float *__restrict__ partial) {
-  __shared__ float sx[kSsimW * kSsimH], sy[kSsimW * kSsimH];
-  __shared__ float hs[5][kSsimH * kSsimTX];
+  __shared__ __align__(16) float sx[kSsimH * kSsimLW], sy[kSsimH * kSsimLW];
+  __shared__ __align__(16) float hs[5][kSsimH * kSsimTX];
   __shared__ float red[4];
   SsimTile tile;
   if (!ssim_tile(nbx, nby, nbc, tile)) return;  // whole workgroup, before any barrier
@@ -100,46 +115,73 @@ __global__ __launch_bounds__(256) void k_dssim_fwd(const float *__restrict__ x, 
     load_halo<2>(src, h, w, x0, y0, dst);
   }
   __syncthreads();
-  // rows: every halo row, the tile's columns
-  for (int k = threadIdx.x; k < kSsimH * kSsimTX; k += 256) {
-    const int r = k / kSsimTX, col = k - r * kSsimTX;
-    float a = 0.f, b = 0.f, aa = 0.f, bb = 0.f, ab = 0.f;
+  // rows: 4 consecutive outputs per lane from 14 staged inputs of each image
+  for (int j = threadIdx.x; j < kRowJobs; j += 256) {
+    const int r = j >> 3, seg = j & 7;
+    float u[16], v[16];
+    row_inputs(sx + r * kSsimLW + seg * kSeg, u);
+    row_inputs(sy + r * kSsimLW + seg * kSeg, v);
+    float uu[kSegIn], vv[kSegIn], uv[kSegIn];
 #pragma unroll
-    for (int t = 0; t <= 2 * kSsimR; ++t) {
-      const float u = sx[r * kSsimW + col + t], v = sy[r * kSsimW + col + t], wt = sw.w[t];
-      a += wt * u;
-      b += wt * v;
-      aa += wt * (u * u);
-      bb += wt * (v * v);
-      ab += wt * (u * v);
+    for (int i = 0; i < kSegIn; ++i) {
+      uu[i] = u[i] * u[i];
+      vv[i] = v[i] * v[i];
+      uv[i] = u[i] * v[i];
     }
-    hs[0][k] = a; hs[1][k] = b; hs[2][k] = aa; hs[3][k] = bb; hs[4][k] = ab;
+    float o[5][kSeg];
+#pragma unroll
+    for (int k = 0; k < kSeg; ++k) {
+      float a = 0.f, b = 0.f, aa = 0.f, bb = 0.f, ab = 0.f;
+#pragma unroll
+      for (int t = 0; t <= 2 * kSsimR; ++t) {
+        const float wt = sw.w[t];
+        a += wt * u[k + t];
+        b += wt * v[k + t];
+        aa += wt * uu[k + t];
+        bb += wt * vv[k + t];
+        ab += wt * uv[k + t];
+      }
+      o[0][k] = a; o[1][k] = b; o[2][k] = aa; o[3][k] = bb; o[4][k] = ab;
+    }
+#pragma unroll
+    for (int m = 0; m < 5; ++m)
+      reinterpret_cast<float4 *>(hs[m] + r * kSsimTX + seg * kSeg)[0] = make_float4(o[m][0], o[m][1], o[m][2], o[m][3]);
   }
   __syncthreads();
-  float part = 0.f;
-  for (int k = threadIdx.x; k < kSsimTY * kSsimTX; k += 256) {
-    const int r = k / kSsimTX, col = k - r * kSsimTX;
-    const int gy = y0 + r, gx = x0 + col;
-    if (gy >= h || gx >= w) continue;
-    float mx = 0.f, my = 0.f, exx = 0.f, eyy = 0.f, exy = 0.f;
+  // columns: lane (col, seg) slides down 4 outputs of one column
+  const int col = threadIdx.x & (kSsimTX - 1), seg = threadIdx.x >> 5;
+  float st[5][kSeg];
 #pragma unroll
-    for (int t = 0; t <= 2 * kSsimR; ++t) {
-      const int i = (r + t) * kSsimTX + col;
-      const float wt = sw.w[t];
-      mx += wt * hs[0][i];
-      my += wt * hs[1][i];
-      exx += wt * hs[2][i];
-      eyy += wt * hs[3][i];
-      exy += wt * hs[4][i];
+  for (int m = 0; m < 5; ++m) {
+    float in[kSegIn];
+#pragma unroll
+    for (int i = 0; i < kSegIn; ++i) in[i] = hs[m][(seg * kSeg + i) * kSsimTX + col];
+#pragma unroll
+    for (int k = 0; k < kSeg; ++k) {
+      float a = 0.f;
+#pragma unroll
+      for (int t = 0; t <= 2 * kSsimR; ++t) a += sw.w[t] * in[k + t];
+      st[m][k] = a;
     }
+  }
+  float part = 0.f;
+  const int gx = x0 + col;
+#pragma unroll
+  for (int k = 0; k < kSeg; ++k) {
+    const int gy = y0 + seg * kSeg + k;
+    if (gy >= h || gx >= w) continue;
+    const float mx = st[0][k], my = st[1][k], exx = st[2][k], eyy = st[3][k], exy = st[4][k];
     const float A = 2.f * mx * my + kC1, B = 2.f * (exy - mx * my) + kC2;
     const float Cc = mx * mx + my * my + kC1, D = (exx - mx * mx) + (eyy - my * my) + kC2;
-    const float S = (A * B) / (Cc * D);
+    // one division: with r = 1 / (C D), S = A B r, S/A = B r, S/B = A r, S/C = S D r, S/D = S C r
+    const float rr = 1.0f / (Cc * D);
+    const float S = A * B * rr;
+    const float sA = B * rr, sB = A * rr, sC = S * D * rr, sD = S * Cc * rr;
     part += S;
     const int64_t p = c * plane + (int64_t)gy * w + gx;
-    dmu[p] = g * (2.f * my * (S / A - S / B) + 2.f * mx * (S / D - S / Cc));
-    dxx[p] = -g * (S / D);
-    dxy[p] = 2.f * g * (S / B);
+    dmu[p] = g * (2.f * my * (sA - sB) + 2.f * mx * (sD - sC));
+    dxx[p] = -g * sD;
+    dxy[p] = 2.f * g * sB;
   }
   // the block's sum of S, reduced in a fixed order by k_dssim_loss
 #pragma unroll
@@ -169,8 +211,8 @@ __global__ __launch_bounds__(256) void k_dssim_bwd(const float *__restrict__ x, 
                                                    int w, int nbx, int nby, int nbc, SsimWeights sw,
                                                    const float *__restrict__ dmu, const float *__restrict__ dxx,
                                                    const float *__restrict__ dxy, float *__restrict__ dldc) {
-  __shared__ float s0[kSsimW * kSsimH], s1[kSsimW * kSsimH], s2[kSsimW * kSsimH];
-  __shared__ float hs[3][kSsimH * kSsimTX];
+  __shared__ __align__(16) float sm[3][kSsimH * kSsimLW];
+  __shared__ __align__(16) float hs[3][kSsimH * kSsimTX];
   SsimTile tile;
   if (!ssim_tile(nbx, nby, nbc, tile)) return;
   const int c = tile.c;
@@ -178,39 +220,50 @@ __global__ __launch_bounds__(256) void k_dssim_bwd(const float *__restrict__ x, 
   const int x0 = tile.tx * kSsimTX, y0 = tile.ty * kSsimTY;
   {
     const float *const src[3] = {dmu + c * plane, dxx + c * plane, dxy + c * plane};
-    float *const dst[3] = {s0, s1, s2};
+    float *const dst[3] = {sm[0], sm[1], sm[2]};
     load_halo<3>(src, h, w, x0, y0, dst);
   }
   __syncthreads();
-  for (int k = threadIdx.x; k < kSsimH * kSsimTX; k += 256) {
-    const int r = k / kSsimTX, col = k - r * kSsimTX;
-    float a = 0.f, b = 0.f, d = 0.f;
+  for (int j = threadIdx.x; j < kRowJobs; j += 256) {
+    const int r = j >> 3, seg = j & 7;
 #pragma unroll
-    for (int t = 0; t <= 2 * kSsimR; ++t) {
-      const int i = r * kSsimW + col + t;
-      const float wt = sw.w[t];
-      a += wt * s0[i];
-      b += wt * s1[i];
-      d += wt * s2[i];
+    for (int m = 0; m < 3; ++m) {
+      float u[16];
+      row_inputs(sm[m] + r * kSsimLW + seg * kSeg, u);
+      float o[kSeg];
+#pragma unroll
+      for (int k = 0; k < kSeg; ++k) {
+        float a = 0.f;
+#pragma unroll
+        for (int t = 0; t <= 2 * kSsimR; ++t) a += sw.w[t] * u[k + t];
+        o[k] = a;
+      }
+      reinterpret_cast<float4 *>(hs[m] + r * kSsimTX + seg * kSeg)[0] = make_float4(o[0], o[1], o[2], o[3]);
     }
-    hs[0][k] = a; hs[1][k] = b; hs[2][k] = d;
   }
   __syncthreads();
-  for (int k = threadIdx.x; k < kSsimTY * kSsimTX; k += 256) {
-    const int r = k / kSsimTX, col = k - r * kSsimTX;
-    const int gy = y0 + r, gx = x0 + col;
-    if (gy >= h || gx >= w) continue;
-    float P = 0.f, Q = 0.f, R = 0.f;
+  const int col = threadIdx.x & (kSsimTX - 1), seg = threadIdx.x >> 5;
+  float st[3][kSeg];
 #pragma unroll
-    for (int t = 0; t <= 2 * kSsimR; ++t) {
-      const int i = (r + t) * kSsimTX + col;
-      const float wt = sw.w[t];
-      P += wt * hs[0][i];
-      Q += wt * hs[1][i];
-      R += wt * hs[2][i];
+  for (int m = 0; m < 3; ++m) {
+    float in[kSegIn];
+#pragma unroll
+    for (int i = 0; i < kSegIn; ++i) in[i] = hs[m][(seg * kSeg + i) * kSsimTX + col];
+#pragma unroll
+    for (int k = 0; k < kSeg; ++k) {
+      float a = 0.f;
+#pragma unroll
+      for (int t = 0; t <= 2 * kSsimR; ++t) a += sw.w[t] * in[k + t];
+      st[m][k] = a;
     }
+  }
+  const int gx = x0 + col;
+#pragma unroll
+  for (int k = 0; k < kSeg; ++k) {
+    const int gy = y0 + seg * kSeg + k;
+    if (gy >= h || gx >= w) continue;
     const int64_t p = c * plane + (int64_t)gy * w + gx;
-    dldc[p] += P + 2.f * x[p] * Q + y[p] * R;
+    dldc[p] += st[0][k] + 2.f * x[p] * st[1][k] + y[p] * st[2][k];
   }
 }
 

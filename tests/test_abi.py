@@ -154,8 +154,8 @@ def test_dssim_argument_errors():
     L = N.lib()
     dummy = C.c_void_p(64)  # never dereferenced: validation fails first
     nb = L.gs_dssim_scratch_bytes(3, 20, 30)
-    # three maps per value, then one partial sum per 32x16 tile of each channel
-    assert nb == 3 * 4 * 3 * 20 * 30 + 4 * 3 * 1 * 2 and L.gs_dssim_scratch_bytes(-1, 2, 2) == 0
+    # three maps per value, then one partial sum per 32x32 tile of each channel
+    assert nb == 3 * 4 * 3 * 20 * 30 + 4 * 3 * 1 * 1 and L.gs_dssim_scratch_bytes(-1, 2, 2) == 0
 
     def call(c=3, h=20, w=30, color=dummy, target=dummy, weight=0.5, scratch=dummy, nbytes=nb):
         return L.gs_loss_dssim(color, target, c, h, w, weight, dummy, dummy, scratch, nbytes, None)
