@@ -92,7 +92,7 @@ def parse():
     ap.add_argument("--tile", type=int, default=8)
     ap.add_argument("--blend-depth", type=int, default=128)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-repeats", type=int, default=1)
+    ap.add_argument("--cpu-repeats", type=int, default=5, help="oracle views timed for the CPU baseline")
     ap.add_argument("--no-batched", action="store_true", help="skip the 8-keyframe batched measurement")
     ap.add_argument("--no-small", action="store_true", help="skip the two small single-view configurations")
     ap.add_argument("--no-serving", action="store_true", help="skip the serving measurement")
