@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -31,6 +32,32 @@ int hip_fail(hipError_t e, const char *where) {
   do {                                          \
     hipError_t e_ = (expr);                     \
     if (e_ != hipSuccess) return hip_fail(e_, where); \
+  } while (0)
+
+// The kernels are built for gfx950 only: the current device's architecture is checked once per
+// device before the first launch of an entry point (GS_ERR_UNSUPPORTED on any other).
+int check_device() {
+  constexpr int kMaxDevices = 64;
+  static std::atomic<int> state[kMaxDevices];  // 0 unknown, 1 gfx950, 2 other
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return hip_fail(e, "current device");
+  int s = (dev >= 0 && dev < kMaxDevices) ? state[dev].load(std::memory_order_relaxed) : 0;
+  if (s == 0) {
+    hipDeviceProp_t prop;
+    e = hipGetDeviceProperties(&prop, dev);
+    if (e != hipSuccess) return hip_fail(e, "device properties");
+    s = std::strncmp(prop.gcnArchName, "gfx950", 6) == 0 ? 1 : 2;
+    if (dev >= 0 && dev < kMaxDevices) state[dev].store(s, std::memory_order_relaxed);
+  }
+  if (s != 1) return fail(GS_ERR_UNSUPPORTED, "device %d is not gfx950 (the only target this library is built for)", dev);
+  return GS_OK;
+}
+
+#define GS_CHECK_DEVICE()            \
+  do {                               \
+    const int rc_ = check_device();  \
+    if (rc_ != GS_OK) return rc_;    \
   } while (0)
 
 inline int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
@@ -329,6 +356,7 @@ int gs_preprocess(const gs_gaussians *g, const gs_camera *cam, int32_t tile_w, i
   gs::ViewTable vt;
   if ((rc = make_table(cam, 1, g->n, g->sh_degree, tile_w, tile_h, vt))) return rc;
   gs::profile_begin(GS_STAGE_PREPROCESS, (hipStream_t)stream);
+  GS_CHECK_DEVICE();
   GS_TRY_HIP(gs::launch_preprocess(vt, *g, *out, (hipStream_t)stream), "preprocess");
   gs::profile_end(GS_STAGE_PREPROCESS, (hipStream_t)stream);
   return GS_OK;
@@ -348,6 +376,7 @@ int gs_bin_sort(const gs_projected *proj, int64_t n, const gs_camera *cam, gs_bi
     return fail(GS_ERR_INVALID_ARG, "bins scratch too small: %zu < %zu", io->scratch_bytes,
                 gs::bin_scratch_bytes(n, io->capacity));
   gs::profile_begin(GS_STAGE_BIN_SORT, (hipStream_t)stream);
+  GS_CHECK_DEVICE();
   GS_TRY_HIP(gs::launch_bin_sort(vt, *proj, n, io->capacity, io->vals, io->tile_range, io->num_pairs, io->scratch,
                                  (hipStream_t)stream),
              "bin/sort");
@@ -371,6 +400,7 @@ int gs_render_fwd(const gs_projected *proj, int64_t n, const gs_bins *bins, cons
   it.v[0] = {out->color, out->depth, out->alpha, out->t_final, out->last, out->n_contrib};
   hipStream_t st = (hipStream_t)stream;
   gs::profile_begin(GS_STAGE_BLEND_FWD, st);
+  GS_CHECK_DEVICE();
   GS_TRY_HIP(gs::launch_blend_fwd(blend_depth, vt, it, *proj, bins->vals, bins->tile_range, out->state,
                                   bins->capacity, st),
              "blend forward");
@@ -413,6 +443,7 @@ int gs_render_bwd(const gs_gaussians *g, const gs_camera *cam, const gs_projecte
   if (lidar) io.lidar = *lidar;
   io.pose = out->pose;
   GradScratch s = carve_grads(out->scratch, g->n, 1, npx);
+  GS_CHECK_DEVICE();
   return enqueue_backward(vt, *g, *proj, bins->vals, bins->tile_range, fwd->state, bins->capacity, &io, blend_depth,
                           *out, s, (hipStream_t)stream);
 }
@@ -472,6 +503,7 @@ int gs_loss_dssim(const float *color, const float *target, int32_t channels, int
   if (!std::isfinite(weight)) return fail(GS_ERR_INVALID_ARG, "weight is not finite");
   if (n > 0 && (!scratch || scratch_bytes < gs::dssim_scratch_bytes(channels, h, w)))
     return fail(GS_ERR_INVALID_ARG, "scratch must hold gs_dssim_scratch_bytes bytes");
+  GS_CHECK_DEVICE();
   GS_TRY_HIP(gs::launch_dssim(color, target, channels, h, w, weight, dL_dC, loss_out, (float *)scratch,
                               (hipStream_t)stream),
              "d-ssim");
@@ -511,6 +543,8 @@ int gs_adam_sparse(const gs_adam *a, gs_stream_t stream) {
                                   G.act == GS_ACT_NONE ? nullptr : G.act_out, G.k, G.act,
                                   (float)((double)G.lr / (double)a->bias1)};
   }
+  if (a->n == 0 || a->n_groups == 0) return GS_OK;  // nothing to launch
+  GS_CHECK_DEVICE();
   GS_TRY_HIP(gs::launch_adam_sparse(d, (hipStream_t)stream), "sparse adam");
   return GS_OK;
 }
@@ -520,6 +554,7 @@ int gs_loss_l1(const float *color, const float *target, int64_t n_values, float 
   if (n_values < 0) return fail(GS_ERR_INVALID_ARG, "n_values < 0");
   if (n_values > 0 && (!color || !target)) return fail(GS_ERR_INVALID_ARG, "color / target is NULL");
   if (!std::isfinite(weight)) return fail(GS_ERR_INVALID_ARG, "weight is not finite");
+  GS_CHECK_DEVICE();
   GS_TRY_HIP(gs::launch_loss_l1(color, target, n_values, weight, dL_dC, loss_out, (hipStream_t)stream), "l1 loss");
   return GS_OK;
 }
@@ -676,6 +711,7 @@ int gs_batch_plan_create(gs_batch_plan **out, int64_t n, int32_t sh_degree, int3
   if (!depth_ok(blend_depth)) return fail(GS_ERR_INVALID_ARG, "blend_depth must be 64, 128 or 256");
   if (max_total_pixels <= 0 || capacity <= 0 || capacity > 0xFFFFFFFFll)
     return fail(GS_ERR_INVALID_ARG, "bad pixel budget or capacity");
+  GS_CHECK_DEVICE();
   gs_batch_plan *p = new gs_batch_plan();
   p->n = n;
   p->deg = sh_degree;
@@ -732,6 +768,7 @@ int gs_render_batch(gs_batch_plan *p, const gs_gaussians *g, int32_t n_views, co
   if (!p) return fail(GS_ERR_INVALID_ARG, "plan is NULL");
   int rc = check_views(p, g, n_views, views, mode, grads);
   if (rc) return rc;
+  GS_CHECK_DEVICE();
   hipStream_t st = (hipStream_t)stream;
   if (!(mode & GS_GRAPH)) return enqueue_batch(p, g, n_views, views, mode, grads, st);
   // The captured graph bakes every argument in; replay only while they are unchanged.
@@ -941,6 +978,7 @@ int gs_track_plan_create(gs_track_plan **out, int64_t n, int32_t sh_degree, int6
   if (!depth_ok(blend_depth)) return fail(GS_ERR_INVALID_ARG, "blend_depth must be 64, 128 or 256");
   if (max_pixels <= 0 || max_pixels > 0x7FFFFFFF || capacity <= 0 || capacity > 0xFFFFFFFFll)
     return fail(GS_ERR_INVALID_ARG, "bad pixel budget or capacity");
+  GS_CHECK_DEVICE();
   gs_track_plan *p = new gs_track_plan();
   p->n = n;
   p->deg = sh_degree;
@@ -1011,6 +1049,7 @@ int gs_track_pose(gs_track_plan *p, const gs_gaussians *g, const gs_camera *cam,
   if ((int64_t)((cam->w + p->tw - 1) / p->tw) * ((cam->h + p->th - 1) / p->th) > p->max_tiles)
     return fail(GS_ERR_INVALID_ARG, "window needs more tiles than the plan holds");
   if (!target || !pose_out) return fail(GS_ERR_INVALID_ARG, "target / pose_out is NULL");
+  GS_CHECK_DEVICE();
   hipStream_t st = (hipStream_t)stream;
   gs::TrackPose p0;
   for (int i = 0; i < 9; ++i) p0.R[i] = cam->R_cw[i];
@@ -1139,6 +1178,7 @@ int gs_expand_select(const gs_points *pts, const gs_camera *cam, const float *op
   if (!count_out) return fail(GS_ERR_INVALID_ARG, "count_out is NULL");
   if (!scratch || scratch_bytes < gs::expand_scratch_bytes(pts->n))
     return fail(GS_ERR_INVALID_ARG, "scratch must hold gs_expand_scratch_bytes bytes");
+  GS_CHECK_DEVICE();
   GS_TRY_HIP(gs::launch_expand_select(expand_args(pts, cam, opacity, tau), scratch, count_out, (hipStream_t)stream),
              "expand select");
   return GS_OK;
@@ -1163,6 +1203,7 @@ int gs_expand_write(const gs_points *pts, const gs_camera *cam, const gs_gaussia
   if (out->n > 0 && (!out->mean || !out->scale || !out->rot || !out->opacity || !out->sh_dc ||
                      (k_rest > 0 && !out->sh_rest)))
     return fail(GS_ERR_INVALID_ARG, "an output plane is NULL");
+  GS_CHECK_DEVICE();
   gs::ExpandOut o{};
   o.n = out->n;
   o.n_old = n_old;

@@ -12,7 +12,8 @@
 // pixel, the derivatives of g S w.r.t. the three maps that depend on x:
 //   d mu_x = g (2 mu_y (S/A - S/B) + 2 mu_x (S/D - S/C)),  d E[x^2] = -g S/D,  d E[xy] = 2 g S/B
 // (mu_x enters A, B through s_xy, C and D through s_x^2), and one partial sum of S per
-// workgroup; the loss weight + g sum S is then summed in a fixed order (deterministic).
+// workgroup; the loss weight + g sum S is then summed in a fixed order (deterministic), by
+// one extra workgroup of the backward launch (or its own launch when no gradient is asked).
 // Backward: the window is symmetric, so the adjoint of each filtering is the same filtering:
 //   dL/dx = G * d mu_x + 2 x (G * d E[x^2]) + y (G * d E[xy]).
 #include <cmath>
@@ -191,10 +192,10 @@ __global__ __launch_bounds__(256) void k_dssim_fwd(const float *__restrict__ x, 
   if (threadIdx.x == 0) partial[tile.id] = (red[0] + red[1]) + (red[2] + red[3]);
 }
 
-// loss = weight + g * sum of the block partials (float64, fixed order): deterministic.
-__global__ __launch_bounds__(256) void k_dssim_loss(const float *__restrict__ partial, int64_t nb, float weight,
-                                                    double g, float *__restrict__ loss) {
-  __shared__ double red[256];
+// loss = weight + g * sum of the block partials (float64, fixed order): deterministic. One
+// workgroup; `red` holds 256 doubles of LDS.
+__device__ __forceinline__ void dssim_loss_sum(const float *__restrict__ partial, int64_t nb, float weight, double g,
+                                               float *__restrict__ loss, double *red) {
   double s = 0.0;
 #pragma unroll 8
   for (int64_t b = threadIdx.x; b < nb; b += 256) s += (double)partial[b];
@@ -207,12 +208,31 @@ __global__ __launch_bounds__(256) void k_dssim_loss(const float *__restrict__ pa
   if (threadIdx.x == 0) *loss = (float)((double)weight + g * red[0]);
 }
 
+__global__ __launch_bounds__(256) void k_dssim_loss(const float *__restrict__ partial, int64_t nb, float weight,
+                                                    double g, float *__restrict__ loss) {
+  __shared__ double red[256];
+  dssim_loss_sum(partial, nb, weight, g, loss, red);
+}
+
+struct DssimLoss {  // the loss sum run by the backward's last workgroup (loss == null: none)
+  const float *partial;
+  int64_t nb;
+  float weight;
+  double g;
+  float *loss;
+};
+
 __global__ __launch_bounds__(256) void k_dssim_bwd(const float *__restrict__ x, const float *__restrict__ y, int h,
                                                    int w, int nbx, int nby, int nbc, SsimWeights sw,
                                                    const float *__restrict__ dmu, const float *__restrict__ dxx,
-                                                   const float *__restrict__ dxy, float *__restrict__ dldc) {
+                                                   const float *__restrict__ dxy, float *__restrict__ dldc,
+                                                   DssimLoss ls) {
   __shared__ __align__(16) float sm[3][kSsimH * kSsimLW];
   __shared__ __align__(16) float hs[3][kSsimH * kSsimTX];
+  if (ls.loss && blockIdx.x == gridDim.x - 1) {  // the extra workgroup: the loss, in parallel with the tiles
+    dssim_loss_sum(ls.partial, ls.nb, ls.weight, ls.g, ls.loss, reinterpret_cast<double *>(sm[0]));
+    return;
+  }
   SsimTile tile;
   if (!ssim_tile(nbx, nby, nbc, tile)) return;
   const int c = tile.c;
@@ -308,9 +328,14 @@ hipError_t launch_dssim(const float *x, const float *y, int c, int h, int w, flo
   const int64_t nb = dssim_blocks(c, h, w);
   const dim3 grid((unsigned)((nb + kSsimXcds - 1) / kSsimXcds * kSsimXcds));
   hipLaunchKernelGGL(k_dssim_fwd, grid, dim3(256), 0, st, x, y, h, w, nbx, nby, c, sw, g, dmu, dxx, dxy, partial);
-  if (loss) hipLaunchKernelGGL(k_dssim_loss, dim3(1), dim3(256), 0, st, partial, nb, weight, gd, loss);
-  if (dldc)
-    hipLaunchKernelGGL(k_dssim_bwd, grid, dim3(256), 0, st, x, y, h, w, nbx, nby, c, sw, dmu, dxx, dxy, dldc);
+  if (dldc) {
+    // the backward carries the loss sum in one extra workgroup
+    const DssimLoss ls{partial, nb, weight, gd, loss};
+    const dim3 gridb(grid.x + (loss ? 1u : 0u));
+    hipLaunchKernelGGL(k_dssim_bwd, gridb, dim3(256), 0, st, x, y, h, w, nbx, nby, c, sw, dmu, dxx, dxy, dldc, ls);
+  } else if (loss) {
+    hipLaunchKernelGGL(k_dssim_loss, dim3(1), dim3(256), 0, st, partial, nb, weight, gd, loss);
+  }
   return hipGetLastError();
 }
 
