@@ -294,7 +294,8 @@ int64_t gs_track_capacity(const gs_track_plan *plan);
  * trace (device, may be NULL): [iters][20] floats per iteration: the pose rendered (12, as
  * pose_out), dL/dxi at that pose (6), the L1 term and the D-SSIM term. The pose is kept in
  * float64 on the device between iterations and rounded to float32 for each render.
- * Asynchronous; no host synchronisation inside the loop. */
+ * Asynchronous; no host synchronisation inside the loop. A plan's buffers (and its pose
+ * state) serve one call at a time: calls on one plan must be ordered on one stream. */
 int gs_track_pose(gs_track_plan *plan, const gs_gaussians *g, const gs_camera *cam, const float *target,
                   const gs_track_params *params, float *pose_out, float *trace, gs_stream_t stream);
 

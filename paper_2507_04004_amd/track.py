@@ -28,6 +28,9 @@ DEFAULTS = dict(iters=30, l1_weight=0.5, ssim_weight=0.5, lr_rho=1e-3, lr_phi=3e
 
 @dataclasses.dataclass
 class TrackResult:
+    """pose and trace are the tracker's own buffers: the next track() call overwrites them
+    (clone them to keep a result)."""
+
     pose: torch.Tensor            # [12] device: refined R_cw (row-major) then t_cw
     trace: torch.Tensor | None    # [iters, 20] device: pose rendered, dL/dxi, L1 term, D-SSIM term
     pairs: int | None = None      # largest pair count over the iterations (when checked)
@@ -39,6 +42,8 @@ class TrackResult:
 
 
 class PoseTracker:
+    """Owns one tracking plan; calls are ordered on the current torch stream."""
+
     def __init__(self, gm: R.GaussianMap, max_pixels: int, tile: int = 8, blend_depth: int = 128,
                  capacity: int | None = None, device="cuda"):
         self.gm, self.max_pixels, self.tile, self.blend_depth = gm, int(max_pixels), tile, blend_depth
