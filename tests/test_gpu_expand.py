@@ -42,7 +42,7 @@ def _points(n, seed, cam):
 
 def _compare(new, added, g_old, xyz, rgb, cam, O, tau=0.99):
     sel = OE.select(xyz, cam, O, tau)
-    ref = OE.new_gaussians(xyz, rgb, cam, sel, 3)
+    ref = OE.new_gaussians(xyz, rgb, cam, sel, new.sh_degree)
     m = int(sel.sum())
     assert added == m, (added, m)
     n_old = 0 if g_old is None else g_old.n
@@ -125,3 +125,17 @@ def test_no_points_and_new_gaussians_cover_the_holes():
     assert added > 1000
     assert (a1 >= a0 - 0.0101).all()
     assert (a1 - a0 > 0.05).mean() > 0.05
+
+
+def test_expansion_of_a_degree_zero_map():
+    """No higher SH planes: only the 14 planes of degree 0 are copied and filled."""
+    cam = S.look_camera((0.0, 0.0, 0.0), 0.0, 0.0, 160, 120, 120.0)
+    g = S.frustum_scene(5000, cam, (2.0, 20.0), sh_degree=0, seed=11)
+    O = oracle.render(g, oracle.camera_f32(cam))["alpha"].astype(np.float32)
+    xyz, rgb = _points(20_000, 12, cam)
+    gm = R.GaussianMap.from_numpy(g, DEV)
+    new, added = X.expand_map(gm, torch.from_numpy(xyz).to(DEV), torch.from_numpy(rgb).to(DEV), cam,
+                              torch.from_numpy(O).to(DEV), 0.99, device=DEV)
+    torch.cuda.synchronize()
+    assert new.sh_degree == 0 and new.sh_rest.shape[0] == 0
+    _compare(new, added, g, xyz, rgb, cam, O)

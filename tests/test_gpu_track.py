@@ -93,11 +93,12 @@ def check_update_rule(tr, pose_out, lr_rho, lr_phi, b1, b2, eps):
     return worst
 
 
-@pytest.mark.parametrize("graph", [False, True])
-def test_loop_matches_oracle(graph):
-    print(f"[track] oracle parity graph={graph}", flush=True)
-    g, cam, start, gm, target = _setup()
-    trk = T.PoseTracker(gm, cam.w * cam.h, tile=8, blend_depth=128, device=DEV)
+@pytest.mark.parametrize("graph,deg,tile,bd", [(False, 3, 8, 128), (True, 3, 8, 128), (False, 0, 16, 256),
+                                               (True, 1, 8, 64), (False, 2, 32, 128)])
+def test_loop_matches_oracle(graph, deg, tile, bd):
+    print(f"[track] oracle parity graph={graph} sh_degree={deg} tile={tile} chunk={bd}", flush=True)
+    g, cam, start, gm, target = _setup(deg=deg)
+    trk = T.PoseTracker(gm, cam.w * cam.h, tile=tile, blend_depth=bd, device=DEV)
     res = trk.track(start, target, graph=graph, trace=True)
     tr = res.trace.double().cpu().numpy()
     pose_out = res.pose.double().cpu().numpy()
