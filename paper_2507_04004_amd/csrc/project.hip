@@ -832,8 +832,17 @@ __global__ void k_pose_reduce_tab(const float *__restrict__ partial, int32_t n_b
 hipError_t launch_preprocess_bwd(const ViewTable &vt, const gs_gaussians &g, const gs_projected &p, const float *g2,
                                  float4 *gdir, const gs_grads &out, float *const *pose_out, float *pose_partial,
                                  hipStream_t st) {
-  if (vt.n == 0) return hipSuccess;
   if (vt.pose_dev && vt.n_views != 1) return hipErrorInvalidValue;
+  if (vt.n == 0) {
+    // no Gaussians: nothing to differentiate, but overwrite mode still writes the pose
+    // gradients (zero; the reduction of zero partials)
+    if (out.overwrite == 0) return hipSuccess;
+    PosePtrs pp;
+    for (int i = 0; i < kMaxViews; ++i) pp.p[i] = i < vt.n_views ? pose_out[i] : nullptr;
+    hipLaunchKernelGGL(k_pose_reduce_tab, dim3((unsigned)(6 * vt.n_views)), dim3(256), 0, st, pose_partial, 0,
+                       vt.n_views, pp, 1);
+    return hipGetLastError();
+  }
   const int64_t nb = preprocess_bwd_blocks(vt.n);
   const bool ow = out.overwrite != 0;
   const bool single = vt.n_views == 1;

@@ -296,6 +296,11 @@ def test_edge_cases():
     assert np.all(img["alpha"] == 0) and np.all(img["t_final"] == 1) and np.all(img["last"] == -1)
     gr = run.backward(np.ones((3, cam.h, cam.w), np.float32))
     assert np.all(gr["pose"] == 0)
+    # overwrite mode writes the (zero) pose gradient over whatever the buffer held
+    junk = R.ParamGrads.empty(run.gm)
+    junk.pose.fill_(7.0)
+    gr = run.backward(np.ones((3, cam.h, cam.w), np.float32), overwrite=True, grads=junk)
+    assert np.all(gr["pose"] == 0)
     # every Gaussian behind the camera
     behind = g.subset(np.arange(g.n))
     behind.mean[2] *= -1
