@@ -14,7 +14,7 @@ DEPTH_RTOL = 1e-4      # depth: 1e-4 absolute up to 1 m, 1e-4 relative beyond (f
 GRAD_RTOL = 2e-3       # gradients: relative
 
 
-class GpuRun:
+class HipRun:
     """One plain single-view pass through the C ABI, keeping every intermediate."""
 
     def __init__(self, g, cam, tile=16, blend_depth=256, lidar=None, capacity=None):

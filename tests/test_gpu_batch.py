@@ -14,7 +14,7 @@ from paper_2507_04004_amd import raster as R
 from paper_2507_04004_amd import scenes as S
 from paper_2507_04004_amd.batch import BatchPlan, ViewSlot
 
-from gpu_common import DEV, GpuRun, assert_grads_close, oracle_cam
+from gpu_common import DEV, HipRun, assert_grads_close, oracle_cam
 
 pytestmark = pytest.mark.gpu
 
@@ -43,7 +43,7 @@ def test_batch_forward_equals_plain(tile):
     torch.cuda.synchronize()
     assert plan.num_pairs() <= plan.capacity
     for k, cam in enumerate(cams):
-        ref = GpuRun(g, cam, tile=tile, blend_depth=128).image()
+        ref = HipRun(g, cam, tile=tile, blend_depth=128).image()
         fr = slots[k].frame
         for key in ("color", "depth", "alpha", "t_final"):
             assert np.array_equal(getattr(fr, key).cpu().numpy(), ref[key]), (k, key)
@@ -85,7 +85,7 @@ def test_batch_fused_l1_and_lidar():
     gp = S.perturb(g, 0.02, seed=4)
     slots, refs = [], []
     for k, c in enumerate(cams):
-        tgt_run = GpuRun(gp, c)
+        tgt_run = HipRun(gp, c)
         tgt = tgt_run.fr.color.clone()
         O = tgt_run.fr.alpha.flatten().cpu().numpy()
         D = tgt_run.fr.depth.flatten().cpu().numpy()
@@ -95,7 +95,7 @@ def test_batch_fused_l1_and_lidar():
         s = ViewSlot.make(c, DEV, backward=True, lidar=lid, target=tgt)
         slots.append(s)
         # plain reference: forward, L1 loss, backward with the same LiDAR term
-        run = GpuRun(g, c, lidar=lid)
+        run = HipRun(g, c, lidar=lid)
         loss, dC = R.loss_l1(run.fr.color, tgt)
         refs.append((run, dC, loss))
     plan = BatchPlan(g.n, 3, len(cams), sum(c.w * c.h for c in cams), device=DEV)

@@ -11,7 +11,7 @@ import oracle
 from paper_2507_04004_amd import raster as R
 from paper_2507_04004_amd import scenes as S
 
-from gpu_common import DEV, GRAD_RTOL, GpuRun, oracle_cam
+from gpu_common import DEV, GRAD_RTOL, HipRun, oracle_cam
 
 pytestmark = pytest.mark.gpu
 
@@ -54,7 +54,7 @@ def c4():
 def test_c4_gradients_match_oracle(c4):
     g, cam, base, gC = c4
     print("[c4] GPU backward", flush=True)
-    run = GpuRun(g, cam, tile=8, blend_depth=128)
+    run = HipRun(g, cam, tile=8, blend_depth=128)
     got = run.backward(gC.astype(np.float32))
     print("[c4] oracle backward", flush=True)
     an = oracle.backward(g, cam, gC, None, None, tile=8)

@@ -18,7 +18,7 @@ import pytest
 import oracle
 from paper_2507_04004_amd import scenes as S
 
-from gpu_common import DEPTH_RTOL, GRAD_RTOL, IMG_ATOL, GpuRun, oracle_cam
+from gpu_common import DEPTH_RTOL, GRAD_RTOL, IMG_ATOL, HipRun, oracle_cam
 
 pytestmark = pytest.mark.gpu
 
@@ -35,7 +35,7 @@ def headline():
 
 def test_fullsize_bins_bit_exact(headline):
     g, cam = headline
-    run = GpuRun(g, cam, tile=TILE, blend_depth=BD)
+    run = HipRun(g, cam, tile=TILE, blend_depth=BD)
     got = run.bins_np()
     ref = oracle.bin32(g, cam, tile=TILE)
     print(f"[fullsize] pairs {got['num_pairs']} (oracle {ref['num_pairs']})", flush=True)
@@ -50,7 +50,7 @@ def test_fullsize_bins_bit_exact(headline):
 
 def test_fullsize_sampled_pixels(headline):
     g, cam = headline
-    run = GpuRun(g, cam, tile=TILE, blend_depth=BD)
+    run = HipRun(g, cam, tile=TILE, blend_depth=BD)
     img = run.image()
     rng = np.random.default_rng(7)
     xs = rng.integers(0, cam.w, 600)
@@ -76,7 +76,7 @@ def test_fullsize_window_gradients(headline):
     rng = np.random.default_rng(11)
     gC = rng.standard_normal((3, win.h, win.w))
     gO = rng.standard_normal((win.h, win.w))
-    run = GpuRun(g, win, tile=TILE, blend_depth=BD)
+    run = HipRun(g, win, tile=TILE, blend_depth=BD)
     got = run.backward(gC.astype(np.float32), None, gO.astype(np.float32))
     print("[fullsize] oracle backward on the window", flush=True)
     an = oracle.backward(g, win, gC, None, gO, tile=TILE)

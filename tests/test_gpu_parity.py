@@ -14,7 +14,7 @@ from oracle.loss import loss_and_grads
 from paper_2507_04004_amd import raster as R
 from paper_2507_04004_amd import scenes as S
 
-from gpu_common import DEV, GpuRun, assert_grads_close, assert_images_close, compare_images, grad_errors, oracle_cam
+from gpu_common import DEV, HipRun, assert_grads_close, assert_images_close, compare_images, grad_errors, oracle_cam
 
 pytestmark = pytest.mark.gpu
 
@@ -67,7 +67,7 @@ CASES = {
 def test_bins_bit_exact(case, tile):
     g, cam = CASES[case]()
     print(f"[bins] case={case} tile={tile} n={g.n}", flush=True)
-    run = GpuRun(g, cam, tile=tile)
+    run = HipRun(g, cam, tile=tile)
     got = run.bins_np()
     ref = oracle.bin32(g, cam, tile=tile)
     np.testing.assert_array_equal(got["n_tiles"], ref["n_tiles"])
@@ -82,7 +82,7 @@ def test_bins_bit_exact(case, tile):
 @pytest.mark.parametrize("case", ["small_sh0", "street_sh3_posed"])
 def test_projection_records(case):
     g, cam = CASES[case]()
-    run = GpuRun(g, cam)
+    run = HipRun(g, cam)
     ref = oracle.project(g, oracle_cam(cam))
     vis = run.bins_np()["n_tiles"] > 0
     assert np.all(ref["valid"][vis] == 1)
@@ -104,7 +104,7 @@ def test_projection_records(case):
 def test_render_matches_oracle(case):
     g, cam = CASES[case]()
     print(f"[render] case={case}", flush=True)
-    run = GpuRun(g, cam)
+    run = HipRun(g, cam)
     got = run.image()
     ref = oracle.render(g, oracle_cam(cam), tile=16, band=1e-4)
     e = assert_images_close(got, ref)
@@ -131,11 +131,11 @@ def test_tile_size_and_blend_depth_invariance(case):
     """Images do not depend on the tile size or chunk length: bitwise when every list fits in
     one chunk (same per-pixel operation sequence), else up to float32 reassociation."""
     g, cam = CASES[case]()
-    base_run = GpuRun(g, cam, tile=16, blend_depth=256)
+    base_run = HipRun(g, cam, tile=16, blend_depth=256)
     base = base_run.image()
     base_single = _max_list(base_run) <= 256
     for tile, bd in [(8, 64), (8, 256), (16, 64), (16, 128), (32, 128), (32, 256)]:
-        run = GpuRun(g, cam, tile=tile, blend_depth=bd)
+        run = HipRun(g, cam, tile=tile, blend_depth=bd)
         got = run.image()
         bitwise = base_single and _max_list(run) <= bd
         for k in ("color", "depth", "alpha", "t_final"):
@@ -150,7 +150,7 @@ def test_tile_size_and_blend_depth_invariance(case):
 def test_multichunk_tiles_match_oracle(bd):
     """Long tile lists split into many chunks, with pixels stopping in late chunks."""
     g, cam = dense_tile()
-    run = GpuRun(g, cam, tile=16, blend_depth=bd)
+    run = HipRun(g, cam, tile=16, blend_depth=bd)
     assert _max_list(run) > 4 * bd
     got = run.image()
     ref = oracle.render(g, oracle_cam(cam), tile=16, band=1e-4)
@@ -167,8 +167,8 @@ def test_multichunk_tiles_match_oracle(bd):
 
 def test_forward_deterministic():
     g, cam = CASES["street_sh3_posed"]()
-    a = GpuRun(g, cam).image()
-    b = GpuRun(g, cam).image()
+    a = HipRun(g, cam).image()
+    b = HipRun(g, cam).image()
     for k in a:
         assert np.array_equal(a[k], b[k]), k
 
@@ -179,7 +179,7 @@ def test_forward_deterministic():
 def test_backward_matches_oracle(case, which):
     g, cam = CASES[case]()
     print(f"[backward] case={case} which={which}", flush=True)
-    run = GpuRun(g, cam)
+    run = HipRun(g, cam)
     npx = cam.w * cam.h
     gC, gD, gO = S.upstream_grads(npx, seed=11)
     gC = gC.reshape(3, cam.h, cam.w) * (which != "depth_only")
@@ -200,7 +200,7 @@ def test_backward_overwrite_and_accumulate(case):
     compared to float32 summation-order level: the compositing backward adds its per-splat
     sums with float atomics.)"""
     g, cam = CASES[case]()
-    run = GpuRun(g, cam)
+    run = HipRun(g, cam)
     gC, gD, gO = S.upstream_grads(cam.w * cam.h, seed=13)
     gC, gD, gO = gC.reshape(3, cam.h, cam.w), gD.reshape(cam.h, cam.w), gO.reshape(cam.h, cam.w)
     acc = run.backward(gC, gD, gO)
@@ -240,7 +240,7 @@ def test_lidar_depth_term():
     pix = pix[keep]
     ds = ds_full[pix].astype(np.float32)
     lid = R.LidarHits(torch.from_numpy(pix.astype(np.int32)).to(DEV), torch.from_numpy(ds).to(DEV), weight=0.7)
-    run = GpuRun(g, cam, lidar=lid)
+    run = HipRun(g, cam, lidar=lid)
     ref_img = oracle.render(g, oracle_cam(cam), band=1e-4)
     _, l_ref, _, gD_ref, gO_ref = loss_and_grads(ref_img["color"], ref_img["depth"], ref_img["alpha"],
                                                  ref_img["color"], pix, ds, gamma=0.7)
@@ -278,7 +278,7 @@ def test_autograd_function_and_checkpoint():
 def test_pose_translation_identity_gpu():
     """d L / d rho = R sum_k d L / d mu_k on the GPU's own gradients."""
     g, cam = CASES["street_sh3_posed"]()
-    run = GpuRun(g, cam)
+    run = HipRun(g, cam)
     gC, gD, gO = S.upstream_grads(cam.w * cam.h, seed=13)
     got = run.backward(gC.reshape(3, cam.h, cam.w), gD.reshape(cam.h, cam.w), gO.reshape(cam.h, cam.w))
     lhs = got["pose"][:3]
@@ -291,7 +291,7 @@ def test_edge_cases():
     g, cam = S.config_small(0)[:2]
     # empty map
     empty = g.subset(np.arange(0))
-    run = GpuRun(empty, cam)
+    run = HipRun(empty, cam)
     img = run.image()
     assert np.all(img["alpha"] == 0) and np.all(img["t_final"] == 1) and np.all(img["last"] == -1)
     gr = run.backward(np.ones((3, cam.h, cam.w), np.float32))
@@ -304,7 +304,7 @@ def test_edge_cases():
     # every Gaussian behind the camera
     behind = g.subset(np.arange(g.n))
     behind.mean[2] *= -1
-    img = GpuRun(behind, cam).image()
+    img = HipRun(behind, cam).image()
     assert np.all(img["alpha"] == 0)
     # degenerate Gaussians are dropped, the rest render as without them
     bad = g.subset(np.arange(50))
@@ -313,13 +313,13 @@ def test_edge_cases():
     bad.mean[0, 2] = np.nan
     bad.opacity[3] = 1e-4
     ok_idx = np.setdiff1d(np.arange(50), [0, 1, 2, 3])
-    a = GpuRun(bad, cam).image()
-    b = GpuRun(g.subset(ok_idx), cam).image()
+    a = HipRun(bad, cam).image()
+    b = HipRun(g.subset(ok_idx), cam).image()
     for k in ("color", "depth", "alpha", "t_final"):
         assert np.array_equal(a[k], b[k]), k
     # a one-pixel window
     one = cam.window(40, 30, 1, 1)
-    img = GpuRun(g, one).image()
+    img = HipRun(g, one).image()
     ref = oracle.render(g, oracle_cam(one), band=1e-4)
     assert_images_close(img, ref)
 

@@ -16,7 +16,7 @@ from paper_2507_04004_amd import scenes as S
 from paper_2507_04004_amd.autotune import autotune
 from paper_2507_04004_amd.serve import RenderServer, poisson_arrivals, simulate
 
-from gpu_common import DEV, GpuRun
+from gpu_common import DEV, HipRun
 
 pytestmark = pytest.mark.gpu
 
@@ -47,7 +47,7 @@ def test_served_frames_equal_plain_renders(batched):
     assert stats["requests"] == len(cams) and stats["p99_ms"] >= stats["p50_ms"] > 0
     # every served frame equals the plain single-view render of its camera
     for i, (c, fr) in enumerate(zip(cams, stats["frames"])):
-        ref = GpuRun(g, c, tile=server.tile, blend_depth=server.bd).image()
+        ref = HipRun(g, c, tile=server.tile, blend_depth=server.bd).image()
         for key in ("color", "depth", "alpha", "t_final"):
             assert np.array_equal(getattr(fr, key).cpu().numpy(), ref[key]), (i, key)
     server.close()
