@@ -13,7 +13,8 @@
  *     planes of n elements (SoA): component j of element i is at ptr[j*n + i].
  *   - Every call is asynchronous on `stream` (a hipStream_t; NULL = the null stream) and
  *     returns GS_OK or an error code. Argument errors are detected on the host before any
- *     launch. No call allocates device memory except gs_batch_plan_create.
+ *     launch. No call allocates device memory except gs_batch_plan_create and
+ *     gs_track_plan_create.
  *   - Buffers are owned by the caller and must stay valid until the stream work completes.
  *   - Gradient outputs are ACCUMULATED (+=): zero them before the first call.
  *   - Pixel centres sit at integer coordinates. A camera carries a render window
