@@ -127,6 +127,19 @@ def test_no_points_and_new_gaussians_cover_the_holes():
     assert (a1 - a0 > 0.05).mean() > 0.05
 
 
+@pytest.mark.parametrize("tau", [0.5, 0.9999])
+def test_expansion_at_other_thresholds(tau):
+    g, cam = _scene(seed=8)
+    O = oracle.render(g, oracle.camera_f32(cam))["alpha"].astype(np.float32)
+    xyz, rgb = _points(50_000, 13, cam)
+    gm = R.GaussianMap.from_numpy(g, DEV)
+    new, added = X.expand_map(gm, torch.from_numpy(xyz).to(DEV), torch.from_numpy(rgb).to(DEV), cam,
+                              torch.from_numpy(O).to(DEV), tau, device=DEV)
+    torch.cuda.synchronize()
+    m = _compare(new, added, g, xyz, rgb, cam, O, tau)
+    print(f"[expand] tau={tau}: added {m} of 50000", flush=True)
+
+
 def test_expansion_of_a_degree_zero_map():
     """No higher SH planes: only the 14 planes of degree 0 are copied and filled."""
     cam = S.look_camera((0.0, 0.0, 0.0), 0.0, 0.0, 160, 120, 120.0)

@@ -126,6 +126,26 @@ def test_loop_matches_oracle(graph, deg, tile, bd):
           f"{tr[-1, 18] + tr[-1, 19]:.4f}", flush=True)
 
 
+def test_loop_in_a_render_window_matches_oracle():
+    """A 112x80 window inside the 160x120 image: the render, L1 and D-SSIM run on the window."""
+    g, cam = _scene(seed=7)
+    win = cam.window(21, 17, 112, 80)
+    target = oracle.render(g, oracle.camera_f32(win))["color"].astype(np.float32)
+    start = _moved(win, (0.008, 0.01, -0.01, -0.003, 0.002, 0.004))
+    gm = R.GaussianMap.from_numpy(g, DEV)
+    trk = T.PoseTracker(gm, win.w * win.h, tile=8, blend_depth=128, device=DEV)
+    res = trk.track(start, torch.from_numpy(target).to(DEV), graph=True, trace=True)
+    tr = res.trace.double().cpu().numpy()
+    q = _params()
+    _, _, otr = OT.track(g, oracle.camera_f32(start), target.astype(np.float64), q)
+    err = np.linalg.norm(tr[0, 12:18] - otr[0]["grad"]) / np.linalg.norm(otr[0]["grad"])
+    dpose = max(float(np.abs(tr[k, :12] - np.r_[otr[k]["R"].ravel(), otr[k]["t"]]).max()) for k in range(q.iters))
+    print(f"[track] window: first-iteration gradient error {err:.2e}, largest pose difference {dpose:.2e}",
+          flush=True)
+    assert err <= 2e-3 and dpose <= 1e-5
+    assert abs(tr[0, 18] - otr[0]["l1"]) <= 1e-4 and abs(tr[0, 19] - otr[0]["ssim"]) <= 1e-4
+
+
 def test_loop_converges_and_graph_replays_match_eager():
     g, cam, start, gm, target = _setup(seed=4)
     trk = T.PoseTracker(gm, cam.w * cam.h, tile=8, blend_depth=128, device=DEV)
