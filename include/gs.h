@@ -140,6 +140,17 @@ typedef struct gs_lidar {
   const float *grad_scale;
 } gs_lidar;
 
+/* Compositing-backward schedules (gs_grads.schedule):
+ *   GS_BWD_CHUNKS  — pixel-parallel: each (tile, chunk) work item walks its pixels' splats back
+ *                    to front, one pixel per lane, and sums each splat's terms over the
+ *                    wavefront before one atomic per term (default);
+ *   GS_BWD_BUCKETS — per-Gaussian buckets (Sec. "CUDA-Related Acceleration Strategies"): lane j
+ *                    owns splat j of a 64-splat bucket and the tile's pixels pass through the
+ *                    lanes, so each lane sums its splat's terms over the pixels; 8x8 and 16x16
+ *                    tiles (GS_ERR_UNSUPPORTED at 32x32). Same results up to float32 summation
+ *                    order. */
+enum { GS_BWD_CHUNKS = 0, GS_BWD_BUCKETS = 1 };
+
 /* Gradient outputs, same layouts as gs_gaussians; pose [6] is dL/dxi for the left
  * perturbation T_cw <- Exp(xi) T_cw with xi = (rho, phi), translation first (the manifold
  * derivative after eq:3dgs_jacobi, taken on the world-to-camera pose).
@@ -153,6 +164,7 @@ typedef struct gs_grads {
   void *scratch;
   size_t scratch_bytes;
   int32_t overwrite;
+  int32_t schedule; /* GS_BWD_CHUNKS (0) or GS_BWD_BUCKETS */
 } gs_grads;
 
 /* Stage a1 — projection, covariance, SH colour, footprint, tile rectangle and alpha-max cull

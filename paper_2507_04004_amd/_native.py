@@ -51,7 +51,10 @@ class Lidar(C.Structure):
 
 class Grads(C.Structure):
     _fields_ = [(k, vp) for k in ("mean", "scale", "rot", "opacity", "sh_dc", "sh_rest", "pose", "scratch")] + [
-        ("scratch_bytes", C.c_size_t), ("overwrite", C.c_int32)]
+        ("scratch_bytes", C.c_size_t), ("overwrite", C.c_int32), ("schedule", C.c_int32)]
+
+
+GS_BWD_CHUNKS, GS_BWD_BUCKETS = 0, 1
 
 
 class View(C.Structure):

@@ -227,7 +227,8 @@ int enqueue_backward(const gs::ViewTable &vt, const gs_gaussians &g, const gs_pr
   if (any_map) GS_TRY_HIP(gs::launch_grad_maps(src, dst, nv, max_npx, lt, it, max_m, st), "lidar/gradient maps");
   GS_TRY_HIP(gs::zero_f32(s.g2, 12 * vt.n * nv, st), "zero grad2d");
   gs::profile_begin(GS_STAGE_BLEND_BWD, st);
-  GS_TRY_HIP(gs::launch_blend_bwd(bd, vt, it, gtab, p, vals, range, state, cap, s.g2, st), "blend backward");
+  GS_TRY_HIP(gs::launch_blend_bwd(bd, vt, it, gtab, p, vals, range, state, cap, s.g2, st, out.schedule),
+             "blend backward");
   gs::profile_end(GS_STAGE_BLEND_BWD, st);
   float *pose_out[gs::kMaxViews] = {};
   for (int i = 0; i < nv; ++i) pose_out[i] = io[i].pose;
@@ -235,6 +236,14 @@ int enqueue_backward(const gs::ViewTable &vt, const gs_gaussians &g, const gs_pr
   GS_TRY_HIP(gs::launch_preprocess_bwd(vt, g, p, s.g2, s.gdir, out, pose_out, s.pose_partial, st),
              "preprocess backward");
   gs::profile_end(GS_STAGE_PREPROCESS_BWD, st);
+  return GS_OK;
+}
+
+int check_schedule(int32_t schedule, int tile_w) {
+  if (schedule != GS_BWD_CHUNKS && schedule != GS_BWD_BUCKETS)
+    return fail(GS_ERR_INVALID_ARG, "unknown backward schedule %d", schedule);
+  if (schedule == GS_BWD_BUCKETS && tile_w == 32)
+    return fail(GS_ERR_UNSUPPORTED, "the bucketed backward runs on 8x8 and 16x16 tiles");
   return GS_OK;
 }
 
@@ -427,6 +436,7 @@ int gs_render_bwd(const gs_gaussians *g, const gs_camera *cam, const gs_projecte
   if (!dL_dC) return fail(GS_ERR_INVALID_ARG, "dL_dC is NULL");
   if (!out || !out->scratch) return fail(GS_ERR_INVALID_ARG, "grads / scratch is NULL");
   if (out->sh_dc && g->sh_degree > 0 && !out->sh_rest) return fail(GS_ERR_INVALID_ARG, "grads.sh_rest is NULL");
+  if ((rc = check_schedule(out->schedule, bins->tile_w))) return rc;
   if ((rc = check_lidar(lidar, (int64_t)cam->w * cam->h))) return rc;
   const int64_t npx = (int64_t)cam->w * cam->h;
   if (out->scratch_bytes < grads_scratch_bytes_impl(g->n, 1, npx))
@@ -693,6 +703,7 @@ int check_views(const gs_batch_plan *p, const gs_gaussians *g, int nv, const gs_
   }
   if ((mode & GS_BWD) && grads && grads->sh_dc && g->sh_degree > 0 && !grads->sh_rest)
     return fail(GS_ERR_INVALID_ARG, "grads.sh_rest is NULL");
+  if ((mode & GS_BWD) && grads && (rc = check_schedule(grads->schedule, p->tw))) return rc;
   return GS_OK;
 }
 

@@ -862,6 +862,150 @@ __global__ __launch_bounds__(NT) void k_blend_bwd_chunk(ViewTable vt, ImgTable i
   }
 }
 
+// ---- per-Gaussian bucketed backward (a second a4 schedule) ---------------------------------
+// The backward schedule of Sec. "CUDA-Related Acceleration Strategies" (per-Gaussian
+// buckets), for 8x8 and 16x16 tiles: one wavefront per (tile, chunk) item; the chunk's splats,
+// back to front, are taken in buckets of 64, lane L owning splat top - L of the bucket. The
+// tile's pixels stream through the lanes: in step s lane L works on pixel s - L, so every pixel
+// meets the bucket's splats in back-to-front order, one per step. A pixel's running state
+// (transmittance and the colour and depth behind) lives in LDS: the lane that takes the pixel
+// reads the state its neighbour wrote in the previous step and writes it back (LDS operations
+// of one wavefront stay in program order). Per (splat, pixel) the operations are those of
+// k_blend_bwd_chunk in the same order, so the pixel states are the same; each lane sums its
+// splat's ten terms over the tile's pixels in registers and issues them as atomics once per
+// bucket, with no wavefront reduction.
+template <int TW, int TH, int BD>
+__global__ __launch_bounds__(64) void k_blend_bwd_bucket(ViewTable vt, ImgTable it, GradTable gtab,
+                                                         const Card *__restrict__ card,
+                                                         const uint32_t *__restrict__ vals,
+                                                         const uint32_t *__restrict__ range,
+                                                         const uint2 *__restrict__ items,
+                                                         const uint32_t *__restrict__ n_items,
+                                                         const ChunkRec *__restrict__ chunk,
+                                                         float *__restrict__ g2 /*[E][12]*/) {
+  constexpr int NPIX = TW * TH;
+  constexpr int NT = 64;
+  __shared__ float4 s_a[BD], s_b[BD], s_c[BD];
+  __shared__ uint32_t s_e[BD];
+  // pixel tables: running state and constants
+  __shared__ float sT[NPIX], sA0[NPIX], sA1[NPIX], sA2[NPIX], sAD[NPIX];
+  __shared__ float sTfin[NPIX], sGC0[NPIX], sGC1[NPIX], sGC2[NPIX], sGD[NPIX], sGOb[NPIX];
+  __shared__ int sLL[NPIX];
+  __shared__ int s_max;
+  uint32_t item;
+  if (!item_of_block(n_items, item)) return;
+  const uint2 tc = items[item];
+  const uint32_t gt = tc.x, c = tc.y;
+  const TileCtx<TW, TH, NPIX> tile(vt, gt);  // pidx(0) = lane index over the whole tile
+  const ViewCam &cam = *tile.cam;
+  const uint32_t s0 = range[2 * gt], e0 = range[2 * gt + 1];
+  const uint32_t K = n_chunks(e0 - s0, BD);
+  const uint32_t cs = s0 + c * BD;
+  const int cnt = (int)min<uint32_t>(BD, e0 - cs);
+  const ViewImg &im = it.v[tile.vi];
+  const ViewGrad &vg = gtab.v[tile.vi];
+  const int lane = threadIdx.x;
+  if (lane == 0) s_max = -1;
+  __syncthreads();
+  int mymax = -1;
+  for (int q = lane; q < NPIX; q += NT) {
+    const int wx = tile.tx * TW + q % TW, wy = tile.ty * TH + q / TW;
+    const bool inside = wx < cam.w && wy < cam.h;
+    const int64_t pi = (int64_t)wy * cam.w + wx;
+    float T = 1.f, A0 = 0.f, A1 = 0.f, A2 = 0.f, AD = 0.f, Tfin = 1.f, gC0 = 0.f, gC1 = 0.f, gC2 = 0.f, gD = 0.f,
+          gOb = 0.f;
+    int ll = -1;
+    if (inside) {
+      Tfin = im.t_final[pi];
+      ll = min(im.last[pi] - (int)(c * BD), cnt - 1);
+      gC0 = vg.gC[pi];
+      gC1 = vg.gC[tile.npx + pi];
+      gC2 = vg.gC[2 * tile.npx + pi];
+      if (vg.gD) gD = vg.gD[pi];
+      const float gO = vg.gO ? vg.gO[pi] : 0.f;
+      gOb = gO - (gC0 * cam.bg[0] + gC1 * cam.bg[1] + gC2 * cam.bg[2]);
+      if (K == 1) {
+        T = Tfin;
+      } else if (ll >= 0) {
+        const ChunkRec r = chunk[(int64_t)item * NPIX + q];
+        T = r.t;
+        A0 = r.c0; A1 = r.c1; A2 = r.c2; AD = r.d;
+      }
+    }
+    sT[q] = T; sA0[q] = A0; sA1[q] = A1; sA2[q] = A2; sAD[q] = AD;
+    sTfin[q] = Tfin; sGC0[q] = gC0; sGC1[q] = gC1; sGC2[q] = gC2; sGD[q] = gD; sGOb[q] = gOb;
+    sLL[q] = ll;
+    mymax = max(mymax, ll);
+  }
+  if (mymax >= 0) atomicMax(&s_max, mymax);
+  __syncthreads();
+  const int maxll = __builtin_amdgcn_readfirstlane(s_max);
+  if (maxll < 0) return;  // uniform: no pixel has a contributor in this chunk
+  stage<BD, NT>(vals, cs, maxll + 1, card, s_a, s_b, s_c, s_e);
+  __syncthreads();
+  const float x0 = (float)(cam.x0 + tile.tx * TW), y0 = (float)(cam.y0 + tile.ty * TH);
+  for (int top = maxll; top >= 0; top -= NT) {
+    const int j = top - lane;  // this lane's splat (j < 0: idle)
+    float4 A = make_float4(0.f, 0.f, 0.f, 0.f), B = A, Cc = A;
+    if (j >= 0) {
+      A = s_a[j];
+      B = s_b[j];
+      Cc = s_c[j];
+    }
+    float g[10];
+#pragma unroll
+    for (int v = 0; v < 10; ++v) g[v] = 0.f;
+    const int steps = NPIX + min(top, NT - 1);
+    for (int st = 0; st < steps; ++st) {
+      const int q = st - lane;
+      if (j < 0 || q < 0 || q >= NPIX) continue;
+      const float px = x0 + (float)(q % TW), py = y0 + (float)(q / TW);
+      const float dx = px - A.x, dy = py - A.y;
+      float m, qc;
+      const float p2 = splat_p2(A, B, dx, dy, m, qc);
+      const float ex = splat_e2(p2);
+      const float ar = B.y * ex;
+      const bool act = j <= sLL[q] && fminf(kAlphaMax, ar) >= kAlphaMin;
+      // a pixel this splat does not reach takes alpha 0 and its state stays as it is
+      if (!act) continue;
+      const float alpha = fminf(kAlphaMax, ar);
+      const float one_m = 1.f - alpha;
+      const float inv = __builtin_amdgcn_rcpf(one_m);
+      const float T = sT[q] * inv;
+      const float w = alpha * T;
+      const float gC0 = sGC0[q], gC1 = sGC1[q], gC2 = sGC2[q], gD = sGD[q];
+      const float A0 = sA0[q], A1 = sA1[q], A2 = sA2[q], AD = sAD[q];
+      g[6] += gC0 * w;
+      g[7] += gC1 * w;
+      g[8] += gC2 * w;
+      float dLda = gC0 * (Cc.x - A0) + gC1 * (Cc.y - A1) + gC2 * (Cc.z - A2);
+      sA0[q] = alpha * Cc.x + one_m * A0;
+      sA1[q] = alpha * Cc.y + one_m * A1;
+      sA2[q] = alpha * Cc.z + one_m * A2;
+      g[9] += gD * w;
+      dLda += gD * (B.z - AD);
+      sAD[q] = alpha * B.z + one_m * AD;
+      sT[q] = T;
+      dLda = T * dLda + (sTfin[q] * inv) * sGOb[q];
+      const float dm = ar < kAlphaMax ? dLda : 0.f;  // clamped alpha: no power path
+      g[5] += dm * ex;
+      const float dp = dm * ar;
+      g[0] += dp * fmaf(B.w, dy, m);
+      g[1] += dp * fmaf(B.w, dx, qc);
+      const float dpx = dp * dx;
+      g[2] += dpx * dx;
+      g[3] += dpx * dy;
+      g[4] += (dp * dy) * dy;
+    }
+    if (j >= 0) {
+      const int64_t base = (int64_t)s_e[j] * 12;
+#pragma unroll
+      for (int v = 0; v < 10; ++v)
+        if (g[v] != 0.f) unsafeAtomicAdd(&g2[base + v], g[v]);
+    }
+  }
+}
+
 // ---- scratch layout and dispatch -----------------------------------------------------------
 static inline size_t a256(size_t x) { return (x + 255) & ~size_t(255); }
 
@@ -955,6 +1099,20 @@ static hipError_t fwd_impl(const ViewTable &vt, const ImgTable &it, const gs_pro
 }
 
 template <int TW, int TH, int BD, int NT>
+static hipError_t bwd_bucket_impl(const ViewTable &vt, const ImgTable &it, const GradTable &gtab,
+                                  const gs_projected &p, const uint32_t *vals, const uint32_t *range,
+                                  const BlendState &s, float *g2, hipStream_t st) {
+  if constexpr (TW == 32) {
+    return hipErrorInvalidValue;  // a 32x32 tile's pixel tables do not fit beside the staged splats
+  } else {
+    hipLaunchKernelGGL((k_blend_bwd_bucket<TW, TH, BD>), dim3((unsigned)s.I), dim3(64), 0, st, vt, it, gtab,
+                       (const Card *)p.card, vals, range, (const uint2 *)s.items, (const uint32_t *)s.n_items,
+                       (const ChunkRec *)s.chunk, g2);
+    return hipGetLastError();
+  }
+}
+
+template <int TW, int TH, int BD, int NT>
 static hipError_t bwd_impl(const ViewTable &vt, const ImgTable &it, const GradTable &gtab, const gs_projected &p,
                            const uint32_t *vals, const uint32_t *range, const BlendState &s, float *g2,
                            hipStream_t st) {
@@ -994,9 +1152,10 @@ hipError_t launch_blend_fwd(int bd, const ViewTable &vt, const ImgTable &it, con
 
 hipError_t launch_blend_bwd(int bd, const ViewTable &vt, const ImgTable &it, const GradTable &gtab,
                             const gs_projected &p, const uint32_t *vals, const uint32_t *range, void *state,
-                            int64_t cap, float *g2, hipStream_t st) {
+                            int64_t cap, float *g2, hipStream_t st, int schedule) {
   if (vt.total_tiles == 0) return hipSuccess;
   const BlendState s = carve_state(state, vt.total_tiles, cap, vt.tile_w, vt.tile_h, bd);
+  if (schedule == GS_BWD_BUCKETS) GS_BLEND_DISPATCH(bwd_bucket_impl, vt, it, gtab, p, vals, range, s, g2, st);
   GS_BLEND_DISPATCH(bwd_impl, vt, it, gtab, p, vals, range, s, g2, st);
 }
 

@@ -35,7 +35,7 @@ hipError_t launch_blend_fwd(int bd, const ViewTable &vt, const ImgTable &it, con
                             const uint32_t *vals, const uint32_t *range, void *state, int64_t cap, hipStream_t st);
 hipError_t launch_blend_bwd(int bd, const ViewTable &vt, const ImgTable &it, const GradTable &gtab,
                             const gs_projected &p, const uint32_t *vals, const uint32_t *range, void *state,
-                            int64_t cap, float *g2, hipStream_t st);
+                            int64_t cap, float *g2, hipStream_t st, int schedule = GS_BWD_CHUNKS);
 hipError_t launch_lidar_loss(const LidarTable &lt, const ImgTable &it, int max_m, hipStream_t st);
 hipError_t launch_grad_maps(const MapSrc &src, const MapTable &dst, int n_views, int64_t max_npx,
                             const LidarTable &lt, const ImgTable &it, int max_m, hipStream_t st);
