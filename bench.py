@@ -223,7 +223,7 @@ def measure_batched(R, N, torch, S, g, gm, tile, bd, dev, reps=20):
     """8 keyframes of the same map (uneven intrinsics and resolutions) per optimisation pass:
     one graph-captured fwd+bwd batch (tile size and chunk length from the autotuner) against 8
     sequential plain fwd+bwd calls on the same stream."""
-    from paper_2507_04004_amd.autotune import autotune
+    from paper_2507_04004_amd.autotune import SCHEDULE_NAMES, autotune_config
     from paper_2507_04004_amd.batch import BatchPlan, ViewSlot
     cams = S.keyframe_cameras(8, seed=2)
     total_px = sum(c.w * c.h for c in cams)
@@ -247,15 +247,18 @@ def measure_batched(R, N, torch, S, g, gm, tile, bd, dev, reps=20):
         pix, ds = lidar_targets(sl.frame, S.lidar_beams(c, 32, 30.0, 0.32, seed=200 + k))
         lidars.append((pix, ds))
     del tslots
-    tile_b, bd_b, timings = autotune(gm, cams, backward=True, candidates=[(8, 128), (8, 256), (16, 128)],
-                                     capacity=cap, reps=3, warmup=1, device=dev, targets=targets)
+    tuned = autotune_config(gm, cams, backward=True,
+                            candidates=[(8, 128), (8, 256), (16, 128), (8, 128, N.GS_BWD_BUCKETS),
+                                        (16, 128, N.GS_BWD_BUCKETS)],
+                            capacity=cap, reps=3, warmup=1, device=dev, targets=targets)
+    tile_b, bd_b, sched_b, timings = tuned["tile"], tuned["blend_depth"], tuned["schedule"], tuned["timings"]
     plan = BatchPlan(gm.n, gm.sh_degree, 8, total_px, tile_b, bd_b, cap, dev)
     slots = [ViewSlot.make(c, dev, backward=True, target=targets[k],
                            lidar=R.LidarHits(torch.from_numpy(lidars[k][0]).to(dev),
                                              torch.from_numpy(lidars[k][1]).to(dev), weight=1.0))
              for k, c in enumerate(cams)]
     grads = R.ParamGrads.empty(gm)
-    run = lambda: plan.run(gm, slots, fwd=True, bwd=True, grads=grads, graph=True, overwrite=True)
+    run = lambda: plan.run(gm, slots, fwd=True, bwd=True, grads=grads, graph=True, overwrite=True, schedule=sched_b)
     ms_b = timed(torch, run, reps, 3)
     assert plan.num_pairs() <= plan.capacity
     plan.close()
@@ -268,6 +271,7 @@ def measure_batched(R, N, torch, S, g, gm, tile, bd, dev, reps=20):
     ms_s = timed(torch, run_seq, reps, 3)
     del seq
     return {"views": 8, "pixels": total_px, "tile": tile_b, "blend_depth": bd_b,
+            "bwd_schedule": SCHEDULE_NAMES[sched_b],
             "autotune_ms": {k: round(v, 4) for k, v in timings.items()},
             "batched_graph_ms": round(ms_b, 4), "batched_views_s": round(8e3 / ms_b, 2),
             "sequential_plain_ms": round(ms_s, 4), "sequential_views_s": round(8e3 / ms_s, 2),
@@ -599,6 +603,24 @@ def main():
     rlat = sorted(a.elapsed_time(b) for a, b in evr)
     pct = lambda xs, q: xs[min(len(xs) - 1, int(round(q * (len(xs) - 1))))]
 
+    # ---- the two compositing-backward schedules on the same step (stage events) ---------------
+    sched_ms = {}
+    for name, sc in (("chunks", N.GS_BWD_CHUNKS), ("buckets", N.GS_BWD_BUCKETS)):
+        if sc == N.GS_BWD_BUCKETS and args.tile == 32:
+            continue
+        ps.s_grads.schedule = sc
+        for _ in range(2):
+            ps.step()
+        N.check(L.gs_profile_enable(1 << N.GS_STAGE_BLEND_BWD, 10))
+        for _ in range(10):
+            ps.step()
+        tot, cnt = C.c_double(), C.c_int32()
+        N.check(L.gs_profile_read(N.GS_STAGE_BLEND_BWD, C.byref(tot), C.byref(cnt)))
+        L.gs_profile_disable()
+        sched_ms[name] = round(tot.value / max(cnt.value, 1), 4)
+    ps.s_grads.schedule = N.GS_BWD_CHUNKS
+    log(f"[bench] compositing backward by schedule (ms): {sched_ms}")
+
     # ---- counts for the roofline (untimed) -----------------------------------------------------
     P = ps.bins.pairs()
     assert P <= ps.capacity, "pair capacity overflow during timing"
@@ -671,6 +693,7 @@ def main():
                        "render_p50": round(pct(rlat, 0.5), 4), "render_p99": round(pct(rlat, 0.99), 4),
                        "calls": n_lat},
         "stages": per_stage,
+        "bwd_schedule_ms": sched_ms,
         "roofline": roofline,
     }
     gC_cpu = None

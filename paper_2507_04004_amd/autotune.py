@@ -1,10 +1,11 @@
-"""Tile-size / blend-depth autotuner for the batched rasterizer.
+"""Tile-size / blend-depth / backward-schedule autotuner for the batched rasterizer.
 
-Times each candidate (tile size in {8, 16, 32}, LDS batch depth in {64, 128, 256}) on the
-real workload (the same map and views, graph-captured, fwd or fwd+bwd) and keeps the fastest.
-The image does not depend on the choice (every pixel composites the same records in the same
-order), so the tuner may pick freely. Results are cached in a JSON file keyed by the workload
-shape.
+Times each candidate (tile size in {8, 16, 32}, LDS batch depth in {64, 128, 256}, and for a
+backward the compositing-backward schedule: pixel-parallel chunks or per-Gaussian buckets) on
+the real workload (the same map and views, graph-captured, fwd or fwd+bwd) and keeps the
+fastest. The image does not depend on the choice (every pixel composites the same records in
+the same order) and the gradients only through float32 summation order, so the tuner may pick
+freely. Results are cached in a JSON file keyed by the workload shape.
 """
 from __future__ import annotations
 
@@ -14,10 +15,23 @@ import statistics
 
 import torch
 
+from . import _native as N
 from . import raster as R
 from .batch import BatchPlan, ViewSlot
 
-DEFAULT_CANDIDATES = [(8, 128), (8, 256), (16, 128), (16, 256), (32, 256)]
+# (tile, chunk length[, backward schedule]); the bucketed schedule runs on 8x8 and 16x16 tiles
+DEFAULT_CANDIDATES = [(8, 128), (8, 256), (16, 128), (16, 256), (32, 256), (8, 128, N.GS_BWD_BUCKETS),
+                      (16, 128, N.GS_BWD_BUCKETS)]
+SCHEDULE_NAMES = {N.GS_BWD_CHUNKS: "chunks", N.GS_BWD_BUCKETS: "buckets"}
+
+
+def _split(c):
+    return (c[0], c[1], c[2]) if len(c) > 2 else (c[0], c[1], N.GS_BWD_CHUNKS)
+
+
+def candidate_key(tile, bd, schedule=N.GS_BWD_CHUNKS) -> str:
+    k = f"{tile}x{tile}/{bd}"
+    return k if schedule == N.GS_BWD_CHUNKS else f"{k}/{SCHEDULE_NAMES[schedule]}"
 
 
 def workload_key(gm: R.GaussianMap, cams, backward: bool) -> str:
@@ -25,7 +39,7 @@ def workload_key(gm: R.GaussianMap, cams, backward: bool) -> str:
     return f"n={gm.n};deg={gm.sh_degree};bwd={int(backward)};views={shapes}"
 
 
-def _time_candidate(gm, cams, tile, bd, backward, capacity, reps, warmup, device, targets):
+def _time_candidate(gm, cams, tile, bd, backward, capacity, reps, warmup, device, targets, schedule):
     plan = BatchPlan(gm.n, gm.sh_degree, len(cams), sum(c.w * c.h for c in cams), tile=tile, blend_depth=bd,
                      capacity=capacity, device=device)
     try:
@@ -35,7 +49,7 @@ def _time_candidate(gm, cams, tile, bd, backward, capacity, reps, warmup, device
             for s, c in zip(slots, cams):  # a fixed upstream gradient stands in for the loss
                 s.dL_dC = torch.full((3, c.h, c.w), 1.0 / (3 * c.w * c.h), device=device)
         grads = R.ParamGrads.zeros(gm) if backward else None
-        run = lambda: plan.run(gm, slots, fwd=True, bwd=backward, grads=grads, graph=True)
+        run = lambda: plan.run(gm, slots, fwd=True, bwd=backward, grads=grads, graph=True, schedule=schedule)
         run()
         if plan.num_pairs() > plan.capacity:
             return float("inf"), plan.num_pairs()
@@ -52,10 +66,11 @@ def _time_candidate(gm, cams, tile, bd, backward, capacity, reps, warmup, device
         plan.close()
 
 
-def autotune(gm: R.GaussianMap, cams, backward: bool = True, candidates=None, capacity: int | None = None,
-             reps: int = 5, warmup: int = 2, device="cuda", cache_path: str | None = None, targets=None,
-             verbose: bool = False):
-    """Returns (tile, blend_depth, timings) for this workload; consults / updates the cache."""
+def autotune_config(gm: R.GaussianMap, cams, backward: bool = True, candidates=None, capacity: int | None = None,
+                    reps: int = 5, warmup: int = 2, device="cuda", cache_path: str | None = None, targets=None,
+                    verbose: bool = False) -> dict:
+    """{"tile", "blend_depth", "schedule", "timings"} of the fastest candidate for this workload;
+    consults / updates the cache. Without a backward the schedule plays no part."""
     key = workload_key(gm, cams, backward)
     cache = {}
     if cache_path and os.path.exists(cache_path):
@@ -63,19 +78,37 @@ def autotune(gm: R.GaussianMap, cams, backward: bool = True, candidates=None, ca
             cache = json.load(fh)
         if key in cache:
             e = cache[key]
-            return e["tile"], e["blend_depth"], e.get("timings", {})
+            return {"tile": e["tile"], "blend_depth": e["blend_depth"],
+                    "schedule": e.get("schedule", N.GS_BWD_CHUNKS), "timings": e.get("timings", {})}
     timings = {}
     best = None
-    for tile, bd in (candidates or DEFAULT_CANDIDATES):
-        ms, pairs = _time_candidate(gm, cams, tile, bd, backward, capacity, reps, warmup, device, targets)
-        timings[f"{tile}x{tile}/{bd}"] = ms
+    seen = set()
+    for c in (candidates or DEFAULT_CANDIDATES):
+        tile, bd, sched = _split(c)
+        if not backward:
+            sched = N.GS_BWD_CHUNKS
+        if (tile, bd, sched) in seen or (sched == N.GS_BWD_BUCKETS and tile == 32):
+            continue
+        seen.add((tile, bd, sched))
+        ms, pairs = _time_candidate(gm, cams, tile, bd, backward, capacity, reps, warmup, device, targets, sched)
+        timings[candidate_key(tile, bd, sched)] = ms
         if verbose:
-            print(f"[autotune] tile={tile} depth={bd}: {ms:.3f} ms (pairs {pairs})", flush=True)
+            print(f"[autotune] tile={tile} depth={bd} schedule={SCHEDULE_NAMES[sched]}: {ms:.3f} ms "
+                  f"(pairs {pairs})", flush=True)
         if best is None or ms < best[0]:
-            best = (ms, tile, bd)
-    _, tile, bd = best
+            best = (ms, tile, bd, sched)
+    _, tile, bd, sched = best
+    out = {"tile": tile, "blend_depth": bd, "schedule": sched, "timings": timings}
     if cache_path:
-        cache[key] = {"tile": tile, "blend_depth": bd, "timings": timings}
+        cache[key] = out
         with open(cache_path, "w") as fh:
             json.dump(cache, fh, indent=1)
-    return tile, bd, timings
+    return out
+
+
+def autotune(gm: R.GaussianMap, cams, backward: bool = True, candidates=None, capacity: int | None = None,
+             reps: int = 5, warmup: int = 2, device="cuda", cache_path: str | None = None, targets=None,
+             verbose: bool = False):
+    """(tile, blend_depth, timings) of autotune_config."""
+    r = autotune_config(gm, cams, backward, candidates, capacity, reps, warmup, device, cache_path, targets, verbose)
+    return r["tile"], r["blend_depth"], r["timings"]

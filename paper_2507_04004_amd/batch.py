@@ -72,12 +72,13 @@ class BatchPlan:
             pass
 
     def run(self, gm: R.GaussianMap, views: list[ViewSlot], fwd=True, bwd=False, grads: R.ParamGrads | None = None,
-            graph=False, grad_scratch=None, overwrite=False):
-        """overwrite=False adds the batch's gradients to `grads`; True writes every element."""
+            graph=False, grad_scratch=None, overwrite=False, schedule: int = N.GS_BWD_CHUNKS):
+        """overwrite=False adds the batch's gradients to `grads`; True writes every element.
+        schedule: the compositing-backward schedule (GS_BWD_CHUNKS or GS_BWD_BUCKETS)."""
         mode = (N.GS_FWD if fwd else 0) | (N.GS_BWD if bwd else 0) | (N.GS_GRAPH if graph else 0)
         arr = (N.View * len(views))(*[v.struct() for v in views])
         gs = gm.struct()
-        gst = (grads.struct(torch.empty(0, dtype=torch.uint8, device=self.device), overwrite)
+        gst = (grads.struct(torch.empty(0, dtype=torch.uint8, device=self.device), overwrite, schedule)
                if grads is not None else None)
         self._keep = (arr, gs, gst)
         st = C.c_void_p(torch.cuda.current_stream().cuda_stream)
