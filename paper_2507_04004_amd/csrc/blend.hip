@@ -866,8 +866,9 @@ __global__ __launch_bounds__(NT) void k_blend_bwd_chunk(ViewTable vt, ImgTable i
 // The backward schedule of Sec. "CUDA-Related Acceleration Strategies" (per-Gaussian
 // buckets), for 8x8 and 16x16 tiles: one wavefront per (tile, chunk) item; the chunk's splats,
 // back to front, are taken in buckets of 64, lane L owning splat top - L of the bucket. The
-// tile's pixels stream through the lanes: in step s lane L works on pixel s - L, so every pixel
-// meets the bucket's splats in back-to-front order, one per step. A pixel's running state
+// pixels that can have a contributor in the bucket (last contributor at or behind its front
+// splat) stream through the lanes: in step s lane L works on the (s - L)-th of them, so every
+// such pixel meets the bucket's splats in back-to-front order, one per step. A pixel's running state
 // (transmittance and the colour and depth behind) lives in LDS: the lane that takes the pixel
 // reads the state its neighbour wrote in the previous step and writes it back (LDS operations
 // of one wavefront stay in program order). Per (splat, pixel) the operations are those of
@@ -891,6 +892,7 @@ __global__ __launch_bounds__(64) void k_blend_bwd_bucket(ViewTable vt, ImgTable 
   __shared__ float sT[NPIX], sA0[NPIX], sA1[NPIX], sA2[NPIX], sAD[NPIX];
   __shared__ float sTfin[NPIX], sGC0[NPIX], sGC1[NPIX], sGC2[NPIX], sGD[NPIX], sGOb[NPIX];
   __shared__ int sLL[NPIX];
+  __shared__ int s_list[NPIX];  // pixels that can have a contributor in the current bucket
   __shared__ int s_max;
   uint32_t item;
   if (!item_of_block(n_items, item)) return;
@@ -955,10 +957,23 @@ __global__ __launch_bounds__(64) void k_blend_bwd_bucket(ViewTable vt, ImgTable 
     float g[10];
 #pragma unroll
     for (int v = 0; v < 10; ++v) g[v] = 0.f;
-    const int steps = NPIX + min(top, NT - 1);
+    // only pixels whose last contributor is at or behind the bucket's front splat pass through
+    // it (the others keep their state); they are listed in tile order with wavefront ballots
+    const int lo = max(top - (NT - 1), 0);
+    int nact = 0;
+#pragma unroll
+    for (int k = 0; k < NPIX / NT; ++k) {
+      const int q = lane + NT * k;
+      const bool a = sLL[q] >= lo;
+      const uint64_t m = __ballot(a);
+      if (a) s_list[nact + __popcll(m & lanemask_lt())] = q;
+      nact += __popcll(m);
+    }
+    const int steps = nact + (top - lo);
     for (int st = 0; st < steps; ++st) {
-      const int q = st - lane;
-      if (j < 0 || q < 0 || q >= NPIX) continue;
+      const int r = st - lane;
+      if (j < 0 || r < 0 || r >= nact) continue;
+      const int q = s_list[r];
       const float px = x0 + (float)(q % TW), py = y0 + (float)(q / TW);
       const float dx = px - A.x, dy = py - A.y;
       float m, qc;
