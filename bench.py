@@ -85,7 +85,7 @@ def measured_traffic(kernel: str, tile: int, bd: int):
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--steps", type=int, default=100)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--latency-calls", type=int, default=200)
     ap.add_argument("--n", type=int, default=1_000_000)
