@@ -1,0 +1,65 @@
+"""Autotuner selection logic without a GPU: the timing of one candidate is replaced by a stub,
+so the test checks which candidates are tried (the bucketed schedule only at 8x8 and 16x16,
+no duplicates, no schedule without a backward), that the fastest is kept, and that the cache
+returns the same choice, schedule included."""
+import dataclasses
+import json
+
+import numpy as np
+
+from paper_2507_04004_amd import _native as N
+from paper_2507_04004_amd import autotune as A
+
+
+@dataclasses.dataclass
+class _Map:
+    n: int = 1000
+    sh_degree: int = 3
+
+
+@dataclasses.dataclass
+class _Cam:
+    w: int = 64
+    h: int = 48
+    fx: float = 50.0
+
+
+def test_candidates_selection_and_cache(monkeypatch, tmp_path):
+    tried = []
+    cost = {(8, 128, 0): 5.0, (8, 256, 0): 6.0, (16, 128, 0): 7.0, (16, 256, 0): 8.0, (32, 256, 0): 9.0,
+            (8, 128, 1): 4.0, (16, 128, 1): 4.5}
+
+    def fake(gm, cams, tile, bd, backward, capacity, reps, warmup, device, targets, schedule):
+        tried.append((tile, bd, schedule))
+        return cost[(tile, bd, schedule)], 123
+
+    monkeypatch.setattr(A, "_time_candidate", fake)
+    cache = tmp_path / "tune.json"
+    cands = A.DEFAULT_CANDIDATES + [(8, 128), (32, 256, N.GS_BWD_BUCKETS)]
+    r = A.autotune_config(_Map(), [_Cam()], backward=True, candidates=cands, cache_path=str(cache))
+    assert (r["tile"], r["blend_depth"], r["schedule"]) == (8, 128, N.GS_BWD_BUCKETS)
+    assert len(tried) == len(set(tried)) == 7                      # duplicate and 32x32 buckets skipped
+    assert (32, 256, N.GS_BWD_BUCKETS) not in tried
+    assert r["timings"]["8x8/128/buckets"] == 4.0 and r["timings"]["8x8/128"] == 5.0
+    # the cache answers without timing again, schedule included
+    tried.clear()
+    r2 = A.autotune_config(_Map(), [_Cam()], backward=True, candidates=cands, cache_path=str(cache))
+    assert not tried and r2["schedule"] == N.GS_BWD_BUCKETS and r2["tile"] == 8
+    assert json.loads(cache.read_text())
+    # the three-value form keeps its shape
+    t, b, timings = A.autotune(_Map(), [_Cam()], backward=True, candidates=cands, cache_path=str(cache))
+    assert (t, b) == (8, 128) and "8x8/128/buckets" in timings
+
+
+def test_forward_only_ignores_schedules(monkeypatch):
+    tried = []
+
+    def fake(gm, cams, tile, bd, backward, capacity, reps, warmup, device, targets, schedule):
+        tried.append((tile, bd, schedule))
+        return float(tile + bd / 1000.0 + np.float64(schedule)), 1
+
+    monkeypatch.setattr(A, "_time_candidate", fake)
+    r = A.autotune_config(_Map(), [_Cam()], backward=False)
+    assert all(s == N.GS_BWD_CHUNKS for _, _, s in tried)
+    assert len(tried) == len(set(tried))
+    assert r["schedule"] == N.GS_BWD_CHUNKS and r["tile"] == 8
