@@ -62,9 +62,18 @@ def lib():
         _lib.or_sh_basis.argtypes = [C.c_int64, d, C.c_int, d]
         _lib.or_rect_qmin.argtypes = [C.c_double] * 9
         _lib.or_rect_qmin.restype = C.c_double
-        _lib.or32_bin.argtypes = [C.c_int64, f, f, f, f, C.POINTER(B32Camera), C.c_int, C.c_int, C.c_uint32,
-                                  C.c_uint32, u32, i32, u32, C.c_int64, u32, u32, u32, i64]
+        _lib.or_lists.argtypes = [G, Cm, C.c_int, C.c_int, i64, i32]
+        _lib.or_pair_margins.argtypes = [G, Cm, C.c_int, C.c_int, C.c_int64, i32, i32, i8, d]
+        bind_bin32(_lib)
     return _lib
+
+
+def bind_bin32(handle):
+    """Argument types of or32_bin on a loaded library (the oracle's, or a test's own build)."""
+    f, i32, i64, u32 = (C.POINTER(t) for t in (C.c_float, C.c_int32, C.c_int64, C.c_uint32))
+    handle.or32_bin.argtypes = [C.c_int64, f, f, f, f, C.POINTER(B32Camera), C.c_int, C.c_int, C.c_uint32,
+                                C.c_uint32, u32, i32, u32, C.c_int64, u32, u32, u32, i64]
+    return handle
 
 
 def _p(a, ct):
@@ -223,9 +232,10 @@ def replay(g, cam, fz: Frozen):
     return out
 
 
-def bin32(g, cam, tile=16, tile_base=0, id_base=0):
-    """FP32 binning: per-Gaussian tile counts, rects, depth keys; sorted pair ids and tile ranges."""
-    L = lib()
+def bin32(g, cam, tile=16, tile_base=0, id_base=0, handle=None):
+    """FP32 binning: per-Gaussian tile counts, rects, depth keys; sorted pair ids and tile ranges.
+    handle: a library exporting or32_bin (bound with bind_bin32); the oracle's own by default."""
+    L = lib() if handle is None else handle
     n = g.n
     f = lambda a: np.ascontiguousarray(a, np.float32)
     mean, scale, rot, opac = f(g.mean), f(g.scale), f(g.rot), f(g.opacity)
@@ -250,3 +260,32 @@ def bin32(g, cam, tile=16, tile_base=0, id_base=0):
                tw, th, tile_base, id_base, _p(n_tiles, C.c_uint32), _p(rect, C.c_int32), _p(dkey, C.c_uint32), P,
                _p(vals, C.c_uint32), _p(tiles, C.c_uint32), _p(tr, C.c_uint32), _p(num, C.c_int64))
     return dict(n_tiles=n_tiles, rect=rect, dkey=dkey, vals=vals[:P], tiles=tiles[:P], tile_range=tr, num_pairs=P)
+
+
+def lists(g, cam, tile=16):
+    """FP64 tile lists (no marginal band): start [T+1] and ids, each tile in (depth, id) order."""
+    L = lib()
+    k = _Keep(g)
+    cs = _cam(cam)
+    tw, th = (tile, tile) if np.isscalar(tile) else tile
+    T = ((cam.w + tw - 1) // tw) * ((cam.h + th - 1) // th)
+    start = np.zeros(T + 1, np.int64)
+    assert L.or_lists(C.byref(k.struct), C.byref(cs), tw, th, _p(start, C.c_int64), None) == 0
+    ids = np.zeros(max(int(start[-1]), 1), np.int32)
+    assert L.or_lists(C.byref(k.struct), C.byref(cs), tw, th, _p(start, C.c_int64), _p(ids, C.c_int32)) == 0
+    return dict(start=start, ids=ids[:int(start[-1])])
+
+
+def pair_margins(g, cam, gid, tile_ids, tile=16):
+    """FP64 decision and relative margin of each queried (Gaussian, window tile) pair."""
+    L = lib()
+    k = _Keep(g)
+    cs = _cam(cam)
+    tw, th = (tile, tile) if np.isscalar(tile) else tile
+    gid = np.ascontiguousarray(gid, np.int32)
+    tid = np.ascontiguousarray(tile_ids, np.int32)
+    listed = np.zeros(gid.size, np.int8)
+    margin = np.zeros(gid.size)
+    L.or_pair_margins(C.byref(k.struct), C.byref(cs), tw, th, gid.size, _p(gid, C.c_int32), _p(tid, C.c_int32),
+                      _p(listed, C.c_int8), _p(margin, C.c_double))
+    return listed.astype(bool), margin

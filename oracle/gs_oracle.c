@@ -269,8 +269,10 @@ void or_project(const or_gaussians *G, const or_camera *cam,
 /* Minimum of q(D) = a Dx^2 + 2 b Dx Dy + c Dy^2 over the rectangle [xl,xh] x [yl,yh] of
  * pixel-centre positions, D = position - (u, v). Zero when the centre is inside; otherwise
  * the minimum of the 1-D constrained minima on the edges that face the centre. */
-static double rect_qmin(double u, double v, double a, double b, double c, double xl, double xh, double yl, double yh) {
+static double rect_qmin_arg(double u, double v, double a, double b, double c, double xl, double xh, double yl,
+                            double yh, double *arg_dx, double *arg_dy) {
   int inx = u >= xl && u <= xh, iny = v >= yl && v <= yh;
+  *arg_dx = *arg_dy = 0.0;
   if (inx && iny) return 0.0;
   double best = INFINITY;
   if (!inx) {
@@ -279,7 +281,7 @@ static double rect_qmin(double u, double v, double a, double b, double c, double
     if (dy < yl - v) dy = yl - v;
     if (dy > yh - v) dy = yh - v;
     double q = a * dx * dx + 2 * b * dx * dy + c * dy * dy;
-    if (q < best) best = q;
+    if (q < best) { best = q; *arg_dx = dx; *arg_dy = dy; }
   }
   if (!iny) {
     double dy = (v < yl ? yl : yh) - v;
@@ -287,9 +289,14 @@ static double rect_qmin(double u, double v, double a, double b, double c, double
     if (dx < xl - u) dx = xl - u;
     if (dx > xh - u) dx = xh - u;
     double q = a * dx * dx + 2 * b * dx * dy + c * dy * dy;
-    if (q < best) best = q;
+    if (q < best) { best = q; *arg_dx = dx; *arg_dy = dy; }
   }
   return best;
+}
+
+static double rect_qmin(double u, double v, double a, double b, double c, double xl, double xh, double yl, double yh) {
+  double dx, dy;
+  return rect_qmin_arg(u, v, a, b, c, xl, xh, yl, yh, &dx, &dy);
 }
 
 double or_rect_qmin(double u, double v, double a, double b, double c, double xl, double xh, double yl, double yh) {
@@ -825,4 +832,98 @@ void or_project_one(const or_gaussians *G, const or_camera *cam, int64_t k, doub
                   p.hx, p.hy, p.rgb[0], p.rgb[1], p.rgb[2], p.J[0], p.J[2], p.J[4], p.J[5],
                   p.Sig[0], p.Sig[1], p.Sig[2], p.Sig[4], p.Sig[5], p.Sig[8], p.clx, p.cly, p.dist, p.o};
   memcpy(out, v, sizeof v);
+}
+
+/* ------------------------------------------------------------------------------------------ */
+/* Float64 tile lists and the margin of each (Gaussian, tile) decision.                        */
+/* ------------------------------------------------------------------------------------------ */
+/* The float64 tile lists (no marginal band) as CSR over the window's tiles: start [T+1] and,
+ * when ids != NULL, ids [start[T]] with each tile's Gaussians in (depth, index) order. */
+int or_lists(const or_gaussians *G, const or_camera *cam, int bw, int bh, int64_t *start, int32_t *ids) {
+  if (bw <= 0 || bh <= 0 || cam->w <= 0 || cam->h <= 0) return 1;
+  proj *P = project_all(G, cam);
+  tiling tg = make_tiling(cam, bw, bh);
+  tile_lists L;
+  build_lists(P, G->n, cam, &tg, 1, 0.0, &L);
+  const int64_t T = (int64_t)tg.tiles_x * tg.tiles_y;
+  memcpy(start, L.start, (size_t)(T + 1) * sizeof(int64_t));
+  if (ids && L.start[T] > 0) memcpy(ids, L.ids, (size_t)L.start[T] * sizeof(int32_t));
+  free(L.start); free(L.ids); free(P);
+  return 0;
+}
+
+/* A conjunction of conditions c_i (true when the signed margin m_i >= 0) flips when its
+ * smallest margin does if it holds, and only when every false term flips if it does not. */
+typedef struct {
+  int all_true;
+  double min_true, max_false;
+} conj;
+
+static void conj_add(conj *c, double m) {
+  if (m >= 0) {
+    if (m < c->min_true) c->min_true = m;
+  } else {
+    c->all_true = 0;
+    if (-m > c->max_false) c->max_false = -m;
+  }
+}
+
+/* For m queried pairs (Gaussian gid[i], window tile tile[i]): listed[i] = the float64
+ * decision, margin[i] = its relative distance from flipping. A pair exists when the Gaussian
+ * is valid, the tile's clipped pixel-centre rectangle meets the footprint's pixel span
+ * [u - hx, u + hx] x [v - hy, v + hy], and the largest weight over the tile,
+ * o exp(-q_min / 2), is at least 1/255 (Sec. "CUDA-Related Acceleration Strategies", fast
+ * tile-based culling). Signed relative margins of the rounded comparisons:
+ *   depth (d - 0.2) / 0.2; determinant det / (s00 s11); opacity 255 o - 1;
+ *   span ends (x_hi - (u - hx)) / s and ((u + hx) - x_lo) / s with s = max(1, |u|, hx)
+ *   (likewise in y), the pixel-centre comparisons that ceil / floor of the span ends take;
+ *   cull: the smaller of 255 o exp(-q_min / 2) - 1 (the largest weight relative to 1/255) and
+ *   (kappa^2 - q_min) / (|grad q_min| max(1, |u|, |v|)), the shift of the centre, relative to
+ *   its coordinates, that moves q_min onto kappa^2 (a float32 centre is off by a few units in
+ *   the last place of u and v, which the small footprints of distant Gaussians magnify).
+ * The exact tests (finite inputs, |q| > 0, S > 0) have no margin. */
+void or_pair_margins(const or_gaussians *G, const or_camera *cam, int bw, int bh, int64_t m, const int32_t *gid,
+                     const int32_t *tile, int8_t *listed, double *margin) {
+  tiling tg = make_tiling(cam, bw, bh);
+#pragma omp parallel for schedule(static)
+  for (int64_t i = 0; i < m; ++i) {
+    proj p;
+    project(G, cam, gid[i], &p, NULL);
+    conj c = {1, INFINITY, 0.0};
+    int exact_ok = finite3(p.m) && finite3(p.S) && isfinite(p.qraw[0]) && isfinite(p.qraw[1]) &&
+                   isfinite(p.qraw[2]) && isfinite(p.qraw[3]) && isfinite(p.o) && p.qlen > 0 && p.S[0] > 0 &&
+                   p.S[1] > 0 && p.S[2] > 0;
+    if (!exact_ok) {
+      listed[i] = 0;
+      margin[i] = INFINITY;
+      continue;
+    }
+    conj_add(&c, (p.d - OR_NEAR) / OR_NEAR);
+    if (p.d > OR_NEAR) {
+      conj_add(&c, p.det / (p.s00 * p.s11));
+      conj_add(&c, 255.0 * p.o - 1.0);
+    }
+    if (c.all_true) {
+      int tx = tile[i] % tg.tiles_x, ty = tile[i] / tg.tiles_x;
+      double xl, xh, yl, yh;
+      tile_rect(cam, &tg, tx, ty, &xl, &xh, &yl, &yh);
+      double sx = fmax(1.0, fmax(fabs(p.u), p.hx)), sy = fmax(1.0, fmax(fabs(p.v), p.hy));
+      conj_add(&c, (xh - (p.u - p.hx)) / sx);
+      conj_add(&c, ((p.u + p.hx) - xl) / sx);
+      conj_add(&c, (yh - (p.v - p.hy)) / sy);
+      conj_add(&c, ((p.v + p.hy) - yl) / sy);
+      double dx, dy;
+      double q = rect_qmin_arg(p.u, p.v, p.a, p.b, p.c, xl, xh, yl, yh, &dx, &dy);
+      /* the cull flips when the largest weight moves by its margin relative to 1/255, or when
+         the centre moves by (kappa^2 - q_min) / |grad q_min|; the gradient of the minimum with
+         respect to the centre is -2 Q D at the minimiser D (zero inside the rectangle) */
+      double wm = expm1(0.5 * (p.kappa2 - q));
+      double gx = 2.0 * (p.a * dx + p.b * dy), gy = 2.0 * (p.b * dx + p.c * dy);
+      double gn = sqrt(gx * gx + gy * gy);
+      double pm = gn > 0 ? (p.kappa2 - q) / (gn * fmax(1.0, fmax(fabs(p.u), fabs(p.v)))) : wm;
+      conj_add(&c, fabs(pm) < fabs(wm) ? pm : wm);
+    }
+    listed[i] = (int8_t)c.all_true;
+    margin[i] = c.all_true ? c.min_true : c.max_false;
+  }
 }
