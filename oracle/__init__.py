@@ -64,6 +64,9 @@ def lib():
         _lib.or_rect_qmin.restype = C.c_double
         _lib.or_lists.argtypes = [G, Cm, C.c_int, C.c_int, i64, i32]
         _lib.or_pair_margins.argtypes = [G, Cm, C.c_int, C.c_int, C.c_int64, i32, i32, i8, d]
+        _lib.or_marginal_gaussians.argtypes = [G, Cm, C.c_int, C.c_int, C.c_double, u8]
+        _lib.or_set_threads.argtypes = [C.c_int]
+        _lib.or_max_threads.restype = C.c_int
         bind_bin32(_lib)
     return _lib
 
@@ -289,3 +292,23 @@ def pair_margins(g, cam, gid, tile_ids, tile=16):
     L.or_pair_margins(C.byref(k.struct), C.byref(cs), tw, th, gid.size, _p(gid, C.c_int32), _p(tid, C.c_int32),
                       _p(listed, C.c_int8), _p(margin, C.c_double))
     return listed.astype(bool), margin
+
+
+def marginal_gaussians(g, cam, tile=16, band=1e-4):
+    """Bool [n]: Gaussians taking a decision within the relative band of a threshold (1/255,
+    0.99, or the 1e-4 stop) at some pixel of the window."""
+    L = lib()
+    k = _Keep(g)
+    cs = _cam(cam)
+    tw, th = (tile, tile) if np.isscalar(tile) else tile
+    flag = np.zeros(max(g.n, 1), np.uint8)
+    assert L.or_marginal_gaussians(C.byref(k.struct), C.byref(cs), tw, th, band, _p(flag, C.c_uint8)) == 0
+    return flag[:g.n].astype(bool)
+
+
+def set_threads(n: int) -> int:
+    """Sets the oracle's OpenMP thread count; returns the previous one."""
+    L = lib()
+    prev = L.or_max_threads()
+    L.or_set_threads(int(n))
+    return prev

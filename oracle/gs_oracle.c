@@ -30,6 +30,7 @@
  * order, which the brute-force NumPy oracle checks.
  */
 #include <math.h>
+#include <omp.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
@@ -927,3 +928,56 @@ void or_pair_margins(const or_gaussians *G, const or_camera *cam, int bw, int bh
     margin[i] = c.all_true ? c.min_true : c.max_false;
   }
 }
+
+/* Gaussians that take a marginal decision at some pixel of the window: weight within the
+ * relative band of 1/255 (enters or not) or of 0.99 (clamped or not), or the transmittance
+ * after it within the band of 1e-4 (blended or the stop). Their gradients may differ between
+ * two correct implementations by a whole pixel's term, so element-wise gradient comparisons
+ * leave them out (the pose gradient, a sum over all Gaussians, keeps them). flag [n]. */
+int or_marginal_gaussians(const or_gaussians *G, const or_camera *cam, int bw, int bh, double band, uint8_t *flag) {
+  if (bw <= 0 || bh <= 0 || cam->w <= 0 || cam->h <= 0) return 1;
+  proj *P = project_all(G, cam);
+  tiling tg = make_tiling(cam, bw, bh);
+  tile_lists L;
+  build_lists(P, G->n, cam, &tg, 1, 2.5 * band, &L);
+  memset(flag, 0, (size_t)G->n);
+  const int64_t T = (int64_t)tg.tiles_x * tg.tiles_y;
+#pragma omp parallel for schedule(dynamic, 1)
+  for (int64_t tt = 0; tt < T; ++tt) {
+    int tx = (int)(tt % tg.tiles_x), ty = (int)(tt / tg.tiles_x);
+    const int32_t *ids = L.ids + L.start[tt];
+    const int64_t len = L.start[tt + 1] - L.start[tt];
+    for (int j = 0; j < bh; ++j)
+      for (int i = 0; i < bw; ++i) {
+        int lx = tx * bw + i, ly = ty * bh + j;
+        if (lx >= cam->w || ly >= cam->h) continue;
+        double T_ = 1.0;
+        for (int64_t k = 0; k < len; ++k) {
+          const proj *p = &P[ids[k]];
+          double araw = pixel_alpha_raw(p, cam->x0 + lx, cam->y0 + ly, NULL);
+          int m = fabs(araw - OR_ALPHA_MIN) <= band * OR_ALPHA_MIN;
+          double alpha = araw < OR_ALPHA_MAX ? araw : OR_ALPHA_MAX;
+          if (alpha >= OR_ALPHA_MIN) {
+            double Tn = T_ * (1.0 - alpha);
+            m |= fabs(Tn - OR_T_MIN) <= band * OR_T_MIN;
+            m |= fabs(araw - OR_ALPHA_MAX) <= band * OR_ALPHA_MAX;
+            if (m) {
+#pragma omp atomic write
+              flag[ids[k]] = 1;
+            }
+            if (Tn < OR_T_MIN) break;
+            T_ = Tn;
+          } else if (m) {
+#pragma omp atomic write
+            flag[ids[k]] = 1;
+          }
+        }
+      }
+  }
+  free(L.start); free(L.ids); free(P);
+  return 0;
+}
+
+/* Thread count of the OpenMP loops (for timing the oracle at one and at all threads). */
+void or_set_threads(int n) { omp_set_num_threads(n > 0 ? n : 1); }
+int or_max_threads(void) { return omp_get_max_threads(); }

@@ -368,5 +368,31 @@ def render(settings: RenderSettings, gm: GaussianMap, pose_tangent: torch.Tensor
 
 
 def checkpoint_bytes(cam) -> int:
-    """Bytes the forward keeps per view for the backward's per-pixel state (T_final + last)."""
+    """Bytes of the per-pixel checkpoint of one view (final transmittance + last contributor)."""
     return int(cam.w) * int(cam.h) * 8
+
+
+def kept_bytes(spl: Splats, bins: TileBins, fr: Frame, cs: N.Camera, blend_depth: int) -> dict:
+    """Device bytes the forward of one view leaves for its backward:
+    checkpoint    final transmittance and last contributor per pixel (8 B);
+    chunk_state   the compositing work list and, per (chunk, pixel) of tiles longer than one
+                  chunk, the transmittance and colour behind the chunk (gs_image_state_bytes:
+                  `allocated` from the pair capacity, `needed` from this view's pair count);
+    tile_lists    sorted record indices (capacity) and per-tile ranges;
+    splat_records the 64-B splat cards, tile counts and depth keys of every Gaussian.
+    Reads the pair count back (synchronises)."""
+    T = tiles_of(cs, bins.tile)
+    lib = N.lib()
+    pairs = bins.pairs()
+    state_alloc = fr.state.numel() if fr.state is not None else 0
+    state_needed = lib.gs_image_state_bytes(pairs, T, bins.tile, bins.tile, blend_depth)
+    out = {
+        "checkpoint": fr.t_final.numel() * 4 + fr.last.numel() * 4,
+        "chunk_state_allocated": int(state_alloc),
+        "chunk_state_needed": int(state_needed),
+        "tile_lists": bins.vals.numel() * 4 + bins.tile_range.numel() * 4,
+        "splat_records": spl.card.numel() * 4 + spl.n_tiles.numel() * 4 + spl.dkey.numel() * 4,
+    }
+    out["total_allocated"] = out["checkpoint"] + out["chunk_state_allocated"] + out["tile_lists"] + \
+        out["splat_records"]
+    return out

@@ -11,7 +11,8 @@ from paper_2507_04004_amd import raster as R
 DEV = "cuda:0"
 IMG_ATOL = 1e-4        # colour / opacity / transmittance, max-abs, non-marginal pixels
 DEPTH_RTOL = 1e-4      # depth: 1e-4 absolute up to 1 m, 1e-4 relative beyond (float32 accumulation)
-GRAD_RTOL = 2e-3       # gradients: relative
+GRAD_RTOL = 2e-3       # gradients: relative, per element
+GRAD_ATOL = 2e-5       # per-element floor, a fraction of the block's largest element (float32 sums that cancel)
 
 
 class HipRun:
@@ -79,19 +80,48 @@ def assert_images_close(gpu, ref, mask=None):
     return e
 
 
-def grad_errors(gpu, ref, keys=("mean", "scale", "rot", "opacity", "sh_dc", "sh_rest", "pose")):
+ALL_GRADS = ("mean", "scale", "rot", "opacity", "sh_dc", "sh_rest", "pose")
+
+
+def grad_errors(gpu, ref, keys=ALL_GRADS, rtol=GRAD_RTOL, atol=GRAD_ATOL, exclude=None):
+    """Element-wise gradient comparison. For every element of a block,
+        |g - r| <= rtol |r| + atol max|r over the block|
+    (atol: the float32 summation floor for elements whose per-pixel terms cancel). Returns, per
+    block, the largest ratio of |g - r| to that bound (<= 1 passes) with the worst element.
+    exclude: bool [n], Gaussians left out of the per-Gaussian blocks (those the oracle flags as
+    taking a marginal decision at some pixel); the pose block keeps every Gaussian."""
     out = {}
     for k in keys:
         a, b = np.asarray(gpu[k], np.float64), np.asarray(ref[k], np.float64)
         if b.size == 0:
             continue
-        nb = np.linalg.norm(b)
-        out[k] = float(np.linalg.norm(a - b) / nb) if nb > 0 else float(np.linalg.norm(a))
+        if exclude is not None and k != "pose" and np.any(exclude):
+            keep = ~np.asarray(exclude, bool)
+            a, b = a[..., keep], b[..., keep]
+        a, b = a.ravel(), b.ravel()
+        if b.size == 0:
+            continue
+        scale = float(np.abs(b).max())
+        err = np.abs(a - b)
+        bound = rtol * np.abs(b) + atol * scale
+        with np.errstate(divide="ignore", invalid="ignore"):
+            ratio = np.where(bound > 0, err / np.where(bound > 0, bound, 1.0), np.where(err > 0, np.inf, 0.0))
+        i = int(np.argmax(ratio))
+        out[k] = dict(ratio=float(ratio[i]), at=i, got=float(a[i]), ref=float(b[i]),
+                      max_err_over_block_max=float(err.max() / scale) if scale > 0 else float(err.max()),
+                      n=int(b.size))
     return out
 
 
-def assert_grads_close(gpu, ref, rtol=GRAD_RTOL, keys=("mean", "scale", "rot", "opacity", "sh_dc", "sh_rest", "pose")):
-    e = grad_errors(gpu, ref, keys)
-    bad = {k: v for k, v in e.items() if v > rtol}
-    assert not bad, e
+def assert_grads_close(gpu, ref, rtol=GRAD_RTOL, keys=ALL_GRADS, atol=GRAD_ATOL, exclude=None):
+    e = grad_errors(gpu, ref, keys, rtol=rtol, atol=atol, exclude=exclude)
+    worst = {k: (round(v["ratio"], 3), v["at"], v["got"], v["ref"]) for k, v in e.items()}
+    print(f"[grads] ratio to bound, element, gpu, oracle: {worst}", flush=True)
+    bad = {k: v for k, v in e.items() if not v["ratio"] <= 1.0}
+    assert not bad, bad
     return e
+
+
+def marginal_gaussians(g, cam, tile=16):
+    """Gaussians the float64 oracle sees taking a decision within 1e-4 of a threshold."""
+    return oracle.marginal_gaussians(g, oracle_cam(cam), tile=tile, band=1e-4)

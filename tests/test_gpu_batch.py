@@ -1,8 +1,9 @@
 """Batched form (several views per launch) and hipGraph replay (needs an MI355X).
 
 Batched view k must equal the plain single-view render of view k bitwise (same per-pixel
-operation sequence); parameter gradients summed over views must match the sum of the plain
-per-view gradients (float32 atomics: 2e-3 relative) and of the oracle; graph replays must
+operation sequence); parameter gradients summed over views must match, element by element, the sum of the
+plain per-view gradients (float32 atomics) and of the oracle (2e-3 relative plus the float32
+summation floor; Gaussians taking marginal decisions in some view left out); graph replays must
 equal eager execution bitwise, replay after replay, with eager work in between.
 """
 import numpy as np
@@ -14,7 +15,7 @@ from paper_2507_04004_amd import raster as R
 from paper_2507_04004_amd import scenes as S
 from paper_2507_04004_amd.batch import BatchPlan, ViewSlot
 
-from gpu_common import DEV, HipRun, assert_grads_close, oracle_cam
+from gpu_common import DEV, HipRun, assert_grads_close, marginal_gaussians, oracle_cam
 
 pytestmark = pytest.mark.gpu
 
@@ -69,13 +70,15 @@ def test_batch_backward_matches_plain_and_oracle():
     got = {k: getattr(grads, k).cpu().numpy().astype(np.float64) for k in
            ("mean", "scale", "rot", "opacity", "sh_dc", "sh_rest")}
     ref_sum = {k: 0.0 for k in got}
+    marg = np.zeros(g.n, bool)
     for k, c in enumerate(cams):
         ref = oracle.backward(g, oracle_cam(c), *(u.astype(np.float64) for u in ups[k]))
         for key in got:
             ref_sum[key] = ref_sum[key] + ref[key]
+        marg |= marginal_gaussians(g, c)
         pose = slots[k].pose_grad.cpu().numpy().astype(np.float64)
-        assert np.linalg.norm(pose - ref["pose"]) <= 2e-3 * np.linalg.norm(ref["pose"]), (k, pose, ref["pose"])
-    assert_grads_close(got, ref_sum, keys=tuple(got))
+        assert_grads_close({"pose": pose}, ref, keys=("pose",))
+    assert_grads_close(got, ref_sum, keys=tuple(got), exclude=marg)
 
 
 def test_batch_fused_l1_and_lidar():
@@ -108,7 +111,7 @@ def test_batch_fused_l1_and_lidar():
         assert abs(slots[k].lidar_loss.item() - run.lidar_loss.item()) <= 1e-5 * max(1.0, run.lidar_loss.item())
         gr = run.backward(dC.cpu().numpy())
         tot = gr if tot is None else {key: tot[key] + gr[key] for key in tot}
-        assert np.linalg.norm(slots[k].pose_grad.cpu().numpy() - gr["pose"]) <= 2e-3 * np.linalg.norm(gr["pose"])
+        assert_grads_close({"pose": slots[k].pose_grad.cpu().numpy()}, gr, keys=("pose",))
     got = {k: getattr(grads, k).cpu().numpy().astype(np.float64) for k in ("mean", "opacity", "sh_dc", "rot")}
     assert_grads_close(got, tot, keys=tuple(got))
 
@@ -151,9 +154,8 @@ def test_graph_backward_replays():
             t.zero_()
         plan.run(gm, slots, fwd=True, bwd=True, grads=grads, graph=True)
         torch.cuda.synchronize()
-        for k, r in ref.items():
-            a = getattr(grads, k)
-            assert torch.linalg.norm(a - r) <= 1e-5 * torch.linalg.norm(r), (rep, k)
+        got = {k: getattr(grads, k).cpu().numpy() for k in ref}
+        assert_grads_close(got, {k: r.cpu().numpy() for k, r in ref.items()}, keys=tuple(ref), rtol=1e-4, atol=2e-6)
 
 
 @pytest.mark.parametrize("tile", [8, 16])
@@ -181,9 +183,9 @@ def test_graph_backward_bucketed_schedule_equals_chunks(tile):
             s.pose_grad.zero_()
         plan.run(gm, slots, fwd=True, bwd=True, grads=grads, graph=True, overwrite=True, schedule=N.GS_BWD_BUCKETS)
         torch.cuda.synchronize()
-        for k, r in ref.items():
-            a = getattr(grads, k)
-            assert torch.linalg.norm(a - r) <= 1e-5 * torch.linalg.norm(r), (rep, k)
+        got = {k: getattr(grads, k).cpu().numpy() for k in ref}
+        assert_grads_close(got, {k: r.cpu().numpy() for k, r in ref.items()}, keys=tuple(ref), rtol=1e-4, atol=2e-6)
         for s, r in zip(slots, ref_pose):
-            assert torch.linalg.norm(s.pose_grad - r) <= 1e-5 * torch.linalg.norm(r), rep
+            assert_grads_close({"pose": s.pose_grad.cpu().numpy()}, {"pose": r.cpu().numpy()}, keys=("pose",),
+                               rtol=1e-4, atol=2e-6)
         torch.randn(100, device=DEV).sum().item()  # eager work between replays

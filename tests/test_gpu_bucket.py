@@ -1,9 +1,10 @@
 """The per-Gaussian bucketed compositing backward (GS_BWD_BUCKETS, needs an MI355X): gradients
-against the float64 oracle within 2e-3 relative (norm per parameter block), and against the
-pixel-parallel schedule on the same forward. The two schedules apply the same operations to
+against the float64 oracle element by element (2e-3 relative plus the float32 summation floor,
+Gaussians taking marginal decisions left out), and against the pixel-parallel schedule on the
+same forward. The two schedules apply the same operations to
 every pixel's state in the same order and differ only in the order in which a splat's terms
 are summed (lane-serial over the tile's pixels here, a wavefront tree there), so they agree to
-float32 summation rounding (1e-5 relative per block). Tiles 8x8 and 16x16, chunk lengths 64,
+float32 summation rounding (per element 1e-4 relative plus 2e-6 of the block's largest). Tiles 8x8 and 16x16, chunk lengths 64,
 128 and 256, lists of many chunks, and RGB, depth and opacity upstream gradients; 32x32 tiles
 are refused with GS_ERR_UNSUPPORTED.
 """
@@ -14,7 +15,7 @@ import oracle
 from paper_2507_04004_amd import _native as N
 from paper_2507_04004_amd import scenes as S
 
-from gpu_common import HipRun, assert_grads_close, grad_errors, oracle_cam
+from gpu_common import HipRun, assert_grads_close, marginal_gaussians, oracle_cam
 from test_gpu_parity import CASES, dense_tile
 
 pytestmark = pytest.mark.gpu
@@ -30,12 +31,9 @@ def test_bucketed_backward_matches_oracle_and_chunks(case, tile, bd):
     gC, gD, gO = gC.reshape(3, cam.h, cam.w), gD.reshape(cam.h, cam.w), gO.reshape(cam.h, cam.w)
     got = run.backward(gC, gD, gO, schedule=N.GS_BWD_BUCKETS)
     ref = oracle.backward(g, oracle_cam(cam), gC.astype(np.float64), gD.astype(np.float64), gO.astype(np.float64))
-    e = grad_errors(got, ref)
     chunks = run.backward(gC, gD, gO, schedule=N.GS_BWD_CHUNKS)
-    d = grad_errors(got, chunks)
-    print(f"[bucket] against the oracle {e}; against the chunk schedule {d}", flush=True)
-    assert_grads_close(got, ref)
-    assert all(v <= 1e-5 for v in d.values()), d
+    assert_grads_close(got, ref, exclude=marginal_gaussians(g, cam))
+    assert_grads_close(got, chunks, rtol=1e-4, atol=2e-6)
 
 
 def test_bucketed_backward_overwrite_and_refusals():

@@ -1,7 +1,8 @@
 """Differentiation at full map size (needs an MI355X): a frozen 2M-Gaussian street map, the
 pose gradient and per-Gaussian gradients on a centred 256x192 window of a 1280x720 view,
-against the float64 oracle (2e-3 relative), whose own pose gradient is checked by central
-finite differences on the frozen branch at the same size."""
+against the float64 oracle element by element (2e-3 relative plus the float32 summation floor),
+whose own pose gradient is checked by central finite differences on the frozen branch at the
+same size."""
 import math
 
 import numpy as np
@@ -11,7 +12,7 @@ import oracle
 from paper_2507_04004_amd import raster as R
 from paper_2507_04004_amd import scenes as S
 
-from gpu_common import DEV, GRAD_RTOL, HipRun, oracle_cam
+from gpu_common import DEV, HipRun, assert_grads_close, marginal_gaussians, oracle_cam
 
 pytestmark = pytest.mark.gpu
 
@@ -58,15 +59,20 @@ def test_c4_gradients_match_oracle(c4):
     got = run.backward(gC.astype(np.float32))
     print("[c4] oracle backward", flush=True)
     an = oracle.backward(g, cam, gC, None, None, tile=8)
-    e_pose = np.linalg.norm(got["pose"] - an["pose"]) / np.linalg.norm(an["pose"])
-    live = np.nonzero(an["opacity"] != 0)[0]
+    marg = marginal_gaussians(g, cam, tile=8)
+    live = np.nonzero((an["opacity"] != 0) & ~marg)[0]
     assert live.size >= 64
     sel = np.sort(np.random.default_rng(4).choice(live, 64, replace=False))
-    e_mean = np.linalg.norm(got["mean"][:, sel] - an["mean"][:, sel]) / np.linalg.norm(an["mean"][:, sel])
-    e_opa = np.linalg.norm(got["opacity"][sel] - an["opacity"][sel]) / np.linalg.norm(an["opacity"][sel])
-    print(f"[c4] relative errors pose {e_pose:.2e} mean {e_mean:.2e} opacity {e_opa:.2e} "
-          f"(live Gaussians {live.size}, marginal pixels {int(base['marginal'].sum())})", flush=True)
-    assert e_pose <= GRAD_RTOL and e_mean <= GRAD_RTOL and e_opa <= GRAD_RTOL
+    print(f"[c4] live Gaussians {live.size}, marginal Gaussians {int(marg.sum())}, "
+          f"marginal pixels {int(base['marginal'].sum())}", flush=True)
+    assert_grads_close(got, an, keys=("pose",))
+    # the 64 seeded Gaussians, against the scale of every live Gaussian's gradient
+    for k in ("mean", "opacity"):
+        scale = np.abs(an[k][..., live]).max()
+        a, b = got[k][..., sel], an[k][..., sel]
+        assert np.all(np.abs(a - b) <= 2e-3 * np.abs(b) + 2e-5 * scale), k
+    # and every live Gaussian
+    assert_grads_close(got, an, keys=("mean", "opacity", "scale", "rot", "sh_dc", "sh_rest"), exclude=marg)
 
 
 def test_c4_oracle_pose_gradient_against_frozen_fd(c4):
@@ -84,7 +90,9 @@ def test_c4_oracle_pose_gradient_against_frozen_fd(c4):
 
 
 def test_c4_checkpoint_memory():
-    """The backward keeps 8 B per pixel (T_final, last) instead of per-fragment state."""
+    """What the forward leaves for the backward, counted from the buffers themselves: the 8-B
+    per-pixel checkpoint, the chunk state (gs_image_state_bytes of the capacity and of this
+    view's pairs), the tile lists and the splat records; against per-fragment state."""
     g = S.street_map(1_000_000, seed=2)
     cam = S.headline_camera()
     gm = R.GaussianMap.from_numpy(g, DEV)
@@ -94,7 +102,14 @@ def test_c4_checkpoint_memory():
     fr = R.Frame.empty(cam.h, cam.w, DEV, count=True)
     R.render_fwd(spl, gs.n, bins, cs, 128, DEV, out=fr)
     fragments = int(fr.n_contrib.long().sum().item())
-    ckpt = R.checkpoint_bytes(cam)
-    print(f"[c4] checkpoint {ckpt / 1e6:.2f} MB vs per-fragment state >= {8 * fragments / 1e6:.1f} MB "
-          f"({fragments} contributing fragments)", flush=True)
-    assert ckpt == cam.w * cam.h * 8 and ckpt < 8 * fragments
+    kept = R.kept_bytes(spl, bins, fr, cs, 128)
+    lib = R.N.lib()
+    T = R.tiles_of(cs, 8)
+    print(f"[c4] kept MB { {k: round(v / 1e6, 2) for k, v in kept.items()} } vs per-fragment state >= "
+          f"{8 * fragments / 1e6:.1f} MB ({fragments} contributing fragments)", flush=True)
+    assert kept["checkpoint"] == R.checkpoint_bytes(cam) == cam.w * cam.h * 8
+    assert kept["chunk_state_allocated"] == lib.gs_image_state_bytes(bins.capacity, T, 8, 8, 128)
+    assert kept["chunk_state_needed"] == lib.gs_image_state_bytes(bins.pairs(), T, 8, 8, 128)
+    assert kept["chunk_state_needed"] <= kept["chunk_state_allocated"]
+    assert kept["splat_records"] == gs.n * (64 + 8)
+    assert kept["total_allocated"] < 8 * fragments

@@ -2,8 +2,11 @@
 
 Bars: tile/pair lists, sort order, tile counts, rectangles and depth keys bit-exact against
 the float32 binning oracle; images within 1e-4 max-abs (depth 1e-4 relative beyond 1 m) on
-pixels the FP64 oracle does not flag as marginal; gradients within 2e-3 relative (norm per
-parameter block) of the FP64 analytic oracle, itself pinned to finite differences.
+pixels the FP64 oracle does not flag as marginal; gradients element by element within 2e-3
+relative (plus a float32 summation floor of 2e-5 of the block's largest element) of the FP64
+analytic oracle, itself pinned to finite differences; Gaussians the oracle flags as taking a
+marginal decision at some pixel are left out of the per-Gaussian blocks (not of the pose).
+The small scenes run at 16x16 tiles / chunk 256 and at the benchmark's 8x8 / 128.
 """
 import numpy as np
 import pytest
@@ -14,7 +17,8 @@ from oracle.loss import loss_and_grads
 from paper_2507_04004_amd import raster as R
 from paper_2507_04004_amd import scenes as S
 
-from gpu_common import DEV, HipRun, assert_grads_close, assert_images_close, compare_images, grad_errors, oracle_cam
+from gpu_common import (DEV, HipRun, assert_grads_close, assert_images_close, compare_images, grad_errors,
+                        marginal_gaussians, oracle_cam)
 
 pytestmark = pytest.mark.gpu
 
@@ -100,11 +104,15 @@ def test_projection_records(case):
 
 
 # ---- stage a3: compositing ------------------------------------------------------------------
+LAUNCH = [(16, 256), (8, 128)]
+
+
+@pytest.mark.parametrize("tile,bd", LAUNCH)
 @pytest.mark.parametrize("case", list(CASES))
-def test_render_matches_oracle(case):
+def test_render_matches_oracle(case, tile, bd):
     g, cam = CASES[case]()
-    print(f"[render] case={case}", flush=True)
-    run = HipRun(g, cam)
+    print(f"[render] case={case} tile={tile} chunk={bd}", flush=True)
+    run = HipRun(g, cam, tile=tile, blend_depth=bd)
     got = run.image()
     ref = oracle.render(g, oracle_cam(cam), tile=16, band=1e-4)
     e = assert_images_close(got, ref)
@@ -113,9 +121,9 @@ def test_render_matches_oracle(case):
     ok = (ref["marginal"] == 0) & (ref["last_id"] >= 0)
     vals = run.bins_np()["vals"]
     tr = run.bins_np()["tile_range"]
-    tiles_x = (cam.w + 15) // 16
+    tiles_x = (cam.w + tile - 1) // tile
     ys, xs = np.nonzero(ok)
-    t = (ys // 16) * tiles_x + xs // 16
+    t = (ys // tile) * tiles_x + xs // tile
     idx = tr[2 * t] + got["last"][ys, xs]
     np.testing.assert_array_equal(vals[idx], ref["last_id"][ys, xs])
     assert np.all(got["last"][ref["last_id"] < 0] == -1)
@@ -160,9 +168,8 @@ def test_multichunk_tiles_match_oracle(bd):
     gC, gD, gO = gC.reshape(3, cam.h, cam.w), gD.reshape(cam.h, cam.w), gO.reshape(cam.h, cam.w)
     gg = run.backward(gC, gD, gO)
     gref = oracle.backward(g, oracle_cam(cam), gC.astype(np.float64), gD.astype(np.float64), gO.astype(np.float64))
-    eg = grad_errors(gg, gref)
-    print(f"[multichunk] bd={bd} image errors={e} grad errors={eg}", flush=True)
-    assert_grads_close(gg, gref)
+    print(f"[multichunk] bd={bd} image errors={e}", flush=True)
+    assert_grads_close(gg, gref, exclude=marginal_gaussians(g, cam))
 
 
 def test_forward_deterministic():
@@ -174,12 +181,13 @@ def test_forward_deterministic():
 
 
 # ---- stages a4 + a5: backward ----------------------------------------------------------------
+@pytest.mark.parametrize("tile,bd", LAUNCH)
 @pytest.mark.parametrize("case", list(CASES))
 @pytest.mark.parametrize("which", ["all", "rgb_only", "depth_only"])
-def test_backward_matches_oracle(case, which):
+def test_backward_matches_oracle(case, which, tile, bd):
     g, cam = CASES[case]()
-    print(f"[backward] case={case} which={which}", flush=True)
-    run = HipRun(g, cam)
+    print(f"[backward] case={case} which={which} tile={tile} chunk={bd}", flush=True)
+    run = HipRun(g, cam, tile=tile, blend_depth=bd)
     npx = cam.w * cam.h
     gC, gD, gO = S.upstream_grads(npx, seed=11)
     gC = gC.reshape(3, cam.h, cam.w) * (which != "depth_only")
@@ -188,9 +196,7 @@ def test_backward_matches_oracle(case, which):
     got = run.backward(gC, gD, gO)
     ref = oracle.backward(g, oracle_cam(cam), gC.astype(np.float64), None if gD is None else gD.astype(np.float64),
                           None if gO is None else gO.astype(np.float64))
-    e = grad_errors(got, ref)
-    print(f"[backward] case={case} which={which} rel errors={e}", flush=True)
-    assert_grads_close(got, ref)
+    assert_grads_close(got, ref, exclude=marginal_gaussians(g, cam))
 
 
 @pytest.mark.parametrize("case", ["street_sh3_posed", "small_sh0"])
@@ -249,9 +255,8 @@ def test_lidar_depth_term():
     gC = np.zeros((3, cam.h, cam.w), np.float32)
     got = run.backward(gC, None, None)
     ref = oracle.backward(g, oracle_cam(cam), gC.astype(np.float64), gD_ref, gO_ref)
-    e = grad_errors(got, ref)
-    print(f"[lidar] loss gpu={l_gpu:.6f} ref={l_ref:.6f} rel errors={e}", flush=True)
-    assert_grads_close(got, ref)
+    print(f"[lidar] loss gpu={l_gpu:.6f} ref={l_ref:.6f}", flush=True)
+    assert_grads_close(got, ref, exclude=marginal_gaussians(g, cam))
 
 
 def test_autograd_function_and_checkpoint():
@@ -271,7 +276,7 @@ def test_autograd_function_and_checkpoint():
     got = dict(mean=gm.mean.grad, scale=gm.scale.grad, rot=gm.rot.grad, opacity=gm.opacity.grad,
                sh_dc=gm.sh_dc.grad, sh_rest=gm.sh_rest.grad, pose=xi.grad)
     got = {k: v.cpu().numpy().astype(np.float64) for k, v in got.items()}
-    assert_grads_close(got, ref)
+    assert_grads_close(got, ref, exclude=marginal_gaussians(g, cam))
     assert R.checkpoint_bytes(cam) == cam.w * cam.h * 8
 
 
