@@ -3,7 +3,7 @@
 A second, independent writing of the forward definition (Sec. "3D Gaussian Splatting
 Representation": the projection, eq:alpha and eq:rendered_rgb / _depth / _opacity) with no
 tiles and no culling: every pixel composites every Gaussian whose weight reaches 1/255, in
-ascending (depth, index) order. It uses matrix algebra where the C oracle writes loops
+ascending (float32 depth, index) order. It uses matrix algebra where the C oracle writes loops
 out, so an error in one is unlikely to repeat in the other. Sized for <= ~100 Gaussians
 and a few thousand pixels.
 """
@@ -71,9 +71,15 @@ def splat(g, cam):
                                g.sh_rest[:, k].astype(float).reshape(-1, 3)], axis=0) if Y.size > 1 else \
             g.sh_dc[:, k][None, :].astype(float)
         rgb = np.maximum(Y @ coef + 0.5, 0.0)
-        out.append(dict(k=k, d=d, mu2=np.array([cam.fx * mh[0] / d + cam.cx, cam.fy * mh[1] / d + cam.cy]),
+        # order key (R12): the depth in float32, ((R6 mx + R7 my) + R8 mz) + tz with every
+        # operation rounded to float32; the index breaks its ties
+        f = np.float32
+        m32 = g.mean[:, k].astype(f)
+        r32, t32 = np.asarray(cam.R_cw, f), np.asarray(cam.t_cw, f)
+        dkey = f(f(f(r32[2, 0] * m32[0]) + f(r32[2, 1] * m32[1])) + f(r32[2, 2] * m32[2])) + t32[2]
+        out.append(dict(k=k, d=d, dkey=float(dkey), mu2=np.array([cam.fx * mh[0] / d + cam.cx, cam.fy * mh[1] / d + cam.cy]),
                         Q=np.linalg.inv(S2), o=o, rgb=rgb))
-    out.sort(key=lambda s: (s["d"], s["k"]))
+    out.sort(key=lambda s: (s["dkey"], s["k"]))
     return out
 
 

@@ -135,6 +135,7 @@ typedef struct {
   double o, kappa2, hx, hy;
   double cw[3], diff[3], dist, dir[3];
   double Y[16], raw[3], rgb[3];
+  float dkey;                 /* float32 depth: the compositing order key */
 } proj;
 
 static int finite3(const double *a) { return isfinite(a[0]) && isfinite(a[1]) && isfinite(a[2]); }
@@ -154,6 +155,17 @@ static void project(const or_gaussians *G, const or_camera *cam, int64_t k, proj
   /* transform into the camera frame; depth is the camera-frame z */
   for (int i = 0; i < 3; ++i) p->mh[i] = R[3 * i] * p->m[0] + R[3 * i + 1] * p->m[1] + R[3 * i + 2] * p->m[2] + t[i];
   p->d = p->mh[2];
+  /* The order key is the depth in float32 (R12): the camera-frame z of the float32 inputs,
+   * formed as ((R6 mx + R7 my) + R8 mz) + tz in float32, each operation rounded (this file is
+   * compiled without contraction). Depths float32 cannot tell apart fall back to the index. */
+  {
+    const float r6 = (float)R[6], r7 = (float)R[7], r8 = (float)R[8], tz = (float)t[2];
+    const float mx = (float)p->m[0], my = (float)p->m[1], mz = (float)p->m[2];
+    float acc = r6 * mx;
+    acc = acc + r7 * my;
+    acc = acc + r8 * mz;
+    p->dkey = acc + tz;
+  }
   ok &= p->d > OR_NEAR;
   /* rotation from the normalised quaternion (Hamilton convention, w first) */
   p->qlen = sqrt(p->qraw[0] * p->qraw[0] + p->qraw[1] * p->qraw[1] + p->qraw[2] * p->qraw[2] + p->qraw[3] * p->qraw[3]);
@@ -335,13 +347,13 @@ static int tile_span(double c, double e, int org, int len, int B, int *t0, int *
 
 typedef struct {
   int64_t *start;  /* [T+1] */
-  int32_t *ids;    /* Gaussian ids, per tile sorted by (depth, id) */
+  int32_t *ids;    /* Gaussian ids, per tile sorted by (float32 depth, id) */
 } tile_lists;
 
 static const proj *g_sort_proj; /* qsort comparator context (lists are sorted serially) */
 static int cmp_depth_id(const void *A, const void *B) {
   int32_t i = *(const int32_t *)A, j = *(const int32_t *)B;
-  double di = g_sort_proj[i].d, dj = g_sort_proj[j].d;
+  float di = g_sort_proj[i].dkey, dj = g_sort_proj[j].dkey;
   if (di < dj) return -1;
   if (di > dj) return 1;
   return (i > j) - (i < j);
@@ -424,7 +436,7 @@ static double pixel_alpha_raw(const proj *p, double px, double py, double *power
   return p->o * exp(power);
 }
 
-/* Front-to-back over `ids` (already in (depth, id) order). If contrib_ids != NULL, the ids of
+/* Front-to-back over `ids` (already in (float32 depth, id) order). If contrib_ids != NULL, the ids of
  * contributors and their alpha-clamp flags are written there. */
 static void composite(const proj *P, const int32_t *ids, int64_t len, double px, double py, const double *bg,
                       double band, pix_out *o, int32_t *contrib_ids, int8_t *contrib_clamped) {
@@ -501,7 +513,7 @@ int or_render(const or_gaussians *G, const or_camera *cam, int bw, int bh, int c
   return 0;
 }
 
-/* Brute force for listed pixels: every valid Gaussian, sorted by (depth, id), no tiles. */
+/* Brute force for listed pixels: every valid Gaussian, sorted by (float32 depth, id), no tiles. */
 int or_render_pixels(const or_gaussians *G, const or_camera *cam, int64_t npix, const int32_t *px, const int32_t *py,
                      double band, double *color /*[3][npix]*/, double *depth, double *alpha, double *t_final,
                      int32_t *last_id, int64_t *ncontrib, uint8_t *marginal) {

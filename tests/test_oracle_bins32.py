@@ -9,8 +9,9 @@ whose pair sets are derived by hand, and planted mistakes that must fail.
 Agreement rule: a (Gaussian, tile) decision may differ between float32 and float64 only where
 its float64 margin (the smallest relative perturbation of the compared quantities that flips
 it, `or_pair_margins`) is at most 1e-5; such decisions are counted, and the disagreements
-must stay below 1e-4 of the pairs. Within each tile the order of the Gaussians both sides
-list may differ only between depths within 1e-5 relative of each other.
+must stay below 1e-4 of the pairs. Within each tile both sides order the Gaussians they both
+list alike (float32 depth, then index), and that order is the float64 depth order up to two
+float32 roundings of the depth.
 """
 import os
 import subprocess
@@ -47,9 +48,17 @@ def compare_lists(g, cam, tile, handle=None):
                 marginal=int((~clear).sum()), worst=float(margin[dis].max(initial=0.0)), b32=b, l64=L)
 
 
+# A float32 depth is within 8.9 * 2^-24 s of the float64 one, s = max(|mu|, |t|) (the rounding
+# of ((R6 mx + R7 my) + R8 mz) + tz, each step at most 2^-24 of a magnitude <= (sqrt(3) + 1) s).
+ORDER_BOUND = 2 * 8.9 * 2.0 ** -24
+
+
 def order_violations(g, cam, tile, r):
-    """Depth-order inversions between the two lists, beyond the relative band."""
+    """Depth order inside each tile: both sides order the Gaussians they both list alike (the
+    key of R12: float32 depth, then index), and along each list the float64 depths never fall by
+    more than two float32 depth roundings (the order is the float64 depth order up to them)."""
     d64 = oracle.project(g, cam)["depth"]
+    scale = np.maximum(np.abs(g.mean.astype(np.float64)).max(axis=0), max(1.0, float(np.abs(cam.t_cw).max())))
     b, L = r["b32"], r["l64"]
     tr = b["tile_range"].reshape(-1, 2)
     bad = 0
@@ -57,14 +66,12 @@ def order_violations(g, cam, tile, r):
         a = b["vals"][tr[t, 0]:tr[t, 1]].astype(np.int64)
         c = L["ids"][L["start"][t]:L["start"][t + 1]].astype(np.int64)
         common = np.intersect1d(a, c)
-        if common.size < 2:
-            continue
-        seq = a[np.isin(a, common)]          # float32 order of the Gaussians both list
-        dd = d64[seq]
-        runmax = np.maximum.accumulate(dd)
-        bad += int(np.sum(dd[1:] < runmax[:-1] * (1 - BAND)))
-        # the float64 list is in (depth, id) order: pinned by brute force in test_oracle_pins
-        assert np.all(np.diff(d64[c]) >= 0)
+        if common.size >= 2:
+            bad += int(np.sum(a[np.isin(a, common)] != c[np.isin(c, common)]))
+        for seq in (a, c):
+            if seq.size >= 2:
+                runmax = np.maximum.accumulate(d64[seq])
+                bad += int(np.sum(d64[seq][1:] < runmax[:-1] - ORDER_BOUND * np.maximum(scale[seq][1:], scale[seq][:-1])))
     return bad
 
 
