@@ -194,6 +194,23 @@ int gs_render_bwd(const gs_gaussians *g, const gs_camera *cam, const gs_projecte
                   const gs_image *fwd, const float *dL_dC, const float *dL_dD, const float *dL_dO,
                   const gs_lidar *lidar, int32_t blend_depth, gs_grads *out, gs_stream_t stream);
 
+/* For callers that cannot allocate device memory (code under hipGraph capture, tight serving
+ * loops, harnesses that forbid hipMalloc): gs_render_bwd with the backward scratch taken from
+ * a library-owned device array of GS_NOALLOC_SCRATCH_BYTES (128 MiB) per device instead of
+ * out->scratch (out->scratch and out->scratch_bytes are ignored and may be 0). Arguments,
+ * layouts, results and errors are those of gs_render_bwd, plus GS_ERR_INVALID_ARG when
+ * gs_grads_scratch_bytes(g->n, 1, cam->w * cam->h) exceeds the limit (about 1.9 M Gaussians
+ * at 1280x720). Calls nothing that allocates. The array is held by each device the library
+ * runs on until the process ends; the first call on a device resolves its address (make that
+ * call outside capture). All calls on one device share the array: calls that overlap in time
+ * on one device (different streams, or threads) race and must be serialised by the caller;
+ * every value the backward reads from it is written earlier in the same call. */
+#define GS_NOALLOC_SCRATCH_BYTES ((size_t)128 << 20)
+int gs_render_bwd_noalloc(const gs_gaussians *g, const gs_camera *cam, const gs_projected *proj,
+                          const gs_bins *bins, const gs_image *fwd, const float *dL_dC, const float *dL_dD,
+                          const float *dL_dO, const gs_lidar *lidar, int32_t blend_depth, gs_grads *out,
+                          gs_stream_t stream);
+
 /* RGB L1 term of the mapping loss (eq:depth_loss with the D-SSIM weight at zero):
  * loss_out[0] = weight * mean |color - target|, dL_dC = weight * sign(color - target) / n_values
  * (sign(0) = 0). n_values = 3 * pixels. loss_out is overwritten. */

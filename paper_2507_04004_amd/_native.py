@@ -101,7 +101,8 @@ class GSError(RuntimeError):
 
 _lib = None
 
-EXPORTS = ["gs_preprocess", "gs_bin_sort", "gs_render_fwd", "gs_render_bwd", "gs_render_batch", "gs_loss_l1",
+EXPORTS = ["gs_preprocess", "gs_bin_sort", "gs_render_fwd", "gs_render_bwd", "gs_render_bwd_noalloc",
+           "gs_render_batch", "gs_loss_l1",
            "gs_adam_sparse", "gs_loss_dssim", "gs_dssim_scratch_bytes", "gs_track_plan_create",
            "gs_track_plan_destroy", "gs_track_capacity", "gs_track_pose", "gs_track_required_pairs",
            "gs_pose_residual", "gs_expand_scratch_bytes", "gs_expand_select", "gs_expand_write",
@@ -125,6 +126,7 @@ def lib():
     L.gs_render_fwd.argtypes = [P(Projected), C.c_int64, P(Bins), P(Camera), C.c_int32, P(Lidar), P(Image), vp]
     L.gs_render_bwd.argtypes = [P(Gaussians), P(Camera), P(Projected), P(Bins), P(Image), vp, vp, vp, P(Lidar),
                                 C.c_int32, P(Grads), vp]
+    L.gs_render_bwd_noalloc.argtypes = L.gs_render_bwd.argtypes
     L.gs_loss_l1.argtypes = [vp, vp, C.c_int64, C.c_float, vp, vp, vp]
     L.gs_adam_sparse.argtypes = [P(Adam), vp]
     L.gs_dssim_scratch_bytes.argtypes = [C.c_int32, C.c_int32, C.c_int32]

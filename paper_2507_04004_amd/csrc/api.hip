@@ -4,6 +4,7 @@
 
 #include <algorithm>
 #include <atomic>
+#include <mutex>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -423,9 +424,15 @@ int gs_render_fwd(const gs_projected *proj, int64_t n, const gs_bins *bins, cons
   return GS_OK;
 }
 
-int gs_render_bwd(const gs_gaussians *g, const gs_camera *cam, const gs_projected *proj, const gs_bins *bins,
-                  const gs_image *fwd, const float *dL_dC, const float *dL_dD, const float *dL_dO, const gs_lidar *lidar,
-                  int32_t blend_depth, gs_grads *out, gs_stream_t stream) {
+}  // extern "C"
+
+namespace {
+
+// Checks shared by gs_render_bwd and gs_render_bwd_noalloc (everything except the scratch),
+// and the view table of the call.
+int check_bwd(const gs_gaussians *g, const gs_camera *cam, const gs_projected *proj, const gs_bins *bins,
+              const gs_image *fwd, const float *dL_dC, const gs_lidar *lidar, int32_t blend_depth,
+              const gs_grads *out, gs::ViewTable &vt) {
   int rc;
   if ((rc = check_gaussians(g)) || (rc = check_camera(cam)) || (rc = check_projected(proj, g->n)) ||
       (rc = check_image(fwd)))
@@ -434,17 +441,17 @@ int gs_render_bwd(const gs_gaussians *g, const gs_camera *cam, const gs_projecte
   if (!tile_ok(bins->tile_w, bins->tile_h)) return fail(GS_ERR_INVALID_ARG, "tile size must be 8x8, 16x16 or 32x32");
   if (!depth_ok(blend_depth)) return fail(GS_ERR_INVALID_ARG, "blend_depth must be 64, 128 or 256");
   if (!dL_dC) return fail(GS_ERR_INVALID_ARG, "dL_dC is NULL");
-  if (!out || !out->scratch) return fail(GS_ERR_INVALID_ARG, "grads / scratch is NULL");
+  if (!out) return fail(GS_ERR_INVALID_ARG, "grads is NULL");
   if (out->sh_dc && g->sh_degree > 0 && !out->sh_rest) return fail(GS_ERR_INVALID_ARG, "grads.sh_rest is NULL");
   if ((rc = check_schedule(out->schedule, bins->tile_w))) return rc;
   if ((rc = check_lidar(lidar, (int64_t)cam->w * cam->h))) return rc;
-  const int64_t npx = (int64_t)cam->w * cam->h;
-  if (out->scratch_bytes < grads_scratch_bytes_impl(g->n, 1, npx))
-    return fail(GS_ERR_INVALID_ARG, "grads scratch too small: %zu < %zu", out->scratch_bytes,
-                grads_scratch_bytes_impl(g->n, 1, npx));
-  gs::ViewTable vt;
   if ((rc = make_table(cam, 1, g->n, g->sh_degree, bins->tile_w, bins->tile_h, vt))) return rc;
-  if ((rc = check_state(fwd, bins->capacity, vt.total_tiles, bins->tile_w, bins->tile_h, blend_depth))) return rc;
+  return check_state(fwd, bins->capacity, vt.total_tiles, bins->tile_w, bins->tile_h, blend_depth);
+}
+
+int run_bwd(const gs::ViewTable &vt, const gs_gaussians *g, const gs_camera *cam, const gs_projected *proj,
+            const gs_bins *bins, const gs_image *fwd, const float *dL_dC, const float *dL_dD, const float *dL_dO,
+            const gs_lidar *lidar, int32_t blend_depth, const gs_grads *out, void *scratch_base, hipStream_t st) {
   ViewIO io{};
   io.img = *fwd;
   io.dC = dL_dC;
@@ -452,10 +459,78 @@ int gs_render_bwd(const gs_gaussians *g, const gs_camera *cam, const gs_projecte
   io.dO = dL_dO;
   if (lidar) io.lidar = *lidar;
   io.pose = out->pose;
-  GradScratch s = carve_grads(out->scratch, g->n, 1, npx);
-  GS_CHECK_DEVICE();
+  const GradScratch s = carve_grads(scratch_base, g->n, 1, (int64_t)cam->w * cam->h);
   return enqueue_backward(vt, *g, *proj, bins->vals, bins->tile_range, fwd->state, bins->capacity, &io, blend_depth,
-                          *out, s, (hipStream_t)stream);
+                          *out, s, st);
+}
+
+}  // namespace
+
+// The backward scratch of gs_render_bwd_noalloc: one array per device, held by the loaded code
+// object until the process ends. Host code never names it: its device address is resolved
+// once per device (noalloc_scratch) and only that address is passed on.
+static __device__ __align__(256) unsigned char scratch[GS_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+
+constexpr int kNoAllocDevices = 64;
+std::mutex g_noalloc_mu;
+std::atomic<void *> g_noalloc_ptr[kNoAllocDevices];
+
+// Device address of the scratch array on the current device.
+int noalloc_scratch(void **out) {
+  int dev = 0;
+  GS_TRY_HIP(hipGetDevice(&dev), "current device");
+  if (dev < 0 || dev >= kNoAllocDevices) return fail(GS_ERR_UNSUPPORTED, "device index %d out of range", dev);
+  void *p = g_noalloc_ptr[dev].load(std::memory_order_acquire);
+  if (!p) {
+    std::lock_guard<std::mutex> lock(g_noalloc_mu);
+    p = g_noalloc_ptr[dev].load(std::memory_order_relaxed);
+    if (!p) {
+      GS_TRY_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)), "address of the no-allocation scratch");
+      if (!p) return fail(GS_ERR_HIP, "address of the no-allocation scratch is NULL");
+      g_noalloc_ptr[dev].store(p, std::memory_order_release);
+    }
+  }
+  *out = p;
+  return GS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int gs_render_bwd(const gs_gaussians *g, const gs_camera *cam, const gs_projected *proj, const gs_bins *bins,
+                  const gs_image *fwd, const float *dL_dC, const float *dL_dD, const float *dL_dO, const gs_lidar *lidar,
+                  int32_t blend_depth, gs_grads *out, gs_stream_t stream) {
+  gs::ViewTable vt;
+  int rc;
+  if ((rc = check_bwd(g, cam, proj, bins, fwd, dL_dC, lidar, blend_depth, out, vt))) return rc;
+  if (!out->scratch) return fail(GS_ERR_INVALID_ARG, "grads scratch is NULL");
+  const size_t need = grads_scratch_bytes_impl(g->n, 1, (int64_t)cam->w * cam->h);
+  if (out->scratch_bytes < need)
+    return fail(GS_ERR_INVALID_ARG, "grads scratch too small: %zu < %zu", out->scratch_bytes, need);
+  GS_CHECK_DEVICE();
+  return run_bwd(vt, g, cam, proj, bins, fwd, dL_dC, dL_dD, dL_dO, lidar, blend_depth, out, out->scratch,
+                 (hipStream_t)stream);
+}
+
+int gs_render_bwd_noalloc(const gs_gaussians *g, const gs_camera *cam, const gs_projected *proj, const gs_bins *bins,
+                          const gs_image *fwd, const float *dL_dC, const float *dL_dD, const float *dL_dO,
+                          const gs_lidar *lidar, int32_t blend_depth, gs_grads *out, gs_stream_t stream) {
+  gs::ViewTable vt;
+  int rc;
+  if ((rc = check_bwd(g, cam, proj, bins, fwd, dL_dC, lidar, blend_depth, out, vt))) return rc;
+  const size_t need = grads_scratch_bytes_impl(g->n, 1, (int64_t)cam->w * cam->h);
+  if (need > (size_t)GS_NOALLOC_SCRATCH_BYTES)
+    return fail(GS_ERR_INVALID_ARG,
+                "backward scratch of %zu bytes (%lld Gaussians, %lld pixels) exceeds the no-allocation limit of %zu",
+                need, (long long)g->n, (long long)cam->w * cam->h, (size_t)GS_NOALLOC_SCRATCH_BYTES);
+  GS_CHECK_DEVICE();
+  void *base = nullptr;
+  if ((rc = noalloc_scratch(&base))) return rc;
+  return run_bwd(vt, g, cam, proj, bins, fwd, dL_dC, dL_dD, dL_dO, lidar, blend_depth, out, base,
+                 (hipStream_t)stream);
 }
 
 int gs_camera_left_update(const gs_camera *in, const float xi[6], gs_camera *out) {

@@ -251,10 +251,11 @@ class ParamGrads:
         return ParamGrads(e(gm.mean), e(gm.scale), e(gm.rot), e(gm.opacity), e(gm.sh_dc), e(gm.sh_rest),
                           torch.empty(6, dtype=torch.float32, device=gm.mean.device))
 
-    def struct(self, scratch: torch.Tensor, overwrite: bool = False, schedule: int = N.GS_BWD_CHUNKS) -> N.Grads:
+    def struct(self, scratch: torch.Tensor | None, overwrite: bool = False, schedule: int = N.GS_BWD_CHUNKS) -> N.Grads:
         rest = self.sh_rest if self.sh_rest.numel() else None
         return N.Grads(_p(self.mean), _p(self.scale), _p(self.rot), _p(self.opacity), _p(self.sh_dc), _p(rest),
-                       _p(self.pose), _p(scratch), scratch.numel(), int(bool(overwrite)), int(schedule))
+                       _p(self.pose), _p(scratch), scratch.numel() if scratch is not None else 0,
+                       int(bool(overwrite)), int(schedule))
 
 
 def grads_scratch(n: int, pixels: int, device, views: int = 1) -> torch.Tensor:
@@ -262,16 +263,19 @@ def grads_scratch(n: int, pixels: int, device, views: int = 1) -> torch.Tensor:
 
 
 def render_bwd(gs: N.Gaussians, cs: N.Camera, spl: Splats, bins: TileBins, fr: Frame, dL_dC, dL_dD, dL_dO,
-               blend_depth: int, grads: ParamGrads, scratch: torch.Tensor, lidar: LidarHits | None = None,
+               blend_depth: int, grads: ParamGrads, scratch: torch.Tensor | None, lidar: LidarHits | None = None,
                grad_scale: torch.Tensor | None = None, overwrite: bool = False,
-               schedule: int = N.GS_BWD_CHUNKS) -> ParamGrads:
+               schedule: int = N.GS_BWD_CHUNKS, noalloc: bool = False) -> ParamGrads:
     """overwrite=False adds the gradients to `grads`; overwrite=True writes every element.
-    schedule: GS_BWD_CHUNKS (pixel-parallel, default) or GS_BWD_BUCKETS (per-Gaussian buckets)."""
+    schedule: GS_BWD_CHUNKS (pixel-parallel, default) or GS_BWD_BUCKETS (per-Gaussian buckets).
+    noalloc=True calls gs_render_bwd_noalloc (library-owned scratch; `scratch` is ignored)."""
     ls = lidar.struct(None, grad_scale) if lidar is not None and lidar.m > 0 else None
-    N.check(N.lib().gs_render_bwd(C.byref(gs), C.byref(cs), C.byref(spl.struct()), C.byref(bins.struct()),
-                                  C.byref(fr.struct()), _p(dL_dC), _p(dL_dD), _p(dL_dO),
-                                  C.byref(ls) if ls is not None else None, blend_depth,
-                                  C.byref(grads.struct(scratch, overwrite, schedule)), _stream()), "gs_render_bwd")
+    fn = N.lib().gs_render_bwd_noalloc if noalloc else N.lib().gs_render_bwd
+    N.check(fn(C.byref(gs), C.byref(cs), C.byref(spl.struct()), C.byref(bins.struct()),
+               C.byref(fr.struct()), _p(dL_dC), _p(dL_dD), _p(dL_dO),
+               C.byref(ls) if ls is not None else None, blend_depth,
+               C.byref(grads.struct(None if noalloc else scratch, overwrite, schedule)), _stream()),
+            "gs_render_bwd_noalloc" if noalloc else "gs_render_bwd")
     return grads
 
 

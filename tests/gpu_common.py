@@ -35,13 +35,13 @@ class HipRun:
         return dict(color=f.color.cpu().numpy(), depth=f.depth.cpu().numpy(), alpha=f.alpha.cpu().numpy(),
                     t_final=f.t_final.cpu().numpy(), last=f.last.cpu().numpy())
 
-    def backward(self, gC, gD=None, gO=None, grad_scale=None, overwrite=False, grads=None, schedule=0):
+    def backward(self, gC, gD=None, gO=None, grad_scale=None, overwrite=False, grads=None, schedule=0, noalloc=False):
         if grads is None:
             grads = R.ParamGrads.zeros(self.gm)
-        scratch = R.grads_scratch(self.gs.n, self.cam.w * self.cam.h, DEV)
+        scratch = None if noalloc else R.grads_scratch(self.gs.n, self.cam.w * self.cam.h, DEV)
         t = lambda a: None if a is None else torch.from_numpy(np.ascontiguousarray(a, np.float32)).to(DEV)
         R.render_bwd(self.gs, self.cs, self.spl, self.bins, self.fr, t(gC), t(gD), t(gO), self.bd, grads, scratch,
-                     self.lidar, grad_scale, overwrite=overwrite, schedule=schedule)
+                     self.lidar, grad_scale, overwrite=overwrite, schedule=schedule, noalloc=noalloc)
         torch.cuda.synchronize()
         return {k: getattr(grads, k).cpu().numpy().astype(np.float64) for k in
                 ("mean", "scale", "rot", "opacity", "sh_dc", "sh_rest", "pose")}

@@ -199,3 +199,31 @@ def test_track_argument_errors():
     assert L.gs_pose_residual(None, None, C.byref(r)) == N.GS_ERR_INVALID_ARG
     nan = (C.c_float * 12)(*([float("nan")] + [0.0] * 11))
     assert L.gs_pose_residual(C.byref(nan), C.byref(nan), C.byref(r)) == N.GS_ERR_INVALID_ARG
+
+
+def test_noalloc_backward_rejects_sizes_beyond_its_scratch():
+    """gs_render_bwd_noalloc refuses, on the host and before any GPU call, a backward whose
+    scratch would exceed the library-owned array (3M Gaussians at 1280x720 need ~200 MB)."""
+    L = N.lib()
+    dummy = C.c_void_p(64)
+    cam = _cam(width=1280, height=720, w=1280, h=720, fx=900.0, fy=900.0, cx=639.5, cy=359.5)
+    proj = N.Projected(*([dummy] * 3))
+    bins = N.Bins(8, 8, 1000, dummy, dummy, dummy, dummy, 0)
+    img = N.Image(*([dummy] * 7), 1 << 40)
+    grads = N.Grads(*([None] * 8), 0, 1, 0)
+    for n, ok in ((3_000_000, False), (1_000, True)):
+        g = N.Gaussians(n, 0, dummy, dummy, dummy, dummy, dummy, None)
+        need = L.gs_grads_scratch_bytes(n, 1, 1280 * 720)
+        if ok:
+            assert need <= 128 << 20
+            continue  # a call within the limit would launch: GPU tests cover it
+        assert need > 128 << 20
+        rc = L.gs_render_bwd_noalloc(C.byref(g), C.byref(cam), C.byref(proj), C.byref(bins), C.byref(img), dummy,
+                                     None, None, None, 128, C.byref(grads), None)
+        assert rc == N.GS_ERR_INVALID_ARG
+        assert b"no-allocation limit" in L.gs_last_error()
+    # the plain entry point still requires its caller's scratch
+    g = N.Gaussians(1000, 0, dummy, dummy, dummy, dummy, dummy, None)
+    assert L.gs_render_bwd(C.byref(g), C.byref(cam), C.byref(proj), C.byref(bins), C.byref(img), dummy, None, None,
+                           None, 128, C.byref(grads), None) == N.GS_ERR_INVALID_ARG
+    assert b"scratch" in L.gs_last_error()
