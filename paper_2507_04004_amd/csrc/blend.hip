@@ -175,15 +175,16 @@ struct TileCtx {
 // Splats per compositing group (the unit of the early exit and of the last-index bookkeeping).
 constexpr int kGroupLen = 8;
 
-template <int BD, int NT>
+// KEEP_ID (the backward kernels): the fourth component of the staged colour holds the record
+// index (as bits) in place of the SH clamp bits, which compositing does not read.
+template <int BD, int NT, bool KEEP_ID = false>
 __device__ __forceinline__ void stage(const uint32_t *__restrict__ vals, uint32_t start, int cnt,
-                                      const Card *__restrict__ card, float4 *s_a, float4 *s_b, float4 *s_c,
-                                      uint32_t *s_e) {
+                                      const Card *__restrict__ card, float4 *s_a, float4 *s_b, float4 *s_c) {
   for (int k = threadIdx.x; k < cnt; k += NT) {
     const uint32_t e = vals[start + k];
-    if (s_e) s_e[k] = e;
     const Card &cd = card[e];
     stage_card(cd.a, cd.b, cd.c, s_a[k], s_b[k], s_c[k]);
+    if (KEEP_ID) s_c[k].w = __uint_as_float(e);
   }
   // up to the next multiple of kGroupLen: records of opacity 0 (alpha 0, never blended), so
   // the compositing loop runs whole groups
@@ -302,7 +303,7 @@ __global__ __launch_bounds__(NT) void k_blend_chunk(ViewTable vt, ImgTable it, c
   const uint32_t K = n_chunks(e0 - s0, BD);
   const uint32_t cs = s0 + c * BD;
   const int cnt = (int)min<uint32_t>(BD, e0 - cs);
-  stage<BD, NT>(vals, cs, cnt, card, s_a, s_b, s_c, nullptr);
+  stage<BD, NT>(vals, cs, cnt, card, s_a, s_b, s_c);
   __syncthreads();
 
   float px[PPT], py[PPT];
@@ -454,7 +455,7 @@ __global__ __launch_bounds__(NT) void k_blend_fix(ViewTable vt, ImgTable it, con
   if (__syncthreads_count(any) == 0) return;
   const uint32_t cs = s0 + c * BD;
   const int cnt = (int)min<uint32_t>(BD, e0 - cs);
-  stage<BD, NT>(vals, cs, cnt, card, s_a, s_b, s_c, nullptr);
+  stage<BD, NT>(vals, cs, cnt, card, s_a, s_b, s_c);
   __syncthreads();
   composite_run<PPT, CNT>(s_a, s_b, s_c, cnt, px, py, (int)(c * BD), st);
 #pragma unroll
@@ -717,23 +718,83 @@ __device__ __forceinline__ int reduce10_slot(int lane) {
   return ok ? base + row : -1;
 }
 
-// Backward state of one pixel.
+// Backward state of one pixel. The colour behind the current splat enters the alpha
+// derivative only through dL/dC . (c - C_behind), so the pixel carries the scalar
+// S = dL/dC . C_behind (updated as S + alpha (dL/dC . c - S)) instead of the three channels.
 struct PixGrad {
-  float Tfin, gC0, gC1, gC2, gD, gOb;  // gOb = dL/dO - dL/dC . bg
-  float T, A0, A1, A2, AD;
+  float gC0, gC1, gC2, gD, TfG;  // TfG = T_final (dL/dO - dL/dC . bg)
+  float T, S, AD;
   int ll;
   float px, py;
 };
 
-// Gradient record per splat and view (grad2d, 12 floats), summed over pixels in the units of
-// the staged splat form (the geometry kernel applies the constant factors):
-//   0: sum dp (a' dx + b'/2 dy)      -> dL/du = slot / kA
-//   1: sum dp (b'/2 dx + c' dy)      -> dL/dv = slot / kA
+// Gradient record per splat and view (grad2d, 12 floats), summed over pixels; the geometry
+// kernel applies the splat's conic and the constant factors:
+//   0: sum dp dx                     -> dL/du = a slot0 + b slot1
+//   1: sum dp dy                     -> dL/dv = b slot0 + c slot1
 //   2: sum dp dx^2                   -> dL/da = -slot / 2
 //   3: sum dp dx dy                  -> dL/db = -slot
 //   4: sum dp dy^2                   -> dL/dc = -slot / 2
 //   5: dL/do;  6-8: dL/d(r, g, b);  9: dL/d(depth)
-// with dp = dL/dpower = dL/dalpha * o exp(power) (zero where alpha is clamped at 0.99).
+// with dp = dL/dpower = dL/dalpha * o exp(power) (zero where alpha is clamped at 0.99) and
+// (a, b, c) the unscaled conic.
+// The chunk's splats back to front (staged at s_a/s_b/s_c, record index in s_c[j].w) for the
+// pixels of this lane; DEPTH: some pixel of the wavefront has a depth gradient.
+template <int PPT, bool DEPTH>
+__device__ __forceinline__ void bwd_splats(int maxll, const float4 *s_a, const float4 *s_b, const float4 *s_c,
+                                           PixGrad (&pg)[PPT], int slot, float *__restrict__ g2) {
+  for (int j = maxll; j >= 0; --j) {
+    const float4 A = s_a[j], B = s_b[j], Cc = s_c[j];
+    // alpha at every pixel first; a splat no pixel of the wavefront blends costs only this
+    float dxs[PPT], dys[PPT], exs[PPT], ars[PPT];
+    bool act[PPT];
+    bool any = false;
+#pragma unroll
+    for (int k = 0; k < PPT; ++k) {
+      float ms, qcs;
+      dxs[k] = pg[k].px - A.x;
+      dys[k] = pg[k].py - A.y;
+      const float p2 = splat_p2(A, B, dxs[k], dys[k], ms, qcs);
+      exs[k] = splat_e2(p2);
+      ars[k] = B.y * exs[k];
+      act[k] = j <= pg[k].ll && fminf(kAlphaMax, ars[k]) >= kAlphaMin;
+      any = any || act[k];
+    }
+    if (!__any(any)) continue;
+    float g[10];
+#pragma unroll
+    for (int k = 0; k < PPT; ++k) {
+      PixGrad &p = pg[k];
+      // a pixel this splat does not reach takes alpha 0: every update below then leaves its
+      // state unchanged exactly (T * 1, S + 0 * r) and adds zeros
+      const float alpha = act[k] ? fminf(kAlphaMax, ars[k]) : 0.f;
+      const float inv = __builtin_amdgcn_rcpf(1.f - alpha);  // 1 ulp; 1 - alpha >= 0.01; exactly 1 at alpha 0
+      p.T = p.T * inv;                                       // transmittance in front of this splat
+      const float w = alpha * p.T;
+      // dL/dC . (c - C_behind), then C_behind <- alpha c + (1 - alpha) C_behind
+      float r = (p.gC0 * Cc.x + p.gC1 * Cc.y + p.gC2 * Cc.z) - p.S;
+      p.S = fmaf(alpha, r, p.S);
+      float t9 = 0.f;
+      if (DEPTH) {
+        t9 = p.gD * w;
+        const float rd = B.z - p.AD;
+        r = fmaf(p.gD, rd, r);
+        p.AD = fmaf(alpha, rd, p.AD);
+      }
+      const float dLda = fmaf(p.T, r, inv * p.TfG);
+      const float dm = (act[k] && ars[k] < kAlphaMax) ? dLda : 0.f;  // clamped alpha: no power path
+      const float dp = dm * ars[k];
+      const float dpx = dp * dxs[k], dpy = dp * dys[k];
+      const float t[10] = {dpx,          dpy,          dpx * dxs[k], dpx * dys[k], dpy * dys[k],
+                           dm * exs[k],  p.gC0 * w,    p.gC1 * w,    p.gC2 * w,    t9};
+#pragma unroll
+      for (int v = 0; v < 10; ++v) g[v] = k == 0 ? t[v] : g[v] + t[v];
+    }
+    const float tot = wave_reduce10(g);
+    if (slot >= 0 && tot != 0.f) unsafeAtomicAdd(&g2[(int64_t)__float_as_uint(Cc.w) * 12 + slot], tot);
+  }
+}
+
 template <int TW, int TH, int BD, int NT>
 __global__ __launch_bounds__(NT) void k_blend_bwd_chunk(ViewTable vt, ImgTable it, GradTable gtab,
                                                         const Card *__restrict__ card,
@@ -746,7 +807,6 @@ __global__ __launch_bounds__(NT) void k_blend_bwd_chunk(ViewTable vt, ImgTable i
   using Ctx = TileCtx<TW, TH, NT>;
   constexpr int PPT = Ctx::PPT;
   __shared__ float4 s_a[BD], s_b[BD], s_c[BD];
-  __shared__ uint32_t s_e[BD];
   __shared__ int s_max;
   uint32_t item;
   if (!item_of_block(n_items, item)) return;
@@ -771,22 +831,23 @@ __global__ __launch_bounds__(NT) void k_blend_bwd_chunk(ViewTable vt, ImgTable i
     int64_t pi;
     float pxf, pyf;
     tile.pixel(k, inside, pxf, pyf, pi);
-    p = PixGrad{1.f, 0.f, 0.f, 0.f, 0.f, 0.f, 1.f, 0.f, 0.f, 0.f, 0.f, -1, pxf, pyf};
+    p = PixGrad{0.f, 0.f, 0.f, 0.f, 0.f, 1.f, 0.f, 0.f, -1, pxf, pyf};
     if (inside) {
-      p.Tfin = im.t_final[pi];
+      const float Tfin = im.t_final[pi];
       p.ll = min(im.last[pi] - (int)(c * BD), cnt - 1);
       p.gC0 = vg.gC[pi];
       p.gC1 = vg.gC[tile.npx + pi];
       p.gC2 = vg.gC[2 * tile.npx + pi];
       if (vg.gD) p.gD = vg.gD[pi];
       const float gO = vg.gO ? vg.gO[pi] : 0.f;
-      p.gOb = gO - (p.gC0 * cam.bg[0] + p.gC1 * cam.bg[1] + p.gC2 * cam.bg[2]);
+      p.TfG = Tfin * (gO - (p.gC0 * cam.bg[0] + p.gC1 * cam.bg[1] + p.gC2 * cam.bg[2]));
       if (K == 1) {
-        p.T = p.Tfin;
+        p.T = Tfin;
       } else if (p.ll >= 0) {
         const ChunkRec r = chunk[(int64_t)item * (TW * TH) + tile.pidx(k)];
         p.T = r.t;
-        p.A0 = r.c0; p.A1 = r.c1; p.A2 = r.c2; p.AD = r.d;
+        p.S = p.gC0 * r.c0 + p.gC1 * r.c1 + p.gC2 * r.c2;
+        p.AD = r.d;
       }
     }
     mymax = max(mymax, p.ll);
@@ -798,68 +859,13 @@ __global__ __launch_bounds__(NT) void k_blend_bwd_chunk(ViewTable vt, ImgTable i
   __syncthreads();
   const int maxll = __builtin_amdgcn_readfirstlane(s_max);  // uniform: the splat loop runs on scalar registers
   if (maxll < 0) return;  // uniform: no pixel has a contributor in this chunk
-  stage<BD, NT>(vals, cs, maxll + 1, card, s_a, s_b, s_c, s_e);
+  stage<BD, NT, true>(vals, cs, maxll + 1, card, s_a, s_b, s_c);
   __syncthreads();
-
-  const int lane = threadIdx.x & 63;
-  const int slot = reduce10_slot(lane);
-  const bool depth_live = __any(depth_any);
-  for (int j = maxll; j >= 0; --j) {
-    const float4 A = s_a[j], B = s_b[j], Cc = s_c[j];
-    // alpha at every pixel first; a splat no pixel of the wavefront blends costs only this
-    float dxs[PPT], dys[PPT], ms[PPT], qcs[PPT], exs[PPT], ars[PPT];
-    bool act[PPT];
-    bool any = false;
-#pragma unroll
-    for (int k = 0; k < PPT; ++k) {
-      dxs[k] = pg[k].px - A.x;
-      dys[k] = pg[k].py - A.y;
-      const float p2 = splat_p2(A, B, dxs[k], dys[k], ms[k], qcs[k]);
-      exs[k] = splat_e2(p2);
-      ars[k] = B.y * exs[k];
-      act[k] = j <= pg[k].ll && fminf(kAlphaMax, ars[k]) >= kAlphaMin;
-      any = any || act[k];
-    }
-    if (!__any(any)) continue;
-    float g[10];
-#pragma unroll
-    for (int v = 0; v < 10; ++v) g[v] = 0.f;
-#pragma unroll
-    for (int k = 0; k < PPT; ++k) {
-      PixGrad &p = pg[k];
-      // a pixel this splat does not reach takes alpha 0: every update below then leaves its
-      // state unchanged exactly (T * 1, 0 * x + 1 * A) and adds zeros
-      const float alpha = act[k] ? fminf(kAlphaMax, ars[k]) : 0.f;
-      const float one_m = 1.f - alpha;
-      const float inv = __builtin_amdgcn_rcpf(one_m);  // 1 ulp; one_m >= 0.01; exactly 1 at alpha 0
-      p.T = p.T * inv;                                  // transmittance in front of this splat
-      const float w = alpha * p.T;
-      g[6] += p.gC0 * w;
-      g[7] += p.gC1 * w;
-      g[8] += p.gC2 * w;
-      float dLda = p.gC0 * (Cc.x - p.A0) + p.gC1 * (Cc.y - p.A1) + p.gC2 * (Cc.z - p.A2);
-      p.A0 = alpha * Cc.x + one_m * p.A0;
-      p.A1 = alpha * Cc.y + one_m * p.A1;
-      p.A2 = alpha * Cc.z + one_m * p.A2;
-      if (depth_live) {
-        g[9] += p.gD * w;
-        dLda += p.gD * (B.z - p.AD);
-        p.AD = alpha * B.z + one_m * p.AD;
-      }
-      dLda = p.T * dLda + (p.Tfin * inv) * p.gOb;
-      const float dm = (act[k] && ars[k] < kAlphaMax) ? dLda : 0.f;  // clamped alpha: no power path
-      g[5] += dm * exs[k];
-      const float dp = dm * ars[k];
-      g[0] += dp * fmaf(B.w, dys[k], ms[k]);
-      g[1] += dp * fmaf(B.w, dxs[k], qcs[k]);
-      const float dpx = dp * dxs[k];
-      g[2] += dpx * dxs[k];
-      g[3] += dpx * dys[k];
-      g[4] += (dp * dys[k]) * dys[k];
-    }
-    const float tot = wave_reduce10(g);
-    if (slot >= 0 && tot != 0.f) unsafeAtomicAdd(&g2[(int64_t)s_e[j] * 12 + slot], tot);
-  }
+  const int slot = reduce10_slot(threadIdx.x & 63);
+  if (__any(depth_any))
+    bwd_splats<PPT, true>(maxll, s_a, s_b, s_c, pg, slot, g2);
+  else
+    bwd_splats<PPT, false>(maxll, s_a, s_b, s_c, pg, slot, g2);
 }
 
 // ---- per-Gaussian bucketed backward (a second a4 schedule) ---------------------------------
@@ -887,10 +893,9 @@ __global__ __launch_bounds__(64) void k_blend_bwd_bucket(ViewTable vt, ImgTable 
   constexpr int NPIX = TW * TH;
   constexpr int NT = 64;
   __shared__ float4 s_a[BD], s_b[BD], s_c[BD];
-  __shared__ uint32_t s_e[BD];
   // pixel tables: running state and constants
-  __shared__ float sT[NPIX], sA0[NPIX], sA1[NPIX], sA2[NPIX], sAD[NPIX];
-  __shared__ float sTfin[NPIX], sGC0[NPIX], sGC1[NPIX], sGC2[NPIX], sGD[NPIX], sGOb[NPIX];
+  __shared__ float sT[NPIX], sS[NPIX], sAD[NPIX];  // S = dL/dC . colour behind
+  __shared__ float sTfG[NPIX], sGC0[NPIX], sGC1[NPIX], sGC2[NPIX], sGD[NPIX];
   __shared__ int sLL[NPIX];
   __shared__ int s_list[NPIX];  // pixels that can have a contributor in the current bucket
   __shared__ int s_max;
@@ -914,28 +919,28 @@ __global__ __launch_bounds__(64) void k_blend_bwd_bucket(ViewTable vt, ImgTable 
     const int wx = tile.tx * TW + q % TW, wy = tile.ty * TH + q / TW;
     const bool inside = wx < cam.w && wy < cam.h;
     const int64_t pi = (int64_t)wy * cam.w + wx;
-    float T = 1.f, A0 = 0.f, A1 = 0.f, A2 = 0.f, AD = 0.f, Tfin = 1.f, gC0 = 0.f, gC1 = 0.f, gC2 = 0.f, gD = 0.f,
-          gOb = 0.f;
+    float T = 1.f, S = 0.f, AD = 0.f, TfG = 0.f, gC0 = 0.f, gC1 = 0.f, gC2 = 0.f, gD = 0.f;
     int ll = -1;
     if (inside) {
-      Tfin = im.t_final[pi];
+      const float Tfin = im.t_final[pi];
       ll = min(im.last[pi] - (int)(c * BD), cnt - 1);
       gC0 = vg.gC[pi];
       gC1 = vg.gC[tile.npx + pi];
       gC2 = vg.gC[2 * tile.npx + pi];
       if (vg.gD) gD = vg.gD[pi];
       const float gO = vg.gO ? vg.gO[pi] : 0.f;
-      gOb = gO - (gC0 * cam.bg[0] + gC1 * cam.bg[1] + gC2 * cam.bg[2]);
+      TfG = Tfin * (gO - (gC0 * cam.bg[0] + gC1 * cam.bg[1] + gC2 * cam.bg[2]));
       if (K == 1) {
         T = Tfin;
       } else if (ll >= 0) {
         const ChunkRec r = chunk[(int64_t)item * NPIX + q];
         T = r.t;
-        A0 = r.c0; A1 = r.c1; A2 = r.c2; AD = r.d;
+        S = gC0 * r.c0 + gC1 * r.c1 + gC2 * r.c2;
+        AD = r.d;
       }
     }
-    sT[q] = T; sA0[q] = A0; sA1[q] = A1; sA2[q] = A2; sAD[q] = AD;
-    sTfin[q] = Tfin; sGC0[q] = gC0; sGC1[q] = gC1; sGC2[q] = gC2; sGD[q] = gD; sGOb[q] = gOb;
+    sT[q] = T; sS[q] = S; sAD[q] = AD;
+    sTfG[q] = TfG; sGC0[q] = gC0; sGC1[q] = gC1; sGC2[q] = gC2; sGD[q] = gD;
     sLL[q] = ll;
     mymax = max(mymax, ll);
   }
@@ -943,7 +948,7 @@ __global__ __launch_bounds__(64) void k_blend_bwd_bucket(ViewTable vt, ImgTable 
   __syncthreads();
   const int maxll = __builtin_amdgcn_readfirstlane(s_max);
   if (maxll < 0) return;  // uniform: no pixel has a contributor in this chunk
-  stage<BD, NT>(vals, cs, maxll + 1, card, s_a, s_b, s_c, s_e);
+  stage<BD, NT, true>(vals, cs, maxll + 1, card, s_a, s_b, s_c);
   __syncthreads();
   const float x0 = (float)(cam.x0 + tile.tx * TW), y0 = (float)(cam.y0 + tile.ty * TH);
   for (int top = maxll; top >= 0; top -= NT) {
@@ -969,8 +974,11 @@ __global__ __launch_bounds__(64) void k_blend_bwd_bucket(ViewTable vt, ImgTable 
       if (a) s_list[nact + __popcll(m & lanemask_lt())] = q;
       nact += __popcll(m);
     }
-    const int steps = nact + (top - lo);
+    const int steps = nact > 0 ? nact + (top - lo) : 0;  // no listed pixel: the bucket adds nothing
     for (int st = 0; st < steps; ++st) {
+      // pixel r's state is written in step st by lane L and read in step st + 1 by lane L + 1:
+      // the wave barrier keeps each step's LDS accesses in program order across the wavefront
+      __builtin_amdgcn_wave_barrier();
       const int r = st - lane;
       if (j < 0 || r < 0 || r >= nact) continue;
       const int q = s_list[r];
@@ -984,36 +992,32 @@ __global__ __launch_bounds__(64) void k_blend_bwd_bucket(ViewTable vt, ImgTable 
       // a pixel this splat does not reach takes alpha 0 and its state stays as it is
       if (!act) continue;
       const float alpha = fminf(kAlphaMax, ar);
-      const float one_m = 1.f - alpha;
-      const float inv = __builtin_amdgcn_rcpf(one_m);
+      const float inv = __builtin_amdgcn_rcpf(1.f - alpha);
       const float T = sT[q] * inv;
       const float w = alpha * T;
       const float gC0 = sGC0[q], gC1 = sGC1[q], gC2 = sGC2[q], gD = sGD[q];
-      const float A0 = sA0[q], A1 = sA1[q], A2 = sA2[q], AD = sAD[q];
+      const float S = sS[q], AD = sAD[q];
       g[6] += gC0 * w;
       g[7] += gC1 * w;
       g[8] += gC2 * w;
-      float dLda = gC0 * (Cc.x - A0) + gC1 * (Cc.y - A1) + gC2 * (Cc.z - A2);
-      sA0[q] = alpha * Cc.x + one_m * A0;
-      sA1[q] = alpha * Cc.y + one_m * A1;
-      sA2[q] = alpha * Cc.z + one_m * A2;
       g[9] += gD * w;
-      dLda += gD * (B.z - AD);
-      sAD[q] = alpha * B.z + one_m * AD;
+      const float rc = (gC0 * Cc.x + gC1 * Cc.y + gC2 * Cc.z) - S, rd = B.z - AD;
+      sS[q] = fmaf(alpha, rc, S);
+      sAD[q] = fmaf(alpha, rd, AD);
       sT[q] = T;
-      dLda = T * dLda + (sTfin[q] * inv) * sGOb[q];
+      const float dLda = fmaf(T, fmaf(gD, rd, rc), inv * sTfG[q]);
       const float dm = ar < kAlphaMax ? dLda : 0.f;  // clamped alpha: no power path
       g[5] += dm * ex;
       const float dp = dm * ar;
-      g[0] += dp * fmaf(B.w, dy, m);
-      g[1] += dp * fmaf(B.w, dx, qc);
-      const float dpx = dp * dx;
+      const float dpx = dp * dx, dpy = dp * dy;
+      g[0] += dpx;
+      g[1] += dpy;
       g[2] += dpx * dx;
       g[3] += dpx * dy;
-      g[4] += (dp * dy) * dy;
+      g[4] += dpy * dy;
     }
     if (j >= 0) {
-      const int64_t base = (int64_t)s_e[j] * 12;
+      const int64_t base = (int64_t)__float_as_uint(Cc.w) * 12;
 #pragma unroll
       for (int v = 0; v < 10; ++v)
         if (g[v] != 0.f) unsafeAtomicAdd(&g2[base + v], g[v]);

@@ -337,8 +337,8 @@ __global__ __launch_bounds__(256) void k_preprocess(ViewTable vt, const float *_
 // ---------------------------------------------------------------------------------------------
 // Stage a5: chain rule from the 2D quantities to the parameters and the pose.
 // grad2d records [E][12] (48 B, last two unused), as the compositing backward leaves them:
-// sums for u, v, a, b, c in its pre-scaled units (see the factors applied below), then
-// dL/do, dL/d(r, g, b), dL/d(depth).
+// sums over pixels of dp dx, dp dy, dp dx^2, dp dx dy, dp dy^2 (the conic and the constant
+// factors are applied below), then dL/do, dL/d(r, g, b), dL/d(depth).
 // ---------------------------------------------------------------------------------------------
 struct ParamGradOut {
   float *mean, *scale, *rot, *opacity, *sh_dc, *sh_rest;
@@ -641,12 +641,13 @@ __global__ __launch_bounds__(256) void k_geo_bwd(ViewTable vt, const float *__re
       const float gdf[3] = {gv4.x, gv4.y, gv4.z};
       Splat s;
       splat_decide(cam, mx, my, mz, sx, sy, sz, qw, qx, qy, qz, o, s);
-      // grad2d slots 0-4 hold the compositing kernel's sums in its pre-scaled units
-      const float gu = G[0] * (1.0f / kA), gv = G[1] * (1.0f / kA);
+      // grad2d slots 0-4 hold the compositing kernel's sums over pixels of dp dx, dp dy,
+      // dp dx^2, dp dx dy, dp dy^2 (dp = dL/dp of the base-2 exponent p = kA q)
+      const float a = s.a, b = s.b, c = s.c;
+      const float gu = a * G[0] + b * G[1], gv = b * G[0] + c * G[1];
       const float ga = -0.5f * G[2], gb = -G[3], gc = -0.5f * G[4], go = G[5];
       const float gd = G[9];
       // conic -> Sigma': G_S = -Q Ghat Q, Ghat = [[ga, gb/2], [gb/2, gc]]
-      const float a = s.a, b = s.b, c = s.c;
       const float hb = 0.5f * gb;
       const float qg00 = a * ga + b * hb, qg01 = a * hb + b * gc;
       const float qg10 = b * ga + c * hb, qg11 = b * hb + c * gc;
