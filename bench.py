@@ -108,6 +108,7 @@ def parse():
     ap.add_argument("--no-adam", action="store_true", help="skip the sparse Adam measurement")
     ap.add_argument("--no-tracking", action="store_true", help="skip the photometric tracking measurement")
     ap.add_argument("--no-expansion", action="store_true", help="skip the map expansion measurement")
+    ap.add_argument("--no-autograd", action="store_true", help="skip timing the autograd function (GSRender)")
     ap.add_argument("--no-c4", action="store_true", help="skip the 2M-Gaussian differentiation measurement")
     ap.add_argument("--tracking-only", action="store_true",
                     help="run only the photometric tracking measurement (for profiling it alone)")
@@ -429,6 +430,46 @@ def measure_expansion(R, N, torch, S, ps, dev, n_pts=1_000_000, reps=10):
     return res
 
 
+def measure_autograd(R, torch, S, g, cam, pix, ds, target_color, tile, bd, dev, calls=200, warmup=20):
+    """The differentiable form users call: GSRender forward (with the LiDAR term), the RGB L1
+    loss in torch, and the backward to every parameter and the pose tangent (a device tensor
+    at zero), one call after another; per-call latency from events around each call."""
+    gm = R.GaussianMap.from_numpy(g, dev)
+    params = [gm.mean, gm.scale, gm.rot, gm.opacity, gm.sh_dc, gm.sh_rest]
+    for t in params:
+        t.requires_grad_(True)
+    xi = torch.zeros(6, device=dev, requires_grad=True)
+    lidar = R.LidarHits(torch.from_numpy(pix).to(dev), torch.from_numpy(ds).to(dev), weight=1.0)
+    settings = R.RenderSettings(cam, tile=tile, blend_depth=bd, lidar=lidar)
+
+    def call():
+        for t in params:
+            t.grad = None
+        xi.grad = None
+        color, _, _, lloss = R.render(settings, gm, xi)
+        loss = (color - target_color).abs().mean() + lloss
+        loss.backward()
+
+    for _ in range(warmup):
+        call()
+    torch.cuda.synchronize()
+    settings.check()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(calls)]
+    t0 = time.perf_counter()
+    for a, b in ev:
+        a.record()
+        call()
+        b.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    settings.check()  # no call overflowed its pair capacity
+    lat = sorted(a.elapsed_time(b) for a, b in ev)
+    pct = lambda xs, q: xs[min(len(xs) - 1, int(round(q * (len(xs) - 1))))]
+    return {"calls": calls, "p50_ms": round(pct(lat, 0.5), 4), "p99_ms": round(pct(lat, 0.99), 4),
+            "views_s": round(1e3 / pct(lat, 0.5), 2), "wall_ms_per_call": round(wall / calls * 1e3, 4),
+            "tile": tile, "blend_depth": bd, "pair_capacity": settings.capacity}
+
+
 def se3_left(cam, xi):
     """Camera with pose Exp(xi) T_cw (closed-form SE(3) exponential; xi = (rho, phi))."""
     import dataclasses
@@ -746,6 +787,11 @@ def main():
         "bwd_schedule_ms": sched_ms,
         "roofline": roofline,
     }
+    if not args.no_autograd:
+        log("[bench] autograd function")
+        out["autograd"] = measure_autograd(R, torch, S, g, cam, pix, ds, target_color, args.tile, args.blend_depth,
+                                           dev, calls=args.latency_calls)
+        log(f"[bench] autograd {out['autograd']}")
     gC_cpu = None
     if not args.no_cpu_baseline:
         gC_cpu = np.sign(ps.frame.color.cpu().numpy().astype(np.float64) - target_color.cpu().numpy()) / ps.nval

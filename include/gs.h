@@ -82,11 +82,17 @@ typedef struct gs_gaussians {
  *   word 15     for rectangles of at most 32 tiles, bit t set when the t-th tile of the
  *               rectangle (row-major) passed the cull; 0 for larger rectangles.
  * n_tiles [n]  number of tiles kept after the alpha-max cull;
- * dkey    [n]  sort key: IEEE bits of d, or 0xFFFFFFFF when n_tiles = 0. */
+ * dkey    [n]  sort key: IEEE bits of d, or 0xFFFFFFFF when n_tiles = 0;
+ * pose         optional (NULL: the camera's): device float [16], the world-to-camera pose
+ *              R_cw (9, row-major), t_cw (3) and camera centre -R^T t (3) (+1 unused), read
+ *              on the device by gs_preprocess and gs_render_bwd in place of cam->R_cw / t_cw,
+ *              so a pose computed on the device (gs_pose_left_update) needs no host round
+ *              trip. Single-view calls only. */
 typedef struct gs_projected {
   float *card;
   uint32_t *n_tiles;
   uint32_t *dkey;
+  const float *pose;
 } gs_projected;
 
 /* Tile lists (Sec. "CUDA-Related Acceleration Strategies", fast tile-based culling; depth
@@ -261,6 +267,14 @@ int64_t gs_batch_capacity(const gs_batch_plan *plan);
 /* Host helper: camera with pose Exp(xi) T_cw (xi = (rho, phi), closed-form SE(3) exponential),
  * the left update whose derivative gs_render_bwd reports. Intrinsics and window are copied. */
 int gs_camera_left_update(const gs_camera *in, const float xi[6], gs_camera *out);
+
+/* Device form of gs_camera_left_update (the left perturbation whose derivative follows
+ * eq:3dgs_jacobi): pose_out (device float [16], the layout of gs_projected.pose) receives
+ * Exp(xi) T_cw for the tangent xi (device float [6], (rho, phi)) and the camera's R_cw, t_cw,
+ * computed in float64 by one lane and rounded once. Asynchronous on `stream`; reads xi when
+ * the stream reaches it. Errors: GS_ERR_INVALID_ARG for NULL pointers or a camera failing the
+ * usual checks. */
+int gs_pose_left_update(const gs_camera *cam, const float *xi, float *pose_out, gs_stream_t stream);
 
 /* Kernel timing. gs_profile_enable creates `max_records` pairs of HIP events per stage
  * (allocation happens here, not in the timed calls); afterwards every launch of a stage in

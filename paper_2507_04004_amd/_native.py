@@ -31,7 +31,7 @@ class Gaussians(C.Structure):
 
 
 class Projected(C.Structure):
-    _fields_ = [(k, vp) for k in ("card", "n_tiles", "dkey")]
+    _fields_ = [(k, vp) for k in ("card", "n_tiles", "dkey", "pose")]
 
 
 class Bins(C.Structure):
@@ -105,7 +105,7 @@ EXPORTS = ["gs_preprocess", "gs_bin_sort", "gs_render_fwd", "gs_render_bwd", "gs
            "gs_render_batch", "gs_loss_l1",
            "gs_adam_sparse", "gs_loss_dssim", "gs_dssim_scratch_bytes", "gs_track_plan_create",
            "gs_track_plan_destroy", "gs_track_capacity", "gs_track_pose", "gs_track_required_pairs",
-           "gs_pose_residual", "gs_expand_scratch_bytes", "gs_expand_select", "gs_expand_write",
+           "gs_pose_residual", "gs_pose_left_update", "gs_expand_scratch_bytes", "gs_expand_select", "gs_expand_write",
            "gs_bins_scratch_bytes", "gs_image_state_bytes", "gs_grads_scratch_bytes", "gs_batch_plan_create", "gs_batch_plan_destroy",
            "gs_batch_num_pairs", "gs_batch_capacity", "gs_camera_left_update", "gs_last_error",
            "gs_profile_enable", "gs_profile_read", "gs_profile_disable"]
@@ -147,6 +147,7 @@ def lib():
     L.gs_batch_capacity.argtypes = [vp]
     L.gs_batch_capacity.restype = C.c_int64
     L.gs_camera_left_update.argtypes = [P(Camera), P(C.c_float * 6), P(Camera)]
+    L.gs_pose_left_update.argtypes = [P(Camera), vp, vp, vp]
     L.gs_track_plan_create.argtypes = [P(vp), C.c_int64, C.c_int32, C.c_int64, C.c_int32, C.c_int32, C.c_int32,
                                        C.c_int64]
     L.gs_track_plan_destroy.argtypes = [vp]

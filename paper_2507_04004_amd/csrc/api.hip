@@ -365,6 +365,7 @@ int gs_preprocess(const gs_gaussians *g, const gs_camera *cam, int32_t tile_w, i
   if (!tile_ok(tile_w, tile_h)) return fail(GS_ERR_INVALID_ARG, "tile size must be 8x8, 16x16 or 32x32");
   gs::ViewTable vt;
   if ((rc = make_table(cam, 1, g->n, g->sh_degree, tile_w, tile_h, vt))) return rc;
+  vt.pose_dev = out->pose;
   gs::profile_begin(GS_STAGE_PREPROCESS, (hipStream_t)stream);
   GS_CHECK_DEVICE();
   GS_TRY_HIP(gs::launch_preprocess(vt, *g, *out, (hipStream_t)stream), "preprocess");
@@ -446,6 +447,7 @@ int check_bwd(const gs_gaussians *g, const gs_camera *cam, const gs_projected *p
   if ((rc = check_schedule(out->schedule, bins->tile_w))) return rc;
   if ((rc = check_lidar(lidar, (int64_t)cam->w * cam->h))) return rc;
   if ((rc = make_table(cam, 1, g->n, g->sh_degree, bins->tile_w, bins->tile_h, vt))) return rc;
+  vt.pose_dev = proj->pose;
   return check_state(fwd, bins->capacity, vt.total_tiles, bins->tile_w, bins->tile_h, blend_depth);
 }
 
@@ -570,6 +572,18 @@ int gs_camera_left_update(const gs_camera *in, const float xi[6], gs_camera *out
     o.t_cw[i] = (float)s;
   }
   *out = o;
+  return GS_OK;
+}
+
+int gs_pose_left_update(const gs_camera *cam, const float *xi, float *pose_out, gs_stream_t stream) {
+  int rc;
+  if ((rc = check_camera(cam))) return rc;
+  if (!xi || !pose_out) return fail(GS_ERR_INVALID_ARG, "NULL argument");
+  gs::TrackPose p0;
+  for (int i = 0; i < 9; ++i) p0.R[i] = cam->R_cw[i];
+  for (int i = 0; i < 3; ++i) p0.t[i] = cam->t_cw[i];
+  GS_CHECK_DEVICE();
+  GS_TRY_HIP(gs::launch_pose_left_update(p0, xi, pose_out, (hipStream_t)stream), "pose update");
   return GS_OK;
 }
 

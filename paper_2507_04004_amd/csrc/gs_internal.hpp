@@ -115,6 +115,7 @@ hipError_t launch_expand_write(const ExpandArgs &a, const void *scratch, const E
 
 constexpr int kTrackTraceStride = 20;  // pose (12), gradient (6), L1 term, D-SSIM term
 hipError_t launch_track_init(TrackState *s, const TrackPose &p0, hipStream_t st);
+hipError_t launch_pose_left_update(const TrackPose &p0, const float *xi, float *pose, hipStream_t st);
 hipError_t launch_track_step(TrackState *s, const TrackStepArgs &a, const int64_t *num_pairs, float *trace,
                              float *pose_out, hipStream_t st);
 

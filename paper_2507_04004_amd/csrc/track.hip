@@ -28,11 +28,44 @@ __device__ void mul3(const double A[9], const double B[9], double C[9]) {
 }
 
 // float32 copies for the kernels: R, t, and the camera centre -R^T t
-__device__ void publish(const TrackState &s, float *pose) {
-  for (int i = 0; i < 9; ++i) pose[i] = (float)s.R[i];
-  for (int i = 0; i < 3; ++i) pose[9 + i] = (float)s.t[i];
-  for (int i = 0; i < 3; ++i) pose[12 + i] = (float)(-(s.R[i] * s.t[0] + s.R[3 + i] * s.t[1] + s.R[6 + i] * s.t[2]));
+__device__ void publish_pose(const double R[9], const double t[3], float *pose) {
+  for (int i = 0; i < 9; ++i) pose[i] = (float)R[i];
+  for (int i = 0; i < 3; ++i) pose[9 + i] = (float)t[i];
+  for (int i = 0; i < 3; ++i) pose[12 + i] = (float)(-(R[i] * t[0] + R[3 + i] * t[1] + R[6 + i] * t[2]));
   pose[15] = 0.f;
+}
+
+__device__ void publish(const TrackState &s, float *pose) { publish_pose(s.R, s.t, pose); }
+
+// Left update (R, t) <- Exp(d) (R0, t0), d = (rho, phi): closed-form SE(3) exponential
+// R = I + A P + B P^2, V = I + B P + C P^2 with P = phi^ (series for small angles).
+__device__ void left_exp(const double d[6], const double R0[9], const double t0[3], double R[9], double t[3]) {
+  const double th2 = d[3] * d[3] + d[4] * d[4] + d[5] * d[5];
+  const double th = sqrt(th2);
+  double A, B, C;
+  if (th < 1e-5) {
+    A = 1.0 - th2 / 6.0;
+    B = 0.5 - th2 / 24.0;
+    C = 1.0 / 6.0 - th2 / 120.0;
+  } else {
+    const double sn = sin(th), cs = cos(th);
+    A = sn / th;
+    B = (1.0 - cs) / th2;
+    C = (th - sn) / (th2 * th);
+  }
+  double P[9], P2[9];
+  hat3(d + 3, P);
+  mul3(P, P, P2);
+  double dR[9], V[9];
+  for (int i = 0; i < 9; ++i) {
+    const double I = (i % 4 == 0) ? 1.0 : 0.0;
+    dR[i] = I + A * P[i] + B * P2[i];
+    V[i] = I + B * P[i] + C * P2[i];
+  }
+  mul3(dR, R0, R);
+  for (int i = 0; i < 3; ++i)
+    t[i] = dR[3 * i] * t0[0] + dR[3 * i + 1] * t0[1] + dR[3 * i + 2] * t0[2] +
+           (V[3 * i] * d[0] + V[3 * i + 1] * d[1] + V[3 * i + 2] * d[2]);
 }
 
 }  // namespace
@@ -73,40 +106,30 @@ __global__ void k_track_step(TrackState *__restrict__ s, TrackStepArgs a, const 
     const double mh = st.m[i] / a.bias1, vh = st.v[i] / a.bias2;
     d[i] = -a.lr[i] * mh / (sqrt(vh) + a.eps);
   }
-  // Exp(delta): R = I + A P + B P^2, V = I + B P + C P^2 (series for small angles)
-  const double th2 = d[3] * d[3] + d[4] * d[4] + d[5] * d[5];
-  const double th = sqrt(th2);
-  double A, B, C;
-  if (th < 1e-5) {
-    A = 1.0 - th2 / 6.0;
-    B = 0.5 - th2 / 24.0;
-    C = 1.0 / 6.0 - th2 / 120.0;
-  } else {
-    const double sn = sin(th), cs = cos(th);
-    A = sn / th;
-    B = (1.0 - cs) / th2;
-    C = (th - sn) / (th2 * th);
-  }
-  double P[9], P2[9];
-  hat3(d + 3, P);
-  mul3(P, P, P2);
-  double dR[9], V[9];
-  for (int i = 0; i < 9; ++i) {
-    const double I = (i % 4 == 0) ? 1.0 : 0.0;
-    dR[i] = I + A * P[i] + B * P2[i];
-    V[i] = I + B * P[i] + C * P2[i];
-  }
   double R[9], t[3];
-  mul3(dR, st.R, R);
-  for (int i = 0; i < 3; ++i)
-    t[i] = dR[3 * i] * st.t[0] + dR[3 * i + 1] * st.t[1] + dR[3 * i + 2] * st.t[2] +
-           (V[3 * i] * d[0] + V[3 * i + 1] * d[1] + V[3 * i + 2] * d[2]);
+  left_exp(d, st.R, st.t, R, t);
   for (int i = 0; i < 9; ++i) st.R[i] = R[i];
   for (int i = 0; i < 3; ++i) st.t[i] = t[i];
   publish(st, st.pose);
   *s = st;
   if (pose_out)
     for (int i = 0; i < 12; ++i) pose_out[i] = st.pose[i];
+}
+
+// One lane: the pose Exp(xi) (R0, t0) of a tangent xi (float32 [6], device) as the float32
+// R (9), t (3) and camera centre (3) the projection kernels read through a device pointer.
+__global__ void k_pose_left_update(TrackPose p0, const float *__restrict__ xi, float *__restrict__ pose) {
+  if (threadIdx.x != 0) return;
+  double d[6];
+  for (int i = 0; i < 6; ++i) d[i] = (double)xi[i];
+  double R[9], t[3];
+  left_exp(d, p0.R, p0.t, R, t);
+  publish_pose(R, t, pose);
+}
+
+hipError_t launch_pose_left_update(const TrackPose &p0, const float *xi, float *pose, hipStream_t st) {
+  hipLaunchKernelGGL(k_pose_left_update, dim3(1), dim3(64), 0, st, p0, xi, pose);
+  return hipGetLastError();
 }
 
 hipError_t launch_track_init(TrackState *s, const TrackPose &p0, hipStream_t st) {

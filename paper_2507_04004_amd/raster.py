@@ -86,6 +86,7 @@ class Splats:
     card: torch.Tensor
     n_tiles: torch.Tensor
     dkey: torch.Tensor
+    pose: torch.Tensor | None = None  # device pose [16] used in place of the camera's (pose_left_update)
 
     @staticmethod
     def empty(n, device) -> "Splats":
@@ -112,7 +113,7 @@ class Splats:
         return self.card[:, 12:14].contiguous().view(torch.int16)
 
     def struct(self) -> N.Projected:
-        return N.Projected(_p(self.card), _p(self.n_tiles), _p(self.dkey))
+        return N.Projected(_p(self.card), _p(self.n_tiles), _p(self.dkey), _p(self.pose))
 
 
 @dataclasses.dataclass
@@ -180,8 +181,18 @@ def tiles_of(cs: N.Camera, tile: int) -> int:
 
 # ---- stage wrappers ------------------------------------------------------------------------
 
-def preprocess(gs: N.Gaussians, cs: N.Camera, tile: int, device, out: Splats | None = None) -> Splats:
+def pose_left_update(cs: N.Camera, xi: torch.Tensor, out: torch.Tensor | None = None) -> torch.Tensor:
+    """Device pose Exp(xi) T_cw of a device tangent xi (6,), in the layout of Splats.pose."""
+    xi = xi.detach().to(torch.float32).contiguous()
+    out = out if out is not None else torch.empty(16, dtype=torch.float32, device=xi.device)
+    N.check(N.lib().gs_pose_left_update(C.byref(cs), _p(xi), _p(out), _stream()), "gs_pose_left_update")
+    return out
+
+
+def preprocess(gs: N.Gaussians, cs: N.Camera, tile: int, device, out: Splats | None = None,
+               pose: torch.Tensor | None = None) -> Splats:
     out = out or Splats.empty(gs.n, device)
+    out.pose = pose
     N.check(N.lib().gs_preprocess(C.byref(gs), C.byref(cs), tile, tile, C.byref(out.struct()), _stream()),
             "gs_preprocess")
     return out
@@ -308,10 +319,49 @@ def loss_dssim(color: torch.Tensor, target: torch.Tensor, weight: float = 1.0,
 @dataclasses.dataclass
 class RenderSettings:
     camera: object                  # scenes.Camera-like
-    tile: int = 16
-    blend_depth: int = 256
+    tile: int = 8
+    blend_depth: int = 128
     lidar: LidarHits | None = None  # sparse depth term evaluated inside the library
-    capacity: int | None = None     # initial pair capacity (grown on overflow)
+    capacity: int | None = None     # pair capacity; learned from the first call when None
+    sync_check: bool = False        # True: read the pair count back after every forward
+    _pending: list = dataclasses.field(default_factory=list, repr=False)
+
+    def check(self, wait: bool = True) -> None:
+        """Raise if an earlier forward needed more pairs than its capacity (its lists were
+        clamped and its outputs are invalid); the capacity is grown for later calls.
+        wait=False only looks at forwards whose pair count has already arrived."""
+        keep, bad = [], None
+        for ev, host, cap in self._pending:
+            if not wait and not ev.query():
+                keep.append((ev, host, cap))
+                continue
+            ev.synchronize()
+            need = int(host.item())
+            if need > 0.8 * (self.capacity or 0):
+                self.capacity = int(math.ceil(need * 1.25))
+            if need > cap and bad is None:
+                bad = (need, cap)
+        self._pending = keep
+        if bad is not None:
+            raise RuntimeError(f"a forward needed {bad[0]} (tile, Gaussian) pairs but had capacity {bad[1]}: its "
+                               f"outputs are invalid; capacity grown to {self.capacity}, render it again")
+
+
+def _bin_sort_async(settings: RenderSettings, spl: Splats, n: int, cs: N.Camera, dev) -> TileBins:
+    """Binning without a host round trip once the capacity is known: the pair count is copied
+    to pinned host memory behind an event and checked by a later call (RenderSettings.check)."""
+    settings.check(wait=False)
+    if settings.capacity is None or settings.sync_check:
+        bins = bin_sort_fit(spl, n, cs, settings.tile, dev, settings.capacity)
+        settings.capacity = max(settings.capacity or 0, int(math.ceil(bins.pairs() * 1.25)), 1024)
+        return bins
+    bins = bin_sort(spl, n, cs, alloc_bins(n, cs, settings.tile, settings.capacity, dev))
+    host = torch.empty(1, dtype=torch.int64, pin_memory=True)
+    host.copy_(bins.num_pairs, non_blocking=True)
+    ev = torch.cuda.Event()
+    ev.record()
+    settings._pending.append((ev, host, bins.capacity))
+    return bins
 
 
 class GSRender(torch.autograd.Function):
@@ -320,6 +370,10 @@ class GSRender(torch.autograd.Function):
     pose_tangent xi (6,) is applied as T_cw <- Exp(xi) T_cw; its gradient is the left-
     perturbation gradient at the rendered pose (exact at xi = 0, the way a tracking loop
     uses it: fold xi into the pose after each step and reset it to zero).
+
+    No host round trip once the settings know the pair capacity: a device tangent is turned
+    into the device pose the projection reads (gs_pose_left_update), and the pair count is
+    checked one call late (RenderSettings.check).
     """
 
     @staticmethod
@@ -327,20 +381,25 @@ class GSRender(torch.autograd.Function):
         dev = mean.device
         deg = int(round(math.sqrt(sh_rest.shape[0] // 3 + 1))) - 1 if sh_rest.numel() else 0
         cs = camera_struct(settings.camera)
+        pose = None
         if pose_tangent is not None:
-            xi = pose_tangent.detach().float().cpu().numpy()
-            if np.any(xi != 0):
-                cs = camera_left_update(cs, xi)
+            if pose_tangent.device.type == "cpu":
+                xi = pose_tangent.detach().float().numpy()
+                if np.any(xi != 0):
+                    cs = camera_left_update(cs, xi)
+            else:
+                pose = pose_left_update(cs, pose_tangent)
         gs = gaussians_struct(mean, scale, rot, opacity, sh_dc, sh_rest, deg)
         n = gs.n
-        spl = preprocess(gs, cs, settings.tile, dev)
-        bins = bin_sort_fit(spl, n, cs, settings.tile, dev, settings.capacity)
+        spl = preprocess(gs, cs, settings.tile, dev, pose=pose)
+        bins = _bin_sort_async(settings, spl, n, cs, dev)
         lidar = settings.lidar
         lloss = torch.zeros(1, dtype=torch.float32, device=dev)
         fr = render_fwd(spl, n, bins, cs, settings.blend_depth, dev, lidar, lloss)
         ctx.settings, ctx.cs, ctx.deg = settings, cs, deg
         ctx.spl, ctx.bins, ctx.fr = spl, bins, fr
         ctx.has_pose = pose_tangent is not None
+        ctx.pose_device = pose_tangent.device if pose_tangent is not None else None
         ctx.save_for_backward(mean, scale, rot, opacity, sh_dc, sh_rest)
         return fr.color, fr.depth, fr.alpha, lloss[0]
 
@@ -362,7 +421,7 @@ class GSRender(torch.autograd.Function):
         scratch = grads_scratch(gs.n, cs.w * cs.h, dev)
         render_bwd(gs, cs, ctx.spl, ctx.bins, ctx.fr, gC, gD, gO, ctx.settings.blend_depth, grads, scratch,
                    lidar, scale_t, overwrite=True)
-        gpose = grads.pose if ctx.has_pose else None
+        gpose = grads.pose.to(ctx.pose_device) if ctx.has_pose else None
         return None, grads.mean, grads.scale, grads.rot, grads.opacity, grads.sh_dc, grads.sh_rest, gpose
 
 

@@ -227,3 +227,11 @@ def test_noalloc_backward_rejects_sizes_beyond_its_scratch():
     assert L.gs_render_bwd(C.byref(g), C.byref(cam), C.byref(proj), C.byref(bins), C.byref(img), dummy, None, None,
                            None, 128, C.byref(grads), None) == N.GS_ERR_INVALID_ARG
     assert b"scratch" in L.gs_last_error()
+
+
+def test_pose_left_update_argument_errors():
+    L = N.lib()
+    dummy = C.c_void_p(64)
+    assert L.gs_pose_left_update(C.byref(_cam()), None, dummy, None) == N.GS_ERR_INVALID_ARG
+    assert L.gs_pose_left_update(C.byref(_cam()), dummy, None, None) == N.GS_ERR_INVALID_ARG
+    assert L.gs_pose_left_update(C.byref(_cam(fx=-1.0)), dummy, dummy, None) == N.GS_ERR_INVALID_ARG
