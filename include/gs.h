@@ -245,10 +245,17 @@ typedef struct gs_batch_plan gs_batch_plan;
 
 /* Creates a plan for up to n_views (<= GS_MAX_VIEWS) views of a map of n Gaussians at the
  * given degree: it owns the splat records, tile lists (pair capacity `capacity`, summed over
- * views), scratch and, with GS_GRAPH, the captured hipGraph. Allocates device memory. */
+ * views), scratch and, with GS_GRAPH, the captured hipGraph. Allocates device memory.
+ * flags: GS_PLAN_FWD_ONLY for a plan that only renders (no backward scratch; gs_render_batch
+ * with GS_BWD then fails with GS_ERR_INVALID_ARG), else 0. */
+enum { GS_PLAN_FWD_ONLY = 1 };
 int gs_batch_plan_create(gs_batch_plan **plan, int64_t n, int32_t sh_degree, int32_t n_views,
                          int64_t max_total_pixels, int32_t tile_w, int32_t tile_h, int32_t blend_depth,
-                         int64_t capacity);
+                         int64_t capacity, uint32_t flags);
+/* Device bytes gs_batch_plan_create allocates for the same arguments (0 when they are
+ * invalid); for admission by memory before a plan exists. */
+size_t gs_batch_plan_bytes(int64_t n, int32_t sh_degree, int32_t n_views, int64_t max_total_pixels,
+                           int32_t tile_w, int32_t tile_h, int32_t blend_depth, int64_t capacity, uint32_t flags);
 void gs_batch_plan_destroy(gs_batch_plan *plan);
 
 /* Renders (GS_FWD) and/or differentiates (GS_BWD) all views in one launch per stage. With

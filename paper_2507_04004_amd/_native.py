@@ -14,6 +14,7 @@ LIB_PATH = os.path.join(_HERE, "_lib", "libgs.so")
 GS_OK, GS_ERR_INVALID_ARG, GS_ERR_HIP, GS_ERR_UNSUPPORTED, GS_ERR_CAPACITY = 0, 1, 2, 3, 4
 GS_MAX_VIEWS = 16
 GS_FWD, GS_BWD, GS_GRAPH = 1, 2, 4
+GS_PLAN_FWD_ONLY = 1
 
 fp = C.POINTER(C.c_float)
 vp = C.c_void_p
@@ -106,7 +107,7 @@ EXPORTS = ["gs_preprocess", "gs_bin_sort", "gs_render_fwd", "gs_render_bwd", "gs
            "gs_adam_sparse", "gs_loss_dssim", "gs_dssim_scratch_bytes", "gs_track_plan_create",
            "gs_track_plan_destroy", "gs_track_capacity", "gs_track_pose", "gs_track_required_pairs",
            "gs_pose_residual", "gs_pose_left_update", "gs_expand_scratch_bytes", "gs_expand_select", "gs_expand_write",
-           "gs_bins_scratch_bytes", "gs_image_state_bytes", "gs_grads_scratch_bytes", "gs_batch_plan_create", "gs_batch_plan_destroy",
+           "gs_bins_scratch_bytes", "gs_image_state_bytes", "gs_grads_scratch_bytes", "gs_batch_plan_create", "gs_batch_plan_bytes", "gs_batch_plan_destroy",
            "gs_batch_num_pairs", "gs_batch_capacity", "gs_camera_left_update", "gs_last_error",
            "gs_profile_enable", "gs_profile_read", "gs_profile_disable"]
 GS_STAGE_PREPROCESS, GS_STAGE_BIN_SORT, GS_STAGE_BLEND_FWD, GS_STAGE_BLEND_BWD, GS_STAGE_PREPROCESS_BWD = range(5)
@@ -139,7 +140,10 @@ def lib():
     L.gs_grads_scratch_bytes.argtypes = [C.c_int64, C.c_int32, C.c_int64]
     L.gs_grads_scratch_bytes.restype = C.c_size_t
     L.gs_batch_plan_create.argtypes = [P(vp), C.c_int64, C.c_int32, C.c_int32, C.c_int64, C.c_int32, C.c_int32,
-                                       C.c_int32, C.c_int64]
+                                       C.c_int32, C.c_int64, C.c_uint32]
+    L.gs_batch_plan_bytes.argtypes = [C.c_int64, C.c_int32, C.c_int32, C.c_int64, C.c_int32, C.c_int32,
+                                      C.c_int32, C.c_int64, C.c_uint32]
+    L.gs_batch_plan_bytes.restype = C.c_size_t
     L.gs_batch_plan_destroy.argtypes = [vp]
     L.gs_batch_plan_destroy.restype = None
     L.gs_render_batch.argtypes = [vp, P(Gaussians), C.c_int32, P(View), C.c_uint32, P(Grads), vp]

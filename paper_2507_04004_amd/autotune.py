@@ -34,9 +34,11 @@ def candidate_key(tile, bd, schedule=N.GS_BWD_CHUNKS) -> str:
     return k if schedule == N.GS_BWD_CHUNKS else f"{k}/{SCHEDULE_NAMES[schedule]}"
 
 
-def workload_key(gm: R.GaussianMap, cams, backward: bool) -> str:
+def workload_key(gm: R.GaussianMap, cams, backward: bool, candidates=None) -> str:
+    """Cache key: the workload's shape and the candidate set it was tuned over."""
     shapes = ",".join(f"{c.w}x{c.h}@{round(float(c.fx))}" for c in cams)
-    return f"n={gm.n};deg={gm.sh_degree};bwd={int(backward)};views={shapes}"
+    cands = ",".join(sorted({candidate_key(*_split(c)) for c in (candidates or DEFAULT_CANDIDATES)}))
+    return f"n={gm.n};deg={gm.sh_degree};bwd={int(backward)};views={shapes};candidates={cands}"
 
 
 def _time_candidate(gm, cams, tile, bd, backward, capacity, reps, warmup, device, targets, schedule):
@@ -71,7 +73,7 @@ def autotune_config(gm: R.GaussianMap, cams, backward: bool = True, candidates=N
                     verbose: bool = False) -> dict:
     """{"tile", "blend_depth", "schedule", "timings"} of the fastest candidate for this workload;
     consults / updates the cache. Without a backward the schedule plays no part."""
-    key = workload_key(gm, cams, backward)
+    key = workload_key(gm, cams, backward, candidates)
     cache = {}
     if cache_path and os.path.exists(cache_path):
         with open(cache_path) as fh:
@@ -109,6 +111,7 @@ def autotune_config(gm: R.GaussianMap, cams, backward: bool = True, candidates=N
 def autotune(gm: R.GaussianMap, cams, backward: bool = True, candidates=None, capacity: int | None = None,
              reps: int = 5, warmup: int = 2, device="cuda", cache_path: str | None = None, targets=None,
              verbose: bool = False):
-    """(tile, blend_depth, timings) of autotune_config."""
+    """(tile, blend_depth, schedule, timings) of autotune_config: the schedule is part of the
+    choice (a tile size and depth timed under the bucketed schedule are only the fastest with it)."""
     r = autotune_config(gm, cams, backward, candidates, capacity, reps, warmup, device, cache_path, targets, verbose)
-    return r["tile"], r["blend_depth"], r["timings"]
+    return r["tile"], r["blend_depth"], r["schedule"], r["timings"]

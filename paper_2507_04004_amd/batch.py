@@ -47,17 +47,29 @@ class ViewSlot:
                       lid, p(self.target), float(self.rgb_weight), p(self.rgb_loss), p(self.pose_grad))
 
 
+def plan_bytes(n: int, sh_degree: int, max_views: int, max_total_pixels: int, tile: int, blend_depth: int,
+               capacity: int, fwd_only: bool = False) -> int:
+    """Device bytes of a BatchPlan with these arguments (gs_batch_plan_bytes)."""
+    return int(N.lib().gs_batch_plan_bytes(n, sh_degree, max_views, max_total_pixels, tile, tile, blend_depth,
+                                           capacity, N.GS_PLAN_FWD_ONLY if fwd_only else 0))
+
+
 class BatchPlan:
     def __init__(self, n: int, sh_degree: int, max_views: int, max_total_pixels: int, tile: int = 16,
-                 blend_depth: int = 256, capacity: int | None = None, device="cuda"):
+                 blend_depth: int = 256, capacity: int | None = None, device="cuda", fwd_only: bool = False):
+        """fwd_only: a plan that only renders (no backward scratch)."""
         self.n, self.sh_degree, self.max_views = n, sh_degree, max_views
         self.max_total_pixels = max_total_pixels
         self.tile, self.blend_depth = tile, blend_depth
         self.capacity = int(capacity or max(1 << 16, 8 * n * max_views // 4))
         self.device = device
+        self.fwd_only = fwd_only
         self._plan = C.c_void_p()
         N.check(N.lib().gs_batch_plan_create(C.byref(self._plan), n, sh_degree, max_views, max_total_pixels, tile, tile,
-                                             blend_depth, self.capacity), "gs_batch_plan_create")
+                                             blend_depth, self.capacity, N.GS_PLAN_FWD_ONLY if fwd_only else 0),
+                "gs_batch_plan_create")
+        self.nbytes = plan_bytes(n, sh_degree, max_views, max_total_pixels, tile, blend_depth, self.capacity,
+                                 fwd_only)
         self._keep = None
 
     def close(self):

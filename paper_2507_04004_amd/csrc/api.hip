@@ -667,6 +667,7 @@ struct gs_batch_plan {
   int64_t n = 0;
   int32_t deg = 0, max_views = 0, tw = 16, th = 16, bd = 256;
   int64_t max_pixels = 0, cap = 0, max_tiles = 0;
+  bool fwd_only = false;
   // owned device memory
   void *block = nullptr;
   gs_projected proj{};
@@ -700,8 +701,8 @@ size_t plan_bytes(const gs_batch_plan &p, size_t *offs) {
   put(4, 8 * std::max<int64_t>(p.max_tiles, 1));       // tile ranges
   put(5, 16);                                          // num_pairs
   put(6, gs::bin_scratch_bytes(E, p.cap));             // bin scratch
-  put(7, grads_scratch_bytes_impl(p.n, p.max_views, p.max_pixels));
-  put(8, 12 * std::max<int64_t>(p.max_pixels, 1));    // dC planes
+  put(7, p.fwd_only ? 0 : grads_scratch_bytes_impl(p.n, p.max_views, p.max_pixels));
+  put(8, p.fwd_only ? 0 : 12 * std::max<int64_t>(p.max_pixels, 1));  // dC planes
   put(9, gs::blend_state_bytes(p.max_tiles, p.cap, p.tw, p.th, p.bd));
   return o;
 }
@@ -784,6 +785,7 @@ int check_views(const gs_batch_plan *p, const gs_gaussians *g, int nv, const gs_
   if (nv <= 0 || nv > p->max_views) return fail(GS_ERR_INVALID_ARG, "n_views must be in 1..%d", p->max_views);
   if (!views) return fail(GS_ERR_INVALID_ARG, "views is NULL");
   if (!(mode & (GS_FWD | GS_BWD))) return fail(GS_ERR_INVALID_ARG, "mode needs GS_FWD and/or GS_BWD");
+  if ((mode & GS_BWD) && p->fwd_only) return fail(GS_ERR_INVALID_ARG, "the plan was created forward-only");
   for (int i = 0; i < nv; ++i) {
     if ((rc = check_camera(&views[i].cam)) || (rc = check_image(&views[i].out))) return rc;
     if ((rc = check_lidar(&views[i].lidar, (int64_t)views[i].cam.w * views[i].cam.h))) return rc;
@@ -800,10 +802,13 @@ int check_views(const gs_batch_plan *p, const gs_gaussians *g, int nv, const gs_
 
 extern "C" {
 
-int gs_batch_plan_create(gs_batch_plan **out, int64_t n, int32_t sh_degree, int32_t n_views, int64_t max_total_pixels,
-                         int32_t tile_w, int32_t tile_h, int32_t blend_depth, int64_t capacity) {
-  if (!out) return fail(GS_ERR_INVALID_ARG, "plan out-pointer is NULL");
-  *out = nullptr;
+}  // extern "C"
+
+namespace {
+
+// Arguments of a batch plan, checked; fills the plan's sizes.
+int plan_args(int64_t n, int32_t sh_degree, int32_t n_views, int64_t max_total_pixels, int32_t tile_w, int32_t tile_h,
+              int32_t blend_depth, int64_t capacity, uint32_t flags, gs_batch_plan &p) {
   if (n < 0 || n > 0x7FFFFFFF || sh_degree < 0 || sh_degree > 3) return fail(GS_ERR_INVALID_ARG, "bad n or degree");
   if (n_views < 1 || n_views > GS_MAX_VIEWS) return fail(GS_ERR_INVALID_ARG, "n_views must be in 1..%d", GS_MAX_VIEWS);
   if (n * n_views > 0xFFFFFFFFll) return fail(GS_ERR_INVALID_ARG, "n * n_views too large");
@@ -811,18 +816,43 @@ int gs_batch_plan_create(gs_batch_plan **out, int64_t n, int32_t sh_degree, int3
   if (!depth_ok(blend_depth)) return fail(GS_ERR_INVALID_ARG, "blend_depth must be 64, 128 or 256");
   if (max_total_pixels <= 0 || capacity <= 0 || capacity > 0xFFFFFFFFll)
     return fail(GS_ERR_INVALID_ARG, "bad pixel budget or capacity");
-  GS_CHECK_DEVICE();
-  gs_batch_plan *p = new gs_batch_plan();
-  p->n = n;
-  p->deg = sh_degree;
-  p->max_views = n_views;
-  p->max_pixels = max_total_pixels;
-  p->tw = tile_w;
-  p->th = tile_h;
-  p->bd = blend_depth;
-  p->cap = capacity;
+  if (flags & ~(uint32_t)GS_PLAN_FWD_ONLY) return fail(GS_ERR_INVALID_ARG, "unknown plan flags 0x%x", flags);
+  p.n = n;
+  p.deg = sh_degree;
+  p.max_views = n_views;
+  p.max_pixels = max_total_pixels;
+  p.tw = tile_w;
+  p.th = tile_h;
+  p.bd = blend_depth;
+  p.cap = capacity;
+  p.fwd_only = (flags & GS_PLAN_FWD_ONLY) != 0;
   // every view adds at most one partial tile row and column beyond pixels / tile area
-  p->max_tiles = max_total_pixels / ((int64_t)tile_w * tile_h) + (int64_t)n_views * (2 * 32768 / tile_w + 1);
+  p.max_tiles = max_total_pixels / ((int64_t)tile_w * tile_h) + (int64_t)n_views * (2 * 32768 / tile_w + 1);
+  return GS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t gs_batch_plan_bytes(int64_t n, int32_t sh_degree, int32_t n_views, int64_t max_total_pixels, int32_t tile_w,
+                           int32_t tile_h, int32_t blend_depth, int64_t capacity, uint32_t flags) {
+  gs_batch_plan p;
+  if (plan_args(n, sh_degree, n_views, max_total_pixels, tile_w, tile_h, blend_depth, capacity, flags, p)) return 0;
+  size_t offs[10];
+  return plan_bytes(p, offs);
+}
+
+int gs_batch_plan_create(gs_batch_plan **out, int64_t n, int32_t sh_degree, int32_t n_views, int64_t max_total_pixels,
+                         int32_t tile_w, int32_t tile_h, int32_t blend_depth, int64_t capacity, uint32_t flags) {
+  if (!out) return fail(GS_ERR_INVALID_ARG, "plan out-pointer is NULL");
+  *out = nullptr;
+  gs_batch_plan args;
+  int rc;
+  if ((rc = plan_args(n, sh_degree, n_views, max_total_pixels, tile_w, tile_h, blend_depth, capacity, flags, args)))
+    return rc;
+  GS_CHECK_DEVICE();
+  gs_batch_plan *p = new gs_batch_plan(args);
   size_t offs[10];
   const size_t bytes = plan_bytes(*p, offs);
   hipError_t e = hipMalloc(&p->block, bytes);

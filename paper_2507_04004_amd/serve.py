@@ -7,10 +7,14 @@ stays on the device between batches. Latency is arrival -> completion; throughpu
 megapixels per second. `simulate` replays an arrival schedule against the real GPU so the
 batched policy and one-at-a-time FIFO can be compared on the same stream of requests.
 
-Admission by memory: a request's estimated device bytes are its output planes (28 B per
-pixel: colour, depth, opacity, transmittance, last) plus its share of tile pairs, estimated
-from the pairs-per-pixel ratio of recent renders with a safety factor; if a batch still
-overflows its pair capacity it is re-run with a larger plan.
+Admission by memory: the device bytes of a batch are those of a forward-only batch plan sized
+for it (splat records of every view, tile lists, sort and compositing scratch; the pair
+capacity from the pairs-per-pixel ratio of recent renders with a safety factor) plus each
+request's output planes (28 B per pixel: colour, depth, opacity, transmittance, last). Requests
+are admitted in arrival order while that total stays within the budget (a single request
+larger than the budget is served alone). The server keeps one plan and re-creates it when a
+batch needs more views, pixels or pairs than it holds; if a batch still overflows its pair
+capacity it is re-run with a larger plan.
 """
 from __future__ import annotations
 
@@ -22,10 +26,9 @@ import numpy as np
 import torch
 
 from . import raster as R
-from .batch import BatchPlan, ViewSlot
+from .batch import BatchPlan, ViewSlot, plan_bytes
 
 PIXEL_BYTES = 28
-PAIR_BYTES = 4 * 6  # vals + two key/value ping-pong buffers per pair during the sort
 
 
 @dataclasses.dataclass
@@ -47,57 +50,65 @@ class RenderServer:
         self.gm, self.max_batch, self.budget = gm, max_batch, memory_budget
         self.tile, self.bd, self.device = tile, blend_depth, device
         self.pairs_per_pixel = 4.0   # running estimate, refined from completed batches
-        self.plans: dict[str, BatchPlan] = {}
+        self.plan: BatchPlan | None = None
+
+    def _sizes(self, reqs: list[Request]) -> tuple[int, int, int]:
+        """Plan arguments for a batch: views, total pixels, pair capacity."""
+        pixels = sum(r.pixels for r in reqs)
+        return len(reqs), pixels, max(1 << 16, int(pixels * self.pairs_per_pixel * 1.5) + 4096)
+
+    def _plan_bytes(self, views: int, pixels: int, cap: int) -> int:
+        return plan_bytes(self.gm.n, self.gm.sh_degree, views, pixels, self.tile, self.bd, cap, fwd_only=True)
+
+    def batch_bytes(self, reqs: list[Request]) -> int:
+        """Device bytes of a batch: its forward-only plan and the requests' output planes."""
+        return self._plan_bytes(*self._sizes(reqs)) + sum(r.pixels for r in reqs) * PIXEL_BYTES
 
     def estimate_bytes(self, req: Request) -> int:
-        return int(req.pixels * (PIXEL_BYTES + 1.5 * self.pairs_per_pixel * PAIR_BYTES))
+        return self.batch_bytes([req])
 
     def admit(self, queue: list[Request]) -> list[Request]:
         """Arrival-order prefix of the queue that fits the batch size and the memory budget."""
-        batch, used = [], 0
+        batch: list[Request] = []
         for r in queue:
-            b = self.estimate_bytes(r)
-            if batch and (len(batch) >= self.max_batch or used + b > self.budget):
+            if len(batch) >= self.max_batch or (batch and self.batch_bytes(batch + [r]) > self.budget):
                 break
             batch.append(r)
-            used += b
         return batch
 
-    def _plan(self, views: int, pixels: int, pairs: int) -> BatchPlan:
-        # one plan sized for max_batch views, grown (re-created) only when a batch needs more
-        # pixels or pairs than it holds: its buffers scale with views x map size, so a plan per
-        # batch shape would multiply the device memory
-        pix_b = 1 << max(16, math.ceil(math.log2(max(pixels, 1))))
-        cap = max(1 << 20, int(pairs * 1.5))
-        p = self.plans.get("main")
-        if p is None or p.capacity < cap or p.max_total_pixels < pixels:
-            if p is not None:
-                pix_b = max(pix_b, p.max_total_pixels)
-                cap = max(cap, p.capacity)
-                p.close()
-            p = BatchPlan(self.gm.n, self.gm.sh_degree, self.max_batch, pix_b, self.tile, self.bd, cap, self.device)
-            self.plans["main"] = p
-        return p
+    def _plan_for(self, views: int, pixels: int, cap: int) -> BatchPlan:
+        p = self.plan
+        if p is not None and p.max_views >= views and p.max_total_pixels >= pixels and p.capacity >= cap:
+            return p
+        if p is not None:
+            # grow to cover both shapes when that still fits the budget, else fit this batch
+            both = (max(views, p.max_views), max(pixels, p.max_total_pixels), max(cap, p.capacity))
+            if self._plan_bytes(*both) + pixels * PIXEL_BYTES <= self.budget:
+                views, pixels, cap = both
+            p.close()
+            self.plan = None
+        self.plan = BatchPlan(self.gm.n, self.gm.sh_degree, views, pixels, self.tile, self.bd, cap, self.device,
+                              fwd_only=True)
+        return self.plan
 
     def render(self, batch: list[Request]) -> None:
-        pixels = sum(r.pixels for r in batch)
-        est_pairs = int(pixels * self.pairs_per_pixel * 1.5) + 4096
+        views, pixels, cap = self._sizes(batch)
         while True:
-            plan = self._plan(len(batch), pixels, est_pairs)
+            plan = self._plan_for(views, pixels, cap)
             slots = [ViewSlot.make(r.camera, self.device) for r in batch]
             plan.run(self.gm, slots, fwd=True)
             need = plan.num_pairs()  # synchronises the stream
             if need <= plan.capacity:
                 break
-            est_pairs = int(need * 1.25)
+            cap = int(need * 1.25)
         self.pairs_per_pixel = 0.8 * self.pairs_per_pixel + 0.2 * (need / max(pixels, 1))
         for r, s in zip(batch, slots):
             r.frame = s.frame
 
     def close(self):
-        for p in self.plans.values():
-            p.close()
-        self.plans.clear()
+        if self.plan is not None:
+            self.plan.close()
+            self.plan = None
 
 
 def poisson_arrivals(n: int, rate: float, seed: int = 0) -> np.ndarray:

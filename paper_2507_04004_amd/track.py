@@ -22,7 +22,7 @@ import torch
 from . import _native as N
 from . import raster as R
 
-DEFAULTS = dict(iters=30, l1_weight=0.5, ssim_weight=0.5, lr_rho=1e-3, lr_phi=3e-3, beta1=0.9, beta2=0.999,
+DEFAULTS = dict(iters=30, l1_weight=0.5, ssim_weight=0.5, lr_rho=1e-2, lr_phi=1e-3, beta1=0.9, beta2=0.999,
                 eps=1e-8)
 
 

@@ -74,8 +74,14 @@ def test_host_argument_errors():
     assert L.gs_preprocess(C.byref(g3), C.byref(_cam()), 16, 16, C.byref(proj), None) == N.GS_ERR_INVALID_ARG
     # plan creation argument errors
     plan = C.c_void_p()
-    assert L.gs_batch_plan_create(C.byref(plan), 10, 0, 0, 100, 16, 16, 256, 100) == N.GS_ERR_INVALID_ARG
-    assert L.gs_batch_plan_create(C.byref(plan), 10, 0, 17, 100, 16, 16, 256, 100) == N.GS_ERR_INVALID_ARG
+    assert L.gs_batch_plan_create(C.byref(plan), 10, 0, 0, 100, 16, 16, 256, 100, 0) == N.GS_ERR_INVALID_ARG
+    assert L.gs_batch_plan_create(C.byref(plan), 10, 0, 17, 100, 16, 16, 256, 100, 0) == N.GS_ERR_INVALID_ARG
+    assert L.gs_batch_plan_create(C.byref(plan), 10, 0, 2, 100, 16, 16, 256, 100, 8) == N.GS_ERR_INVALID_ARG
+    # a forward-only plan leaves out the backward scratch; invalid arguments size to 0
+    full = L.gs_batch_plan_bytes(100_000, 3, 4, 640 * 480 * 4, 8, 8, 128, 1 << 20, 0)
+    fwd = L.gs_batch_plan_bytes(100_000, 3, 4, 640 * 480 * 4, 8, 8, 128, 1 << 20, N.GS_PLAN_FWD_ONLY)
+    assert 0 < fwd < full and full - fwd >= L.gs_grads_scratch_bytes(100_000, 4, 640 * 480 * 4)
+    assert L.gs_batch_plan_bytes(100_000, 3, 0, 640 * 480, 8, 8, 128, 1 << 20, 0) == 0
     assert L.gs_loss_l1(None, None, -1, 1.0, None, None, None) == N.GS_ERR_INVALID_ARG
 
 

@@ -46,9 +46,15 @@ def test_candidates_selection_and_cache(monkeypatch, tmp_path):
     r2 = A.autotune_config(_Map(), [_Cam()], backward=True, candidates=cands, cache_path=str(cache))
     assert not tried and r2["schedule"] == N.GS_BWD_BUCKETS and r2["tile"] == 8
     assert json.loads(cache.read_text())
-    # the three-value form keeps its shape
-    t, b, timings = A.autotune(_Map(), [_Cam()], backward=True, candidates=cands, cache_path=str(cache))
-    assert (t, b) == (8, 128) and "8x8/128/buckets" in timings
+    # the tuple form carries the schedule with the tile and depth
+    t, b, sched, timings = A.autotune(_Map(), [_Cam()], backward=True, candidates=cands, cache_path=str(cache))
+    assert (t, b, sched) == (8, 128, N.GS_BWD_BUCKETS) and "8x8/128/buckets" in timings
+    # another candidate set is another cache entry: tuned again, not answered from the first
+    tried.clear()
+    r3 = A.autotune_config(_Map(), [_Cam()], backward=True, candidates=[(16, 256), (32, 256)],
+                           cache_path=str(cache))
+    assert tried == [(16, 256, 0), (32, 256, 0)] and (r3["tile"], r3["blend_depth"]) == (16, 256)
+    assert len(json.loads(cache.read_text())) == 2
 
 
 def test_forward_only_ignores_schedules(monkeypatch):

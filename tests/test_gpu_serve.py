@@ -60,16 +60,33 @@ def test_served_frames_equal_plain_renders(batched):
 
 
 def test_admission_respects_budget_and_batch_size():
-    g = small_map(2000)
+    """Admitted batches fit the budget with the memory the server then allocates: the plan it
+    renders them with (forward-only, sized for the batch) and the output planes."""
+    from paper_2507_04004_amd.serve import PIXEL_BYTES, Request
+    g = small_map(20000)
     gm = R.GaussianMap.from_numpy(g, DEV)
-    from paper_2507_04004_amd.serve import Request
-    server = RenderServer(gm, max_batch=4, memory_budget=10 << 20, device=DEV)
     cams = small_requests(10, seed=5)
+    one = RenderServer(gm, device=DEV).batch_bytes([Request(0, cams[0], 0.0)])
+    budget = int(2.5 * one)
+    server = RenderServer(gm, max_batch=4, memory_budget=budget, device=DEV)
     queue = [Request(i, c, 0.0) for i, c in enumerate(cams)]
-    batch = server.admit(queue)
-    assert 1 <= len(batch) <= 4
-    assert sum(server.estimate_bytes(r) for r in batch) <= max(10 << 20, server.estimate_bytes(batch[0]))
-    assert [r.rid for r in batch] == list(range(len(batch)))  # arrival order
+    served = 0
+    while queue:
+        batch = server.admit(queue)
+        assert 1 <= len(batch) <= 4
+        assert [r.rid for r in batch] == list(range(served, served + len(batch)))  # arrival order
+        est = server.batch_bytes(batch)
+        assert est <= budget or len(batch) == 1
+        server.render(batch)
+        held = server.plan.nbytes + sum(r.frame.color.numel() * 4 + r.frame.depth.numel() * 4 +
+                                        r.frame.alpha.numel() * 4 + r.frame.t_final.numel() * 4 +
+                                        r.frame.last.numel() * 4 for r in batch)
+        frames = sum(r.pixels for r in batch) * PIXEL_BYTES
+        assert held - frames == server.plan.nbytes
+        assert held <= max(budget, est), (held, budget, est)
+        assert server.plan.fwd_only
+        queue = queue[len(batch):]
+        served += len(batch)
     server.close()
 
 
@@ -79,12 +96,12 @@ def test_autotune_picks_a_candidate_and_caches(tmp_path):
     cams = small_requests(3, seed=7)
     cache = str(tmp_path / "tune.json")
     cands = [(8, 64), (16, 128), (16, 256)]
-    tile, bd, timings = autotune(gm, cams, backward=True, candidates=cands, reps=3, warmup=1, device=DEV,
+    tile, bd, sched, timings = autotune(gm, cams, backward=True, candidates=cands, reps=3, warmup=1, device=DEV,
                                  cache_path=cache)
     assert (tile, bd) in cands and len(timings) == 3
     assert all(np.isfinite(v) and v > 0 for v in timings.values())
     with open(cache) as fh:
         assert len(json.load(fh)) == 1
     # cached answer comes back without re-timing
-    t2, b2, _ = autotune(gm, cams, backward=True, candidates=cands, cache_path=cache, device=DEV)
-    assert (t2, b2) == (tile, bd)
+    t2, b2, s2, _ = autotune(gm, cams, backward=True, candidates=cands, cache_path=cache, device=DEV)
+    assert (t2, b2, s2) == (tile, bd, sched)

@@ -57,11 +57,21 @@ def _setup(seed=3, xi0=(0.01, -0.008, 0.012, 0.003, -0.004, 0.002), **kw):
     return g, cam, start, gm, torch.from_numpy(target).to(DEV)
 
 
-def _params():
-    p = OT.TrackParams()
+def _params(**over):
+    """The loop's parameters as both sides use them (float32 values): the oracle's defaults
+    with `over` applied (product=True: the library's defaults)."""
+    if over.pop("product", False):
+        over = {**{k: T.DEFAULTS[k] for k in ("lr_rho", "lr_phi")}, **over}
+    p = dataclasses.replace(OT.TrackParams(), **over)
     return OT.TrackParams(iters=p.iters, l1_weight=F32(p.l1_weight), ssim_weight=F32(p.ssim_weight),
                           lr_rho=F32(p.lr_rho), lr_phi=F32(p.lr_phi), beta1=F32(p.beta1), beta2=F32(p.beta2),
                           eps=F32(p.eps))
+
+
+def _kw(q):
+    """The same parameters for PoseTracker.track."""
+    return dict(iters=q.iters, l1_weight=q.l1_weight, ssim_weight=q.ssim_weight, lr_rho=q.lr_rho, lr_phi=q.lr_phi,
+                beta1=q.beta1, beta2=q.beta2, eps=q.eps)
 
 
 def _twist(xi):
@@ -93,17 +103,19 @@ def check_update_rule(tr, pose_out, lr_rho, lr_phi, b1, b2, eps):
     return worst
 
 
-@pytest.mark.parametrize("graph,deg,tile,bd", [(False, 3, 8, 128), (True, 3, 8, 128), (False, 0, 16, 256),
-                                               (True, 1, 8, 64), (False, 2, 32, 128)])
-def test_loop_matches_oracle(graph, deg, tile, bd):
-    print(f"[track] oracle parity graph={graph} sh_degree={deg} tile={tile} chunk={bd}", flush=True)
+@pytest.mark.parametrize("graph,deg,tile,bd,product", [(False, 3, 8, 128, False), (True, 3, 8, 128, False),
+                                                       (False, 0, 16, 256, False), (True, 1, 8, 64, False),
+                                                       (False, 2, 32, 128, False), (True, 3, 8, 128, True)])
+def test_loop_matches_oracle(graph, deg, tile, bd, product):
+    print(f"[track] oracle parity graph={graph} sh_degree={deg} tile={tile} chunk={bd} "
+          f"{'library' if product else 'oracle'} step sizes", flush=True)
     g, cam, start, gm, target = _setup(deg=deg)
+    q = _params(product=product)
     trk = T.PoseTracker(gm, cam.w * cam.h, tile=tile, blend_depth=bd, device=DEV)
-    res = trk.track(start, target, graph=graph, trace=True)
+    res = trk.track(start, target, graph=graph, trace=True, **_kw(q))
     tr = res.trace.double().cpu().numpy()
     pose_out = res.pose.double().cpu().numpy()
     assert res.pairs <= trk.capacity
-    q = _params()
     tgt = target.double().cpu().numpy()
     # the oracle's own loop from the same float32 starting pose
     R_or, t_or, otr = OT.track(g, oracle.camera_f32(start), tgt, q)
@@ -134,9 +146,9 @@ def test_loop_in_a_render_window_matches_oracle():
     start = _moved(win, (0.008, 0.01, -0.01, -0.003, 0.002, 0.004))
     gm = R.GaussianMap.from_numpy(g, DEV)
     trk = T.PoseTracker(gm, win.w * win.h, tile=8, blend_depth=128, device=DEV)
-    res = trk.track(start, torch.from_numpy(target).to(DEV), graph=True, trace=True)
-    tr = res.trace.double().cpu().numpy()
     q = _params()
+    res = trk.track(start, torch.from_numpy(target).to(DEV), graph=True, trace=True, **_kw(q))
+    tr = res.trace.double().cpu().numpy()
     _, _, otr = OT.track(g, oracle.camera_f32(start), target.astype(np.float64), q)
     err = np.linalg.norm(tr[0, 12:18] - otr[0]["grad"]) / np.linalg.norm(otr[0]["grad"])
     dpose = max(float(np.abs(tr[k, :12] - np.r_[otr[k]["R"].ravel(), otr[k]["t"]]).max()) for k in range(q.iters))
@@ -205,15 +217,20 @@ def test_loop_at_benchmark_size():
     rng = np.random.default_rng(8)
     start = R.camera_left_update(cs, np.r_[rng.normal(0, 0.03, 3), rng.normal(0, 0.003, 3)])
     trk = T.PoseTracker(gm, cam.w * cam.h, tile=8, blend_depth=128, device=DEV)
-    res = trk.track(start, target, graph=True, trace=True)
+    res = trk.track(start, target, graph=True, trace=True)  # the library's default step sizes
     tr = res.trace.double().cpu().numpy()
     pose = res.pose.double().cpu().numpy()
     assert res.pairs <= trk.capacity
-    q = _params()
+    q = _params(product=True)
     worst = check_update_rule(tr, pose, q.lr_rho, q.lr_phi, q.beta1, q.beta2, q.eps)
     loss = tr[:, 18] + tr[:, 19]
     print(f"[track] benchmark size: pairs {res.pairs}, loss {loss[0]:.4f} -> {loss[-1]:.4f}, update rule "
           f"deviation {worst:.2e}", flush=True)
     assert loss[-1] < 0.5 * loss[0]
+    d0 = T.pose_residual(np.r_[np.asarray(cs.R_cw[:]), np.asarray(cs.t_cw[:])], tr[0, :12])
+    d1 = T.pose_residual(np.r_[np.asarray(cs.R_cw[:]), np.asarray(cs.t_cw[:])], pose)
+    print(f"[track] benchmark size: pose error {np.linalg.norm(d0[:3]):.4f} m / {np.linalg.norm(d0[3:]):.5f} rad "
+          f"-> {np.linalg.norm(d1[:3]):.4f} / {np.linalg.norm(d1[3:]):.5f}", flush=True)
+    assert np.linalg.norm(d1[:3]) < 0.5 * np.linalg.norm(d0[:3]) and np.linalg.norm(d1[3:]) < 0.5 * np.linalg.norm(d0[3:])
     eager = trk.track(start, target, graph=False).pose.double().cpu().numpy()
     np.testing.assert_allclose(eager, pose, atol=5e-5)
