@@ -1,7 +1,8 @@
 """ctypes view of the C ABI in include/gs.h (argument marshalling only).
 
-The library is loaded from the package's _lib/ directory. There is no fallback: if the
-HIP library is missing, loading raises, so nothing silently runs elsewhere.
+The library is loaded from the package's _lib/ directory (or from GS_LIB_PATH, which the
+sanitizer test sets to an instrumented build of the same sources). There is no fallback: if
+the HIP library is missing, loading raises, so nothing silently runs elsewhere.
 """
 from __future__ import annotations
 
@@ -9,7 +10,7 @@ import ctypes as C
 import os
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "_lib", "libgs.so")
+LIB_PATH = os.environ.get("GS_LIB_PATH") or os.path.join(_HERE, "_lib", "libgs.so")
 
 GS_OK, GS_ERR_INVALID_ARG, GS_ERR_HIP, GS_ERR_UNSUPPORTED, GS_ERR_CAPACITY = 0, 1, 2, 3, 4
 GS_MAX_VIEWS = 16

@@ -50,5 +50,28 @@ def build(verbose: bool = False) -> str:
     return LIB
 
 
+# Host-side sanitizers for the argument checks and host logic of the C ABI: the host pass of
+# api.hip built with AddressSanitizer and UndefinedBehaviorSanitizer (device code unchanged),
+# linked with the regular objects of the other sources. Loaded into a process that preloads
+# clang's AddressSanitizer runtime (which carries the UndefinedBehaviorSanitizer handlers).
+HOST_SANITIZE = ["-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined", "-Xarch_host",
+                 "-fno-sanitize-recover=all", "-Xarch_host", "-fno-omit-frame-pointer"]
+
+
+def build_host_sanitized(out: str, verbose: bool = False) -> str:
+    if not os.path.exists(LIB):
+        build(verbose)
+    obj = out + ".api.o"
+    cmd = [HIPCC] + FLAGS + HOST_SANITIZE + ["-c", os.path.join(CSRC, "api.hip"), "-o", obj]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError(f"hipcc failed for the sanitized api.hip:\n{r.stdout}{r.stderr}")
+    objs = [os.path.join(OUT_DIR, os.path.splitext(s)[0] + ".o") for s in SOURCES if s != "api.hip"]
+    subprocess.run([HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", out, obj] + objs, check=True)
+    return out
+
+
 if __name__ == "__main__":
     build(verbose="-v" in sys.argv)
