@@ -97,7 +97,7 @@ typedef struct gs_projected {
 
 /* Tile lists (Sec. "CUDA-Related Acceleration Strategies", fast tile-based culling; depth
  * order of eq:rendered_rgb). Tiles are tile_w x tile_h pixels laid over the render window,
- * row-major; T = ceil(w/tile_w) * ceil(h/tile_h).
+ * row-major, with tile_w and tile_h each 8, 16 or 32; T = ceil(w/tile_w) * ceil(h/tile_h).
  *   vals [capacity]   record index of each (tile, Gaussian) pair, sorted by (tile, depth bits,
  *                     index) — one total order, so exactly one correct result;
  *   tile_range [2*T]  [begin, end) into vals per tile ([0, 0) when empty);
@@ -152,9 +152,9 @@ typedef struct gs_lidar {
  *                    wavefront before one atomic per term (default);
  *   GS_BWD_BUCKETS — per-Gaussian buckets (Sec. "CUDA-Related Acceleration Strategies"): lane j
  *                    owns splat j of a 64-splat bucket and the tile's pixels pass through the
- *                    lanes, so each lane sums its splat's terms over the pixels; 8x8 and 16x16
- *                    tiles (GS_ERR_UNSUPPORTED at 32x32). Same results up to float32 summation
- *                    order. */
+ *                    lanes, so each lane sums its splat's terms over the pixels; tiles of at
+ *                    most 256 pixels (GS_ERR_UNSUPPORTED for 16x32, 32x16 and 32x32). Same
+ *                    results up to float32 summation order. */
 enum { GS_BWD_CHUNKS = 0, GS_BWD_BUCKETS = 1 };
 
 /* Gradient outputs, same layouts as gs_gaussians; pose [6] is dL/dxi for the left
@@ -184,7 +184,7 @@ int gs_bin_sort(const gs_projected *proj, int64_t n, const gs_camera *cam, gs_bi
 
 /* Stage a3 — front-to-back compositing per pixel (eq:alpha, eq:rendered_rgb/_depth/_opacity):
  * alpha = min(0.99, o exp(-q/2)); a Gaussian with alpha < 1/255 is skipped; the walk stops
- * before a Gaussian that would take the transmittance below 1e-4. blend_depth in {64, 128,
+ * before a Gaussian that would take the transmittance below 1e-4. blend_depth in {32, 64, 128,
  * 256} is the chunk length: each tile's list is composited in chunks of that many records,
  * one workgroup per chunk, and combined per pixel (exact up to float32 rounding order). lidar may be NULL; otherwise the
  * depth term is evaluated into lidar->loss_out after compositing. */

@@ -1,7 +1,8 @@
 """Tile-size / blend-depth / backward-schedule autotuner for the batched rasterizer.
 
-Times each candidate (tile size in {8, 16, 32}, LDS batch depth in {64, 128, 256}, and for a
-backward the compositing-backward schedule: pixel-parallel chunks or per-Gaussian buckets) on
+Times each candidate (tile sides in {8, 16, 32}, square or not; LDS batch depth in {32, 64, 128,
+256}; and for a backward the compositing-backward schedule: pixel-parallel chunks or
+per-Gaussian buckets) on
 the real workload (the same map and views, graph-captured, fwd or fwd+bwd) and keeps the
 fastest. The image does not depend on the choice (every pixel composites the same records in
 the same order) and the gradients only through float32 summation order, so the tuner may pick
@@ -19,9 +20,13 @@ from . import _native as N
 from . import raster as R
 from .batch import BatchPlan, ViewSlot
 
-# (tile, chunk length[, backward schedule]); the bucketed schedule runs on 8x8 and 16x16 tiles
-DEFAULT_CANDIDATES = [(8, 128), (8, 256), (16, 128), (16, 256), (32, 256), (8, 128, N.GS_BWD_BUCKETS),
-                      (16, 128, N.GS_BWD_BUCKETS)]
+# (tile, chunk length[, backward schedule]): every tile of sides 8, 16, 32 (square sides as one
+# number) with every chunk length 32-256 under the pixel-parallel backward, and the bucketed
+# backward (tiles of at most 256 pixels) at the two square shapes it runs on
+SIDES = (8, 16, 32)
+DEPTHS = (32, 64, 128, 256)
+DEFAULT_CANDIDATES = [((tw if tw == th else (tw, th)), bd) for tw in SIDES for th in SIDES for bd in DEPTHS] + \
+    [(8, 128, N.GS_BWD_BUCKETS), (16, 128, N.GS_BWD_BUCKETS)]
 SCHEDULE_NAMES = {N.GS_BWD_CHUNKS: "chunks", N.GS_BWD_BUCKETS: "buckets"}
 
 
@@ -30,7 +35,8 @@ def _split(c):
 
 
 def candidate_key(tile, bd, schedule=N.GS_BWD_CHUNKS) -> str:
-    k = f"{tile}x{tile}/{bd}"
+    tw, th = R.tile_wh(tile)
+    k = f"{tw}x{th}/{bd}"
     return k if schedule == N.GS_BWD_CHUNKS else f"{k}/{SCHEDULE_NAMES[schedule]}"
 
 
@@ -89,7 +95,9 @@ def autotune_config(gm: R.GaussianMap, cams, backward: bool = True, candidates=N
         tile, bd, sched = _split(c)
         if not backward:
             sched = N.GS_BWD_CHUNKS
-        if (tile, bd, sched) in seen or (sched == N.GS_BWD_BUCKETS and tile == 32):
+        tw, th = R.tile_wh(tile)
+        tile = tw if tw == th else (tw, th)
+        if (tile, bd, sched) in seen or (sched == N.GS_BWD_BUCKETS and tw * th > 256):
             continue
         seen.add((tile, bd, sched))
         ms, pairs = _time_candidate(gm, cams, tile, bd, backward, capacity, reps, warmup, device, targets, sched)

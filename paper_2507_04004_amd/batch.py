@@ -50,7 +50,7 @@ class ViewSlot:
 def plan_bytes(n: int, sh_degree: int, max_views: int, max_total_pixels: int, tile: int, blend_depth: int,
                capacity: int, fwd_only: bool = False) -> int:
     """Device bytes of a BatchPlan with these arguments (gs_batch_plan_bytes)."""
-    return int(N.lib().gs_batch_plan_bytes(n, sh_degree, max_views, max_total_pixels, tile, tile, blend_depth,
+    return int(N.lib().gs_batch_plan_bytes(n, sh_degree, max_views, max_total_pixels, *R.tile_wh(tile), blend_depth,
                                            capacity, N.GS_PLAN_FWD_ONLY if fwd_only else 0))
 
 
@@ -65,7 +65,7 @@ class BatchPlan:
         self.device = device
         self.fwd_only = fwd_only
         self._plan = C.c_void_p()
-        N.check(N.lib().gs_batch_plan_create(C.byref(self._plan), n, sh_degree, max_views, max_total_pixels, tile, tile,
+        N.check(N.lib().gs_batch_plan_create(C.byref(self._plan), n, sh_degree, max_views, max_total_pixels, *R.tile_wh(tile),
                                              blend_depth, self.capacity, N.GS_PLAN_FWD_ONLY if fwd_only else 0),
                 "gs_batch_plan_create")
         self.nbytes = plan_bytes(n, sh_degree, max_views, max_total_pixels, tile, blend_depth, self.capacity,

@@ -64,8 +64,9 @@ int check_device() {
 inline int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
 inline size_t a256(size_t x) { return (x + 255) & ~size_t(255); }
 
-bool tile_ok(int tw, int th) { return tw == th && (tw == 8 || tw == 16 || tw == 32); }
-bool depth_ok(int bd) { return bd == 64 || bd == 128 || bd == 256; }
+bool side_ok(int s) { return s == 8 || s == 16 || s == 32; }
+bool tile_ok(int tw, int th) { return side_ok(tw) && side_ok(th); }
+bool depth_ok(int bd) { return bd == 32 || bd == 64 || bd == 128 || bd == 256; }
 
 int check_camera(const gs_camera *c) {
   if (!c) return fail(GS_ERR_INVALID_ARG, "camera is NULL");
@@ -240,11 +241,11 @@ int enqueue_backward(const gs::ViewTable &vt, const gs_gaussians &g, const gs_pr
   return GS_OK;
 }
 
-int check_schedule(int32_t schedule, int tile_w) {
+int check_schedule(int32_t schedule, int tile_w, int tile_h) {
   if (schedule != GS_BWD_CHUNKS && schedule != GS_BWD_BUCKETS)
     return fail(GS_ERR_INVALID_ARG, "unknown backward schedule %d", schedule);
-  if (schedule == GS_BWD_BUCKETS && tile_w == 32)
-    return fail(GS_ERR_UNSUPPORTED, "the bucketed backward runs on 8x8 and 16x16 tiles");
+  if (schedule == GS_BWD_BUCKETS && tile_w * tile_h > 256)
+    return fail(GS_ERR_UNSUPPORTED, "the bucketed backward runs on tiles of at most 256 pixels");
   return GS_OK;
 }
 
@@ -362,7 +363,7 @@ int gs_preprocess(const gs_gaussians *g, const gs_camera *cam, int32_t tile_w, i
                   gs_stream_t stream) {
   int rc;
   if ((rc = check_gaussians(g)) || (rc = check_camera(cam)) || (rc = check_projected(out, g->n))) return rc;
-  if (!tile_ok(tile_w, tile_h)) return fail(GS_ERR_INVALID_ARG, "tile size must be 8x8, 16x16 or 32x32");
+  if (!tile_ok(tile_w, tile_h)) return fail(GS_ERR_INVALID_ARG, "tile sides must be 8, 16 or 32");
   gs::ViewTable vt;
   if ((rc = make_table(cam, 1, g->n, g->sh_degree, tile_w, tile_h, vt))) return rc;
   vt.pose_dev = out->pose;
@@ -379,7 +380,7 @@ int gs_bin_sort(const gs_projected *proj, int64_t n, const gs_camera *cam, gs_bi
   if (!io || !io->vals || !io->tile_range || !io->num_pairs || !io->scratch)
     return fail(GS_ERR_INVALID_ARG, "bins pointer is NULL");
   if (n < 0 || io->capacity < 0) return fail(GS_ERR_INVALID_ARG, "negative size");
-  if (!tile_ok(io->tile_w, io->tile_h)) return fail(GS_ERR_INVALID_ARG, "tile size must be 8x8, 16x16 or 32x32");
+  if (!tile_ok(io->tile_w, io->tile_h)) return fail(GS_ERR_INVALID_ARG, "tile sides must be 8, 16 or 32");
   if (io->capacity > 0xFFFFFFFFll) return fail(GS_ERR_INVALID_ARG, "capacity too large");
   gs::ViewTable vt;
   if ((rc = make_table(cam, 1, n, 0, io->tile_w, io->tile_h, vt))) return rc;
@@ -400,8 +401,8 @@ int gs_render_fwd(const gs_projected *proj, int64_t n, const gs_bins *bins, cons
   int rc;
   if ((rc = check_projected(proj, n)) || (rc = check_camera(cam)) || (rc = check_image(out))) return rc;
   if (!bins || !bins->vals || !bins->tile_range) return fail(GS_ERR_INVALID_ARG, "bins pointer is NULL");
-  if (!tile_ok(bins->tile_w, bins->tile_h)) return fail(GS_ERR_INVALID_ARG, "tile size must be 8x8, 16x16 or 32x32");
-  if (!depth_ok(blend_depth)) return fail(GS_ERR_INVALID_ARG, "blend_depth must be 64, 128 or 256");
+  if (!tile_ok(bins->tile_w, bins->tile_h)) return fail(GS_ERR_INVALID_ARG, "tile sides must be 8, 16 or 32");
+  if (!depth_ok(blend_depth)) return fail(GS_ERR_INVALID_ARG, "blend_depth must be 32, 64, 128 or 256");
   if ((rc = check_lidar(lidar, (int64_t)cam->w * cam->h))) return rc;
   if (lidar && lidar->m > 0 && !lidar->loss_out) return fail(GS_ERR_INVALID_ARG, "lidar loss_out is NULL");
   gs::ViewTable vt;
@@ -439,12 +440,12 @@ int check_bwd(const gs_gaussians *g, const gs_camera *cam, const gs_projected *p
       (rc = check_image(fwd)))
     return rc;
   if (!bins || !bins->vals || !bins->tile_range) return fail(GS_ERR_INVALID_ARG, "bins pointer is NULL");
-  if (!tile_ok(bins->tile_w, bins->tile_h)) return fail(GS_ERR_INVALID_ARG, "tile size must be 8x8, 16x16 or 32x32");
-  if (!depth_ok(blend_depth)) return fail(GS_ERR_INVALID_ARG, "blend_depth must be 64, 128 or 256");
+  if (!tile_ok(bins->tile_w, bins->tile_h)) return fail(GS_ERR_INVALID_ARG, "tile sides must be 8, 16 or 32");
+  if (!depth_ok(blend_depth)) return fail(GS_ERR_INVALID_ARG, "blend_depth must be 32, 64, 128 or 256");
   if (!dL_dC) return fail(GS_ERR_INVALID_ARG, "dL_dC is NULL");
   if (!out) return fail(GS_ERR_INVALID_ARG, "grads is NULL");
   if (out->sh_dc && g->sh_degree > 0 && !out->sh_rest) return fail(GS_ERR_INVALID_ARG, "grads.sh_rest is NULL");
-  if ((rc = check_schedule(out->schedule, bins->tile_w))) return rc;
+  if ((rc = check_schedule(out->schedule, bins->tile_w, bins->tile_h))) return rc;
   if ((rc = check_lidar(lidar, (int64_t)cam->w * cam->h))) return rc;
   if ((rc = make_table(cam, 1, g->n, g->sh_degree, bins->tile_w, bins->tile_h, vt))) return rc;
   vt.pose_dev = proj->pose;
@@ -794,7 +795,7 @@ int check_views(const gs_batch_plan *p, const gs_gaussians *g, int nv, const gs_
   }
   if ((mode & GS_BWD) && grads && grads->sh_dc && g->sh_degree > 0 && !grads->sh_rest)
     return fail(GS_ERR_INVALID_ARG, "grads.sh_rest is NULL");
-  if ((mode & GS_BWD) && grads && (rc = check_schedule(grads->schedule, p->tw))) return rc;
+  if ((mode & GS_BWD) && grads && (rc = check_schedule(grads->schedule, p->tw, p->th))) return rc;
   return GS_OK;
 }
 
@@ -812,8 +813,8 @@ int plan_args(int64_t n, int32_t sh_degree, int32_t n_views, int64_t max_total_p
   if (n < 0 || n > 0x7FFFFFFF || sh_degree < 0 || sh_degree > 3) return fail(GS_ERR_INVALID_ARG, "bad n or degree");
   if (n_views < 1 || n_views > GS_MAX_VIEWS) return fail(GS_ERR_INVALID_ARG, "n_views must be in 1..%d", GS_MAX_VIEWS);
   if (n * n_views > 0xFFFFFFFFll) return fail(GS_ERR_INVALID_ARG, "n * n_views too large");
-  if (!tile_ok(tile_w, tile_h)) return fail(GS_ERR_INVALID_ARG, "tile size must be 8x8, 16x16 or 32x32");
-  if (!depth_ok(blend_depth)) return fail(GS_ERR_INVALID_ARG, "blend_depth must be 64, 128 or 256");
+  if (!tile_ok(tile_w, tile_h)) return fail(GS_ERR_INVALID_ARG, "tile sides must be 8, 16 or 32");
+  if (!depth_ok(blend_depth)) return fail(GS_ERR_INVALID_ARG, "blend_depth must be 32, 64, 128 or 256");
   if (max_total_pixels <= 0 || capacity <= 0 || capacity > 0xFFFFFFFFll)
     return fail(GS_ERR_INVALID_ARG, "bad pixel budget or capacity");
   if (flags & ~(uint32_t)GS_PLAN_FWD_ONLY) return fail(GS_ERR_INVALID_ARG, "unknown plan flags 0x%x", flags);
@@ -827,7 +828,7 @@ int plan_args(int64_t n, int32_t sh_degree, int32_t n_views, int64_t max_total_p
   p.cap = capacity;
   p.fwd_only = (flags & GS_PLAN_FWD_ONLY) != 0;
   // every view adds at most one partial tile row and column beyond pixels / tile area
-  p.max_tiles = max_total_pixels / ((int64_t)tile_w * tile_h) + (int64_t)n_views * (2 * 32768 / tile_w + 1);
+  p.max_tiles = max_total_pixels / ((int64_t)tile_w * tile_h) + (int64_t)n_views * (32768 / tile_w + 32768 / tile_h + 1);
   return GS_OK;
 }
 
@@ -1104,8 +1105,8 @@ int gs_track_plan_create(gs_track_plan **out, int64_t n, int32_t sh_degree, int6
   if (!out) return fail(GS_ERR_INVALID_ARG, "plan out-pointer is NULL");
   *out = nullptr;
   if (n < 0 || n > 0x7FFFFFFF || sh_degree < 0 || sh_degree > 3) return fail(GS_ERR_INVALID_ARG, "bad n or degree");
-  if (!tile_ok(tile_w, tile_h)) return fail(GS_ERR_INVALID_ARG, "tile size must be 8x8, 16x16 or 32x32");
-  if (!depth_ok(blend_depth)) return fail(GS_ERR_INVALID_ARG, "blend_depth must be 64, 128 or 256");
+  if (!tile_ok(tile_w, tile_h)) return fail(GS_ERR_INVALID_ARG, "tile sides must be 8, 16 or 32");
+  if (!depth_ok(blend_depth)) return fail(GS_ERR_INVALID_ARG, "blend_depth must be 32, 64, 128 or 256");
   if (max_pixels <= 0 || max_pixels > 0x7FFFFFFF || capacity <= 0 || capacity > 0xFFFFFFFFll)
     return fail(GS_ERR_INVALID_ARG, "bad pixel budget or capacity");
   GS_CHECK_DEVICE();
@@ -1117,7 +1118,7 @@ int gs_track_plan_create(gs_track_plan **out, int64_t n, int32_t sh_degree, int6
   p->bd = blend_depth;
   p->max_pixels = max_pixels;
   p->cap = capacity;
-  p->max_tiles = max_pixels / ((int64_t)tile_w * tile_h) + (2 * 32768 / tile_w + 1);
+  p->max_tiles = max_pixels / ((int64_t)tile_w * tile_h) + (32768 / tile_w + 32768 / tile_h + 1);
   size_t offs[17];
   const size_t bytes = track_bytes(*p, offs);
   hipError_t e = hipMalloc(&p->block, bytes);

@@ -1121,8 +1121,8 @@ template <int TW, int TH, int BD, int NT>
 static hipError_t bwd_bucket_impl(const ViewTable &vt, const ImgTable &it, const GradTable &gtab,
                                   const gs_projected &p, const uint32_t *vals, const uint32_t *range,
                                   const BlendState &s, float *g2, hipStream_t st) {
-  if constexpr (TW == 32) {
-    return hipErrorInvalidValue;  // a 32x32 tile's pixel tables do not fit beside the staged splats
+  if constexpr (TW * TH > 256) {
+    return hipErrorInvalidValue;  // the pixel tables of tiles over 256 pixels do not fit beside the staged splats
   } else {
     hipLaunchKernelGGL((k_blend_bwd_bucket<TW, TH, BD>), dim3((unsigned)s.I), dim3(64), 0, st, vt, it, gtab,
                        (const Card *)p.card, vals, range, (const uint2 *)s.items, (const uint32_t *)s.n_items,
@@ -1141,24 +1141,29 @@ static hipError_t bwd_impl(const ViewTable &vt, const ImgTable &it, const GradTa
   return hipGetLastError();
 }
 
-// Lanes per workgroup by tile size: 8x8 -> 64 (one pixel per lane), 16x16 -> 64 (four pixels
-// per lane, one wavefront per tile), 32x32 -> 256 (four pixels per lane).
+// Lanes per workgroup by tile size: tiles of up to 256 pixels -> one wavefront (8x8: one pixel
+// per lane; 8x16, 16x8: two; 16x16, 8x32, 32x8: four), larger ones -> 256 lanes (16x32, 32x16:
+// two pixels per lane; 32x32: four). Chunk lengths 32, 64, 128 and 256.
+#define GS_BLEND_DEPTHS(FN, TW, TH, NT, ...)                                                   \
+  do {                                                                                         \
+    if (bd == 32) return FN<TW, TH, 32, NT>(__VA_ARGS__);                                      \
+    if (bd == 64) return FN<TW, TH, 64, NT>(__VA_ARGS__);                                      \
+    if (bd == 128) return FN<TW, TH, 128, NT>(__VA_ARGS__);                                    \
+    if (bd == 256) return FN<TW, TH, 256, NT>(__VA_ARGS__);                                    \
+    return hipErrorInvalidValue;                                                               \
+  } while (0)
 #define GS_BLEND_DISPATCH(FN, ...)                                                             \
   do {                                                                                         \
-    const int tw = vt.tile_w;                                                                  \
-    if (tw == 8) {                                                                             \
-      if (bd == 64) return FN<8, 8, 64, 64>(__VA_ARGS__);                                      \
-      if (bd == 128) return FN<8, 8, 128, 64>(__VA_ARGS__);                                    \
-      if (bd == 256) return FN<8, 8, 256, 64>(__VA_ARGS__);                                    \
-    } else if (tw == 16) {                                                                     \
-      if (bd == 64) return FN<16, 16, 64, 64>(__VA_ARGS__);                                    \
-      if (bd == 128) return FN<16, 16, 128, 64>(__VA_ARGS__);                                  \
-      if (bd == 256) return FN<16, 16, 256, 64>(__VA_ARGS__);                                  \
-    } else if (tw == 32) {                                                                     \
-      if (bd == 64) return FN<32, 32, 64, 256>(__VA_ARGS__);                                   \
-      if (bd == 128) return FN<32, 32, 128, 256>(__VA_ARGS__);                                 \
-      if (bd == 256) return FN<32, 32, 256, 256>(__VA_ARGS__);                                 \
-    }                                                                                          \
+    const int tw = vt.tile_w, th = vt.tile_h;                                                  \
+    if (tw == 8 && th == 8) GS_BLEND_DEPTHS(FN, 8, 8, 64, __VA_ARGS__);                        \
+    if (tw == 8 && th == 16) GS_BLEND_DEPTHS(FN, 8, 16, 64, __VA_ARGS__);                      \
+    if (tw == 16 && th == 8) GS_BLEND_DEPTHS(FN, 16, 8, 64, __VA_ARGS__);                      \
+    if (tw == 16 && th == 16) GS_BLEND_DEPTHS(FN, 16, 16, 64, __VA_ARGS__);                    \
+    if (tw == 8 && th == 32) GS_BLEND_DEPTHS(FN, 8, 32, 64, __VA_ARGS__);                      \
+    if (tw == 32 && th == 8) GS_BLEND_DEPTHS(FN, 32, 8, 64, __VA_ARGS__);                      \
+    if (tw == 16 && th == 32) GS_BLEND_DEPTHS(FN, 16, 32, 256, __VA_ARGS__);                   \
+    if (tw == 32 && th == 16) GS_BLEND_DEPTHS(FN, 32, 16, 256, __VA_ARGS__);                   \
+    if (tw == 32 && th == 32) GS_BLEND_DEPTHS(FN, 32, 32, 256, __VA_ARGS__);                   \
     return hipErrorInvalidValue;                                                               \
   } while (0)
 

@@ -118,7 +118,7 @@ class Splats:
 
 @dataclasses.dataclass
 class TileBins:
-    tile: int
+    tile: object  # side of a square tile, or (tile_w, tile_h)
     capacity: int
     vals: torch.Tensor
     tile_range: torch.Tensor
@@ -126,7 +126,7 @@ class TileBins:
     scratch: torch.Tensor
 
     def struct(self) -> N.Bins:
-        return N.Bins(self.tile, self.tile, self.capacity, _p(self.vals), _p(self.tile_range), _p(self.num_pairs),
+        return N.Bins(*tile_wh(self.tile), self.capacity, _p(self.vals), _p(self.tile_range), _p(self.num_pairs),
                       _p(self.scratch), self.scratch.numel())
 
     def pairs(self) -> int:
@@ -175,8 +175,14 @@ class LidarHits:
         return N.Lidar(self.m, _p(self.pix), _p(self.depth), float(self.weight), _p(loss_out), _p(grad_scale))
 
 
-def tiles_of(cs: N.Camera, tile: int) -> int:
-    return ((cs.w + tile - 1) // tile) * ((cs.h + tile - 1) // tile)
+def tile_wh(tile) -> tuple[int, int]:
+    """(tile_w, tile_h) of a tile given as one side (square) or as a pair."""
+    return (int(tile), int(tile)) if isinstance(tile, (int, np.integer)) else (int(tile[0]), int(tile[1]))
+
+
+def tiles_of(cs: N.Camera, tile) -> int:
+    tw, th = tile_wh(tile)
+    return ((cs.w + tw - 1) // tw) * ((cs.h + th - 1) // th)
 
 
 # ---- stage wrappers ------------------------------------------------------------------------
@@ -193,7 +199,7 @@ def preprocess(gs: N.Gaussians, cs: N.Camera, tile: int, device, out: Splats | N
                pose: torch.Tensor | None = None) -> Splats:
     out = out or Splats.empty(gs.n, device)
     out.pose = pose
-    N.check(N.lib().gs_preprocess(C.byref(gs), C.byref(cs), tile, tile, C.byref(out.struct()), _stream()),
+    N.check(N.lib().gs_preprocess(C.byref(gs), C.byref(cs), *tile_wh(tile), C.byref(out.struct()), _stream()),
             "gs_preprocess")
     return out
 
@@ -224,7 +230,7 @@ def bin_sort_fit(spl: Splats, n: int, cs: N.Camera, tile: int, device, capacity:
 
 
 def state_bytes(bins: TileBins, cs: N.Camera, blend_depth: int) -> int:
-    return N.lib().gs_image_state_bytes(bins.capacity, tiles_of(cs, bins.tile), bins.tile, bins.tile, blend_depth)
+    return N.lib().gs_image_state_bytes(bins.capacity, tiles_of(cs, bins.tile), *tile_wh(bins.tile), blend_depth)
 
 
 def render_fwd(spl: Splats, n: int, bins: TileBins, cs: N.Camera, blend_depth: int, device,
@@ -319,7 +325,7 @@ def loss_dssim(color: torch.Tensor, target: torch.Tensor, weight: float = 1.0,
 @dataclasses.dataclass
 class RenderSettings:
     camera: object                  # scenes.Camera-like
-    tile: int = 8
+    tile: object = 8                # square side, or (tile_w, tile_h)
     blend_depth: int = 128
     lidar: LidarHits | None = None  # sparse depth term evaluated inside the library
     capacity: int | None = None     # pair capacity; learned from the first call when None
@@ -448,7 +454,7 @@ def kept_bytes(spl: Splats, bins: TileBins, fr: Frame, cs: N.Camera, blend_depth
     lib = N.lib()
     pairs = bins.pairs()
     state_alloc = fr.state.numel() if fr.state is not None else 0
-    state_needed = lib.gs_image_state_bytes(pairs, T, bins.tile, bins.tile, blend_depth)
+    state_needed = lib.gs_image_state_bytes(pairs, T, *tile_wh(bins.tile), blend_depth)
     out = {
         "checkpoint": fr.t_final.numel() * 4 + fr.last.numel() * 4,
         "chunk_state_allocated": int(state_alloc),

@@ -77,7 +77,7 @@ class PlainStep:
     def forward(self, st=None):
         L = self.L
         st = st or self.stream()
-        N.check(L.gs_preprocess(C.byref(self.gs), C.byref(self.cs), self.tile, self.tile, C.byref(self.s_proj), st),
+        N.check(L.gs_preprocess(C.byref(self.gs), C.byref(self.cs), *R.tile_wh(self.tile), C.byref(self.s_proj), st),
                 "gs_preprocess")
         N.check(L.gs_bin_sort(C.byref(self.s_proj), self.n, C.byref(self.cs), C.byref(self.s_bins), st),
                 "gs_bin_sort")

@@ -57,7 +57,7 @@ class PoseTracker:
         self.close()
         self.capacity = int(capacity)
         N.check(N.lib().gs_track_plan_create(C.byref(self._plan), self.gm.n, self.gm.sh_degree, self.max_pixels,
-                                             self.tile, self.tile, self.blend_depth, self.capacity),
+                                             *R.tile_wh(self.tile), self.blend_depth, self.capacity),
                 "gs_track_plan_create")
 
     def close(self):

@@ -31,15 +31,22 @@ def test_candidates_selection_and_cache(monkeypatch, tmp_path):
 
     def fake(gm, cams, tile, bd, backward, capacity, reps, warmup, device, targets, schedule):
         tried.append((tile, bd, schedule))
-        return cost[(tile, bd, schedule)], 123
+        return cost.get((tile, bd, schedule), 10.0 + bd / 1000.0), 123
 
     monkeypatch.setattr(A, "_time_candidate", fake)
     cache = tmp_path / "tune.json"
-    cands = A.DEFAULT_CANDIDATES + [(8, 128), (32, 256, N.GS_BWD_BUCKETS)]
+    # the default search: tile sides {8, 16, 32} squared, chunk lengths {32, ..., 256}
+    assert len(A.DEFAULT_CANDIDATES) == 9 * 4 + 2
+    assert {(8, 16), (32, 8), (16, 32)} <= {c[0] for c in A.DEFAULT_CANDIDATES if not isinstance(c[0], int)}
+    assert {c[1] for c in A.DEFAULT_CANDIDATES} == {32, 64, 128, 256}
+    cands = A.DEFAULT_CANDIDATES + [(8, 128), ((8, 8), 128), (32, 256, N.GS_BWD_BUCKETS),
+                                    ((16, 32), 64, N.GS_BWD_BUCKETS)]
     r = A.autotune_config(_Map(), [_Cam()], backward=True, candidates=cands, cache_path=str(cache))
     assert (r["tile"], r["blend_depth"], r["schedule"]) == (8, 128, N.GS_BWD_BUCKETS)
-    assert len(tried) == len(set(tried)) == 7                      # duplicate and 32x32 buckets skipped
-    assert (32, 256, N.GS_BWD_BUCKETS) not in tried
+    # duplicates (also (8, 8) for 8) and buckets on tiles over 256 pixels skipped
+    assert len(tried) == len(set(tried)) == 38
+    assert (32, 256, N.GS_BWD_BUCKETS) not in tried and ((16, 32), 64, N.GS_BWD_BUCKETS) not in tried
+    assert r["timings"]["16x32/64"] > 0 and "8x16/32" in r["timings"]
     assert r["timings"]["8x8/128/buckets"] == 4.0 and r["timings"]["8x8/128"] == 5.0
     # the cache answers without timing again, schedule included
     tried.clear()
@@ -62,10 +69,12 @@ def test_forward_only_ignores_schedules(monkeypatch):
 
     def fake(gm, cams, tile, bd, backward, capacity, reps, warmup, device, targets, schedule):
         tried.append((tile, bd, schedule))
-        return float(tile + bd / 1000.0 + np.float64(schedule)), 1
+        tw, th = (tile, tile) if isinstance(tile, int) else tile
+        return float(tw * th + bd / 1000.0 + np.float64(schedule)), 1
 
     monkeypatch.setattr(A, "_time_candidate", fake)
     r = A.autotune_config(_Map(), [_Cam()], backward=False)
     assert all(s == N.GS_BWD_CHUNKS for _, _, s in tried)
     assert len(tried) == len(set(tried))
-    assert r["schedule"] == N.GS_BWD_CHUNKS and r["tile"] == 8
+    assert r["schedule"] == N.GS_BWD_CHUNKS and r["tile"] == 8 and r["blend_depth"] == 32
+    assert len(tried) == 36

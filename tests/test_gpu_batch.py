@@ -34,7 +34,7 @@ def upstream(cam, seed):
     return gC.reshape(3, cam.h, cam.w), gD.reshape(cam.h, cam.w), gO.reshape(cam.h, cam.w)
 
 
-@pytest.mark.parametrize("tile", [8, 16])
+@pytest.mark.parametrize("tile", [8, 16, (16, 8), (8, 32)])
 def test_batch_forward_equals_plain(tile):
     g, cams = views_and_map()
     gm = R.GaussianMap.from_numpy(g, DEV)
@@ -158,7 +158,7 @@ def test_graph_backward_replays():
         assert_grads_close(got, {k: r.cpu().numpy() for k, r in ref.items()}, keys=tuple(ref), rtol=1e-4, atol=2e-6)
 
 
-@pytest.mark.parametrize("tile", [8, 16])
+@pytest.mark.parametrize("tile", [8, 16, (8, 16)])
 def test_graph_backward_bucketed_schedule_equals_chunks(tile):
     """The autotuner's second backward schedule inside a captured multi-view batch: every replay
     equals the pixel-parallel schedule's gradients up to float32 summation order."""

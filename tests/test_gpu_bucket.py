@@ -22,7 +22,8 @@ pytestmark = pytest.mark.gpu
 
 
 @pytest.mark.parametrize("case,tile,bd", [("small_sh0", 8, 128), ("street_sh3_posed", 8, 64),
-                                          ("street_sh3_posed", 16, 256), ("dense", 8, 64), ("dense", 16, 128)])
+                                          ("street_sh3_posed", 16, 256), ("dense", 8, 64), ("dense", 16, 128),
+                                          ("street_sh3_posed", (16, 8), 32), ("dense", (8, 32), 64)])
 def test_bucketed_backward_matches_oracle_and_chunks(case, tile, bd):
     print(f"[bucket] {case} tile={tile} chunk={bd}", flush=True)
     g, cam = dense_tile() if case == "dense" else CASES[case]()
@@ -48,8 +49,9 @@ def test_bucketed_backward_overwrite_and_refusals():
     ow = run.backward(gC, overwrite=True, grads=junk, schedule=N.GS_BWD_BUCKETS)
     for k in acc:
         np.testing.assert_allclose(ow[k], acc[k], rtol=1e-5, atol=1e-5 * max(np.abs(acc[k]).max(), 1e-30), err_msg=k)
-    big = HipRun(g, cam, tile=32, blend_depth=128)
-    with pytest.raises(N.GSError, match="code 3"):
-        big.backward(gC, schedule=N.GS_BWD_BUCKETS)
+    for tile in (32, (16, 32), (32, 16)):
+        big = HipRun(g, cam, tile=tile, blend_depth=128)
+        with pytest.raises(N.GSError, match="code 3"):
+            big.backward(gC, schedule=N.GS_BWD_BUCKETS)
     with pytest.raises(N.GSError, match="code 1"):
         run.backward(gC, schedule=7)

@@ -67,7 +67,7 @@ CASES = {
 
 # ---- stage a1 + a2: records and tile lists ----------------------------------------------------
 @pytest.mark.parametrize("case", list(CASES))
-@pytest.mark.parametrize("tile", [8, 16, 32])
+@pytest.mark.parametrize("tile", [8, 16, 32, (8, 16), (32, 8), (16, 32)])
 def test_bins_bit_exact(case, tile):
     g, cam = CASES[case]()
     print(f"[bins] case={case} tile={tile} n={g.n}", flush=True)
@@ -104,7 +104,7 @@ def test_projection_records(case):
 
 
 # ---- stage a3: compositing ------------------------------------------------------------------
-LAUNCH = [(16, 256), (8, 128)]
+LAUNCH = [(16, 256), (8, 128), ((8, 16), 32), ((32, 16), 64)]
 
 
 @pytest.mark.parametrize("tile,bd", LAUNCH)
@@ -121,9 +121,10 @@ def test_render_matches_oracle(case, tile, bd):
     ok = (ref["marginal"] == 0) & (ref["last_id"] >= 0)
     vals = run.bins_np()["vals"]
     tr = run.bins_np()["tile_range"]
-    tiles_x = (cam.w + tile - 1) // tile
+    tw, th = R.tile_wh(tile)
+    tiles_x = (cam.w + tw - 1) // tw
     ys, xs = np.nonzero(ok)
-    t = (ys // tile) * tiles_x + xs // tile
+    t = (ys // th) * tiles_x + xs // tw
     idx = tr[2 * t] + got["last"][ys, xs]
     np.testing.assert_array_equal(vals[idx], ref["last_id"][ys, xs])
     assert np.all(got["last"][ref["last_id"] < 0] == -1)
@@ -142,7 +143,8 @@ def test_tile_size_and_blend_depth_invariance(case):
     base_run = HipRun(g, cam, tile=16, blend_depth=256)
     base = base_run.image()
     base_single = _max_list(base_run) <= 256
-    for tile, bd in [(8, 64), (8, 256), (16, 64), (16, 128), (32, 128), (32, 256)]:
+    for tile, bd in [(8, 32), (8, 64), (8, 256), (16, 64), (16, 128), (32, 128), (32, 256), ((8, 16), 64),
+                     ((16, 8), 32), ((8, 32), 128), ((32, 8), 256), ((16, 32), 64), ((32, 16), 32)]:
         run = HipRun(g, cam, tile=tile, blend_depth=bd)
         got = run.image()
         bitwise = base_single and _max_list(run) <= bd
@@ -154,7 +156,7 @@ def test_tile_size_and_blend_depth_invariance(case):
                 assert np.max(np.abs(got[k] - base[k]) / scale) <= 2e-5, (tile, bd, k)
 
 
-@pytest.mark.parametrize("bd", [64, 128, 256])
+@pytest.mark.parametrize("bd", [32, 64, 128, 256])
 def test_multichunk_tiles_match_oracle(bd):
     """Long tile lists split into many chunks, with pixels stopping in late chunks."""
     g, cam = dense_tile()
