@@ -192,10 +192,9 @@ def measure_batched(R, N, torch, S, g, gm, tile, bd, dev, reps=20):
         pix, ds = lidar_targets(sl.frame, S.lidar_beams(c, 32, 30.0, 0.32, seed=200 + k))
         lidars.append((pix, ds))
     del tslots
-    tuned = autotune_config(gm, cams, backward=True,
-                            candidates=[(8, 128), (8, 256), (16, 128), (8, 128, N.GS_BWD_BUCKETS),
-                                        (16, 128, N.GS_BWD_BUCKETS)],
-                            capacity=cap, reps=3, warmup=1, device=dev, targets=targets)
+    # the autotuner's whole search: nine tile shapes x chunk lengths 32-256, and the bucketed
+    # backward at 8x8 and 16x16
+    tuned = autotune_config(gm, cams, backward=True, capacity=cap, reps=3, warmup=1, device=dev, targets=targets)
     tile_b, bd_b, sched_b, timings = tuned["tile"], tuned["blend_depth"], tuned["schedule"], tuned["timings"]
     plan = BatchPlan(gm.n, gm.sh_degree, 8, total_px, tile_b, bd_b, cap, dev)
     slots = [ViewSlot.make(c, dev, backward=True, target=targets[k],
@@ -215,7 +214,7 @@ def measure_batched(R, N, torch, S, g, gm, tile, bd, dev, reps=20):
             st.step()
     ms_s = timed(torch, run_seq, reps, 3)
     del seq
-    return {"views": 8, "pixels": total_px, "tile": tile_b, "blend_depth": bd_b,
+    return {"views": 8, "pixels": total_px, "tile": list(R.tile_wh(tile_b)), "blend_depth": bd_b,
             "bwd_schedule": SCHEDULE_NAMES[sched_b],
             "autotune_ms": {k: round(v, 4) for k, v in timings.items()},
             "batched_graph_ms": round(ms_b, 4), "batched_views_s": round(8e3 / ms_b, 2),
