@@ -4,14 +4,16 @@
 // Strategies": tiles whose largest weight is below 1/255 are culled).
 //
 // Order: one total order (tile, depth bits, record index). Built as
-//   1. a stable LSD radix sort of all records by depth key (invisible records sort last),
+//   1. a stable LSD radix sort of the visible records by depth key (the first pass drops the
+//      invisible ones, whose key is all ones, and stores how many remain on the device),
 //   2. an exclusive scan of the per-record tile counts in that order,
 //   3. emission of (global tile id, record) pairs in depth order, repeating the cull test on
 //      the stored float32 splat record so the decisions equal those of the projection stage,
 //   4. a stable LSD radix sort of the pairs by tile id, which keeps depth order inside a tile,
 //   5. per-tile [begin, end) ranges.
-// Radix passes use 8-bit digits. Ranks inside a block come from wave64 ballots (peer masks of
-// equal digits), so the sort is stable without per-item atomics. The pair count lives on the
+// Radix passes use digits of at most 8 bits (the tile sort splits the tile-id bits evenly over
+// its passes). Ranks inside a block come from wave64 ballots (peer masks of equal digits), so
+// the sort is stable without per-item atomics. The pair count lives on the
 // device; every kernel after the scan reads it, so no host synchronisation is needed.
 #include <algorithm>
 
@@ -19,9 +21,10 @@
 
 namespace gs {
 
-constexpr int kRadixBits = 8;
+constexpr int kRadixBits = 8;  // widest digit
 constexpr int kRadixDigits = 1 << kRadixBits;
-constexpr int kRadixThreads = 256;
+constexpr int kRadixThreads = 256;  // one thread per digit of the widest digit
+static_assert(kRadixThreads == kRadixDigits, "a radix block owns one digit per thread");
 // Elements per block: the depth sort (one record per Gaussian and view) uses smaller blocks
 // so that a 1M-record pass still spreads over the whole chip; the pair sort uses larger
 // blocks, whose longer per-digit runs make the stores more contiguous.
@@ -51,11 +54,12 @@ __device__ __forceinline__ int64_t live_count(int64_t n_static, const int64_t *n
   return v < cap ? v : cap;
 }
 
-// Lanes of this wavefront whose digit equals this lane's digit (only valid lanes).
+// Lanes of this wavefront whose BITS-bit digit equals this lane's digit (only valid lanes).
+template <int BITS>
 __device__ __forceinline__ uint64_t digit_peers(uint32_t d, bool valid) {
   uint64_t m = __ballot(valid);
 #pragma unroll
-  for (int b = 0; b < kRadixBits; ++b) {
+  for (int b = 0; b < BITS; ++b) {
     const bool bit = (d >> b) & 1u;
     const uint64_t bal = __ballot(bit);
     m &= bit ? bal : ~bal;
@@ -64,15 +68,20 @@ __device__ __forceinline__ uint64_t digit_peers(uint32_t d, bool valid) {
 }
 
 // ---- radix passes --------------------------------------------------------------------------
-template <int ITEMS>
+// drop: keys equal to kDropKey are left out (not counted here, not written by the scatter).
+constexpr uint32_t kDropKey = 0xFFFFFFFFu;
+
+template <int ITEMS, int BITS>
 __global__ __launch_bounds__(kRadixThreads) void k_radix_hist(const uint32_t *__restrict__ keys, int64_t n_static,
                                                               const int64_t *n_dev, int64_t cap, int shift,
-                                                              uint32_t *__restrict__ hist, int nblocks, int stride) {
-  __shared__ uint32_t h[kRadixDigits];
+                                                              uint32_t *__restrict__ hist, int nblocks, int stride,
+                                                              bool drop) {
+  constexpr int D = 1 << BITS;
+  __shared__ uint32_t h[D];
   const int chunk = chunk_of_block();
   if (chunk >= nblocks) return;  // uniform per block
   const int64_t n = live_count(n_static, n_dev, cap);
-  h[threadIdx.x] = 0;
+  if (threadIdx.x < D) h[threadIdx.x] = 0;
   __syncthreads();
   const int64_t base = (int64_t)chunk * (kRadixThreads * ITEMS);
   if (base < n) {
@@ -86,14 +95,14 @@ __global__ __launch_bounds__(kRadixThreads) void k_radix_hist(const uint32_t *__
     const uint64_t lt = lanemask_lt();
 #pragma unroll
     for (int r = 0; r < ITEMS; ++r) {
-      const bool valid = base + r * kRadixThreads + threadIdx.x < n;
-      const uint32_t d = (kr[r] >> shift) & (kRadixDigits - 1);
-      const uint64_t peers = digit_peers(d, valid);
+      const bool valid = base + r * kRadixThreads + threadIdx.x < n && !(drop && kr[r] == kDropKey);
+      const uint32_t d = (kr[r] >> shift) & (D - 1);
+      const uint64_t peers = digit_peers<BITS>(d, valid);
       if (valid && (peers & lt) == 0) atomicAdd(&h[d], (uint32_t)__popcll(peers));
     }
   }
   __syncthreads();
-  hist[(int64_t)threadIdx.x * stride + chunk] = h[threadIdx.x];
+  if (threadIdx.x < D) hist[(int64_t)threadIdx.x * stride + chunk] = h[threadIdx.x];
 }
 
 // One workgroup per digit: exclusive scan of that digit's counts over the chunks, in place;
@@ -130,7 +139,7 @@ __global__ __launch_bounds__(kRadixThreads) void k_radix_scan(uint32_t *__restri
 // The block first orders its chunk by digit in LDS (stable: round, then wavefront, then lane
 // rank), then writes each digit's run to consecutive global positions, so the stores leave
 // as contiguous runs instead of one scattered element per lane.
-template <int ITEMS>
+template <int ITEMS, int BITS>
 __global__ __launch_bounds__(kRadixThreads) void k_radix_scatter(const uint32_t *__restrict__ kin,
                                                                  const uint32_t *__restrict__ vin,
                                                                  uint32_t *__restrict__ kout,
@@ -138,14 +147,15 @@ __global__ __launch_bounds__(kRadixThreads) void k_radix_scatter(const uint32_t 
                                                                  const int64_t *n_dev, int64_t cap, int shift,
                                                                  const uint32_t *__restrict__ hist,
                                                                  const uint32_t *__restrict__ tot, int nblocks,
-                                                                 int stride) {
+                                                                 int stride, bool drop, int64_t *kept_total) {
   constexpr int NW = kRadixThreads / 64;
   constexpr int CHUNK = kRadixThreads * ITEMS;
+  constexpr int D = 1 << BITS;
   __shared__ uint32_t s_k[CHUNK], s_v[CHUNK];
-  __shared__ uint32_t s_glob[kRadixDigits];  // global start of this block's run of each digit
-  __shared__ uint32_t s_loc[kRadixDigits];   // start of each digit's run inside the block
-  __shared__ uint32_t s_run[kRadixDigits];
-  __shared__ uint32_t s_wcnt[NW][kRadixDigits];
+  __shared__ uint32_t s_glob[D];  // global start of this block's run of each digit
+  __shared__ uint32_t s_loc[D];   // start of each digit's run inside the block
+  __shared__ uint32_t s_run[D];
+  __shared__ uint32_t s_wcnt[NW][D];
   __shared__ uint32_t lds[NW + 1];
   const int chunk = chunk_of_block();
   if (chunk >= nblocks) return;  // uniform per block
@@ -163,25 +173,32 @@ __global__ __launch_bounds__(kRadixThreads) void k_radix_scatter(const uint32_t 
     vr[r] = li < cnt ? (vin ? vin[base + li] : (uint32_t)(base + li)) : 0u;
   }
   uint32_t total;
-  const uint32_t pre = block_exclusive_scan<kRadixThreads>(tot[t], lds, total);
-  const uint32_t h0 = hist[(int64_t)t * stride + chunk];
-  const uint32_t h1 = chunk + 1 < nblocks ? hist[(int64_t)t * stride + chunk + 1] : tot[t];
-  s_glob[t] = pre + h0;
-  const uint32_t loc = block_exclusive_scan<kRadixThreads>(h1 - h0, lds, total);
-  s_loc[t] = loc;
-  s_run[t] = 0;
+  const bool own = t < D;  // this thread owns digit t
+  const uint32_t tt = own ? tot[t] : 0u;
+  const uint32_t pre = block_exclusive_scan<kRadixThreads>(tt, lds, total);
+  // the number of keys the pass keeps (all of them unless drop) for the passes and kernels after it
+  if (kept_total && chunk == 0 && t == 0) *kept_total = (int64_t)total;
+  const uint32_t h0 = own ? hist[(int64_t)t * stride + chunk] : 0u;
+  const uint32_t h1 = !own ? 0u : (chunk + 1 < nblocks ? hist[(int64_t)t * stride + chunk + 1] : tt);
+  uint32_t kept;  // keys of this block that the pass keeps
+  const uint32_t loc = block_exclusive_scan<kRadixThreads>(h1 - h0, lds, kept);
+  if (own) {
+    s_glob[t] = pre + h0;
+    s_loc[t] = loc;
+    s_run[t] = 0;
 #pragma unroll
-  for (int w = 0; w < NW; ++w) s_wcnt[w][t] = 0;
+    for (int w = 0; w < NW; ++w) s_wcnt[w][t] = 0;
+  }
   __syncthreads();
   const int wave = t >> 6;
   const uint64_t lt = lanemask_lt();
 #pragma unroll
   for (int r = 0; r < ITEMS; ++r) {
     const int li = r * kRadixThreads + t;
-    const bool valid = li < cnt;
     const uint32_t k = kr[r];
-    const uint32_t d = (k >> shift) & (kRadixDigits - 1);
-    const uint64_t peers = digit_peers(d, valid);
+    const bool valid = li < cnt && !(drop && k == kDropKey);
+    const uint32_t d = (k >> shift) & (D - 1);
+    const uint64_t peers = digit_peers<BITS>(d, valid);
     const uint32_t rank = (uint32_t)__popcll(peers & lt);
     if (valid && rank == 0) s_wcnt[wave][d] = (uint32_t)__popcll(peers);
     __syncthreads();
@@ -192,19 +209,21 @@ __global__ __launch_bounds__(kRadixThreads) void k_radix_scatter(const uint32_t 
       s_v[off + rank] = vr[r];
     }
     __syncthreads();
-    uint32_t add = 0;
+    if (own) {
+      uint32_t add = 0;
 #pragma unroll
-    for (int w = 0; w < NW; ++w) {
-      add += s_wcnt[w][t];
-      s_wcnt[w][t] = 0;
+      for (int w = 0; w < NW; ++w) {
+        add += s_wcnt[w][t];
+        s_wcnt[w][t] = 0;
+      }
+      s_run[t] += add;
     }
-    s_run[t] += add;
     __syncthreads();
   }
-  // the chunk is in digit order in LDS: element j goes to its digit's global run
-  for (int j = t; j < cnt; j += kRadixThreads) {
+  // the chunk's kept keys are in digit order in LDS: element j goes to its digit's global run
+  for (int j = t; j < (int)kept; j += kRadixThreads) {
     const uint32_t k = s_k[j];
-    const uint32_t d = (k >> shift) & (kRadixDigits - 1);
+    const uint32_t d = (k >> shift) & (D - 1);
     const uint32_t pos = s_glob[d] + (uint32_t)j - s_loc[d];
     if (kout) kout[pos] = k;
     vout[pos] = s_v[j];
@@ -213,11 +232,14 @@ __global__ __launch_bounds__(kRadixThreads) void k_radix_scatter(const uint32_t 
 
 // ---- pair counts, scan, emission -----------------------------------------------------------
 // Also clears the tile ranges (an empty tile keeps [0, 0)).
+// n_vis: the number of records in depth order (the visible ones), on the device.
 __global__ __launch_bounds__(kScanThreads) void k_count_reduce(const uint32_t *__restrict__ order,
-                                                               const uint32_t *__restrict__ n_tiles, int64_t n,
+                                                               const uint32_t *__restrict__ n_tiles,
+                                                               const int64_t *__restrict__ n_vis,
                                                                uint32_t *__restrict__ bsum,
                                                                uint32_t *__restrict__ tile_range, int64_t n_range) {
   __shared__ uint32_t lds[kScanThreads / 64 + 1];
+  const int64_t n = *n_vis;
   for (int64_t i = (int64_t)blockIdx.x * kScanThreads + threadIdx.x; i < n_range;
        i += (int64_t)gridDim.x * kScanThreads)
     tile_range[i] = 0u;
@@ -255,7 +277,7 @@ __global__ __launch_bounds__(1024) void k_count_scan_bsums(uint32_t *__restrict_
 }
 
 __global__ __launch_bounds__(kScanThreads) void k_emit_pairs(ViewTable vt, const uint32_t *__restrict__ order,
-                                                             int64_t n,
+                                                             const int64_t *__restrict__ n_vis,
                                                              const Card *__restrict__ card,
                                                              const uint32_t *__restrict__ bsum, int64_t cap,
                                                              uint32_t *__restrict__ pkey, uint32_t *__restrict__ pval,
@@ -264,6 +286,7 @@ __global__ __launch_bounds__(kScanThreads) void k_emit_pairs(ViewTable vt, const
   __shared__ uint32_t lds[kScanThreads / 64 + 1];
   __shared__ uint32_t s_key[kEmitStage], s_val[kEmitStage];
   const int64_t i = (int64_t)blockIdx.x * kScanChunk + threadIdx.x;
+  const int64_t n = *n_vis;
   // one card gather per record (a single memory line) supplies the count, centre, conic and
   // rectangle together
   uint32_t e = 0, cnt = 0;
@@ -412,6 +435,7 @@ struct BinScratch {
   uint32_t *hist;                       // [256][row stride: chunks rounded to kChunkRound]
   uint32_t *tot;                        // [256]
   uint32_t *big_n;                      // [1] length of the large-rectangle list
+  int64_t *n_vis;                       // [1] visible records (kept by the first depth pass)
 };
 
 size_t bin_scratch_bytes(int64_t n, int64_t cap) {
@@ -424,6 +448,7 @@ size_t bin_scratch_bytes(int64_t n, int64_t cap) {
   s += 4 * align256(sizeof(uint32_t) * std::max<int64_t>(cap, 1));
   s += align256(sizeof(uint32_t) * kRadixDigits * nb_max);
   s += align256(sizeof(uint32_t) * kRadixDigits);
+  s += align256(16);
   s += align256(16);
   return s;
 }
@@ -447,21 +472,35 @@ static BinScratch carve(void *base, int64_t n, int64_t cap) {
   s.hist = take(sizeof(uint32_t) * kRadixDigits * nb_max);
   s.tot = take(sizeof(uint32_t) * kRadixDigits);
   s.big_n = take(16);
+  s.n_vis = (int64_t *)take(16);
   return s;
 }
 
-template <int ITEMS>
+template <int ITEMS, int BITS>
 static hipError_t radix_pass(const uint32_t *kin, const uint32_t *vin, uint32_t *kout, uint32_t *vout, int64_t n_static,
-                             const int64_t *n_dev, int64_t cap, int shift, const BinScratch &s, hipStream_t st) {
+                             const int64_t *n_dev, int64_t cap, int shift, const BinScratch &s, hipStream_t st,
+                             bool drop = false, int64_t *kept_total = nullptr) {
+  static_assert(BITS >= 1 && BITS <= kRadixBits, "digit width");
   const int64_t nmax = n_dev ? cap : n_static;
   const int nb = (int)std::max<int64_t>(cdiv(nmax, kRadixThreads * ITEMS), 1);
   const int grid = (int)round_up(nb, kChunkRound);  // also the histogram's row stride
-  hipLaunchKernelGGL(k_radix_hist<ITEMS>, dim3(grid), dim3(kRadixThreads), 0, st, kin, n_static, n_dev, cap, shift,
-                     s.hist, nb, grid);
-  hipLaunchKernelGGL(k_radix_scan, dim3(kRadixDigits), dim3(kRadixThreads), 0, st, s.hist, nb, grid, s.tot);
-  hipLaunchKernelGGL(k_radix_scatter<ITEMS>, dim3(grid), dim3(kRadixThreads), 0, st, kin, vin, kout, vout, n_static,
-                     n_dev, cap, shift, s.hist, s.tot, nb, grid);
+  hipLaunchKernelGGL((k_radix_hist<ITEMS, BITS>), dim3(grid), dim3(kRadixThreads), 0, st, kin, n_static, n_dev, cap,
+                     shift, s.hist, nb, grid, drop);
+  hipLaunchKernelGGL(k_radix_scan, dim3(1 << BITS), dim3(kRadixThreads), 0, st, s.hist, nb, grid, s.tot);
+  hipLaunchKernelGGL((k_radix_scatter<ITEMS, BITS>), dim3(grid), dim3(kRadixThreads), 0, st, kin, vin, kout, vout,
+                     n_static, n_dev, cap, shift, s.hist, s.tot, nb, grid, drop, kept_total);
   return hipGetLastError();
+}
+
+// One pass of the tile sort with digits of `bits` bits (5 to 8).
+static hipError_t tile_pass(int bits, const uint32_t *kin, const uint32_t *vin, uint32_t *kout, uint32_t *vout,
+                            const int64_t *n_dev, int64_t cap, int shift, const BinScratch &s, hipStream_t st) {
+  switch (bits) {
+    case 5: return radix_pass<kItemsPairs, 5>(kin, vin, kout, vout, 0, n_dev, cap, shift, s, st);
+    case 6: return radix_pass<kItemsPairs, 6>(kin, vin, kout, vout, 0, n_dev, cap, shift, s, st);
+    case 7: return radix_pass<kItemsPairs, 7>(kin, vin, kout, vout, 0, n_dev, cap, shift, s, st);
+    default: return radix_pass<kItemsPairs, 8>(kin, vin, kout, vout, 0, n_dev, cap, shift, s, st);
+  }
 }
 
 hipError_t fill_u32(uint32_t *p, int64_t n, uint32_t v, hipStream_t st) {
@@ -480,43 +519,48 @@ hipError_t launch_bin_sort(const ViewTable &vt, const gs_projected &p, int64_t n
     hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(64), 0, st, (uint32_t *)num_pairs, 2, 0u);
     return hipGetLastError();
   }
-  // 1. depth order of all records (stable; the record index breaks ties)
+  // 1. depth order of the visible records (stable; the record index breaks ties). The first
+  // pass drops the invisible records and leaves their number in s.n_vis; the later passes
+  // run over that many.
   const uint32_t *kin = p.dkey;
   const uint32_t *vin = nullptr;
   uint32_t *kb[2] = {s.dk_a, s.dk_b}, *vb[2] = {s.dv_a, s.dv_b};
   for (int pass = 0; pass < 4; ++pass) {
     uint32_t *ko = pass == 3 ? nullptr : kb[pass & 1];
     uint32_t *vo = vb[pass & 1];
-    if ((err = radix_pass<kItemsDepth>(kin, vin, ko, vo, n, nullptr, 0, pass * kRadixBits, s, st)) != hipSuccess)
-      return err;
+    err = pass == 0 ? radix_pass<kItemsDepth, kRadixBits>(kin, vin, ko, vo, n, nullptr, 0, 0, s, st, true, s.n_vis)
+                    : radix_pass<kItemsDepth, kRadixBits>(kin, vin, ko, vo, 0, s.n_vis, n, pass * kRadixBits, s, st);
+    if (err != hipSuccess) return err;
     kin = ko;
     vin = vo;
   }
-  const uint32_t *order = vin;  // == s.dv_b
+  const uint32_t *order = vin;  // == s.dv_b, s.n_vis entries
   // 2. exclusive scan of tile counts in depth order; total -> num_pairs
   const int64_t nbs = cdiv(n, kScanChunk);
-  hipLaunchKernelGGL(k_count_reduce, dim3((unsigned)nbs), dim3(kScanThreads), 0, st, order, p.n_tiles, n, s.bsum,
-                     tile_range, 2 * (int64_t)vt.total_tiles);
+  hipLaunchKernelGGL(k_count_reduce, dim3((unsigned)nbs), dim3(kScanThreads), 0, st, order, p.n_tiles,
+                     (const int64_t *)s.n_vis, s.bsum, tile_range, 2 * (int64_t)vt.total_tiles);
   hipLaunchKernelGGL(k_count_scan_bsums, dim3(1), dim3(1024), 0, st, s.bsum, nbs, num_pairs, s.big_n);
   // 3. emission in depth order
   // the depth keys' ping-pong buffers are free now: they hold the large-rectangle list
-  hipLaunchKernelGGL(k_emit_pairs, dim3((unsigned)nbs), dim3(kScanThreads), 0, st, vt, order, n,
+  hipLaunchKernelGGL(k_emit_pairs, dim3((unsigned)nbs), dim3(kScanThreads), 0, st, vt, order,
+                     (const int64_t *)s.n_vis,
                      (const Card *)p.card, s.bsum, cap, s.pk_a, s.pv_a, s.dk_a, s.dk_b, s.big_n);
   hipLaunchKernelGGL(k_emit_big, dim3(kBigBlocks), dim3(kScanThreads), 0, st, vt, (const Card *)p.card,
                      (const uint32_t *)s.dk_a, (const uint32_t *)s.dk_b, (const uint32_t *)s.big_n, cap, s.pk_a,
                      s.pv_a);
   if ((err = hipGetLastError()) != hipSuccess) return err;
-  // 4. stable sort by global tile id
+  // 4. stable sort by global tile id; the id bits are split evenly over the passes (narrower
+  // digits: fewer ballot rounds per key and longer runs per digit)
   int tile_bits = 1;
   while ((1ull << tile_bits) < (uint64_t)vt.total_tiles) ++tile_bits;
   const int passes = (int)cdiv(tile_bits, kRadixBits);
+  const int digit_bits = std::max(5, (int)cdiv(tile_bits, passes));
   const uint32_t *pk = s.pk_a, *pv = s.pv_a;
   uint32_t *pkb[2] = {s.pk_b, s.pk_a}, *pvb[2] = {s.pv_b, s.pv_a};
   for (int pass = 0; pass < passes; ++pass) {
     uint32_t *ko = pkb[pass & 1];
     uint32_t *vo = pass == passes - 1 ? vals : pvb[pass & 1];
-    if ((err = radix_pass<kItemsPairs>(pk, pv, ko, vo, 0, num_pairs, cap, pass * kRadixBits, s, st)) !=
-        hipSuccess)
+    if ((err = tile_pass(digit_bits, pk, pv, ko, vo, num_pairs, cap, pass * digit_bits, s, st)) != hipSuccess)
       return err;
     pk = ko;
     pv = vo;

@@ -721,6 +721,8 @@ __device__ __forceinline__ int reduce10_slot(int lane) {
 // Backward state of one pixel. The colour behind the current splat enters the alpha
 // derivative only through dL/dC . (c - C_behind), so the pixel carries the scalar
 // S = dL/dC . C_behind (updated as S + alpha (dL/dC . c - S)) instead of the three channels.
+constexpr int kBwdSub = 64;  // splats staged at a time by the compositing backward
+
 struct PixGrad {
   float gC0, gC1, gC2, gD, TfG;  // TfG = T_final (dL/dO - dL/dC . bg)
   float T, S, AD;
@@ -738,13 +740,14 @@ struct PixGrad {
 //   5: dL/do;  6-8: dL/d(r, g, b);  9: dL/d(depth)
 // with dp = dL/dpower = dL/dalpha * o exp(power) (zero where alpha is clamped at 0.99) and
 // (a, b, c) the unscaled conic.
-// The chunk's splats back to front (staged at s_a/s_b/s_c, record index in s_c[j].w) for the
-// pixels of this lane; DEPTH: some pixel of the wavefront has a depth gradient.
+// Splats hi down to lo of the chunk, back to front, for the pixels of this lane; splat j is
+// staged at s_a/s_b/s_c[j - lo] (record index in s_c[.].w). DEPTH: some pixel of the
+// wavefront has a depth gradient.
 template <int PPT, bool DEPTH>
-__device__ __forceinline__ void bwd_splats(int maxll, const float4 *s_a, const float4 *s_b, const float4 *s_c,
+__device__ __forceinline__ void bwd_splats(int hi, int lo, const float4 *s_a, const float4 *s_b, const float4 *s_c,
                                            PixGrad (&pg)[PPT], int slot, float *__restrict__ g2) {
-  for (int j = maxll; j >= 0; --j) {
-    const float4 A = s_a[j], B = s_b[j], Cc = s_c[j];
+  for (int j = hi; j >= lo; --j) {
+    const float4 A = s_a[j - lo], B = s_b[j - lo], Cc = s_c[j - lo];
     // alpha at every pixel first; a splat no pixel of the wavefront blends costs only this
     float dxs[PPT], dys[PPT], exs[PPT], ars[PPT];
     bool act[PPT];
@@ -806,7 +809,10 @@ __global__ __launch_bounds__(NT) void k_blend_bwd_chunk(ViewTable vt, ImgTable i
                                                         float *__restrict__ g2 /*[E][12]*/) {
   using Ctx = TileCtx<TW, TH, NT>;
   constexpr int PPT = Ctx::PPT;
-  __shared__ float4 s_a[BD], s_b[BD], s_c[BD];
+  // the chunk is staged kBwdSub splats at a time, back to front: LDS and registers do not
+  // grow with the chunk length
+  constexpr int SUB = BD < kBwdSub ? BD : kBwdSub;
+  __shared__ float4 s_a[SUB], s_b[SUB], s_c[SUB];
   __shared__ int s_max;
   uint32_t item;
   if (!item_of_block(n_items, item)) return;
@@ -859,13 +865,18 @@ __global__ __launch_bounds__(NT) void k_blend_bwd_chunk(ViewTable vt, ImgTable i
   __syncthreads();
   const int maxll = __builtin_amdgcn_readfirstlane(s_max);  // uniform: the splat loop runs on scalar registers
   if (maxll < 0) return;  // uniform: no pixel has a contributor in this chunk
-  stage<BD, NT, true>(vals, cs, maxll + 1, card, s_a, s_b, s_c);
-  __syncthreads();
   const int slot = reduce10_slot(threadIdx.x & 63);
-  if (__any(depth_any))
-    bwd_splats<PPT, true>(maxll, s_a, s_b, s_c, pg, slot, g2);
-  else
-    bwd_splats<PPT, false>(maxll, s_a, s_b, s_c, pg, slot, g2);
+  const bool dep = __any(depth_any);
+  for (int lo = maxll / SUB * SUB; lo >= 0; lo -= SUB) {
+    const int hi = min(maxll, lo + SUB - 1);
+    if (lo != maxll / SUB * SUB) __syncthreads();  // every wavefront is done with the previous sub-chunk
+    stage<SUB, NT, true>(vals, cs + lo, hi - lo + 1, card, s_a, s_b, s_c);
+    __syncthreads();
+    if (dep)
+      bwd_splats<PPT, true>(hi, lo, s_a, s_b, s_c, pg, slot, g2);
+    else
+      bwd_splats<PPT, false>(hi, lo, s_a, s_b, s_c, pg, slot, g2);
+  }
 }
 
 // ---- per-Gaussian bucketed backward (a second a4 schedule) ---------------------------------
