@@ -18,6 +18,9 @@
 //   2. k_blend_scan walks the chunk partials of each multi-chunk tile in order per pixel. A
 //      chunk whose product keeps the transmittance at or above 1e-4 is accumulated as a whole;
 //      at the chunk in which the pixel stops it records the incoming state.
+//   Passes 1 and 2 run in three windows of chunks (the first kWin0 splats of every list, up
+//   to kWin1, the rest): a window's chunks are composited only for the tiles in which some
+//   pixel was still running at the end of the previous window.
 //   3. k_blend_fix (one workgroup per chunk, in parallel) composites each pixel's stop chunk
 //      again record by record from the true incoming transmittance, which applies the stop
 //      rule exactly.
@@ -79,66 +82,92 @@ __device__ __forceinline__ bool item_of_block(const uint32_t *n_items, uint32_t 
   return item < *n_items;
 }
 
+// Per block of tiles: the number of items and of first-window work items (chunks below w0).
 __global__ __launch_bounds__(kItemThreads) void k_items_reduce(ViewTable vt, const uint32_t *__restrict__ range,
-                                                                int bd, uint32_t *__restrict__ bsum) {
+                                                                int bd, uint32_t w0, uint32_t *__restrict__ bsum,
+                                                                uint32_t *__restrict__ bsum0) {
   __shared__ uint32_t lds[kItemThreads / 64 + 1];
   const uint32_t T = vt.total_tiles;
-  uint32_t s = 0;
+  uint32_t s = 0, s0 = 0;
 #pragma unroll
   for (int r = 0; r < kItemPer; ++r) {
     const uint32_t j = blockIdx.x * kItemChunk + r * kItemThreads + threadIdx.x;
     if (j < T) {
       const uint32_t t = tile_at(vt, j);
-      s += n_chunks(range[2 * t + 1] - range[2 * t], bd);
+      const uint32_t k = n_chunks(range[2 * t + 1] - range[2 * t], bd);
+      s += k;
+      s0 += min(k, w0);
     }
   }
-  uint32_t total;
+  uint32_t total, total0;
   block_exclusive_scan<kItemThreads>(s, lds, total);
-  if (threadIdx.x == 0) bsum[blockIdx.x] = total;
+  block_exclusive_scan<kItemThreads>(s0, lds, total0);
+  if (threadIdx.x == 0) {
+    bsum[blockIdx.x] = total;
+    bsum0[blockIdx.x] = total0;
+  }
 }
 
-__global__ __launch_bounds__(1024) void k_items_scan(uint32_t *__restrict__ bsum, uint32_t nb,
-                                                      uint32_t *__restrict__ n_items, uint32_t *__restrict__ item_base,
-                                                      uint32_t T) {
+// n_work[0]: the first window's work items; n_work[1] (the second window's) is cleared.
+__global__ __launch_bounds__(1024) void k_items_scan(uint32_t *__restrict__ bsum, uint32_t *__restrict__ bsum0,
+                                                      uint32_t nb, uint32_t *__restrict__ n_items,
+                                                      uint32_t *__restrict__ item_base, uint32_t T,
+                                                      uint32_t *__restrict__ n_work) {
   __shared__ uint32_t lds[1024 / 64 + 1];
-  uint32_t running = 0;
+  uint32_t running = 0, running0 = 0;
   for (uint32_t base = 0; base < nb; base += 1024) {
     const uint32_t i = base + threadIdx.x;
     const uint32_t v = i < nb ? bsum[i] : 0u;
-    uint32_t total;
+    const uint32_t v0 = i < nb ? bsum0[i] : 0u;
+    uint32_t total, total0;
     const uint32_t ex = block_exclusive_scan<1024>(v, lds, total);
-    if (i < nb) bsum[i] = running + ex;
+    const uint32_t ex0 = block_exclusive_scan<1024>(v0, lds, total0);
+    if (i < nb) {
+      bsum[i] = running + ex;
+      bsum0[i] = running0 + ex0;
+    }
     running += total;
+    running0 += total0;
   }
   if (threadIdx.x == 0) {
     *n_items = running;
     item_base[T] = running;
+    n_work[0] = running0;
+    n_work[1] = 0u;
   }
 }
 
+// The item list (every chunk, tile by tile: the item of chunk c of tile t is item_base[t] + c,
+// which also indexes its chunk records) and the first window's work list (its chunks below w0,
+// in the same order).
 __global__ __launch_bounds__(kItemThreads) void k_items_apply(ViewTable vt, const uint32_t *__restrict__ range, int bd,
-                                                               const uint32_t *__restrict__ bsum,
+                                                               uint32_t w0, const uint32_t *__restrict__ bsum,
+                                                               const uint32_t *__restrict__ bsum0,
                                                                uint32_t *__restrict__ item_base,
-                                                               uint2 *__restrict__ items,
+                                                               uint2 *__restrict__ items, uint2 *__restrict__ work,
                                                                uint32_t *__restrict__ need_fix) {
   __shared__ uint32_t lds[kItemThreads / 64 + 1];
   const uint32_t T = vt.total_tiles;
-  uint32_t running = bsum[blockIdx.x];
+  uint32_t running = bsum[blockIdx.x], running0 = bsum0[blockIdx.x];
   for (int r = 0; r < kItemPer; ++r) {
     const uint32_t j = blockIdx.x * kItemChunk + r * kItemThreads + threadIdx.x;
     const uint32_t t = j < T ? tile_at(vt, j) : 0u;
     const uint32_t k = j < T ? n_chunks(range[2 * t + 1] - range[2 * t], bd) : 0u;
-    uint32_t total;
+    const uint32_t k0 = min(k, w0);
+    uint32_t total, total0;
     const uint32_t ex = block_exclusive_scan<kItemThreads>(k, lds, total);
+    const uint32_t ex0 = block_exclusive_scan<kItemThreads>(k0, lds, total0);
     if (j < T) {
-      const uint32_t b = running + ex;
+      const uint32_t b = running + ex, b0 = running0 + ex0;
       item_base[t] = b;
       for (uint32_t c = 0; c < k; ++c) {
         items[b + c] = make_uint2(t, c);
         need_fix[b + c] = 0u;  // set again by k_blend_scan where a pixel stops inside
       }
+      for (uint32_t c = 0; c < k0; ++c) work[b0 + c] = make_uint2(t, c);
     }
     running += total;
+    running0 += total0;
   }
 }
 
@@ -283,52 +312,77 @@ __device__ __forceinline__ bool composite_run(const float4 *s_a, const float4 *s
   return true;
 }
 
-// ---- forward pass 1: every chunk from transmittance 1 ------------------------------------
-template <int TW, int TH, int BD, int NT, bool CNT>
+// ---- forward pass 1: every chunk of a window's work list from transmittance 1 -------------
+// work / n_work: this window's work items (tile, chunk); n_next, l_next: the next window's
+// work and tile counts, cleared here for k_blend_scan to append to. A chunk's records sit at
+// item item_base[t] + c. PERSIST: a fixed grid walks the list (the later windows, whose lists
+// are short: a grid for the longest list would mostly launch empty workgroups); otherwise one
+// item per workgroup in the XCD-grouped order.
+template <int TW, int TH, int BD, int NT, bool CNT, bool PERSIST>
 __global__ __launch_bounds__(NT) void k_blend_chunk(ViewTable vt, ImgTable it, const Card *__restrict__ card,
                                                     const uint32_t *__restrict__ vals,
                                                     const uint32_t *__restrict__ range,
-                                                    const uint2 *__restrict__ items,
-                                                    const uint32_t *__restrict__ n_items,
+                                                    const uint2 *__restrict__ work,
+                                                    const uint32_t *__restrict__ n_work,
+                                                    uint32_t *__restrict__ n_next, uint32_t *__restrict__ l_next,
+                                                    const uint32_t *__restrict__ item_base,
                                                     ChunkRec *__restrict__ chunk) {
   using Ctx = TileCtx<TW, TH, NT>;
   constexpr int PPT = Ctx::PPT;
   __shared__ float4 s_a[BD], s_b[BD], s_c[BD];
-  uint32_t item;
-  if (!item_of_block(n_items, item)) return;
-  const uint2 tc = items[item];
-  const uint32_t gt = tc.x, c = tc.y;
-  const Ctx tile(vt, gt);
-  const uint32_t s0 = range[2 * gt], e0 = range[2 * gt + 1];
-  const uint32_t K = n_chunks(e0 - s0, BD);
-  const uint32_t cs = s0 + c * BD;
-  const int cnt = (int)min<uint32_t>(BD, e0 - cs);
-  stage<BD, NT>(vals, cs, cnt, card, s_a, s_b, s_c);
-  __syncthreads();
-
-  float px[PPT], py[PPT];
-  bool inside[PPT];
-  int64_t pi[PPT];
-  PixState st[PPT];
-#pragma unroll
-  for (int k = 0; k < PPT; ++k) {
-    tile.pixel(k, inside[k], px[k], py[k], pi[k]);
-    st[k] = PixState{1.f, 0.f, 0.f, 0.f, 0.f, 0.f, -1, 0, 0, !inside[k]};
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    *n_next = 0u;
+    *l_next = 0u;
   }
-  composite_run<PPT, CNT>(s_a, s_b, s_c, cnt, px, py, 0, st);
+  uint32_t w;
+  if (PERSIST) {
+    w = blockIdx.x;
+    if (w >= *n_work) return;
+  } else if (!item_of_block(n_work, w)) {
+    return;
+  }
+  const uint32_t nw = PERSIST ? *n_work : 0u;
+#pragma unroll 1
+  for (;;) {
+    const uint2 tc = work[w];
+    const uint32_t gt = tc.x, c = tc.y;
+    const uint32_t item = item_base[gt] + c;
+    const Ctx tile(vt, gt);
+    const uint32_t s0 = range[2 * gt], e0 = range[2 * gt + 1];
+    const uint32_t K = n_chunks(e0 - s0, BD);
+    const uint32_t cs = s0 + c * BD;
+    const int cnt = (int)min<uint32_t>(BD, e0 - cs);
+    stage<BD, NT>(vals, cs, cnt, card, s_a, s_b, s_c);
+    __syncthreads();
+
+    float px[PPT], py[PPT];
+    bool inside[PPT];
+    int64_t pi[PPT];
+    PixState st[PPT];
 #pragma unroll
-  for (int k = 0; k < PPT; ++k) {
-    if (!inside[k]) continue;
-    const PixState &p = st[k];
-    if (K == 1) {
-      write_pixel(it.v[tile.vi], *tile.cam, pi[k], tile.npx, p.C0, p.C1, p.C2, p.D, p.O, p.T, p.last(), p.nc);
-    } else {
-      ChunkRec r;
-      r.c0 = p.C0; r.c1 = p.C1; r.c2 = p.C2; r.d = p.D; r.o = p.O; r.t = p.T;
-      r.info = (uint32_t)(p.last() + 1) | ((uint32_t)p.nc << 10) | ((uint32_t)p.stopped << 20);
-      r.pad = 0.f;
-      chunk[(int64_t)item * (TW * TH) + tile.pidx(k)] = r;
+    for (int k = 0; k < PPT; ++k) {
+      tile.pixel(k, inside[k], px[k], py[k], pi[k]);
+      st[k] = PixState{1.f, 0.f, 0.f, 0.f, 0.f, 0.f, -1, 0, 0, !inside[k]};
     }
+    composite_run<PPT, CNT>(s_a, s_b, s_c, cnt, px, py, 0, st);
+#pragma unroll
+    for (int k = 0; k < PPT; ++k) {
+      if (!inside[k]) continue;
+      const PixState &p = st[k];
+      if (K == 1) {
+        write_pixel(it.v[tile.vi], *tile.cam, pi[k], tile.npx, p.C0, p.C1, p.C2, p.D, p.O, p.T, p.last(), p.nc);
+      } else {
+        ChunkRec r;
+        r.c0 = p.C0; r.c1 = p.C1; r.c2 = p.C2; r.d = p.D; r.o = p.O; r.t = p.T;
+        r.info = (uint32_t)(p.last() + 1) | ((uint32_t)p.nc << 10) | ((uint32_t)p.stopped << 20);
+        r.pad = 0.f;
+        chunk[(int64_t)item * (TW * TH) + tile.pidx(k)] = r;
+      }
+    }
+    if (!PERSIST) return;
+    w += gridDim.x;
+    if (w >= nw) return;
+    __syncthreads();  // the staged splats are read by every wavefront before the next item
   }
 }
 
@@ -340,23 +394,39 @@ __global__ __launch_bounds__(NT) void k_blend_chunk(ViewTable vt, ImgTable it, c
 // item is marked for k_blend_fix. Chunks behind that point are not touched: later passes stop
 // at the pixel's last contributor. Chunk records are loaded kScanBatch at a time, so a long
 // tile's chain costs one memory latency per batch instead of one per chunk.
+//
+// The chunks are composited and scanned in windows of increasing length ([0, q_hi), then
+// [q_hi, q_next), ...), so that a tile all of whose pixels have stopped in one window has none
+// of its later chunks composited (in a street view most long tile lists lie mostly behind
+// the point where every pixel of the tile is opaque). This pass scans the window
+// [q_lo, q_hi) and, when some pixel is still running, appends the tile's next window
+// [q_hi, q_next) to the next work list and the tile to the next tile list. The first window
+// takes one workgroup per tile; the later ones walk the tile list with a fixed grid. Between
+// windows a running pixel keeps its state in its own output planes: colour without the
+// background, depth, opacity, last, count, and the transmittance negated in t_final (a pixel
+// whose t_final is not negative is finished or waits for k_blend_fix).
 constexpr uint32_t kPending = 1u << 31;
 constexpr int kScanBatch = 8;
 
 template <int TW, int TH, int BD>
-__global__ __launch_bounds__(TW * TH) void k_blend_scan(ViewTable vt, ImgTable it, const uint32_t *__restrict__ range,
-                                                   const uint32_t *__restrict__ item_base,
-                                                   ChunkRec *__restrict__ chunk, uint32_t *__restrict__ need_fix) {
+__device__ __forceinline__ void scan_tile(const ViewTable &vt, const ImgTable &it, const uint32_t *__restrict__ range,
+                                          const uint32_t *__restrict__ item_base, ChunkRec *__restrict__ chunk,
+                                          uint32_t *__restrict__ need_fix, uint32_t q_lo, uint32_t q_hi,
+                                          uint32_t q_next, uint2 *__restrict__ work, uint32_t *__restrict__ n_next,
+                                          uint32_t *__restrict__ live_next, uint32_t *__restrict__ l_next,
+                                          uint32_t &s_base, uint32_t gt) {
   // one pixel per lane: the per-pixel chain over the chunks is serial, so spread it wide
   using Ctx = TileCtx<TW, TH, TW * TH>;
   constexpr int PPT = Ctx::PPT;
   constexpr int64_t TT = TW * TH;
-  const uint32_t gt = blockIdx.x;
   const uint32_t s0 = range[2 * gt], e0 = range[2 * gt + 1];
   const uint32_t K = n_chunks(e0 - s0, BD);
-  if (K == 1) return;  // written by k_blend_chunk
+  if (K == 1) return;                // written by the chunk pass
+  if (q_lo > 0 && K <= q_lo) return;  // finished in an earlier window
   const Ctx tile(vt, gt);
   const ViewImg &im = it.v[tile.vi];
+  const uint32_t q_end = min(K, q_hi);
+  bool running_any = false;
 #pragma unroll 1
   for (int k = 0; k < PPT; ++k) {
     bool inside;
@@ -368,20 +438,32 @@ __global__ __launch_bounds__(TW * TH) void k_blend_scan(ViewTable vt, ImgTable i
       write_pixel(im, *tile.cam, pi, tile.npx, 0.f, 0.f, 0.f, 0.f, 0.f, 1.f, -1, 0);
       continue;
     }
-    const uint32_t ib = item_base[gt];
-    ChunkRec *base = chunk + (int64_t)ib * TT + tile.pidx(k);
     float T = 1.f, C0 = 0.f, C1 = 0.f, C2 = 0.f, D = 0.f, O = 0.f;
     int32_t last = -1, nc = 0;
+    if (q_lo > 0) {
+      const float tf = im.t_final[pi];
+      if (!(tf < 0.f)) continue;  // finished in an earlier window, or waiting for the fix
+      T = -tf;
+      C0 = im.color[pi];
+      C1 = im.color[tile.npx + pi];
+      C2 = im.color[2 * tile.npx + pi];
+      D = im.depth[pi];
+      O = im.alpha[pi];
+      last = im.last[pi];
+      if (im.n_contrib) nc = im.n_contrib[pi];
+    }
+    const uint32_t ib = item_base[gt];
+    ChunkRec *base = chunk + (int64_t)ib * TT + tile.pidx(k);
     bool done = false, pending = false;
-    for (uint32_t q0 = 0; q0 < K && !done; q0 += kScanBatch) {
+    for (uint32_t q0 = q_lo; q0 < q_end && !done; q0 += kScanBatch) {
       ChunkRec rb[kScanBatch];
 #pragma unroll
       for (int i = 0; i < kScanBatch; ++i)
-        if (q0 + i < K) rb[i] = base[(int64_t)(q0 + i) * TT];
+        if (q0 + i < q_end) rb[i] = base[(int64_t)(q0 + i) * TT];
 #pragma unroll
       for (int i = 0; i < kScanBatch; ++i) {
         const uint32_t q = q0 + i;
-        if (done || q >= K) continue;
+        if (done || q >= q_end) continue;
         const ChunkRec &r = rb[i];
         const int ll = (int)(r.info & 1023u) - 1;
         const int ncl = (int)((r.info >> 10) & 1023u);
@@ -412,25 +494,63 @@ __global__ __launch_bounds__(TW * TH) void k_blend_scan(ViewTable vt, ImgTable i
         base[(int64_t)q * TT] = w;
       }
     }
-    if (!pending) write_pixel(im, *tile.cam, pi, tile.npx, C0, C1, C2, D, O, T, last, nc);
+    if (pending) {
+      if (q_hi < K) im.t_final[pi] = 1.f;  // not running (the fix writes the pixel)
+    } else if (!done && q_hi < K) {
+      // still running: keep the state for the next window
+      im.color[pi] = C0;
+      im.color[tile.npx + pi] = C1;
+      im.color[2 * tile.npx + pi] = C2;
+      im.depth[pi] = D;
+      im.alpha[pi] = O;
+      im.t_final[pi] = -T;
+      im.last[pi] = last;
+      if (im.n_contrib) im.n_contrib[pi] = nc;
+      running_any = true;
+    } else {
+      write_pixel(im, *tile.cam, pi, tile.npx, C0, C1, C2, D, O, T, last, nc);
+    }
   }
+  if (__syncthreads_or(running_any) == 0) return;
+  // some pixel is still running: the tile's next window goes to the next work list
+  const uint32_t n = min(K, q_next) - q_hi;
+  if (threadIdx.x == 0) {
+    s_base = atomicAdd(n_next, n);
+    live_next[atomicAdd(l_next, 1u)] = gt;
+  }
+  __syncthreads();
+  for (uint32_t i = threadIdx.x; i < n; i += TW * TH) work[s_base + i] = make_uint2(gt, q_hi + i);
 }
 
-// ---- forward pass 3: exact compositing of each pixel's stop chunk (chunk-parallel) -------
+// live == nullptr: the first window, one workgroup per tile; else the tiles of live[0, *n_live).
+template <int TW, int TH, int BD>
+__global__ __launch_bounds__(TW * TH) void k_blend_scan(ViewTable vt, ImgTable it, const uint32_t *__restrict__ range,
+                                                   const uint32_t *__restrict__ item_base,
+                                                   ChunkRec *__restrict__ chunk, uint32_t *__restrict__ need_fix,
+                                                   uint32_t q_lo, uint32_t q_hi, uint32_t q_next,
+                                                   uint2 *__restrict__ work, uint32_t *__restrict__ n_next,
+                                                   const uint32_t *__restrict__ live,
+                                                   const uint32_t *__restrict__ n_live,
+                                                   uint32_t *__restrict__ live_next, uint32_t *__restrict__ l_next) {
+  __shared__ uint32_t s_base;
+  if (!live) {
+    scan_tile<TW, TH, BD>(vt, it, range, item_base, chunk, need_fix, q_lo, q_hi, q_next, work, n_next, live_next,
+                          l_next, s_base, blockIdx.x);
+    return;
+  }
+  const uint32_t nl = *n_live;
+  for (uint32_t i = blockIdx.x; i < nl; i += gridDim.x)
+    scan_tile<TW, TH, BD>(vt, it, range, item_base, chunk, need_fix, q_lo, q_hi, q_next, work, n_next, live_next,
+                          l_next, s_base, live[i]);
+}
+
 template <int TW, int TH, int BD, int NT, bool CNT>
-__global__ __launch_bounds__(NT) void k_blend_fix(ViewTable vt, ImgTable it, const Card *__restrict__ card,
-                                                  const uint32_t *__restrict__ vals,
-                                                  const uint32_t *__restrict__ range,
-                                                  const uint2 *__restrict__ items,
-                                                  const uint32_t *__restrict__ n_items,
-                                                  const uint32_t *__restrict__ need_fix,
-                                                  ChunkRec *__restrict__ chunk) {
+__device__ __forceinline__ void fix_item(const ViewTable &vt, const ImgTable &it, const Card *__restrict__ card,
+                                         const uint32_t *__restrict__ vals, const uint32_t *__restrict__ range,
+                                         const uint2 *__restrict__ items, uint32_t item, ChunkRec *__restrict__ chunk,
+                                         float4 *s_a, float4 *s_b, float4 *s_c) {
   using Ctx = TileCtx<TW, TH, NT>;
   constexpr int PPT = Ctx::PPT;
-  __shared__ float4 s_a[BD], s_b[BD], s_c[BD];
-  uint32_t item;
-  if (!item_of_block(n_items, item)) return;
-  if (!need_fix[item]) return;  // no pixel stops inside this chunk
   const uint2 tc = items[item];
   const uint32_t gt = tc.x, c = tc.y;
   const uint32_t s0 = range[2 * gt], e0 = range[2 * gt + 1];
@@ -452,7 +572,7 @@ __global__ __launch_bounds__(NT) void k_blend_fix(ViewTable vt, ImgTable it, con
     st[k] = PixState{r[k].t, 0.f, 0.f, 0.f, 0.f, r[k].o, (int32_t)(r[k].info & 0x3FFFFFFFu) - 1, 0,
                      __float_as_int(r[k].pad), !pending[k]};
   }
-  if (__syncthreads_count(any) == 0) return;
+  if (__syncthreads_count(any) == 0) return;  // uniform
   const uint32_t cs = s0 + c * BD;
   const int cnt = (int)min<uint32_t>(BD, e0 - cs);
   stage<BD, NT>(vals, cs, cnt, card, s_a, s_b, s_c);
@@ -468,6 +588,22 @@ __global__ __launch_bounds__(NT) void k_blend_fix(ViewTable vt, ImgTable it, con
     w.c0 = p.C0; w.c1 = p.C1; w.c2 = p.C2; w.d = p.D; w.o = 0.f; w.t = p.T; w.info = 0u; w.pad = 0.f;
     chunk[(int64_t)item * (TW * TH) + tile.pidx(k)] = w;
   }
+}
+
+// ---- forward pass 3: exact compositing of each pixel's stop chunk (chunk-parallel) -------
+template <int TW, int TH, int BD, int NT, bool CNT>
+__global__ __launch_bounds__(NT) void k_blend_fix(ViewTable vt, ImgTable it, const Card *__restrict__ card,
+                                                  const uint32_t *__restrict__ vals,
+                                                  const uint32_t *__restrict__ range,
+                                                  const uint2 *__restrict__ items,
+                                                  const uint32_t *__restrict__ n_items,
+                                                  const uint32_t *__restrict__ need_fix,
+                                                  ChunkRec *__restrict__ chunk) {
+  __shared__ float4 s_a[BD], s_b[BD], s_c[BD];
+  uint32_t item;
+  if (!item_of_block(n_items, item)) return;
+  if (!need_fix[item]) return;  // no pixel stops inside this chunk
+  fix_item<TW, TH, BD, NT, CNT>(vt, it, card, vals, range, items, item, chunk, s_a, s_b, s_c);
 }
 
 // ---- forward passes 1 and 3 for 8x8 tiles: two work items per wavefront ----------------
@@ -503,13 +639,13 @@ struct HalfItem {
   int64_t pi[2];
   int q[2];  // row-major pixel index in the tile
 
-  __device__ __forceinline__ HalfItem(const ViewTable &vt, const uint2 *items, const uint32_t *range, uint32_t nI,
-                                      uint32_t it, int hl) {
-    item = it;
+  __device__ __forceinline__ HalfItem(const ViewTable &vt, const uint2 *work, const uint32_t *item_base,
+                                      const uint32_t *range, uint32_t nI, uint32_t it, int hl) {
     valid = it < nI;
-    const uint2 tc = valid ? items[it] : make_uint2(0u, 0u);
+    const uint2 tc = valid ? work[it] : make_uint2(0u, 0u);
     gt = tc.x;
     c = tc.y;
+    item = valid ? item_base[gt] + c : 0u;
     const uint32_t s0 = valid ? range[2 * gt] : 0u, e0 = valid ? range[2 * gt + 1] : 0u;
     K = n_chunks(e0 - s0, BD);
     cs = s0 + c * BD;
@@ -570,17 +706,13 @@ __device__ __forceinline__ void composite_pair(const uint32_t *__restrict__ vals
 }
 
 template <int BD, bool CNT>
-__global__ __launch_bounds__(64) void k_blend_chunk_pair(ViewTable vt, ImgTable it, const Card *__restrict__ card,
-                                                         const uint32_t *__restrict__ vals,
-                                                         const uint32_t *__restrict__ range,
-                                                         const uint2 *__restrict__ items,
-                                                         const uint32_t *__restrict__ n_items,
-                                                         ChunkRec *__restrict__ chunk) {
-  __shared__ float4 s_a[2 * kHalfStride], s_b[2 * kHalfStride], s_c[2 * kHalfStride];
-  uint32_t pair;
-  if (!pair_of_block(n_items, pair)) return;
+__device__ __forceinline__ void pair_item(const ViewTable &vt, const ImgTable &it, const Card *__restrict__ card,
+                                          const uint32_t *__restrict__ vals, const uint2 *__restrict__ work,
+                                          uint32_t nw, const uint32_t *__restrict__ item_base,
+                                          const uint32_t *__restrict__ range, uint32_t pair,
+                                          ChunkRec *__restrict__ chunk, float4 *s_a, float4 *s_b, float4 *s_c) {
   const int hl = (int)threadIdx.x & 31;
-  const HalfItem<BD> hi(vt, items, range, *n_items, 2 * pair + (threadIdx.x >> 5), hl);
+  const HalfItem<BD> hi(vt, work, item_base, range, nw, 2 * pair + (threadIdx.x >> 5), hl);
   PixState st[2];
 #pragma unroll
   for (int k = 0; k < 2; ++k) st[k] = PixState{1.f, 0.f, 0.f, 0.f, 0.f, 0.f, -1, 0, 0, !hi.inside[k]};
@@ -599,6 +731,26 @@ __global__ __launch_bounds__(64) void k_blend_chunk_pair(ViewTable vt, ImgTable 
       chunk[(int64_t)hi.item * 64 + hi.q[k]] = r;
     }
   }
+}
+
+template <int BD, bool CNT>
+__global__ __launch_bounds__(64) void k_blend_chunk_pair(ViewTable vt, ImgTable it, const Card *__restrict__ card,
+                                                         const uint32_t *__restrict__ vals,
+                                                         const uint32_t *__restrict__ range,
+                                                         const uint2 *__restrict__ work,
+                                                         const uint32_t *__restrict__ n_work,
+                                                         uint32_t *__restrict__ n_next,
+                                                         uint32_t *__restrict__ l_next,
+                                                         const uint32_t *__restrict__ item_base,
+                                                         ChunkRec *__restrict__ chunk) {
+  __shared__ float4 s_a[2 * kHalfStride], s_b[2 * kHalfStride], s_c[2 * kHalfStride];
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    *n_next = 0u;
+    *l_next = 0u;
+  }
+  uint32_t pair;
+  if (!pair_of_block(n_work, pair)) return;
+  pair_item<BD, CNT>(vt, it, card, vals, work, *n_work, item_base, range, pair, chunk, s_a, s_b, s_c);
 }
 
 // ---- forward pass 4: backward starting state per chunk (suffix sums, per tile) ------------
@@ -1053,9 +1205,12 @@ size_t blend_state_bytes(int64_t total_tiles, int64_t cap, int tw, int th, int b
   size_t s = a256(4 * (T + 1));                                     // item_base
   s += a256(8 * I);                                                 // items
   s += a256(4 * ((T + kItemChunk - 1) / kItemChunk + 1));          // block sums
-  s += a256(16);                                                    // n_items
+  s += a256(16);                                                    // n_items, work list counts
   s += a256(sizeof(ChunkRec) * (size_t)I * tw * th);                // chunk records
   s += a256(4 * (size_t)I);                                         // fix-needed flags
+  s += a256(8 * I);                                                 // window work list
+  s += a256(4 * ((T + kItemChunk - 1) / kItemChunk + 1));          // first-window block sums
+  s += 2 * a256(4 * (size_t)T);                                     // window tile lists
   return s;
 }
 
@@ -1063,9 +1218,12 @@ struct BlendState {
   uint32_t *item_base;
   uint2 *items;
   uint32_t *bsum;
-  uint32_t *n_items;
+  uint32_t *n_items;  // [0] items; [1], [2] work and [3], [4] tile list counts of alternating windows
   ChunkRec *chunk;
   uint32_t *need_fix;
+  uint2 *work;
+  uint32_t *bsum0;
+  uint32_t *live[2];
   int64_t I;
 };
 
@@ -1085,34 +1243,64 @@ static BlendState carve_state(void *base, int64_t total_tiles, int64_t cap, int 
   s.chunk = (ChunkRec *)p;
   p += a256(sizeof(ChunkRec) * (size_t)s.I * tw * th);
   s.need_fix = (uint32_t *)p;
+  p += a256(4 * (size_t)s.I);
+  s.work = (uint2 *)p;
+  p += a256(8 * s.I);
+  s.bsum0 = (uint32_t *)p;
+  p += a256(4 * ((T + kItemChunk - 1) / kItemChunk + 1));
+  s.live[0] = (uint32_t *)p;
+  p += a256(4 * (size_t)T);
+  s.live[1] = (uint32_t *)p;
   return s;
 }
+
+// Compositing windows, in splats: chunks below kWin0 / BD first, then up to kWin1 / BD, then
+// the rest (each at least one chunk longer than the one before).
+constexpr uint32_t kWin0 = 512, kWin1 = 2048;
+constexpr unsigned kLateChunkGrid = 4096, kLateScanGrid = 2048;  // fixed grids of the later windows
 
 template <int TW, int TH, int BD, int NT, bool CNT>
 static hipError_t fwd_impl_cnt(const ViewTable &vt, const ImgTable &it, const gs_projected &p, const uint32_t *vals,
                                const uint32_t *range, const BlendState &s, hipStream_t st) {
   const uint32_t T = vt.total_tiles;
   const uint32_t nb = (T + kItemChunk - 1) / kItemChunk;
-  hipLaunchKernelGGL(k_items_reduce, dim3(nb), dim3(kItemThreads), 0, st, vt, range, BD, s.bsum);
-  hipLaunchKernelGGL(k_items_scan, dim3(1), dim3(1024), 0, st, s.bsum, nb, s.n_items, s.item_base, T);
-  hipLaunchKernelGGL(k_items_apply, dim3(nb), dim3(kItemThreads), 0, st, vt, range, BD, s.bsum, s.item_base, s.items,
-                     s.need_fix);
+  const uint32_t w0 = std::max<uint32_t>(1, kWin0 / BD), w1 = std::max<uint32_t>(w0 + 1, kWin1 / BD);
+  const uint32_t q_bounds[4] = {0u, w0, w1, 0xFFFFFFFFu};
+  uint32_t *n_work = s.n_items + 1;  // the first window's count is written by k_items_scan
+  hipLaunchKernelGGL(k_items_reduce, dim3(nb), dim3(kItemThreads), 0, st, vt, range, BD, w0, s.bsum, s.bsum0);
+  hipLaunchKernelGGL(k_items_scan, dim3(1), dim3(1024), 0, st, s.bsum, s.bsum0, nb, s.n_items, s.item_base, T,
+                     n_work);
+  hipLaunchKernelGGL(k_items_apply, dim3(nb), dim3(kItemThreads), 0, st, vt, range, BD, w0, (const uint32_t *)s.bsum,
+                     (const uint32_t *)s.bsum0, s.item_base, s.items, s.work, s.need_fix);
   // 8x8 tiles: two items per wavefront (rounded up to whole rounds of the XCD remap)
   constexpr bool kPair = TW == 8 && TH == 8;
   const int64_t r = (int64_t)kXcds * kGroup;
   const unsigned pairs = (unsigned)(((s.I + 1) / 2 + r - 1) / r * r);
-  if constexpr (kPair)
-    hipLaunchKernelGGL((k_blend_chunk_pair<BD, CNT>), dim3(pairs), dim3(64), 0, st, vt, it, (const Card *)p.card,
-                       vals, range, (const uint2 *)s.items, (const uint32_t *)s.n_items, s.chunk);
-  else
-    hipLaunchKernelGGL((k_blend_chunk<TW, TH, BD, NT, CNT>), dim3((unsigned)s.I), dim3(NT), 0, st, vt, it,
-                       (const Card *)p.card, vals, range,
-                       (const uint2 *)s.items, (const uint32_t *)s.n_items, s.chunk);
-  hipLaunchKernelGGL((k_blend_scan<TW, TH, BD>), dim3(T), dim3(TW * TH), 0, st, vt, it, range,
-                     (const uint32_t *)s.item_base, s.chunk, s.need_fix);
+  uint32_t *ctr = s.n_items;  // [1], [2]: work list counts; [3], [4]: tile list counts
+  for (int win = 0; win < 3; ++win) {
+    const int cur = win & 1, nxt = cur ^ 1;
+    if (win == 0 && kPair)
+      hipLaunchKernelGGL((k_blend_chunk_pair<BD, CNT>), dim3(pairs), dim3(64), 0, st, vt, it, (const Card *)p.card,
+                         vals, range, (const uint2 *)s.work, (const uint32_t *)(ctr + 1 + cur), ctr + 1 + nxt,
+                         ctr + 3 + nxt, (const uint32_t *)s.item_base, s.chunk);
+    else if (win == 0)
+      hipLaunchKernelGGL((k_blend_chunk<TW, TH, BD, NT, CNT, false>), dim3((unsigned)s.I), dim3(NT), 0, st, vt, it,
+                         (const Card *)p.card, vals, range, (const uint2 *)s.work, (const uint32_t *)(ctr + 1 + cur),
+                         ctr + 1 + nxt, ctr + 3 + nxt, (const uint32_t *)s.item_base, s.chunk);
+    else  // the later windows hold far fewer items: one item per workgroup (the latency of a
+          // two-item wavefront is not hidden there), walked by a fixed grid
+      hipLaunchKernelGGL((k_blend_chunk<TW, TH, BD, NT, CNT, true>), dim3(kLateChunkGrid), dim3(NT), 0, st, vt, it,
+                         (const Card *)p.card, vals, range, (const uint2 *)s.work, (const uint32_t *)(ctr + 1 + cur),
+                         ctr + 1 + nxt, ctr + 3 + nxt, (const uint32_t *)s.item_base, s.chunk);
+    hipLaunchKernelGGL((k_blend_scan<TW, TH, BD>), dim3(win == 0 ? T : kLateScanGrid), dim3(TW * TH), 0, st, vt, it,
+                       range, (const uint32_t *)s.item_base, s.chunk, s.need_fix, q_bounds[win], q_bounds[win + 1],
+                       q_bounds[std::min(win + 2, 3)], s.work, ctr + 1 + nxt,
+                       win == 0 ? (const uint32_t *)nullptr : (const uint32_t *)s.live[cur],
+                       (const uint32_t *)(ctr + 3 + cur), s.live[nxt], ctr + 3 + nxt);
+  }
   hipLaunchKernelGGL((k_blend_fix<TW, TH, BD, NT, CNT>), dim3((unsigned)s.I), dim3(NT), 0, st, vt, it,
-                     (const Card *)p.card, vals, range,
-                     (const uint2 *)s.items, (const uint32_t *)s.n_items, (const uint32_t *)s.need_fix, s.chunk);
+                     (const Card *)p.card, vals, range, (const uint2 *)s.items, (const uint32_t *)s.n_items,
+                     (const uint32_t *)s.need_fix, s.chunk);
   hipLaunchKernelGGL((k_blend_suffix<TW, TH, BD>), dim3(T), dim3(TW * TH), 0, st, vt, it, range,
                      (const uint32_t *)s.item_base, s.chunk);
   return hipGetLastError();
