@@ -226,8 +226,8 @@ int enqueue_backward(const gs::ViewTable &vt, const gs_gaussians &g, const gs_pr
       max_m = std::max(max_m, io[i].lidar.m);
     }
   }
-  if (any_map) GS_TRY_HIP(gs::launch_grad_maps(src, dst, nv, max_npx, lt, it, max_m, st), "lidar/gradient maps");
-  GS_TRY_HIP(gs::zero_f32(s.g2, 12 * vt.n * nv, st), "zero grad2d");
+  GS_TRY_HIP(gs::launch_bwd_prep(s.g2, 12 * vt.n * nv, src, dst, nv, any_map ? max_npx : 0, lt, it, max_m, st),
+             "grad2d and gradient maps");
   gs::profile_begin(GS_STAGE_BLEND_BWD, st);
   GS_TRY_HIP(gs::launch_blend_bwd(bd, vt, it, gtab, p, vals, range, state, cap, s.g2, st, out.schedule),
              "blend backward");

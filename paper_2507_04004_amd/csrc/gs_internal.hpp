@@ -37,9 +37,10 @@ hipError_t launch_blend_bwd(int bd, const ViewTable &vt, const ImgTable &it, con
                             const gs_projected &p, const uint32_t *vals, const uint32_t *range, void *state,
                             int64_t cap, float *g2, hipStream_t st, int schedule = GS_BWD_CHUNKS);
 hipError_t launch_lidar_loss(const LidarTable &lt, const ImgTable &it, int max_m, hipStream_t st);
-hipError_t launch_grad_maps(const MapSrc &src, const MapTable &dst, int n_views, int64_t max_npx,
-                            const LidarTable &lt, const ImgTable &it, int max_m, hipStream_t st);
-hipError_t zero_f32(float *p, int64_t n, hipStream_t st);
+// grad2d (n floats) zeroed, the views' dense gradient maps set (max_npx 0: none), the LiDAR
+// term's gradient added to them.
+hipError_t launch_bwd_prep(float *g2, int64_t n, const MapSrc &src, const MapTable &dst, int n_views, int64_t max_npx,
+                           const LidarTable &lt, const ImgTable &it, int max_m, hipStream_t st);
 hipError_t launch_loss_l1(const float *c, const float *t, int64_t n, float weight, float *dldc, float *loss,
                           hipStream_t st);
 

@@ -59,13 +59,27 @@ __global__ __launch_bounds__(256) void k_lidar_grad(LidarTable lt, ImgTable it, 
   mt.gO[vi][p] += -s * D / (O * O);
 }
 
-// Dense gradient maps = user-given planes (or zero), before the LiDAR term is added.
-__global__ __launch_bounds__(256) void k_init_maps(MapSrc src, MapTable dst) {
-  const int vi = blockIdx.y;
-  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (i >= src.npx[vi]) return;
-  if (dst.gD[vi]) dst.gD[vi][i] = src.gD[vi] ? src.gD[vi][i] : 0.f;
-  if (dst.gO[vi]) dst.gO[vi][i] = src.gO[vi] ? src.gO[vi][i] : 0.f;
+// Backward preparation in one pass: grad2d (n floats, float4 stores when vec) zeroed and the
+// dense gradient maps of the views set to the caller's planes (or zero), before the LiDAR
+// term is added.
+__global__ __launch_bounds__(256) void k_bwd_prep(float *__restrict__ g2, int64_t n, int vec, MapSrc src,
+                                                  MapTable dst, int n_views, int64_t max_npx) {
+  const int64_t stride = (int64_t)gridDim.x * 256;
+  const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (vec) {
+    float4 *g4 = reinterpret_cast<float4 *>(g2);
+    for (int64_t i = t; i < n / 4; i += stride) g4[i] = make_float4(0.f, 0.f, 0.f, 0.f);
+  } else {
+    for (int64_t i = t; i < n; i += stride) g2[i] = 0.f;
+  }
+  const int64_t total = (int64_t)n_views * max_npx;
+  for (int64_t j = t; j < total; j += stride) {
+    const int vi = (int)(j / max_npx);
+    const int64_t i = j - (int64_t)vi * max_npx;
+    if (i >= src.npx[vi]) continue;
+    if (dst.gD[vi]) dst.gD[vi][i] = src.gD[vi] ? src.gD[vi][i] : 0.f;
+    if (dst.gO[vi]) dst.gO[vi][i] = src.gO[vi] ? src.gO[vi][i] : 0.f;
+  }
 }
 
 // ---- RGB L1 term ---------------------------------------------------------------------------
@@ -130,19 +144,15 @@ hipError_t launch_lidar_loss(const LidarTable &lt, const ImgTable &it, int max_m
   return hipGetLastError();
 }
 
-hipError_t launch_grad_maps(const MapSrc &src, const MapTable &dst, int n_views, int64_t max_npx, const LidarTable &lt,
-                            const ImgTable &it, int max_m, hipStream_t st) {
-  hipLaunchKernelGGL(k_init_maps, dim3((unsigned)((max_npx + 255) / 256), (unsigned)n_views), dim3(256), 0, st, src,
-                     dst);
+hipError_t launch_bwd_prep(float *g2, int64_t n, const MapSrc &src, const MapTable &dst, int n_views, int64_t max_npx,
+                           const LidarTable &lt, const ImgTable &it, int max_m, hipStream_t st) {
+  const int vec = (reinterpret_cast<uintptr_t>(g2) & 15u) == 0 && n % 4 == 0;
+  const int64_t work = std::max<int64_t>(vec ? n / 4 : n, (int64_t)n_views * max_npx);
+  const int64_t blocks = std::min<int64_t>(std::max<int64_t>((work + 255) / 256, 1), 8192);
+  hipLaunchKernelGGL(k_bwd_prep, dim3((unsigned)blocks), dim3(256), 0, st, g2, n, vec, src, dst, n_views, max_npx);
   if (max_m > 0)
     hipLaunchKernelGGL(k_lidar_grad, dim3((unsigned)((max_m + 255) / 256), (unsigned)lt.n_views), dim3(256), 0, st,
                        lt, it, dst);
-  return hipGetLastError();
-}
-
-hipError_t zero_f32(float *p, int64_t n, hipStream_t st) {
-  if (n <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_zero_f32, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, p, n);
   return hipGetLastError();
 }
 
