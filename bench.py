@@ -723,9 +723,10 @@ def main():
     cnt_frame = R.Frame.empty(cam.h, cam.w, dev, count=True)
     R.render_fwd(ps.spl, ps.n, ps.bins, ps.cs, args.blend_depth, dev, out=cnt_frame)
     torch.cuda.synchronize()
-    # evaluations: the forward walks each tile's whole list for every pixel of the tile (every
-    # tile of this scene keeps a pixel below the stop threshold); the backward walks each
-    # pixel's list from its last contributor to the front
+    # evaluations: the forward count takes every splat of a tile's list for every pixel of the
+    # tile (an upper bound: pixels stop early, and the forward skips the later chunks of a tile
+    # whose pixels have all stopped); the backward walks each pixel's list from its last
+    # contributor to the front
     tr = ps.bins.tile_range.view(-1, 2).long()
     lens = (tr[:, 1] - tr[:, 0]).cpu().numpy()
     tx, ty = (cam.w + args.tile - 1) // args.tile, (cam.h + args.tile - 1) // args.tile
