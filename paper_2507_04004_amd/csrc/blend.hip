@@ -20,7 +20,8 @@
 //      at the chunk in which the pixel stops it records the incoming state.
 //   Passes 1 and 2 run in three windows of chunks (the first kWin0 splats of every list, up
 //   to kWin1, the rest): a window's chunks are composited only for the tiles in which some
-//   pixel was still running at the end of the previous window.
+//   pixel was still running at the end of the previous window. With a pair capacity too small
+//   for long lists one window takes every chunk.
 //   3. k_blend_fix (one workgroup per chunk, in parallel) composites each pixel's stop chunk
 //      again record by record from the true incoming transmittance, which applies the stop
 //      rule exactly.
@@ -1224,13 +1225,14 @@ struct BlendState {
   uint2 *work;
   uint32_t *bsum0;
   uint32_t *live[2];
-  int64_t I;
+  int64_t I, cap;
 };
 
 static BlendState carve_state(void *base, int64_t total_tiles, int64_t cap, int tw, int th, int bd) {
   const int64_t T = std::max<int64_t>(total_tiles, 1);
   BlendState s;
   s.I = max_items(T, cap, bd);
+  s.cap = cap;
   char *p = (char *)base;
   s.item_base = (uint32_t *)p;
   p += a256(4 * (T + 1));
@@ -1264,7 +1266,11 @@ static hipError_t fwd_impl_cnt(const ViewTable &vt, const ImgTable &it, const gs
                                const uint32_t *range, const BlendState &s, hipStream_t st) {
   const uint32_t T = vt.total_tiles;
   const uint32_t nb = (T + kItemChunk - 1) / kItemChunk;
-  const uint32_t w0 = std::max<uint32_t>(1, kWin0 / BD), w1 = std::max<uint32_t>(w0 + 1, kWin1 / BD);
+  // the later windows cost four more launches: they are enqueued only when the pair capacity
+  // allows tile lists that average more than kWin0 / 2 splats (else one window takes all)
+  const int n_win = s.cap > (int64_t)T * (kWin0 / 2) ? 3 : 1;
+  const uint32_t w0 = n_win == 1 ? 0xFFFFFFFFu : std::max<uint32_t>(1, kWin0 / BD);
+  const uint32_t w1 = n_win == 1 ? 0xFFFFFFFFu : std::max<uint32_t>(w0 + 1, kWin1 / BD);
   const uint32_t q_bounds[4] = {0u, w0, w1, 0xFFFFFFFFu};
   uint32_t *n_work = s.n_items + 1;  // the first window's count is written by k_items_scan
   hipLaunchKernelGGL(k_items_reduce, dim3(nb), dim3(kItemThreads), 0, st, vt, range, BD, w0, s.bsum, s.bsum0);
@@ -1277,7 +1283,7 @@ static hipError_t fwd_impl_cnt(const ViewTable &vt, const ImgTable &it, const gs
   const int64_t r = (int64_t)kXcds * kGroup;
   const unsigned pairs = (unsigned)(((s.I + 1) / 2 + r - 1) / r * r);
   uint32_t *ctr = s.n_items;  // [1], [2]: work list counts; [3], [4]: tile list counts
-  for (int win = 0; win < 3; ++win) {
+  for (int win = 0; win < n_win; ++win) {
     const int cur = win & 1, nxt = cur ^ 1;
     if (win == 0 && kPair)
       hipLaunchKernelGGL((k_blend_chunk_pair<BD, CNT>), dim3(pairs), dim3(64), 0, st, vt, it, (const Card *)p.card,

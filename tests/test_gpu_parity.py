@@ -311,8 +311,13 @@ def test_edge_cases():
     # every Gaussian behind the camera
     behind = g.subset(np.arange(g.n))
     behind.mean[2] *= -1
-    img = HipRun(behind, cam).image()
-    assert np.all(img["alpha"] == 0)
+    run_b = HipRun(behind, cam)
+    img = run_b.image()
+    assert np.all(img["alpha"] == 0) and np.all(img["last"] == -1)
+    assert run_b.bins_np()["num_pairs"] == 0  # no record survives the first depth pass
+    gr = run_b.backward(np.ones((3, cam.h, cam.w), np.float32), overwrite=True)
+    for k in ("mean", "opacity", "sh_dc", "pose"):
+        assert np.all(np.asarray(gr[k]) == 0), k
     # degenerate Gaussians are dropped, the rest render as without them
     bad = g.subset(np.arange(50))
     bad.rot[:, 0] = 0.0
