@@ -121,9 +121,12 @@ typedef struct gs_bins {
  * pixel's tile list, of the last Gaussian blended (-1 if none). n_contrib [h][w] int32 is
  * optional (NULL = not written): the number of Gaussians blended at each pixel.
  * state: device scratch of at least gs_image_state_bytes(...) bytes holding the chunk work
- * list and, per (chunk, pixel) of tiles longer than one chunk, the transmittance and the
+ * lists and, per (chunk, pixel) of tiles longer than one chunk, the transmittance and the
  * composited colour behind the chunk (the backward's starting state). Written by
- * gs_render_fwd, read by gs_render_bwd; the same bins and blend_depth must be passed to both. */
+ * gs_render_fwd, read by gs_render_bwd; the same bins and blend_depth must be passed to both.
+ * While gs_render_fwd's work runs, the planes of a pixel that is still compositing hold its
+ * running state (the forward walks long tile lists in windows); they are final when the
+ * call's work on the stream has completed. */
 typedef struct gs_image {
   float *color, *depth, *alpha, *t_final;
   int32_t *last;
