@@ -366,7 +366,7 @@ __global__ __launch_bounds__(kScanThreads) void k_emit_pairs(ViewTable vt, const
 
 // One wavefront per large rectangle (grid-stride over the list): the wavefront tests 64
 // tiles per step and compacts the kept ones with a ballot.
-constexpr int kBigBlocks = 2048;
+constexpr int kBigBlocks = 8192;  // more wavefronts than large rectangles at the headline view (32 k, 18.8 k)
 __global__ __launch_bounds__(kScanThreads) void k_emit_big(ViewTable vt, const Card *__restrict__ card,
                                                            const uint32_t *__restrict__ big_e,
                                                            const uint32_t *__restrict__ big_off,
