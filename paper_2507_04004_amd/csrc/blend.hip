@@ -1062,6 +1062,8 @@ __global__ __launch_bounds__(64) void k_blend_bwd_bucket(ViewTable vt, ImgTable 
   __shared__ float sTfG[NPIX], sGC0[NPIX], sGC1[NPIX], sGC2[NPIX], sGD[NPIX];
   __shared__ int sLL[NPIX];
   __shared__ int s_list[NPIX];  // pixels that can have a contributor in the current bucket
+  __shared__ float s_g[NT * 10];  // the bucket's ten sums per splat, for the transposed atomics
+  __shared__ uint32_t s_rec[NT];
   __shared__ int s_max;
   uint32_t item;
   if (!item_of_block(n_items, item)) return;
@@ -1180,11 +1182,20 @@ __global__ __launch_bounds__(64) void k_blend_bwd_bucket(ViewTable vt, ImgTable 
       g[3] += dpx * dy;
       g[4] += dpy * dy;
     }
-    if (j >= 0) {
-      const int64_t base = (int64_t)__float_as_uint(Cc.w) * 12;
+    // the lanes' sums leave through LDS, transposed: each atomic instruction then covers the
+    // ten consecutive values of six or seven splats' records instead of one value in each of
+    // 64 records, so its updates fall on a few memory lines
+    __syncthreads();  // the previous bucket's reads of s_g are done
 #pragma unroll
-      for (int v = 0; v < 10; ++v)
-        if (g[v] != 0.f) unsafeAtomicAdd(&g2[base + v], g[v]);
+    for (int v = 0; v < 10; ++v) s_g[lane * 10 + v] = g[v];
+    s_rec[lane] = j >= 0 ? __float_as_uint(Cc.w) : 0xFFFFFFFFu;
+    __syncthreads();
+#pragma unroll
+    for (int i = lane; i < NT * 10; i += NT) {
+      const int sl = i / 10, v = i - sl * 10;
+      const uint32_t rec = s_rec[sl];
+      const float val = s_g[i];
+      if (rec != 0xFFFFFFFFu && val != 0.f) unsafeAtomicAdd(&g2[(int64_t)rec * 12 + v], val);
     }
   }
 }
