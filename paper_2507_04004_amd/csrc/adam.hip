@@ -25,6 +25,8 @@ __device__ __forceinline__ float act_slope(float a, int act) {
   return 1.0f;
 }
 
+constexpr int kAdamBatch = 8;  // planes whose loads are in flight together
+
 __global__ __launch_bounds__(256) void k_adam_sparse(AdamArgs a) {
   const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
   const bool in = i < a.n;
@@ -34,21 +36,37 @@ __global__ __launch_bounds__(256) void k_adam_sparse(AdamArgs a) {
   if (!__any(reached)) return;  // uniform per wavefront
   if (!in) return;
   const Planes P(a.n, (uint32_t)i);
+  // Planes are taken kAdamBatch at a time, every load of a batch issued before its first
+  // store: the buffer stores may alias any plane, so a load placed after a store waits for it,
+  // and one plane per round trip would leave a wavefront with four loads in flight.
   for (int gi = 0; gi < a.n_groups; ++gi) {
     const AdamGroupDev &G = a.group[gi];
-#pragma unroll 4
-    for (int j = 0; j < G.k; ++j) {
-      float p = P.ld(G.param, j), m = P.ld(G.exp_avg, j), v = P.ld(G.exp_avg_sq, j);
-      if (reached) {
-        const float g = P.ld(G.grad, j) * act_slope(act_value(p, G.act), G.act);
-        m = a.beta1 * m + (1.0f - a.beta1) * g;
-        v = a.beta2 * v + (1.0f - a.beta2) * (g * g);
-        p = p - G.step_size * m / (sqrtf(v) / a.sqrt_bias2 + a.eps);
-        if (G.act_out) P.st(G.act_out, j, act_value(p, G.act));
+    for (int j0 = 0; j0 < G.k; j0 += kAdamBatch) {
+      const int nb = min(kAdamBatch, G.k - j0);  // uniform
+      float p[kAdamBatch], m[kAdamBatch], v[kAdamBatch], g[kAdamBatch];
+#pragma unroll
+      for (int u = 0; u < kAdamBatch; ++u) {
+        if (u < nb) {
+          p[u] = P.ld(G.param, j0 + u);
+          m[u] = P.ld(G.exp_avg, j0 + u);
+          v[u] = P.ld(G.exp_avg_sq, j0 + u);
+          g[u] = reached ? P.ld(G.grad, j0 + u) : 0.f;
+        }
       }
-      P.st(G.param, j, p);
-      P.st(G.exp_avg, j, m);
-      P.st(G.exp_avg_sq, j, v);
+#pragma unroll
+      for (int u = 0; u < kAdamBatch; ++u) {
+        if (u >= nb) break;
+        if (reached) {
+          const float gr = g[u] * act_slope(act_value(p[u], G.act), G.act);
+          m[u] = a.beta1 * m[u] + (1.0f - a.beta1) * gr;
+          v[u] = a.beta2 * v[u] + (1.0f - a.beta2) * (gr * gr);
+          p[u] = p[u] - G.step_size * m[u] / (sqrtf(v[u]) / a.sqrt_bias2 + a.eps);
+          if (G.act_out) P.st(G.act_out, j0 + u, act_value(p[u], G.act));
+        }
+        P.st(G.param, j0 + u, p[u]);
+        P.st(G.exp_avg, j0 + u, m[u]);
+        P.st(G.exp_avg_sq, j0 + u, v[u]);
+      }
     }
   }
 }

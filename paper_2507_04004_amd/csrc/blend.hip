@@ -219,12 +219,7 @@ __device__ __forceinline__ void stage(const uint32_t *__restrict__ vals, uint32_
   // up to the next multiple of kGroupLen: records of opacity 0 (alpha 0, never blended), so
   // the compositing loop runs whole groups
   const int padded = min(BD, (cnt + kGroupLen - 1) / kGroupLen * kGroupLen);
-  for (int k = cnt + (int)threadIdx.x; k < padded; k += NT) {
-    const float4 z = make_float4(0.f, 0.f, 0.f, 0.f);
-    s_a[k] = z;
-    s_b[k] = z;
-    s_c[k] = z;
-  }
+  for (int k = cnt + (int)threadIdx.x; k < padded; k += NT) stage_empty(s_a[k], s_b[k], s_c[k]);
 }
 
 __device__ __forceinline__ void write_pixel(const ViewImg &im, const ViewCam &cam, int64_t pi, int64_t npx, float C0,
@@ -261,9 +256,8 @@ __device__ __forceinline__ void composite_splat(const float4 &A, const float4 &B
 #pragma unroll
   for (int k = 0; k < PPT; ++k) {
     PixState &p = st[k];
-    float m, qc;
-    const float p2 = splat_p2(A, B, px[k] - A.x, py[k] - A.y, m, qc);
-    const float alpha = fminf(kAlphaMax, B.y * splat_e2(p2));
+    const float p2 = splat_p2(A, B, px[k] - A.x, py[k] - A.y);
+    const float alpha = fminf(kAlphaMax, splat_e2(p2));
     const float wt = alpha * p.T;  // the weight, and T's decrement: T (1 - alpha) = T - alpha T
     const float Tn = p.T - wt;
     // take = !stopped && alpha_ok && !low, written through the updated stop flag so that the
@@ -675,7 +669,8 @@ __device__ __forceinline__ void stage_half(const uint32_t *__restrict__ vals, co
 #pragma unroll
   for (int r = 0; r < 2; ++r) {
     const int kk = hl + 32 * r;
-    float4 sa = make_float4(0.f, 0.f, 0.f, 0.f), sb = sa, sc = sa;
+    float4 sa, sb, sc;
+    stage_empty(sa, sb, sc);
     if (base + kk < cnt) {
       const Card &cd = card[vals[cs + base + kk]];
       stage_card(cd.a, cd.b, cd.c, sa, sb, sc);
@@ -815,10 +810,11 @@ __device__ __forceinline__ float dpp(float v) {
 //   1. row_mirror pairs lane i with 15 - i (bit 3 differs). Two DPP adds per output, each
 //      writing half of the banks: lanes with bit 3 clear keep slots 0-4, the others 5-9.
 //   2. row_half_mirror pairs i with 7 - i (bit 2 differs): bit 2 clear keeps the first three
-//      of its five slots, set keeps the last two (its third output is 0).
+//      of its five slots, set keeps the last two (its third output is left unwritten there:
+//      the later steps never move it into a lane that holds a result).
 //   3. permlane16 swaps add row pairs (0+1, 2+3) of two outputs in one register, and of the
 //      third in another; a permlane32 swap adds the halves: row 0 then holds output 0, row 1
-//      output 1, rows 2 and 3 output 2, each summed over the four rows.
+//      output 1, row 2 output 2, each summed over the four rows (row 3: nothing of use).
 //   4. two quad DPP adds sum the four lanes of a quad (bits 0 and 1).
 // Afterwards lane l holds the total of value reduce10_slot(l) (-1: nothing to store).
 // The DPP sources are written by ordinary VALU code just before each block, hence the two
@@ -843,7 +839,6 @@ __device__ __forceinline__ float wave_reduce10(const float (&g)[10]) {
   float b0, b1, b2;
   asm volatile(
       "s_nop 1\n"
-      "v_mov_b32 %2, 0\n"
       "v_add_f32_dpp %0, %3, %3 row_half_mirror row_mask:0xf bank_mask:0x5\n"
       "v_add_f32_dpp %0, %6, %6 row_half_mirror row_mask:0xf bank_mask:0xa\n"
       "v_add_f32_dpp %1, %4, %4 row_half_mirror row_mask:0xf bank_mask:0x5\n"
@@ -853,7 +848,9 @@ __device__ __forceinline__ float wave_reduce10(const float (&g)[10]) {
       : "v"(a0), "v"(a1), "v"(a2), "v"(a3), "v"(a4));
   const auto p01 = __builtin_amdgcn_permlane16_swap(__float_as_uint(b0), __float_as_uint(b1), false, false);
   const float r01 = __uint_as_float(p01[0]) + __uint_as_float(p01[1]);
-  const auto p22 = __builtin_amdgcn_permlane16_swap(__float_as_uint(b2), __float_as_uint(b2), false, false);
+  // b2's second operand is a spent register: rows 1 and 3 of the sum then hold its rows, which
+  // only reach row 3 of the result, where no value is read
+  const auto p22 = __builtin_amdgcn_permlane16_swap(__float_as_uint(b2), __float_as_uint(a0), false, false);
   const float r22 = __uint_as_float(p22[0]) + __uint_as_float(p22[1]);
   const auto q = __builtin_amdgcn_permlane32_swap(__float_as_uint(r01), __float_as_uint(r22), false, false);
   float v = __uint_as_float(q[0]) + __uint_as_float(q[1]);
@@ -890,7 +887,8 @@ struct PixGrad {
 //   2: sum dp dx^2                   -> dL/da = -slot / 2
 //   3: sum dp dx dy                  -> dL/db = -slot
 //   4: sum dp dy^2                   -> dL/dc = -slot / 2
-//   5: dL/do;  6-8: dL/d(r, g, b);  9: dL/d(depth)
+//   5: sum dp                        -> dL/do = slot / o
+//   6-8: dL/d(r, g, b);  9: dL/d(depth)
 // with dp = dL/dpower = dL/dalpha * o exp(power) (zero where alpha is clamped at 0.99) and
 // (a, b, c) the unscaled conic.
 // Splats hi down to lo of the chunk, back to front, for the pixels of this lane; splat j is
@@ -899,20 +897,23 @@ struct PixGrad {
 template <int PPT, bool DEPTH>
 __device__ __forceinline__ void bwd_splats(int hi, int lo, const float4 *s_a, const float4 *s_b, const float4 *s_c,
                                            PixGrad (&pg)[PPT], int slot, float *__restrict__ g2) {
-  for (int j = hi; j >= lo; --j) {
-    const float4 A = s_a[j - lo], B = s_b[j - lo], Cc = s_c[j - lo];
+  // the staged record's byte offset lives in a vector register: the LDS reads take their
+  // address from one, and a scalar index would be copied over twice per splat
+  int off = (hi - lo) * (int)sizeof(float4);
+  for (int j = hi; j >= lo; --j, off -= (int)sizeof(float4)) {
+    asm volatile("" : "+v"(off));
+    const float4 A = *reinterpret_cast<const float4 *>(reinterpret_cast<const char *>(s_a) + off);
+    const float4 B = *reinterpret_cast<const float4 *>(reinterpret_cast<const char *>(s_b) + off);
+    const float4 Cc = *reinterpret_cast<const float4 *>(reinterpret_cast<const char *>(s_c) + off);
     // alpha at every pixel first; a splat no pixel of the wavefront blends costs only this
-    float dxs[PPT], dys[PPT], exs[PPT], ars[PPT];
+    float dxs[PPT], dys[PPT], ars[PPT];
     bool act[PPT];
     bool any = false;
 #pragma unroll
     for (int k = 0; k < PPT; ++k) {
-      float ms, qcs;
       dxs[k] = pg[k].px - A.x;
       dys[k] = pg[k].py - A.y;
-      const float p2 = splat_p2(A, B, dxs[k], dys[k], ms, qcs);
-      exs[k] = splat_e2(p2);
-      ars[k] = B.y * exs[k];
+      ars[k] = splat_e2(splat_p2(A, B, dxs[k], dys[k]));
       act[k] = j <= pg[k].ll && fminf(kAlphaMax, ars[k]) >= kAlphaMin;
       any = any || act[k];
     }
@@ -942,7 +943,7 @@ __device__ __forceinline__ void bwd_splats(int hi, int lo, const float4 *s_a, co
       const float dp = dm * ars[k];
       const float dpx = dp * dxs[k], dpy = dp * dys[k];
       const float t[10] = {dpx,          dpy,          dpx * dxs[k], dpx * dys[k], dpy * dys[k],
-                           dm * exs[k],  p.gC0 * w,    p.gC1 * w,    p.gC2 * w,    t9};
+                           dp,           p.gC0 * w,    p.gC1 * w,    p.gC2 * w,    t9};
 #pragma unroll
       for (int v = 0; v < 10; ++v) g[v] = k == 0 ? t[v] : g[v] + t[v];
     }
@@ -1150,10 +1151,7 @@ __global__ __launch_bounds__(64) void k_blend_bwd_bucket(ViewTable vt, ImgTable 
       const int q = s_list[r];
       const float px = x0 + (float)(q % TW), py = y0 + (float)(q / TW);
       const float dx = px - A.x, dy = py - A.y;
-      float m, qc;
-      const float p2 = splat_p2(A, B, dx, dy, m, qc);
-      const float ex = splat_e2(p2);
-      const float ar = B.y * ex;
+      const float ar = splat_e2(splat_p2(A, B, dx, dy));
       const bool act = j <= sLL[q] && fminf(kAlphaMax, ar) >= kAlphaMin;
       // a pixel this splat does not reach takes alpha 0 and its state stays as it is
       if (!act) continue;
@@ -1173,8 +1171,8 @@ __global__ __launch_bounds__(64) void k_blend_bwd_bucket(ViewTable vt, ImgTable 
       sT[q] = T;
       const float dLda = fmaf(T, fmaf(gD, rd, rc), inv * sTfG[q]);
       const float dm = ar < kAlphaMax ? dLda : 0.f;  // clamped alpha: no power path
-      g[5] += dm * ex;
       const float dp = dm * ar;
+      g[5] += dp;
       const float dpx = dp * dx, dpy = dp * dy;
       g[0] += dpx;
       g[1] += dpy;

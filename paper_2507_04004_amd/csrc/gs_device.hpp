@@ -106,32 +106,37 @@ __device__ __forceinline__ int view_of_tile(const ViewTable &vt, uint32_t gt) {
 }
 
 // Compositing form of a splat, staged once per chunk: the conic is pre-scaled so that the
-// exponent comes out in base 2 (alpha = o 2^p, p = log2(e) * (-q/2)) with the -1/2 folded in:
-//   sa = (u, v, a', b'), sb = (c', o, d, b'/2), with a' = kA a, b' = 2 kA b, c' = kA c,
-//   kA = -log2(e) / 2.
-// p = dx (a' dx + b' dy) + c' dy^2 <= 0 in exact arithmetic; splat_e2 returns 2^p clamped to
-// at most 1, which equals 2^min(p, 0) and so absorbs the rounding that can leave p slightly
-// positive. The forward and the backward both evaluate it through splat_p2 and splat_e2,
-// with fixed FMA placement, so they take identical alpha decisions.
+// exponent comes out in base 2 with the -1/2 folded in, and the opacity enters the exponent
+// as its base-2 logarithm (alpha = o exp(-q/2) = 2^p, p = log2(e) (-q/2) + log2 o):
+//   sa = (u, v, a', b'), sb = (c', log2 o, d, b'/2), with a' = kA a, b' = 2 kA b, c' = kA c,
+//   kA = -log2(e) / 2, and log2 o = -inf for o <= 0 (and for the padding records).
+// p = dx (a' dx + b' dy) + c' dy^2 + log2 o <= log2 o in exact arithmetic; splat_e2 returns
+// 2^p clamped to [0, 1]. The forward and the backward both evaluate it through splat_p2 and
+// splat_e2, with fixed FMA placement, so they take identical alpha decisions.
 constexpr float kA = -0.72134752044448170368f;  // -log2(e) / 2
 
 __device__ __forceinline__ void stage_card(const float4 &A, const float4 &B, const float4 &C, float4 &sa, float4 &sb,
                                            float4 &sc) {
   const float bp = (2.0f * kA) * B.y;
   sa = make_float4(A.x, A.y, kA * B.x, bp);
-  sb = make_float4(kA * B.z, A.z, A.w, 0.5f * bp);
+  sb = make_float4(kA * B.z, A.z > 0.0f ? log2f(A.z) : -INFINITY, A.w, 0.5f * bp);
   sc = C;
 }
 
-// Exponent p at pixel offset (dx, dy); also returns a' dx and c' dy for the backward.
-__device__ __forceinline__ float splat_p2(const float4 &sa, const float4 &sb, float dx, float dy, float &m,
-                                          float &qc) {
+// Exponent p at pixel offset (dx, dy), the opacity's logarithm included.
+__device__ __forceinline__ float splat_p2(const float4 &sa, const float4 &sb, float dx, float dy) {
 #pragma clang fp contract(off)
-  m = sa.z * dx;
+  const float m = sa.z * dx;
   const float t = fmaf(sa.w, dy, m);
-  qc = sb.x * dy;
-  const float q = qc * dy;
+  const float q = fmaf(sb.x * dy, dy, sb.y);
   return fmaf(dx, t, q);
+}
+
+// A staged record that no pixel blends (alpha 0 everywhere): the padding of a chunk.
+__device__ __forceinline__ void stage_empty(float4 &sa, float4 &sb, float4 &sc) {
+  sa = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+  sb = make_float4(0.0f, -INFINITY, 0.0f, 0.0f);
+  sc = sa;
 }
 
 // 2^p clamped to [0, 1] (the median with 0 and 1 becomes the clamp bit of the exp instruction).

@@ -337,8 +337,8 @@ __global__ __launch_bounds__(256) void k_preprocess(ViewTable vt, const float *_
 // ---------------------------------------------------------------------------------------------
 // Stage a5: chain rule from the 2D quantities to the parameters and the pose.
 // grad2d records [E][12] (48 B, last two unused), as the compositing backward leaves them:
-// sums over pixels of dp dx, dp dy, dp dx^2, dp dx dy, dp dy^2 (the conic and the constant
-// factors are applied below), then dL/do, dL/d(r, g, b), dL/d(depth).
+// sums over pixels of dp dx, dp dy, dp dx^2, dp dx dy, dp dy^2 and dp (the conic, the
+// constant factors and the opacity are applied below), then dL/d(r, g, b), dL/d(depth).
 // ---------------------------------------------------------------------------------------------
 struct ParamGradOut {
   float *mean, *scale, *rot, *opacity, *sh_dc, *sh_rest;
@@ -645,7 +645,9 @@ __global__ __launch_bounds__(256) void k_geo_bwd(ViewTable vt, const float *__re
       // dp dx^2, dp dx dy, dp dy^2 (dp = dL/dp of the base-2 exponent p = kA q)
       const float a = s.a, b = s.b, c = s.c;
       const float gu = a * G[0] + b * G[1], gv = b * G[0] + c * G[1];
-      const float ga = -0.5f * G[2], gb = -G[3], gc = -0.5f * G[4], go = G[5];
+      // dalpha/do = alpha / o: slot 5 sums dp = dL/dalpha alpha over the pixels (a splat of
+      // opacity 0 reaches no pixel, and its slot stays 0)
+      const float ga = -0.5f * G[2], gb = -G[3], gc = -0.5f * G[4], go = o > 0.f ? G[5] / o : 0.f;
       const float gd = G[9];
       // conic -> Sigma': G_S = -Q Ghat Q, Ghat = [[ga, gb/2], [gb/2, gc]]
       const float hb = 0.5f * gb;
