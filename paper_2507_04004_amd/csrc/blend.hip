@@ -179,6 +179,7 @@ __global__ __launch_bounds__(kItemThreads) void k_items_apply(ViewTable vt, cons
 template <int TW, int TH, int NT>
 struct TileCtx {
   static constexpr int PPT = TW * TH / NT;
+  static_assert(NT % TW == 0, "a lane's pixels share a column (pixel k of a lane is k NT further)");
   int vi, tx, ty;
   int64_t npx;
   const ViewCam *cam;
@@ -253,11 +254,11 @@ template <int PPT, bool CNT>
 __device__ __forceinline__ void composite_splat(const float4 &A, const float4 &B, const float4 &Cc, int u,
                                                 const float (&px)[PPT], const float (&py)[PPT],
                                                 PixState (&st)[PPT], bool (&took)[PPT]) {
+  const SplatCol col = splat_col(A, B, px[0] - A.x);  // the lane's pixels share a column
 #pragma unroll
   for (int k = 0; k < PPT; ++k) {
     PixState &p = st[k];
-    const float p2 = splat_p2(A, B, px[k] - A.x, py[k] - A.y);
-    const float alpha = fminf(kAlphaMax, splat_e2(p2));
+    const float alpha = fminf(kAlphaMax, splat_e2(splat_p2(B, col, py[k] - A.y)));
     const float wt = alpha * p.T;  // the weight, and T's decrement: T (1 - alpha) = T - alpha T
     const float Tn = p.T - wt;
     // take = !stopped && alpha_ok && !low, written through the updated stop flag so that the
@@ -909,11 +910,12 @@ __device__ __forceinline__ void bwd_splats(int hi, int lo, const float4 *s_a, co
     float dxs[PPT], dys[PPT], ars[PPT];
     bool act[PPT];
     bool any = false;
+    const SplatCol col = splat_col(A, B, pg[0].px - A.x);  // the lane's pixels share a column
 #pragma unroll
     for (int k = 0; k < PPT; ++k) {
       dxs[k] = pg[k].px - A.x;
       dys[k] = pg[k].py - A.y;
-      ars[k] = splat_e2(splat_p2(A, B, dxs[k], dys[k]));
+      ars[k] = splat_e2(splat_p2(B, col, dys[k]));
       act[k] = j <= pg[k].ll && fminf(kAlphaMax, ars[k]) >= kAlphaMin;
       any = any || act[k];
     }
@@ -1151,7 +1153,7 @@ __global__ __launch_bounds__(64) void k_blend_bwd_bucket(ViewTable vt, ImgTable 
       const int q = s_list[r];
       const float px = x0 + (float)(q % TW), py = y0 + (float)(q / TW);
       const float dx = px - A.x, dy = py - A.y;
-      const float ar = splat_e2(splat_p2(A, B, dx, dy));
+      const float ar = splat_e2(splat_p2(B, splat_col(A, B, dx), dy));
       const bool act = j <= sLL[q] && fminf(kAlphaMax, ar) >= kAlphaMin;
       // a pixel this splat does not reach takes alpha 0 and its state stays as it is
       if (!act) continue;

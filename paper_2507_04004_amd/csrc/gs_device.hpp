@@ -110,9 +110,12 @@ __device__ __forceinline__ int view_of_tile(const ViewTable &vt, uint32_t gt) {
 // as its base-2 logarithm (alpha = o exp(-q/2) = 2^p, p = log2(e) (-q/2) + log2 o):
 //   sa = (u, v, a', b'), sb = (c', log2 o, d, b'/2), with a' = kA a, b' = 2 kA b, c' = kA c,
 //   kA = -log2(e) / 2, and log2 o = -inf for o <= 0 (and for the padding records).
-// p = dx (a' dx + b' dy) + c' dy^2 + log2 o <= log2 o in exact arithmetic; splat_e2 returns
-// 2^p clamped to [0, 1]. The forward and the backward both evaluate it through splat_p2 and
-// splat_e2, with fixed FMA placement, so they take identical alpha decisions.
+// p = (a' dx^2 + log2 o) + dy (b' dx + c' dy) <= log2 o in exact arithmetic, evaluated as a
+// column part (splat_col: the terms in dx alone, shared by the pixels of a lane, which sit in
+// one column of the tile) and the rest (splat_p2); splat_e2 returns 2^p clamped to [0, 1]. The
+// forward and the backward both evaluate it through these with fixed FMA placement, so they
+// take identical alpha decisions, and p depends on the pixel's offset from the splat only, not
+// on the tile size.
 constexpr float kA = -0.72134752044448170368f;  // -log2(e) / 2
 
 __device__ __forceinline__ void stage_card(const float4 &A, const float4 &B, const float4 &C, float4 &sa, float4 &sb,
@@ -123,13 +126,18 @@ __device__ __forceinline__ void stage_card(const float4 &A, const float4 &B, con
   sc = C;
 }
 
-// Exponent p at pixel offset (dx, dy), the opacity's logarithm included.
-__device__ __forceinline__ float splat_p2(const float4 &sa, const float4 &sb, float dx, float dy) {
+// The terms of the exponent in the column offset dx alone: a' dx^2 + log2 o, and b' dx.
+struct SplatCol {
+  float p0, bx;
+};
+__device__ __forceinline__ SplatCol splat_col(const float4 &sa, const float4 &sb, float dx) {
 #pragma clang fp contract(off)
-  const float m = sa.z * dx;
-  const float t = fmaf(sa.w, dy, m);
-  const float q = fmaf(sb.x * dy, dy, sb.y);
-  return fmaf(dx, t, q);
+  return SplatCol{fmaf(sa.z * dx, dx, sb.y), sa.w * dx};
+}
+
+// Exponent p at row offset dy from the column part, the opacity's logarithm included.
+__device__ __forceinline__ float splat_p2(const float4 &sb, const SplatCol &col, float dy) {
+  return fmaf(dy, fmaf(sb.x, dy, col.bx), col.p0);
 }
 
 // A staged record that no pixel blends (alpha 0 everywhere): the padding of a chunk.
